@@ -1,0 +1,165 @@
+/*
+ * plm.h -- C ABI of libplm, an MI355X (gfx950) implementation of asymmetric
+ * l2-regularised pseudolikelihood maximisation for direct-coupling analysis
+ * (asymmetric plmDCA: Ekeberg, Hartonen & Aurell, "Fast pseudolikelihood
+ * maximization for direct-coupling analysis of protein structure from many
+ * homologous amino-acid sequences", arXiv:1401.4832).
+ *
+ * The calls follow the method's rundown (sec. 3.4): reweight the alignment,
+ * evaluate or minimise the N per-site objectives, then score the couplings.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Pointers named *_dev, and every array argument unless stated otherwise,
+ *    are DEVICE pointers on the context's device, owned by the caller.  The
+ *    library never allocates device memory; scratch space comes from a
+ *    caller-provided workspace whose size the matching *_workspace_bytes call
+ *    returns (any 256-byte-aligned device buffer of at least that size).
+ *  - Arrays are C row-major:
+ *      msa  uint8  [B][N]        symbols 0..q-1 (20 = gap for q = 21)
+ *      w    double [B]           sequence weights; beff: one double
+ *      h    float  [N][q]        h[r][s] = h_r(s)
+ *      J    float  [N][N][q][q]  J[r][i][k][s] = J^{(r)}_{ri}(s,k): coupling of
+ *                                state s at site r with state k at site i, as
+ *                                seen by the site-r problem.  The self blocks
+ *                                J[r][r] are ignored on input, zero on output.
+ *  - Objective scale: f_r = B_eff * g_r^reg (eq. g_regdef2 multiplied by B_eff);
+ *    gradients are of f_r.  Convergence tolerances are on the paper's
+ *    normalised scale g_r^reg = f_r / B_eff.
+ *  - lambda_J is the symmetric-model strength; the per-site problems use
+ *    lambda'_J = 0.5 * lambda_J (sec. 3.4 step 1).
+ *  - Supported sizes: 2 <= q <= 21, N >= 2, B >= 1, N * q <= 65535.
+ *  - Calls enqueue work on the context's HIP stream and return without
+ *    waiting, except plm_fit, plm_fit_batch and plm_sync, which synchronise.
+ *    Errors detected on the device (a symbol >= q) are reported by the next
+ *    synchronising call.  A context is not thread-safe; use one per stream.
+ *  - Status codes: PLM_OK (0); PLM_W_MAXITER (+1, results written, some site
+ *    stopped at the iteration cap: see its stats); negative values are errors
+ *    after which outputs are unspecified.
+ */
+#ifndef PLM_H
+#define PLM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PLM_OK 0
+#define PLM_W_MAXITER 1
+#define PLM_E_INVALID -1     /* null pointer, bad size, theta outside [0,1], lambda < 0 */
+#define PLM_E_SYMBOL -2      /* an alignment symbol >= q (detected on the device) */
+#define PLM_E_NONFINITE -3   /* a non-finite value in an input */
+#define PLM_E_WORKSPACE -4   /* workspace missing, misaligned or too small */
+#define PLM_E_HIP -5         /* a HIP runtime error; plm_last_error() has the text */
+#define PLM_E_UNSUPPORTED -6 /* device is not gfx950, or an option not built */
+
+/* Objective/gradient evaluation paths. */
+#define PLM_PATH_GATHER_FP32 0 /* LDS gather/scatter, FP32 arithmetic, FP64 reductions */
+#define PLM_PATH_MFMA_BF16X2 1 /* one-hot BF16 MFMA contraction, hi/lo split operands */
+
+typedef struct plm_ctx plm_ctx;
+
+/* Create a context bound to `device` and to the HIP stream `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Fails with PLM_E_UNSUPPORTED on a
+ * device that is not gfx950.  The context holds host state and a few bytes of
+ * pinned host memory for device-to-host status flags. */
+int plm_ctx_create(plm_ctx **out, int device, void *hip_stream);
+int plm_ctx_destroy(plm_ctx *ctx);
+/* Text of the last error seen by this context (never NULL). */
+const char *plm_last_error(const plm_ctx *ctx);
+const char *plm_status_string(int status);
+/* Wait for the context's stream and report deferred device-side errors. */
+int plm_sync(plm_ctx *ctx);
+
+/* ---- Reweighting (sec. 3.1, eq. inverse_weights; sec. 3.4 step 2) --------
+ * m_b = #{a : id(a,b)/N >= theta} where id counts columns with equal symbols
+ * (gap equal to gap counts); the row itself is counted, so m_b >= 1.
+ * w_b = 1/m_b (correctly rounded FP64 division) and B_eff = sum_b w_b added in
+ * index order.  Integer counting makes m, w and B_eff exactly reproducible.
+ * uniform != 0 sets w_b = 1, B_eff = B (no similarity counting).
+ * Outputs (device): m_out int32[B] (may be NULL), w_out double[B],
+ * beff_out double[1].  No workspace. */
+int plm_reweight(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, int32_t q,
+                 double theta, int32_t uniform, int32_t *m_out, double *w_out,
+                 double *beff_out);
+
+/* ---- Objective and gradient (sec. 3.4 step 3: eqs. g_regdef2, g_gradh2,
+ * g_gradJ2), all listed sites at once ---------------------------------------
+ * sites: device int32[n_sites] of distinct site indices, or NULL for all N
+ * (then n_sites is ignored).  Outputs are indexed by site; only the rows of
+ * listed sites are written:
+ *   f_out  double[N]          f_r = B_eff * g_r^reg
+ *   gh_out float [N][q]       d f_r / d h_r(s)
+ *   gJ_out float [N][N][q][q] d f_r / d J_ri(s,k) at [r][i][k][s]; zero for i == r
+ * gh_out / gJ_out may be NULL to skip the gradient.  path is one of
+ * PLM_PATH_*.  beff is a device pointer (as written by plm_reweight). */
+size_t plm_objgrad_workspace_bytes(int32_t B, int32_t N, int32_t q, int32_t path);
+int plm_objgrad(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, int32_t q,
+                const double *w, const double *beff, const float *h, const float *J,
+                double lambda_h, double lambda_J, const int32_t *sites, int32_t n_sites,
+                int32_t path, void *workspace, size_t workspace_bytes, double *f_out,
+                float *gh_out, float *gJ_out);
+
+/* ---- Minimisation of every site (sec. 3.4 step 3) --------------------------
+ * One limited-memory BFGS state per site, all sites advanced together on the
+ * device; one replay of the captured iteration graph evaluates the trial
+ * point of every active site and takes each site's line-search decision.
+ * Starts from (h_io, J_io) -- zero gives the paper's cold start (sec. 6) --
+ * and leaves the minimiser there.  A site stops when ||grad g_r^reg||_2 <= tol
+ * (normalised scale), at max_iter, or on line-search failure. */
+typedef struct {
+  double lambda_h;      /* 0.01 */
+  double lambda_J;      /* 0.01 (lambda'_J = lambda_J / 2) */
+  double tol;           /* 1e-6 */
+  int32_t max_iter;     /* per site; 2000 */
+  int32_t lbfgs_m;      /* history pairs, 1..32; 10 */
+  int32_t max_linesearch; /* backtracking steps before a history reset; 20 */
+  int32_t path;         /* PLM_PATH_* */
+  int32_t sync_every;   /* graph replays between host checks of the active count; 8 */
+  int32_t use_graph;    /* 1: capture one iteration in a hipGraph; 0: eager launches */
+  int32_t single_site;  /* 1: the plain path -- one site per launch, eager, no graph */
+  int32_t tile_seqs;    /* forward tile rows per wave (16/32/64); 0 = default */
+  int32_t reserved[6];
+} plm_fit_opts;
+
+/* Fill *opts with the defaults listed above. */
+void plm_fit_opts_default(plm_fit_opts *opts);
+
+#define PLM_SITE_CONVERGED 0
+#define PLM_SITE_MAXITER 1
+#define PLM_SITE_LINESEARCH 2
+#define PLM_SITE_NONFINITE 3
+
+typedef struct {
+  int32_t iterations;   /* accepted steps */
+  int32_t evaluations;  /* objective+gradient evaluations */
+  int32_t status;       /* PLM_SITE_* */
+  int32_t pad;
+  double f;             /* final g_r^reg (normalised) */
+  double gnorm;         /* final ||grad g_r^reg||_2 as computed on the device */
+} plm_site_stats;
+
+/* stats_out: HOST array of N records (may be NULL). */
+size_t plm_fit_workspace_bytes(int32_t B, int32_t N, int32_t q, const plm_fit_opts *opts);
+int plm_fit(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, int32_t q,
+            const double *w, const double *beff, const plm_fit_opts *opts, void *workspace,
+            size_t workspace_bytes, float *h_io, float *J_io, plm_site_stats *stats_out);
+
+/* ---- Scoring (sec. 3.4 steps 4-6) ------------------------------------------
+ * For every pair i != j: both estimates are moved to the Ising gauge
+ * (eq. gauge_change2: subtract row and column means over all q states, add
+ * the grand mean), averaged (eq. average2, the site-j estimate transposed),
+ * reduced to a Frobenius norm FN_ij (eq. frob_normtrans2), and corrected by
+ * the average product (eq. corr_norm2) with means over all N positions,
+ * FN_ii = 0.  Outputs (device) double[N][N], symmetric, zero diagonal.
+ * FP64 arithmetic on the FP32 couplings.  No workspace. */
+int plm_score(plm_ctx *ctx, const float *J, int32_t N, int32_t q, double *fn_out,
+              double *cfn_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PLM_H */

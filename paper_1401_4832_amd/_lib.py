@@ -1,0 +1,99 @@
+"""ctypes declarations of libplm's C ABI (include/plm.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libplm.so")
+
+PLM_OK = 0
+PLM_W_MAXITER = 1
+PLM_E_INVALID = -1
+PLM_E_SYMBOL = -2
+PLM_E_NONFINITE = -3
+PLM_E_WORKSPACE = -4
+PLM_E_HIP = -5
+PLM_E_UNSUPPORTED = -6
+
+PATH_GATHER_FP32 = 0
+PATH_MFMA_BF16X2 = 1
+
+SITE_STATUS = {0: "converged", 1: "maxiter", 2: "linesearch", 3: "nonfinite"}
+
+
+class FitOpts(ctypes.Structure):
+    _fields_ = [
+        ("lambda_h", ctypes.c_double),
+        ("lambda_J", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("lbfgs_m", ctypes.c_int32),
+        ("max_linesearch", ctypes.c_int32),
+        ("path", ctypes.c_int32),
+        ("sync_every", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
+        ("single_site", ctypes.c_int32),
+        ("tile_seqs", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
+    ]
+
+
+class SiteStats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32),
+        ("evaluations", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("f", ctypes.c_double),
+        ("gnorm", ctypes.c_double),
+    ]
+
+
+class PlmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libplm status {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libplm.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python -m paper_1401_4832_amd._build")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+        sig = {
+            "plm_ctx_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, P]),
+            "plm_ctx_destroy": (ctypes.c_int, [P]),
+            "plm_last_error": (ctypes.c_char_p, [P]),
+            "plm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+            "plm_sync": (ctypes.c_int, [P]),
+            "plm_reweight": (ctypes.c_int, [P, P, I32, I32, I32, D, I32, P, P, P]),
+            "plm_objgrad_workspace_bytes": (SZ, [I32, I32, I32, I32]),
+            "plm_objgrad": (ctypes.c_int, [P, P, I32, I32, I32, P, P, P, P, D, D, P, I32, I32, P, SZ,
+                                           P, P, P]),
+            "plm_fit_opts_default": (None, [ctypes.POINTER(FitOpts)]),
+            "plm_fit_workspace_bytes": (SZ, [I32, I32, I32, ctypes.POINTER(FitOpts)]),
+            "plm_fit": (ctypes.c_int, [P, P, I32, I32, I32, P, P, ctypes.POINTER(FitOpts), P, SZ, P, P,
+                                       ctypes.POINTER(SiteStats)]),
+            "plm_score": (ctypes.c_int, [P, P, I32, I32, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """Names declared in include/plm.h that the ABI tests check for."""
+    return ["plm_ctx_create", "plm_ctx_destroy", "plm_last_error", "plm_status_string", "plm_sync",
+            "plm_reweight", "plm_objgrad_workspace_bytes", "plm_objgrad", "plm_fit_opts_default",
+            "plm_fit_workspace_bytes", "plm_fit", "plm_score"]

@@ -1,0 +1,190 @@
+"""Python binding of libplm over torch tensors (device memory and streams only).
+
+Every function marshals tensors into the C ABI of include/plm.h; all arithmetic
+runs in the library's HIP kernels on the tensor's device, on the current
+stream.  There is no CPU fallback: without the built library or a gfx950
+device the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib as L
+
+_ctx_cache: dict = {}
+
+
+def _check(rc: int, ctx) -> int:
+    if rc < 0:
+        msg = L.lib().plm_last_error(ctx).decode() if ctx else L.lib().plm_status_string(rc).decode()
+        raise L.PlmError(rc, msg)
+    return rc
+
+
+def context(device=None):
+    """The library context bound to `device` and torch's current stream there."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    if dev.type != "cuda":
+        raise ValueError("libplm runs on a GPU device")
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    stream = torch.cuda.current_stream(idx).cuda_stream
+    key = (idx, stream)
+    c = _ctx_cache.get(key)
+    if c is None:
+        p = ctypes.c_void_p()
+        rc = L.lib().plm_ctx_create(ctypes.byref(p), idx, ctypes.c_void_p(stream))
+        if rc != 0:
+            raise L.PlmError(rc, L.lib().plm_status_string(rc).decode())
+        c = p
+        _ctx_cache[key] = c
+    return c
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev_tensor(t, dtype, device, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def sync(device=None):
+    ctx = context(device)
+    _check(L.lib().plm_sync(ctx), ctx)
+
+
+def reweight(msa: torch.Tensor, theta: float = 0.8, uniform: bool = False, q: int = 21):
+    """(m int32[B], w float64[B], beff float64[1]) on msa's device (sec. 3.1)."""
+    dev = msa.device
+    _dev_tensor(msa, torch.uint8, dev, "msa")
+    B, N = msa.shape
+    m = torch.empty(B, dtype=torch.int32, device=dev)
+    w = torch.empty(B, dtype=torch.float64, device=dev)
+    beff = torch.empty(1, dtype=torch.float64, device=dev)
+    ctx = context(dev)
+    _check(L.lib().plm_reweight(ctx, _ptr(msa), B, N, q, float(theta), int(bool(uniform)), _ptr(m),
+                                _ptr(w), _ptr(beff)), ctx)
+    return m, w, beff
+
+
+def objgrad(msa, w, beff, h, J, lambda_h=0.01, lambda_J=0.01, sites=None, grad=True,
+            path=L.PATH_GATHER_FP32):
+    """f float64[N], gh float32[N,q], gJ float32[N,N,q,q] for the listed sites (all if None).
+
+    Rows of unlisted sites are left zero.  f_r = B_eff * g_r^reg."""
+    dev = msa.device
+    _dev_tensor(msa, torch.uint8, dev, "msa")
+    B, N = msa.shape
+    q = h.shape[1]
+    _dev_tensor(w, torch.float64, dev, "w")
+    _dev_tensor(beff, torch.float64, dev, "beff")
+    _dev_tensor(h, torch.float32, dev, "h")
+    _dev_tensor(J, torch.float32, dev, "J")
+    if tuple(J.shape) != (N, N, q, q) or tuple(h.shape) != (N, q) or w.numel() != B:
+        raise ValueError("shape mismatch between msa, w, h and J")
+    if sites is not None:
+        sites = torch.as_tensor(sites, dtype=torch.int32).to(dev).contiguous()
+        ns = int(sites.numel())
+    else:
+        ns = N
+    f = torch.zeros(N, dtype=torch.float64, device=dev)
+    gh = torch.zeros(N, q, dtype=torch.float32, device=dev) if grad else None
+    gJ = torch.zeros(N, N, q, q, dtype=torch.float32, device=dev) if grad else None
+    nbytes = L.lib().plm_objgrad_workspace_bytes(B, N, q, path)
+    ws = workspace(nbytes, dev)
+    ctx = context(dev)
+    _check(L.lib().plm_objgrad(ctx, _ptr(msa), B, N, q, _ptr(w), _ptr(beff), _ptr(h), _ptr(J),
+                               float(lambda_h), float(lambda_J), _ptr(sites), ns, path, _ptr(ws),
+                               ws.numel(), _ptr(f), _ptr(gh), _ptr(gJ)), ctx)
+    return f, gh, gJ
+
+
+@dataclass
+class FitOptions:
+    lambda_h: float = 0.01
+    lambda_J: float = 0.01
+    tol: float = 1e-6
+    max_iter: int = 2000
+    lbfgs_m: int = 10
+    max_linesearch: int = 20
+    path: int = L.PATH_GATHER_FP32
+    sync_every: int = 8
+    use_graph: bool = True
+    single_site: bool = False
+    tile_seqs: int = 0
+
+    def to_c(self) -> L.FitOpts:
+        o = L.FitOpts()
+        L.lib().plm_fit_opts_default(ctypes.byref(o))
+        for k in ("lambda_h", "lambda_J", "tol"):
+            setattr(o, k, float(getattr(self, k)))
+        for k in ("max_iter", "lbfgs_m", "max_linesearch", "path", "sync_every", "tile_seqs"):
+            setattr(o, k, int(getattr(self, k)))
+        o.use_graph = int(bool(self.use_graph))
+        o.single_site = int(bool(self.single_site))
+        return o
+
+
+@dataclass
+class FitResult:
+    h: torch.Tensor
+    J: torch.Tensor
+    stats: list = field(default_factory=list)
+    status: int = 0
+
+    @property
+    def evaluations(self) -> int:
+        return int(sum(s["evaluations"] for s in self.stats))
+
+
+def fit(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None) -> FitResult:
+    """Minimise every site's g_r^reg (sec. 3.4 step 3) from (h0, J0) (zeros by default)."""
+    opts = opts or FitOptions()
+    dev = msa.device
+    _dev_tensor(msa, torch.uint8, dev, "msa")
+    B, N = msa.shape
+    q = 21 if h0 is None else h0.shape[1]
+    h = torch.zeros(N, q, dtype=torch.float32, device=dev) if h0 is None else h0.clone().contiguous()
+    J = torch.zeros(N, N, q, q, dtype=torch.float32, device=dev) if J0 is None else J0.clone().contiguous()
+    _dev_tensor(w, torch.float64, dev, "w")
+    _dev_tensor(beff, torch.float64, dev, "beff")
+    co = opts.to_c()
+    nbytes = L.lib().plm_fit_workspace_bytes(B, N, q, ctypes.byref(co))
+    if nbytes == 0:
+        raise L.PlmError(L.PLM_E_INVALID, "invalid sizes or options")
+    ws = workspace(nbytes, dev)
+    stats = (L.SiteStats * N)()
+    ctx = context(dev)
+    rc = _check(L.lib().plm_fit(ctx, _ptr(msa), B, N, q, _ptr(w), _ptr(beff), ctypes.byref(co), _ptr(ws),
+                                ws.numel(), _ptr(h), _ptr(J), stats), ctx)
+    del ws
+    st = [dict(iterations=s.iterations, evaluations=s.evaluations, status=L.SITE_STATUS.get(s.status, "?"),
+               f=s.f, gnorm=s.gnorm) for s in stats]
+    return FitResult(h, J, st, rc)
+
+
+def score(J: torch.Tensor):
+    """(FN, CFN) float64 [N, N] (sec. 3.4 steps 4-6)."""
+    dev = J.device
+    _dev_tensor(J, torch.float32, dev, "J")
+    N, _, q, _ = J.shape
+    fn = torch.empty(N, N, dtype=torch.float64, device=dev)
+    cfn = torch.empty(N, N, dtype=torch.float64, device=dev)
+    ctx = context(dev)
+    _check(L.lib().plm_score(ctx, _ptr(J), N, q, _ptr(fn), _ptr(cfn)), ctx)
+    return fn, cfn

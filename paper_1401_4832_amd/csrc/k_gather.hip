@@ -1,0 +1,267 @@
+// k_gather.hip -- FP32 gather/scatter evaluation of the per-site objective and
+// gradient of asymmetric plmDCA (sec. 3.4 step 3: eqs. g_regdef2, g_gradh2,
+// g_gradJ2) for many sites at once.
+//
+// Forward (one block = one site r x a tile of sequences): the site's coupling
+// slice J_r is streamed through LDS sixteen columns at a time; each lane adds
+// J_ri(s, sigma_i^b) into the energy E_b(s) of its (sequence, state) pair
+// (eq. condpfinal), then a 21-lane segmented reduction gives log Z_b, the
+// objective term w_b (log Z_b - E_b(sigma_r^b)) and the residual
+// R_b(s) = w_b (P_b(s) - [sigma_r^b = s]), which is written to HBM.
+//
+// Backward (one block = one site r x 24 alignment columns, all sequences):
+// dJ_ri(s,k) = sum_b [sigma_i^b = k] R_b(s).  Each wave owns three columns, so
+// its read-modify-write scatter into LDS never races with another wave, and
+// the three 21-lane slots of a wave write three bank-disjoint copies of each
+// row.  FP32 LDS partials are folded into FP64 registers every 768 sequences.
+#include "plm_internal.h"
+
+namespace plm {
+
+__global__ void pad_msa_kernel(const uint8_t* __restrict__ msa, int32_t B, int32_t N, int32_t q,
+                               uint8_t* __restrict__ out, int32_t B_pad, int32_t N_pad,
+                               int32_t* flag) {
+  const size_t total = (size_t)B_pad * N_pad;
+  int bad = 0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int32_t b = (int32_t)(e / N_pad), i = (int32_t)(e - (size_t)b * N_pad);
+    uint8_t v = 0;
+    if (b < B && i < N) {
+      v = msa[(size_t)b * N + i];
+      if (v >= q) { bad = 1; v = 0; }
+    }
+    out[e] = v;
+  }
+  if (bad && flag) atomicOr(flag, 1);
+}
+
+hipError_t launch_pad_msa(const uint8_t* msa, int32_t B, int32_t N, int32_t q, uint8_t* msa_pad,
+                          int32_t B_pad, int32_t N_pad, int32_t* flag_dev, hipStream_t st) {
+  const size_t total = (size_t)B_pad * N_pad;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(pad_msa_kernel, dim3(blocks), dim3(256), 0, st, msa, B, N, q, msa_pad, B_pad,
+                     N_pad, flag_dev);
+  return hipGetLastError();
+}
+
+int32_t forward_tile_seqs(int32_t nb) { return kFwdWaves * kSlots * nb; }
+
+template <int NB>
+__global__ __launch_bounds__(kFwdThreads) void fwd_kernel(EvalArgs a) {
+  constexpr int tileSeq = kFwdWaves * kSlots * NB;
+  __shared__ float lds[kFwdChunk * kQMax * kRowF];  // 86 KB: J_r for 16 columns, 3 copies per row
+  __shared__ uint4 sgl[tileSeq];                    // symbols of the tile's rows for those columns
+  __shared__ double red[kFwdWaves * 64];
+  const int idx = blockIdx.y;
+  const int nact = a.n_active ? *a.n_active : a.n_active_host;
+  if (idx >= nact) return;
+  const int r = a.sites ? a.sites[idx] : idx;
+  const int q = a.q, N = a.N, qq = q * q;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int slot = lane / kSlot, s = lane - slot * kSlot;
+  const int slotA = slot < kSlots ? slot : kSlots - 1;  // lane 63 shadows slot 2 for addressing
+  const bool act = (slot < kSlots) && (s < q);
+  const int tile0 = blockIdx.x * tileSeq;
+  const int tw = wid * (NB * kSlots) + slotA;  // tile row of row j: tw + 3j
+  const int bw = tile0 + tw;
+
+  float E[NB];
+  const float hv = act ? a.h[r * q + s] : 0.f;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) E[j] = hv;
+
+  const size_t Jr = (size_t)r * N * qq;
+  const int nchunks = a.N_pad / kFwdChunk;
+  const char* L = reinterpret_cast<const char*>(lds);
+  const uint32_t lane4 = 4u * lane;
+  for (int c = 0; c < nchunks; ++c) {
+    __syncthreads();
+    for (int e = tid; e < kFwdChunk * qq; e += kFwdThreads) {
+      const int p = e / qq, rem = e - p * qq, k = rem / q, ss = rem - k * q;
+      const int i = c * kFwdChunk + p;
+      const float v = (i < N && i != r) ? a.J[Jr + (size_t)i * qq + rem] : 0.f;
+      float* row = lds + (p * q + k) * kRowF;
+      row[ss] = v;
+      row[ss + kSlot] = v;
+      row[ss + 2 * kSlot] = v;
+    }
+    for (int e = tid; e < tileSeq; e += kFwdThreads)
+      sgl[e] = *reinterpret_cast<const uint4*>(a.msa_pad + (size_t)(tile0 + e) * a.N_pad + c * kFwdChunk);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const uint4 sg = sgl[tw + 3 * j];
+      float acc = E[j];
+#pragma unroll
+      for (int p = 0; p < kFwdChunk; ++p) {
+        const uint32_t word = p < 4 ? sg.x : p < 8 ? sg.y : p < 12 ? sg.z : sg.w;
+        const uint32_t sig = (word >> (8 * (p & 3))) & 0xffu;
+        // row (p, sig) of 64 floats = 256 bytes; the lane's column is fixed
+        const uint32_t off = (uint32_t)(p * q) * 256u + lane4 + (sig << 8);
+        acc += *reinterpret_cast<const float*>(L + off);
+      }
+      E[j] = acc;
+      // keep one row's loads in flight at a time, so rows do not pile up in registers
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+
+  // log-softmax over the 21 lanes of each slot, objective and residuals.  The
+  // energies are parked in the (now free) LDS sixteen rows at a time so that
+  // the per-row work below runs as a loop rather than unrolled over all rows.
+  double facc = 0.0, ghacc = 0.0;
+  const int sbase = slotA * kSlot;
+  float* park = lds + wid * (16 * 64);  // 16 rows x 64 lanes per wave (64 KB in all)
+#pragma unroll
+  for (int g = 0; g < NB / 16; ++g) {
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) park[jj * 64 + lane] = E[g * 16 + jj];
+    __syncthreads();
+#pragma unroll 1
+    for (int jj = 0; jj < 16; ++jj) {
+      const int b = bw + 3 * (g * 16 + jj);
+      const float e = act ? park[jj * 64 + lane] : -INFINITY;
+      float m = e;
+#pragma unroll
+      for (int d = 1; d < 32; d <<= 1) {
+        const float o = __shfl_down(m, d, 64);
+        if (s + d < kSlot) m = fmaxf(m, o);
+      }
+      m = __shfl(m, sbase, 64);
+      const float ex = act ? expf(e - m) : 0.f;
+      float sum = ex;
+#pragma unroll
+      for (int d = 1; d < 32; d <<= 1) {
+        const float o = __shfl_down(sum, d, 64);
+        if (s + d < kSlot) sum += o;
+      }
+      sum = __shfl(sum, sbase, 64);
+      const float lse = m + logf(sum);
+      const int sr = a.msa_pad[(size_t)b * a.N_pad + r];
+      const double wb = (slot < kSlots && b < a.B) ? a.w[b] : 0.0;
+      const float P = ex / sum;
+      const float Rv = act ? (float)wb * (P - (s == sr ? 1.f : 0.f)) : 0.f;
+      if (act && s == sr) facc += wb * (double)(lse - e);
+      ghacc += (double)Rv;
+      if (slot < kSlots && b < a.B3) a.R[((size_t)r * a.B3 + b) * kSlot + s] = Rv;
+    }
+  }
+  const double ftot = block_sum_f64(facc, red);
+  if (tid == 0) a.f_part[(size_t)blockIdx.x * N + r] = ftot;
+  red[wid * 64 + lane] = (slot < kSlots) ? ghacc : 0.0;
+  __syncthreads();
+  if (tid < kSlot) {
+    double t = 0.0;
+    for (int w = 0; w < kFwdWaves; ++w)
+      for (int c = 0; c < kSlots; ++c) t += red[w * 64 + c * kSlot + tid];
+    a.gh_part[((size_t)blockIdx.x * N + r) * kSlot + tid] = t;
+  }
+}
+
+hipError_t launch_forward(const EvalArgs& a, int32_t n_sites_grid, int32_t nb, hipStream_t st) {
+  const int tiles = (a.B + forward_tile_seqs(nb) - 1) / forward_tile_seqs(nb);
+  dim3 grid(tiles, n_sites_grid);
+  switch (nb) {
+    case 16: hipLaunchKernelGGL(fwd_kernel<16>, grid, dim3(kFwdThreads), 0, st, a); break;
+    case 32: hipLaunchKernelGGL(fwd_kernel<32>, grid, dim3(kFwdThreads), 0, st, a); break;
+    case 64: hipLaunchKernelGGL(fwd_kernel<64>, grid, dim3(kFwdThreads), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBwdThreads) void bwd_kernel(EvalArgs a) {
+  __shared__ float acc[kBwdPos * kQMax * kRowF];       // 129 KB
+  __shared__ float Rs[kBwdSeqChunk * kSlot];           // 16 KB
+  __shared__ uint32_t sg[kBwdWaves * kBwdSeqChunk];    // 6 KB
+  constexpr int KOWN = (kBwdPos * kQMax * kQMax + kBwdThreads - 1) / kBwdThreads;
+  const int idx = blockIdx.y;
+  const int nact = a.n_active ? *a.n_active : a.n_active_host;
+  if (idx >= nact) return;
+  const int r = a.sites ? a.sites[idx] : idx;
+  const int q = a.q, N = a.N, qq = q * q;
+  const int i0 = blockIdx.x * kBwdPos;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int slot = lane / kSlot, s = lane - slot * kSlot;
+
+  for (int e = tid; e < kBwdPos * q * kRowF; e += kBwdThreads) acc[e] = 0.f;
+  double dacc[KOWN];
+#pragma unroll
+  for (int k = 0; k < KOWN; ++k) dacc[k] = 0.0;
+
+  const int nchunks = (a.B3 + kBwdSeqChunk - 1) / kBwdSeqChunk;
+  const float* Rr = a.R + (size_t)r * a.B3 * kSlot;
+  const int pbase = wid * kBwdPosPerWave;
+  for (int c = 0; c < nchunks; ++c) {
+    const int bc = c * kBwdSeqChunk;
+    __syncthreads();
+    for (int e = tid; e < kBwdSeqChunk * kSlot; e += kBwdThreads) {
+      const int b = bc + e / kSlot;
+      Rs[e] = (b < a.B3) ? Rr[(size_t)bc * kSlot + e] : 0.f;
+    }
+    for (int e = tid; e < kBwdWaves * kBwdSeqChunk; e += kBwdThreads) {
+      const int w = e / kBwdSeqChunk, t = e - w * kBwdSeqChunk, b = bc + t;
+      uint32_t v = 0;
+      if (b < a.B3) {
+        const uint8_t* mrow = a.msa_pad + (size_t)b * a.N_pad;
+#pragma unroll
+        for (int p = 0; p < kBwdPosPerWave; ++p) {
+          const int i = i0 + w * kBwdPosPerWave + p;
+          if (i < a.N_pad) v |= (uint32_t)mrow[i] << (8 * p);
+        }
+      }
+      sg[e] = v;
+    }
+    __syncthreads();
+    if (slot < kSlots) {
+      const int nt = min(kBwdSeqChunk, a.B3 - bc) / kSlots;
+      for (int j = 0; j < nt; ++j) {
+        const int t = kSlots * j + slot;
+        const float Rv = Rs[t * kSlot + s];
+        const uint32_t sv = sg[wid * kBwdSeqChunk + t];
+        const int a0 = ((pbase + 0) * q + (int)(sv & 0xffu)) * kRowF + lane;
+        const int a1 = ((pbase + 1) * q + (int)((sv >> 8) & 0xffu)) * kRowF + lane;
+        const int a2 = ((pbase + 2) * q + (int)((sv >> 16) & 0xffu)) * kRowF + lane;
+        // the three columns are distinct, so the reads may all precede the writes
+        const float v0 = acc[a0], v1 = acc[a1], v2 = acc[a2];
+        acc[a0] = v0 + Rv;
+        acc[a1] = v1 + Rv;
+        acc[a2] = v2 + Rv;
+      }
+    }
+    if ((c + 1) % kBwdFlushChunks == 0 || c == nchunks - 1) {
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < KOWN; ++k) {
+        const int e = tid + k * kBwdThreads;
+        if (e < kBwdPos * qq) {
+          const int p = e / qq, rem = e - p * qq, kk = rem / q, ss = rem - kk * q;
+          float* row = acc + (p * q + kk) * kRowF;
+          dacc[k] += (double)row[ss] + (double)row[ss + kSlot] + (double)row[ss + 2 * kSlot];
+          row[ss] = 0.f;
+          row[ss + kSlot] = 0.f;
+          row[ss + 2 * kSlot] = 0.f;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KOWN; ++k) {
+    const int e = tid + k * kBwdThreads;
+    if (e < kBwdPos * qq) {
+      const int p = e / qq, rem = e - p * qq, i = i0 + p;
+      if (i < N) a.gJ[((size_t)r * N + i) * qq + rem] = (i == r) ? 0.0 : dacc[k];
+    }
+  }
+}
+
+hipError_t launch_backward(const EvalArgs& a, int32_t n_sites_grid, hipStream_t st) {
+  dim3 grid((a.N + kBwdPos - 1) / kBwdPos, n_sites_grid);
+  hipLaunchKernelGGL(bwd_kernel, grid, dim3(kBwdThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace plm

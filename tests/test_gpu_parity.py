@@ -1,0 +1,197 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (on the paper's normalised scale g = f / B_eff):
+  * reweighting: bit-exact (integer counts, correctly rounded 1/m, index-order B_eff);
+  * objective: |f_gpu - f_oracle| / |f_oracle| <= 1e-5 per site;
+  * gradient: max |g_gpu - g_oracle| / B_eff <= 2e-6.  The energies are FP32 sums
+    of up to N - 1 couplings (|J| ~ 0.1-1 here), so each softmax probability
+    carries a relative error of order sqrt(N) * 2^-24 * max|E| (~1e-6); the
+    data gradient is a B_eff-normalised sum of w_b (P - I) and inherits it;
+  * scores: relative 1e-9 (FP64 on identical FP32 couplings).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.helpers import clustered_msa, load_reweight_golden, random_params
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def plm():
+    import paper_1401_4832_amd as plm
+    return plm
+
+
+def _note(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _to(x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(DEV)
+
+
+# ---------------------------------------------------------------- reweighting
+@pytest.mark.parametrize("theta", [0.0, 0.6, 0.8, 1.0])
+def test_reweight_golden(plm, theta):
+    import os
+    rows, cases = load_reweight_golden(os.path.join(os.path.dirname(__file__), "golden", "reweight_tiny.txt"))
+    _note(f"reweight golden theta={theta}")
+    m, w, beff = plm.reweight(_to(rows), theta=theta)
+    plm.sync(DEV)
+    m_o, w_o, beff_o = oracle.reweight(rows, theta=theta)
+    assert np.array_equal(m.cpu().numpy(), m_o)
+    assert np.array_equal(w.cpu().numpy(), w_o)
+    assert beff.item() == beff_o
+
+
+@pytest.mark.parametrize("B,N,p_mut,theta", [(1, 7, 0.1, 0.8), (65, 13, 0.1, 0.8), (700, 37, 0.12, 0.8),
+                                             (1300, 120, 0.2, 0.8), (999, 64, 0.15, 0.7),
+                                             (513, 5, 0.3, 0.6)])
+def test_reweight_clustered_bit_exact(plm, B, N, p_mut, theta):
+    _note(f"reweight clustered B={B} N={N} theta={theta}")
+    msa = clustered_msa(seed=B + N, B=B, N=N, n_anc=max(1, B // 40), p_mut=p_mut)
+    m, w, beff = plm.reweight(_to(msa), theta=theta)
+    plm.sync(DEV)
+    m_o, w_o, beff_o = oracle.reweight(msa, theta=theta)
+    assert np.array_equal(m.cpu().numpy(), m_o)
+    assert np.array_equal(w.cpu().numpy(), w_o)
+    assert beff.item() == beff_o
+
+
+def test_reweight_workload_gapped(plm):
+    s = synth.workload("potts_n120_b5000_gaps")
+    _note("reweight potts_n120_b5000_gaps")
+    m, w, beff = plm.reweight(_to(s.msa), theta=0.8)
+    plm.sync(DEV)
+    m_o, w_o, beff_o = oracle.reweight(s.msa, theta=0.8)
+    assert np.array_equal(m.cpu().numpy(), m_o) and beff.item() == beff_o
+
+
+def test_reweight_uniform(plm):
+    msa = clustered_msa(seed=1, B=300, N=20, n_anc=3, p_mut=0.05)
+    m, w, beff = plm.reweight(_to(msa), uniform=True)
+    plm.sync(DEV)
+    assert torch.all(w == 1.0) and beff.item() == 300.0
+
+
+# ----------------------------------------------------------- objective/grad
+def _objgrad_case(plm, msa, w_o, beff_o, h, J, lh=0.01, lJ=0.01, sites=None):
+    B, N = msa.shape
+    q = h.shape[1]
+    w = _to(w_o)
+    beff = _to(np.array([beff_o]))
+    f, gh, gJ = plm.objgrad(_to(msa), w, beff, _to(h.astype(np.float32)), _to(J.astype(np.float32)),
+                            lh, lJ, sites=sites)
+    plm.sync(DEV)
+    Jz = J.astype(np.float32).astype(np.float64)
+    for r in range(N):
+        Jz[r, r] = 0
+    hz = h.astype(np.float32).astype(np.float64)
+    idx = np.arange(N) if sites is None else np.asarray(sites)
+    fo, gho, gJo = oracle.objgrad(msa, w_o, beff_o, hz, Jz, lh, lJ, sites=idx)
+    f = f.cpu().numpy()[idx]
+    gh = gh.cpu().numpy()[idx]
+    gJ = gJ.cpu().numpy()[idx]
+    frel = np.max(np.abs(f - fo) / np.abs(fo))
+    gerr = max(np.max(np.abs(gJ - gJo)), np.max(np.abs(gh - gho))) / beff_o
+    return frel, gerr, gJ
+
+
+@pytest.mark.parametrize("B,N,q", [(500, 40, 21), (1, 2, 21), (7, 17, 21), (3001, 33, 21), (800, 25, 3),
+                                   (1537, 49, 11), (4000, 70, 21)])
+def test_objgrad_random_point(plm, B, N, q):
+    _note(f"objgrad random B={B} N={N} q={q}")
+    rng = np.random.default_rng(B * 7 + N)
+    msa = rng.integers(0, q, size=(B, N), dtype=np.uint8)
+    w_o = rng.uniform(0.2, 1.0, size=B)
+    beff_o = float(np.sum(w_o))
+    h, J = random_params(B + q, N, q, 0.3, 0.2)
+    frel, gerr, gJ = _objgrad_case(plm, msa, w_o, beff_o, h, J)
+    assert frel <= 1e-5, frel
+    assert gerr <= 2e-6, gerr
+    for r in range(N):
+        assert np.all(gJ[r, r] == 0)
+
+
+def test_objgrad_workload_gapped(plm):
+    s = synth.workload("potts_n120_b5000_gaps")
+    _note("objgrad potts_n120_b5000_gaps")
+    m_o, w_o, beff_o = oracle.reweight(s.msa, theta=0.8)
+    h, J = random_params(3, s.N, 21, 0.1, 0.1)
+    frel, gerr, _ = _objgrad_case(plm, s.msa, w_o, beff_o, h, J, sites=[0, 5, 60, 119])
+    assert frel <= 1e-5 and gerr <= 2e-6, (frel, gerr)
+
+
+def test_objgrad_at_origin_is_beff_log_q(plm):
+    s = synth.workload("potts_n40_b500")
+    msa = _to(s.msa)
+    m, w, beff = plm.reweight(msa, uniform=True)
+    f, gh, gJ = plm.objgrad(msa, w, beff, torch.zeros(40, 21, device=DEV),
+                            torch.zeros(40, 40, 21, 21, device=DEV))
+    plm.sync(DEV)
+    np.testing.assert_allclose(f.cpu().numpy(), 500 * np.log(21.0), rtol=1e-7)
+
+
+def test_objgrad_deterministic(plm):
+    rng = np.random.default_rng(9)
+    msa = rng.integers(0, 21, size=(2000, 30), dtype=np.uint8)
+    w = _to(np.ones(2000))
+    beff = _to(np.array([2000.0]))
+    h, J = random_params(10, 30, 21)
+    ht, Jt = _to(h.astype(np.float32)), _to(J.astype(np.float32))
+    a = plm.objgrad(_to(msa), w, beff, ht, Jt)
+    b = plm.objgrad(_to(msa), w, beff, ht, Jt)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2])
+
+
+# ---------------------------------------------------------------- scoring
+@pytest.mark.parametrize("N,q", [(2, 21), (40, 21), (9, 4), (130, 21)])
+def test_score_matches_oracle(plm, N, q):
+    _note(f"score N={N} q={q}")
+    rng = np.random.default_rng(N)
+    J = rng.standard_normal((N, N, q, q)).astype(np.float32)
+    fn, cfn = plm.score(_to(J))
+    plm.sync(DEV)
+    fn_o, cfn_o = oracle.score(J)
+    np.testing.assert_allclose(fn.cpu().numpy(), fn_o, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(cfn.cpu().numpy(), cfn_o, rtol=1e-9, atol=1e-12)
+
+
+# ---------------------------------------------------------------- errors
+def test_symbol_out_of_range_is_reported(plm):
+    msa = np.zeros((10, 5), dtype=np.uint8)
+    msa[3, 2] = 21
+    plm.reweight(_to(msa), theta=0.8)
+    with pytest.raises(plm.PlmError) as e:
+        plm.sync(DEV)
+    assert e.value.code == -2
+
+
+def test_nonfinite_input_is_reported(plm):
+    msa = np.zeros((10, 5), dtype=np.uint8)
+    w = _to(np.ones(10))
+    beff = _to(np.array([10.0]))
+    J = torch.zeros(5, 5, 21, 21, device=DEV)
+    J[1, 2, 3, 4] = float("nan")
+    plm.objgrad(_to(msa), w, beff, torch.zeros(5, 21, device=DEV), J)
+    with pytest.raises(plm.PlmError) as e:
+        plm.sync(DEV)
+    assert e.value.code == -3
+
+
+def test_invalid_arguments_are_rejected(plm):
+    msa = _to(np.zeros((10, 5), dtype=np.uint8))
+    with pytest.raises(plm.PlmError) as e:
+        plm.reweight(msa, theta=1.5)
+    assert e.value.code == -1
+    with pytest.raises(plm.PlmError):
+        plm.reweight(msa, q=22)
