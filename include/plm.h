@@ -80,8 +80,8 @@ int plm_sync(plm_ctx *ctx);
  * w_b = 1/m_b (correctly rounded FP64 division) and B_eff = sum_b w_b added in
  * index order.  Integer counting makes m, w and B_eff exactly reproducible.
  * uniform != 0 sets w_b = 1, B_eff = B (no similarity counting).
- * Outputs (device): m_out int32[B] (may be NULL), w_out double[B],
- * beff_out double[1].  No workspace. */
+ * Outputs (device): m_out int32[B], w_out double[B], beff_out double[1].
+ * No workspace. */
 int plm_reweight(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, int32_t q,
                  double theta, int32_t uniform, int32_t *m_out, double *w_out,
                  double *beff_out);
@@ -122,7 +122,11 @@ typedef struct {
   int32_t use_graph;    /* 1: capture one iteration in a hipGraph; 0: eager launches */
   int32_t single_site;  /* 1: the plain path -- one site per launch, eager, no graph */
   int32_t tile_seqs;    /* forward tile rows per wave (16/32/64); 0 = default */
-  int32_t reserved[6];
+  int32_t site_limit;   /* single_site only: fit sites 0..site_limit-1 (0 = all) */
+  int32_t timing;       /* 1: launch the iteration eagerly (no graph) with HIP events
+                           between the kernels on the fit's stream, synchronise every
+                           iteration, and keep the kernel times: plm_fit_last_timing */
+  int32_t reserved[4];
 } plm_fit_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -141,6 +145,20 @@ typedef struct {
   double f;             /* final g_r^reg (normalised) */
   double gnorm;         /* final ||grad g_r^reg||_2 as computed on the device */
 } plm_site_stats;
+
+/* Kernel times of the last plm_fit on this context that ran with timing = 1,
+ * summed over all iterations (milliseconds, from HIP events recorded on the
+ * stream the kernels run on), and the number of iterations timed. */
+typedef struct {
+  double forward_ms;    /* energies, log-softmax, residuals */
+  double backward_ms;   /* coupling-gradient scatter */
+  double lbfgs_ms;      /* line search decision, history update, two-loop recursion */
+  double total_ms;      /* wall time of the fit on the device stream */
+  int64_t iterations;   /* graph replays (or eager iterations) executed */
+  int64_t site_evals;   /* site objective+gradient evaluations performed */
+} plm_fit_timing;
+
+int plm_fit_last_timing(const plm_ctx *ctx, plm_fit_timing *out);
 
 /* stats_out: HOST array of N records (may be NULL). */
 size_t plm_fit_workspace_bytes(int32_t B, int32_t N, int32_t q, const plm_fit_opts *opts);

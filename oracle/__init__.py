@@ -59,6 +59,8 @@ def _lib():
         L.oracle_site_objgrad.restype = D
         L.oracle_objgrad.argtypes = [P, I, I, I, P, D, P, P, D, D, P, I, P, P, P, I]
         L.oracle_objgrad.restype = None
+        L.oracle_objgrad_slices.argtypes = [P, I, I, I, P, D, P, P, D, D, P, I, P, P, P, I]
+        L.oracle_objgrad_slices.restype = None
         L.oracle_site_fit.argtypes = [P, I, I, I, I, P, D, D, D, ctypes.POINTER(FitOpts), P, P,
                                       ctypes.POINTER(FitStats)]
         L.oracle_site_fit.restype = I
@@ -147,6 +149,27 @@ def objgrad(msa, w, beff, h, J, lambda_h=0.01, lambda_J=0.01, sites=None, nthrea
     gJ = np.zeros((ns, N, q, q))
     _lib().oracle_objgrad(_p(msa), B, N, q, _p(w), float(beff), _p(h), _p(J), float(lambda_h),
                           float(lambda_J), _p(sites), ns, _p(f), _p(gh), _p(gJ), _threads(nthreads))
+    return f, gh, gJ
+
+
+def objgrad_slices(msa, w, beff, hr, Jr, sites, lambda_h=0.01, lambda_J=0.01, grad=True,
+                   nthreads=None):
+    """objgrad for the listed sites from their own slices hr [ns, q], Jr [ns, N, q, q]."""
+    msa = _msa(msa)
+    B, N = msa.shape
+    sites = np.ascontiguousarray(sites, dtype=np.int32)
+    ns = sites.shape[0]
+    hr = np.ascontiguousarray(hr, dtype=np.float64).reshape(ns, -1)
+    q = hr.shape[1]
+    Jr = np.ascontiguousarray(Jr, dtype=np.float64).reshape(ns, N, q, q)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    f = np.zeros(ns)
+    gh = np.zeros((ns, q)) if grad else None
+    gJ = np.zeros((ns, N, q, q)) if grad else None
+    _lib().oracle_objgrad_slices(_p(msa), B, N, q, _p(w), float(beff), _p(hr), _p(Jr),
+                                 float(lambda_h), float(lambda_J), _p(sites), ns, _p(f),
+                                 _p(gh) if grad else None, _p(gJ) if grad else None,
+                                 _threads(nthreads))
     return f, gh, gJ
 
 

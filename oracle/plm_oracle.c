@@ -228,6 +228,28 @@ void oracle_objgrad(const uint8_t *msa, int B, int N, int q, const double *w,
   run_items(og_item, &c, nsites, nthreads);
 }
 
+typedef struct {
+  og_ctx base;
+} ogs_ctx;
+
+static void ogs_item(void *vc, int t) {
+  og_ctx *c = &((ogs_ctx *)vc)->base;
+  size_t qq = (size_t)c->q * c->q;
+  c->f[t] = oracle_site_objgrad(c->msa, c->B, c->N, c->q, c->sites[t], c->w, c->beff,
+                                c->h + (size_t)t * c->q, c->J + (size_t)t * c->N * qq,
+                                c->lh, c->lJ, c->gh ? c->gh + (size_t)t * c->q : NULL,
+                                c->gJ ? c->gJ + (size_t)t * c->N * qq : NULL);
+}
+
+void oracle_objgrad_slices(const uint8_t *msa, int B, int N, int q, const double *w,
+                           double beff, const double *hr, const double *Jr,
+                           double lambda_h, double lambda_J, const int32_t *sites,
+                           int nsites, double *f_out, double *gh_out, double *gJ_out,
+                           int nthreads) {
+  ogs_ctx c = {{msa, B, N, q, w, beff, hr, Jr, lambda_h, lambda_J, sites, f_out, gh_out, gJ_out}};
+  run_items(ogs_item, &c, nsites, nthreads);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Per-site minimisation (sec. 3.4 step 3; L-BFGS per sec. 5, cold start at   */
 /* the origin per sec. 6).  Textbook limited-memory BFGS (two-loop recursion, */

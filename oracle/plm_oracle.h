@@ -55,6 +55,15 @@ void oracle_objgrad(const uint8_t *msa, int B, int N, int q, const double *w,
                     double lambda_J, const int32_t *sites, int nsites, double *f_out,
                     double *gh_out, double *gJ_out, int nthreads);
 
+/* The same from per-site slices: hr[ns][q], Jr[ns][N][q][q] hold the
+ * parameters of the listed sites only (for alignments whose full J is too
+ * large to hold in FP64). */
+void oracle_objgrad_slices(const uint8_t *msa, int B, int N, int q, const double *w,
+                           double beff, const double *hr, const double *Jr,
+                           double lambda_h, double lambda_J, const int32_t *sites,
+                           int nsites, double *f_out, double *gh_out, double *gJ_out,
+                           int nthreads);
+
 typedef struct {
   int m;            /* L-BFGS memory (10) */
   double tol;       /* stop when ||grad g_r^reg||_2 <= tol (normalised scale) */

@@ -35,7 +35,20 @@ class FitOpts(ctypes.Structure):
         ("use_graph", ctypes.c_int32),
         ("single_site", ctypes.c_int32),
         ("tile_seqs", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("site_limit", ctypes.c_int32),
+        ("timing", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
+    ]
+
+
+class FitTiming(ctypes.Structure):
+    _fields_ = [
+        ("forward_ms", ctypes.c_double),
+        ("backward_ms", ctypes.c_double),
+        ("lbfgs_ms", ctypes.c_double),
+        ("total_ms", ctypes.c_double),
+        ("iterations", ctypes.c_int64),
+        ("site_evals", ctypes.c_int64),
     ]
 
 
@@ -83,6 +96,7 @@ def lib():
             "plm_fit": (ctypes.c_int, [P, P, I32, I32, I32, P, P, ctypes.POINTER(FitOpts), P, SZ, P, P,
                                        ctypes.POINTER(SiteStats)]),
             "plm_score": (ctypes.c_int, [P, P, I32, I32, P, P]),
+            "plm_fit_last_timing": (ctypes.c_int, [P, ctypes.POINTER(FitTiming)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -96,4 +110,4 @@ def exported_symbols():
     """Names declared in include/plm.h that the ABI tests check for."""
     return ["plm_ctx_create", "plm_ctx_destroy", "plm_last_error", "plm_status_string", "plm_sync",
             "plm_reweight", "plm_objgrad_workspace_bytes", "plm_objgrad", "plm_fit_opts_default",
-            "plm_fit_workspace_bytes", "plm_fit", "plm_score"]
+            "plm_fit_workspace_bytes", "plm_fit", "plm_score", "plm_fit_last_timing"]

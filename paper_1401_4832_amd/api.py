@@ -127,16 +127,19 @@ class FitOptions:
     use_graph: bool = True
     single_site: bool = False
     tile_seqs: int = 0
+    site_limit: int = 0
+    timing: bool = False
 
     def to_c(self) -> L.FitOpts:
         o = L.FitOpts()
         L.lib().plm_fit_opts_default(ctypes.byref(o))
         for k in ("lambda_h", "lambda_J", "tol"):
             setattr(o, k, float(getattr(self, k)))
-        for k in ("max_iter", "lbfgs_m", "max_linesearch", "path", "sync_every", "tile_seqs"):
+        for k in ("max_iter", "lbfgs_m", "max_linesearch", "path", "sync_every", "tile_seqs", "site_limit"):
             setattr(o, k, int(getattr(self, k)))
         o.use_graph = int(bool(self.use_graph))
         o.single_site = int(bool(self.single_site))
+        o.timing = int(bool(self.timing))
         return o
 
 
@@ -176,6 +179,15 @@ def fit(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None) -> FitRe
     st = [dict(iterations=s.iterations, evaluations=s.evaluations, status=L.SITE_STATUS.get(s.status, "?"),
                f=s.f, gnorm=s.gnorm) for s in stats]
     return FitResult(h, J, st, rc)
+
+
+def last_fit_timing(device=None) -> dict:
+    """Kernel times (ms) of the last fit run with timing=True on this device/stream."""
+    ctx = context(device)
+    t = L.FitTiming()
+    _check(L.lib().plm_fit_last_timing(ctx, ctypes.byref(t)), ctx)
+    return dict(forward_ms=t.forward_ms, backward_ms=t.backward_ms, lbfgs_ms=t.lbfgs_ms,
+                total_ms=t.total_ms, iterations=int(t.iterations), site_evals=int(t.site_evals))
 
 
 def score(J: torch.Tensor):

@@ -173,11 +173,63 @@ hipError_t launch_forward(const EvalArgs& a, int32_t n_sites_grid, int32_t nb, h
   return hipGetLastError();
 }
 
+// Stable counting sort of each chunk's rows by their symbol at each column,
+// done once per alignment.  Entry = (chunk-local row << 8) | symbol; the row
+// field is then directly the byte offset of the row in the LDS residual tile
+// (rows of 64 floats = 256 bytes), and the low byte the symbol.
+__global__ __launch_bounds__(256) void chunk_sort_kernel(const uint8_t* __restrict__ msa_pad,
+                                                         int32_t B3, int32_t N, int32_t N_pad,
+                                                         int32_t q, uint16_t* __restrict__ sorted) {
+  __shared__ uint16_t cnt[256][kQMax + 1];
+  const int c = blockIdx.x, i = blockIdx.y * 256 + threadIdx.x;
+  if (i >= N) return;
+  const int b0 = c * kBwdSeqChunk, n = min(kBwdSeqChunk, B3 - b0);
+  uint16_t* ct = cnt[threadIdx.x];
+  for (int k = 0; k <= kQMax; ++k) ct[k] = 0;
+  for (int t = 0; t < n; ++t) ct[msa_pad[(size_t)(b0 + t) * N_pad + i]]++;
+  int run = 0;
+  for (int k = 0; k < q; ++k) {
+    const int v = ct[k];
+    ct[k] = (uint16_t)run;
+    run += v;
+  }
+  uint16_t* out = sorted + ((size_t)c * N + i) * kBwdSeqChunk;
+  for (int t = 0; t < n; ++t) {
+    const int k = msa_pad[(size_t)(b0 + t) * N_pad + i];
+    out[ct[k]++] = (uint16_t)((t << 8) | k);
+  }
+}
+
+hipError_t launch_chunk_sort(const uint8_t* msa_pad, int32_t B3, int32_t N, int32_t N_pad, int32_t q,
+                             uint16_t* sorted, hipStream_t st) {
+  const int nchunks = (B3 + kBwdSeqChunk - 1) / kBwdSeqChunk;
+  hipLaunchKernelGGL(chunk_sort_kernel, dim3(nchunks, (N + 255) / 256), dim3(256), 0, st, msa_pad,
+                     B3, N, N_pad, q, sorted);
+  return hipGetLastError();
+}
+
+// dJ_ri(s,k) = sum over the rows b with sigma_i^b = k of R_b(s).  Per chunk of
+// 192 rows, the residual rows are staged in LDS (three bank-disjoint copies of
+// each 21-float row, one per slot).  Each slot owns one column and walks the
+// chunk's rows in symbol order, keeping a running FP32 sum in a register.  A
+// symbol's rows are contiguous, so each group sum is final when the symbol
+// changes and is stored (plain store, no read-back) into the column's slot for
+// that symbol; after the chunk every lane folds its 21 slots into FP64
+// registers and clears them.  No two lanes ever write the same LDS word.
 __global__ __launch_bounds__(kBwdThreads) void bwd_kernel(EvalArgs a) {
-  __shared__ float acc[kBwdPos * kQMax * kRowF];       // 129 KB
-  __shared__ float Rs[kBwdSeqChunk * kSlot];           // 16 KB
-  __shared__ uint32_t sg[kBwdWaves * kBwdSeqChunk];    // 6 KB
-  constexpr int KOWN = (kBwdPos * kQMax * kQMax + kBwdThreads - 1) / kBwdThreads;
+  // one LDS arena: residual rows first (so a row's byte offset is its address)
+  // Pitches chosen so that the three slots of a wave, which work on three
+  // consecutive columns, hit disjoint LDS banks: 200 entries (100 dwords) per
+  // column, and 469 = 7 * 64 + 21 floats per column of group sums.
+  constexpr int kEntPitch = kBwdSeqChunk + 8;
+  constexpr int kSegPitch = 7 * 64 + kSlot;
+  constexpr int kRsBytes = kBwdSeqChunk * kRowF * 4;              // 48 KB
+  constexpr int kEntBytes = kBwdPos * kEntPitch * 2;              // 19 KB
+  constexpr int kSegBytes = kBwdPos * kSegPitch * 4;              // 88 KB
+  __shared__ __attribute__((aligned(16))) char arena[kRsBytes + kEntBytes + kSegBytes];
+  float* Rs = reinterpret_cast<float*>(arena);
+  uint16_t* ent = reinterpret_cast<uint16_t*>(arena + kRsBytes);
+  float* seg = reinterpret_cast<float*>(arena + kRsBytes + kEntBytes);
   const int idx = blockIdx.y;
   const int nact = a.n_active ? *a.n_active : a.n_active_host;
   if (idx >= nact) return;
@@ -186,75 +238,96 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_kernel(EvalArgs a) {
   const int i0 = blockIdx.x * kBwdPos;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int slot = lane / kSlot, s = lane - slot * kSlot;
+  const int slotA = slot < kSlots ? slot : kSlots - 1;  // lane 63 shadows lane 42 and never writes
+  const int pl = wid * kSlots + slotA;                   // this lane's column within the block
+  const int i = i0 + pl;
+  const bool writer = lane < kSlots * kSlot;
+  const int npos = min(kBwdPos, N - i0);
 
-  for (int e = tid; e < kBwdPos * q * kRowF; e += kBwdThreads) acc[e] = 0.f;
-  double dacc[KOWN];
+  for (int e = tid; e < kBwdPos * kSegPitch; e += kBwdThreads) seg[e] = 0.f;
+  double acc64[kQMax];
 #pragma unroll
-  for (int k = 0; k < KOWN; ++k) dacc[k] = 0.0;
+  for (int k = 0; k < kQMax; ++k) acc64[k] = 0.0;
+  float* myseg = seg + pl * kSegPitch + s;                // + 21 * symbol
+  const uint32_t lane_off = 4u * (uint32_t)(slotA * kSlot + s);
+  const uint16_t* myent = ent + pl * kEntPitch;
 
   const int nchunks = (a.B3 + kBwdSeqChunk - 1) / kBwdSeqChunk;
   const float* Rr = a.R + (size_t)r * a.B3 * kSlot;
-  const int pbase = wid * kBwdPosPerWave;
   for (int c = 0; c < nchunks; ++c) {
-    const int bc = c * kBwdSeqChunk;
+    const int bc = c * kBwdSeqChunk, n = min(kBwdSeqChunk, a.B3 - bc);
     __syncthreads();
-    for (int e = tid; e < kBwdSeqChunk * kSlot; e += kBwdThreads) {
-      const int b = bc + e / kSlot;
-      Rs[e] = (b < a.B3) ? Rr[(size_t)bc * kSlot + e] : 0.f;
+    for (int e = tid; e < n * kSlot; e += kBwdThreads) {
+      const int t = e / kSlot, ss = e - t * kSlot;
+      const float v = Rr[(size_t)bc * kSlot + e];
+      float* row = Rs + t * kRowF;
+      row[ss] = v;
+      row[ss + kSlot] = v;
+      row[ss + 2 * kSlot] = v;
     }
-    for (int e = tid; e < kBwdWaves * kBwdSeqChunk; e += kBwdThreads) {
-      const int w = e / kBwdSeqChunk, t = e - w * kBwdSeqChunk, b = bc + t;
-      uint32_t v = 0;
-      if (b < a.B3) {
-        const uint8_t* mrow = a.msa_pad + (size_t)b * a.N_pad;
+    {
+      constexpr int kV = kBwdSeqChunk / 8, kVP = kEntPitch / 8;   // uint4 per column: data, pitch
+      const uint4* src = reinterpret_cast<const uint4*>(a.sorted + ((size_t)c * N + i0) * kBwdSeqChunk);
+      uint4* dst = reinterpret_cast<uint4*>(ent);
+      for (int e = tid; e < kBwdPos * kV; e += kBwdThreads) {
+        const int col = e / kV, x = e - col * kV;
+        dst[col * kVP + x] = col < npos ? src[e] : make_uint4(0, 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    uint32_t cur = myent[0] & 0xffu;
+    float run = 0.f;
+    auto rowval = [&](uint32_t e) {
+      return *reinterpret_cast<const float*>(arena + ((e & 0xff00u) | lane_off));
+    };
+    int j = 0;
+    for (; j + 8 <= n; j += 8) {
+      // eight sorted entries at once; they all continue the current group
+      // exactly when the last one does, since symbols ascend within the chunk
+      const uint4 e8 = *reinterpret_cast<const uint4*>(myent + j);
+      const uint32_t e[8] = {e8.x & 0xffffu, e8.x >> 16, e8.y & 0xffffu, e8.y >> 16,
+                             e8.z & 0xffffu, e8.z >> 16, e8.w & 0xffffu, e8.w >> 16};
+      float v[8];
 #pragma unroll
-        for (int p = 0; p < kBwdPosPerWave; ++p) {
-          const int i = i0 + w * kBwdPosPerWave + p;
-          if (i < a.N_pad) v |= (uint32_t)mrow[i] << (8 * p);
+      for (int u = 0; u < 8; ++u) v[u] = rowval(e[u]);
+      if ((e[7] & 0xffu) == cur) {
+        run += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t sg = e[u] & 0xffu;
+          if (sg != cur) {
+            if (writer) myseg[cur * kQMax] = run;
+            run = 0.f;
+            cur = sg;
+          }
+          run += v[u];
         }
       }
-      sg[e] = v;
     }
-    __syncthreads();
-    if (slot < kSlots) {
-      const int nt = min(kBwdSeqChunk, a.B3 - bc) / kSlots;
-      for (int j = 0; j < nt; ++j) {
-        const int t = kSlots * j + slot;
-        const float Rv = Rs[t * kSlot + s];
-        const uint32_t sv = sg[wid * kBwdSeqChunk + t];
-        const int a0 = ((pbase + 0) * q + (int)(sv & 0xffu)) * kRowF + lane;
-        const int a1 = ((pbase + 1) * q + (int)((sv >> 8) & 0xffu)) * kRowF + lane;
-        const int a2 = ((pbase + 2) * q + (int)((sv >> 16) & 0xffu)) * kRowF + lane;
-        // the three columns are distinct, so the reads may all precede the writes
-        const float v0 = acc[a0], v1 = acc[a1], v2 = acc[a2];
-        acc[a0] = v0 + Rv;
-        acc[a1] = v1 + Rv;
-        acc[a2] = v2 + Rv;
+    for (; j < n; ++j) {
+      const uint32_t e = myent[j];
+      const uint32_t sg = e & 0xffu;
+      const float v = rowval(e);
+      if (sg != cur) {
+        if (writer) myseg[cur * kQMax] = run;
+        run = 0.f;
+        cur = sg;
       }
+      run += v;
     }
-    if ((c + 1) % kBwdFlushChunks == 0 || c == nchunks - 1) {
-      __syncthreads();
+    if (writer) myseg[cur * kQMax] = run;
+    // fold this chunk's group sums (the lane's own words) into FP64
 #pragma unroll
-      for (int k = 0; k < KOWN; ++k) {
-        const int e = tid + k * kBwdThreads;
-        if (e < kBwdPos * qq) {
-          const int p = e / qq, rem = e - p * qq, kk = rem / q, ss = rem - kk * q;
-          float* row = acc + (p * q + kk) * kRowF;
-          dacc[k] += (double)row[ss] + (double)row[ss + kSlot] + (double)row[ss + 2 * kSlot];
-          row[ss] = 0.f;
-          row[ss + kSlot] = 0.f;
-          row[ss + 2 * kSlot] = 0.f;
-        }
-      }
+    for (int k = 0; k < kQMax; ++k) {
+      acc64[k] += (double)myseg[k * kQMax];
+      if (writer) myseg[k * kQMax] = 0.f;
     }
   }
+  if (writer && s < q && i < N) {
 #pragma unroll
-  for (int k = 0; k < KOWN; ++k) {
-    const int e = tid + k * kBwdThreads;
-    if (e < kBwdPos * qq) {
-      const int p = e / qq, rem = e - p * qq, i = i0 + p;
-      if (i < N) a.gJ[((size_t)r * N + i) * qq + rem] = (i == r) ? 0.0 : dacc[k];
-    }
+    for (int k = 0; k < kQMax; ++k)
+      if (k < q) a.gJ[((size_t)r * N + i) * qq + (size_t)k * q + s] = (i == r) ? 0.0 : acc64[k];
   }
 }
 

@@ -18,6 +18,8 @@ struct plm_ctx {
   int32_t* pin_dev;  // device view of pin
   size_t pin_words;
   hipStream_t fit_stream;  // private stream of the synchronous fit (graph capture needs one)
+  hipEvent_t ev[5];        // kernel timing marks of the fit iteration
+  plm_fit_timing timing;   // of the last timed fit
 };
 
 namespace {
@@ -59,7 +61,8 @@ struct EvalBufs {
   double* f_part;
   double* gh_part;
   double* gJ;
-  int32_t B_pad, N_pad, B3, tiles_max;
+  uint16_t* sorted;
+  int32_t B_pad, N_pad, B3, tiles_max, nchunks;
 };
 
 void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
@@ -72,6 +75,8 @@ void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
   e.f_part = bp.take<double>((size_t)e.tiles_max * N);
   e.gh_part = bp.take<double>((size_t)e.tiles_max * N * kSlot);
   e.gJ = bp.take<double>((size_t)N * N * q * q);
+  e.nchunks = (e.B3 + kBwdSeqChunk - 1) / kBwdSeqChunk;
+  e.sorted = bp.take<uint16_t>((size_t)e.nchunks * N * kBwdSeqChunk);
 }
 
 struct FitBufs {
@@ -187,7 +192,12 @@ int plm_ctx_create(plm_ctx** out, int device, void* hip_stream) {
   c->pin_dev = nullptr;
   c->pin_words = 0;
   c->fit_stream = nullptr;
-  if (hipSetDevice(device) != hipSuccess || ensure_pin(c, 64) != PLM_OK ||
+  memset(&c->timing, 0, sizeof(c->timing));
+  for (int k = 0; k < 5; ++k) c->ev[k] = nullptr;
+  bool ev_ok = true;
+  if (hipSetDevice(device) == hipSuccess)
+    for (int k = 0; k < 5; ++k) ev_ok = ev_ok && hipEventCreate(&c->ev[k]) == hipSuccess;
+  if (!ev_ok || hipSetDevice(device) != hipSuccess || ensure_pin(c, 64) != PLM_OK ||
       hipStreamCreateWithFlags(&c->fit_stream, hipStreamNonBlocking) != hipSuccess) {
     if (c->pin) (void)hipHostFree(c->pin);
     delete c;
@@ -201,6 +211,8 @@ int plm_ctx_destroy(plm_ctx* c) {
   if (!c) return PLM_E_INVALID;
   if (c->pin) (void)hipHostFree(c->pin);
   if (c->fit_stream) (void)hipStreamDestroy(c->fit_stream);
+  for (int k = 0; k < 5; ++k)
+    if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
   delete c;
   return PLM_OK;
 }
@@ -256,6 +268,7 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
   HIPCHK(c, launch_check_f32(h, (size_t)N * q, c->pin_dev, c->stream));
   HIPCHK(c, launch_check_f32(J, (size_t)N * N * q * q, c->pin_dev, c->stream));
   HIPCHK(c, launch_pad_msa(msa, B, N, q, e.msa_pad, e.B_pad, e.N_pad, c->pin_dev, c->stream));
+  HIPCHK(c, launch_chunk_sort(e.msa_pad, e.B3, N, e.N_pad, q, e.sorted, c->stream));
   const int32_t nb = pick_nb(B, 0);
   EvalArgs a;
   a.msa_pad = e.msa_pad;
@@ -263,6 +276,7 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
   a.w = w; a.h = h; a.J = J;
   a.sites = sites; a.n_active = nullptr; a.n_active_host = n_sites;
   a.R = e.R; a.f_part = e.f_part; a.gh_part = e.gh_part; a.gJ = e.gJ;
+  a.sorted = e.sorted;
   a.tiles = (B + forward_tile_seqs(nb) - 1) / forward_tile_seqs(nb);
   HIPCHK(c, launch_forward(a, n_sites, nb, c->stream));
   HIPCHK(c, launch_backward(a, n_sites, c->stream));
@@ -289,6 +303,8 @@ void plm_fit_opts_default(plm_fit_opts* o) {
   o->use_graph = 1;
   o->single_site = 0;
   o->tile_seqs = 0;
+  o->site_limit = 0;
+  o->timing = 0;
 }
 
 size_t plm_fit_workspace_bytes(int32_t B, int32_t N, int32_t q, const plm_fit_opts* o) {
@@ -333,6 +349,7 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
   HIPCHK(c, launch_check_f64(w, (size_t)B, c->pin_dev, st));
   HIPCHK(c, launch_check_f32(h_io, (size_t)N * q, c->pin_dev, st));
   HIPCHK(c, launch_pad_msa(msa, B, N, q, f.ev.msa_pad, f.ev.B_pad, f.ev.N_pad, c->pin_dev, st));
+  HIPCHK(c, launch_chunk_sort(f.ev.msa_pad, f.ev.B3, N, f.ev.N_pad, q, f.ev.sorted, st));
   HIPCHK(c, launch_init_fit(N, q, h_io, J_io, f.Th, f.TJ, f.st, f.sites, f.n_active, phase_host_dev, st));
   HIPCHK(c, launch_check_f32(J_io, (size_t)N * N * q * q, c->pin_dev, st));
   HIPCHK(c, launch_zero_u64(f.site_evals, st));
@@ -347,6 +364,7 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
   a.w = w; a.h = f.Th; a.J = f.TJ;
   a.sites = f.sites; a.n_active = f.n_active; a.n_active_host = N;
   a.R = f.ev.R; a.f_part = f.ev.f_part; a.gh_part = f.ev.gh_part; a.gJ = f.ev.gJ;
+  a.sorted = f.ev.sorted;
   a.tiles = (B + forward_tile_seqs(nb) - 1) / forward_tile_seqs(nb);
 
   LbfgsArgs L;
@@ -368,7 +386,8 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
     EvalArgs a1 = a;
     a1.n_active = nullptr;
     a1.n_active_host = 1;
-    for (int32_t r = 0; r < N; ++r) {
+    const int32_t nsites = (o->site_limit > 0 && o->site_limit < N) ? o->site_limit : N;
+    for (int32_t r = 0; r < nsites; ++r) {
       a1.sites = f.sites + r;  // sites[r] == r after initialisation
       LbfgsArgs L1 = L;
       L1.site_offset = r;
@@ -383,16 +402,24 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
   } else {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    const bool timed = o->timing != 0;
+    auto mark = [&](int k) -> hipError_t { return timed ? hipEventRecord(c->ev[k], st) : hipSuccess; };
     auto enqueue = [&]() -> hipError_t {
-      hipError_t e = launch_forward(a, N, nb, st);
-      if (e != hipSuccess) return e;
-      e = launch_backward(a, N, st);
-      if (e != hipSuccess) return e;
-      e = launch_lbfgs(L, N, st);
-      if (e != hipSuccess) return e;
-      return launch_compact(N, f.st, f.sites, f.n_active, c->pin_dev + 1, f.site_evals, st);
+      hipError_t e = mark(0);
+      if (e == hipSuccess) e = launch_forward(a, N, nb, st);
+      if (e == hipSuccess) e = mark(1);
+      if (e == hipSuccess) e = launch_backward(a, N, st);
+      if (e == hipSuccess) e = mark(2);
+      if (e == hipSuccess) e = launch_lbfgs(L, N, st);
+      if (e == hipSuccess) e = mark(3);
+      if (e == hipSuccess) e = launch_compact(N, f.st, f.sites, f.n_active, c->pin_dev + 1, f.site_evals, st);
+      return e;
     };
-    if (o->use_graph) {
+    plm_fit_timing tm;
+    memset(&tm, 0, sizeof(tm));
+    // timing records events between the kernels, which needs eager launches
+    const bool use_graph = o->use_graph && !timed;
+    if (use_graph) {
       HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
       hipError_t e = enqueue();
       hipError_t e2 = hipStreamEndCapture(st, &graph);
@@ -400,12 +427,12 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
       HIPCHK(c, e2);
       HIPCHK(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     }
-    const int every = o->sync_every > 0 ? o->sync_every : 1;
+    const int every = timed ? 1 : (o->sync_every > 0 ? o->sync_every : 1);
     int64_t launched = 0;
     int err = PLM_OK;
     while (launched < cap) {
       for (int k = 0; k < every; ++k, ++launched) {
-        hipError_t e = o->use_graph ? hipGraphLaunch(exec, st) : enqueue();
+        hipError_t e = use_graph ? hipGraphLaunch(exec, st) : enqueue();
         if (e != hipSuccess) {
           err = set_err(c, PLM_E_HIP, "iteration launch: %s", hipGetErrorString(e));
           break;
@@ -417,7 +444,27 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
         err = set_err(c, PLM_E_HIP, "sync: %s", hipGetErrorString(e));
         break;
       }
+      if (timed) {
+        float t01 = 0.f, t12 = 0.f, t23 = 0.f;
+        if (hipEventElapsedTime(&t01, c->ev[0], c->ev[1]) == hipSuccess &&
+            hipEventElapsedTime(&t12, c->ev[1], c->ev[2]) == hipSuccess &&
+            hipEventElapsedTime(&t23, c->ev[2], c->ev[3]) == hipSuccess) {
+          tm.forward_ms += t01;
+          tm.backward_ms += t12;
+          tm.lbfgs_ms += t23;
+        } else {
+          (void)hipGetLastError();  // do not leave a timing failure for the next launch check
+        }
+        tm.iterations += 1;
+      }
       if (((volatile int32_t*)c->pin)[1] == 0) break;
+    }
+    if (timed) {
+      unsigned long long se = 0;
+      (void)hipMemcpy(&se, f.site_evals, sizeof(se), hipMemcpyDeviceToHost);
+      tm.site_evals = (int64_t)se;
+      tm.total_ms = tm.forward_ms + tm.backward_ms + tm.lbfgs_ms;
+      c->timing = tm;
     }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -442,6 +489,12 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
     }
   }
   return any_max ? PLM_W_MAXITER : PLM_OK;
+}
+
+int plm_fit_last_timing(const plm_ctx* c, plm_fit_timing* out) {
+  if (!c || !out) return PLM_E_INVALID;
+  *out = c->timing;
+  return PLM_OK;
 }
 
 int plm_score(plm_ctx* c, const float* J, int32_t N, int32_t q, double* fn_out, double* cfn_out) {

@@ -23,13 +23,13 @@ constexpr int kMMax = 32;  // L-BFGS history cap
 constexpr int kFwdWaves = 16;
 constexpr int kFwdThreads = kFwdWaves * 64;
 constexpr int kFwdChunk = 16;
-// Backward kernel: 8 waves, each owning 3 alignment columns.
-constexpr int kBwdWaves = 8;
+// Backward kernel: 16 waves; the three slots of a wave own three different
+// alignment columns (48 per block).  Sequences are processed in chunks of 192
+// whose rows are sorted by symbol at every column (once per alignment).
+constexpr int kBwdWaves = 16;
 constexpr int kBwdThreads = kBwdWaves * 64;
-constexpr int kBwdPosPerWave = 3;
-constexpr int kBwdPos = kBwdWaves * kBwdPosPerWave;  // 24
-constexpr int kBwdSeqChunk = 192;                     // 64 sequence triples
-constexpr int kBwdFlushChunks = 4;                    // FP32 -> FP64 every 768 sequences
+constexpr int kBwdPos = kBwdWaves * kSlots;  // 48
+constexpr int kBwdSeqChunk = 192;
 
 // Per-site optimiser state (device).
 struct SiteState {
@@ -67,6 +67,7 @@ struct EvalArgs {
   double* gh_part;         // [tiles][N][21]
   double* gJ;              // [N][N][q][q] data part of d f / d J (FP64)
   int32_t tiles;
+  const uint16_t* sorted;  // [nchunks][N][kBwdSeqChunk]: (row << 8) | symbol, rows sorted by symbol
 };
 
 
@@ -131,6 +132,8 @@ hipError_t launch_pad_msa(const uint8_t* msa, int32_t B, int32_t N, int32_t q, u
                           int32_t B_pad, int32_t N_pad, int32_t* flag_dev, hipStream_t st);
 hipError_t launch_forward(const EvalArgs& a, int32_t n_sites_grid, int32_t nb, hipStream_t st);
 hipError_t launch_backward(const EvalArgs& a, int32_t n_sites_grid, hipStream_t st);
+hipError_t launch_chunk_sort(const uint8_t* msa_pad, int32_t B3, int32_t N, int32_t N_pad, int32_t q,
+                             uint16_t* sorted, hipStream_t st);
 int32_t forward_tile_seqs(int32_t nb);
 hipError_t launch_lbfgs(const LbfgsArgs& a, int32_t nblocks, hipStream_t st);
 hipError_t launch_reweight(const uint8_t* msa, int32_t B, int32_t N, int32_t q, double theta,

@@ -1,0 +1,131 @@
+"""Profiling helpers for the benchmark's roofline numbers.
+
+python -m paper_1401_4832_amd.profiling drive [workload]
+    one reweight + one all-sites objective/gradient evaluation on the workload,
+    then a 1 GiB device-to-device copy (the calibration kernel for the HBM
+    byte counters); the program rocprofv3 runs for kernel traces and counters.
+python -m paper_1401_4832_amd.profiling stats <kernel_stats.csv> <out.md> <command...>
+    short markdown summary of a rocprofv3 --stats kernel table.
+python -m paper_1401_4832_amd.profiling traffic <fetch.csv> <write.csv> <workload> <out_prefix>
+    HBM bytes per launch of the forward and backward kernels from FETCH_SIZE
+    and WRITE_SIZE (KiB per dispatch), each scaled by what the same counter
+    reads for the 1 GiB copy; writes <out_prefix>_<kernel>_<workload>.json.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 1 << 30
+KERNELS = {"forward": "fwd_kernel", "backward": "bwd_kernel", "lbfgs": "lbfgs_kernel",
+           "reweight": "identity_kernel"}
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1401_4832_amd", "csrc", "*"))):
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def drive(workload: str = "potts_n500_b50000"):
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import torch
+
+    import paper_1401_4832_amd as plm
+    import synth
+    s = synth.workload(workload)
+    dev = torch.device("cuda:0")
+    msa = torch.from_numpy(s.msa).to(dev)
+    m, w, beff = plm.reweight(msa, theta=0.8)
+    N, q = s.N, 21
+    rng = np.random.default_rng(0)
+    h = torch.from_numpy((0.1 * rng.standard_normal((N, q))).astype(np.float32)).to(dev)
+    J = torch.from_numpy((0.1 * rng.standard_normal((N, N, q, q))).astype(np.float32)).to(dev)
+    f, gh, gJ = plm.objgrad(msa, w, beff, h, J)
+    plm.sync(dev)
+    del gJ, J
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print("drive done", workload, float(f.sum()), flush=True)
+
+
+def _rows(path):
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def stats(csv_path: str, out_md: str, command: str):
+    rows = _rows(csv_path)
+    lines = [f"# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
+             "| kernel | calls | total ms | average ms | % |", "|---|---|---|---|---|"]
+    for r in rows[:12]:
+        name = r.get("Name") or r.get("KERNEL_NAME") or r.get("name")
+        calls = int(float(r.get("Calls") or r.get("calls")))
+        tot = float(r.get("TotalDurationNs") or r.get("total_duration")) / 1e6
+        avg = float(r.get("AverageNs") or r.get("average")) / 1e6
+        pct = float(r.get("Percentage") or r.get("percentage"))
+        lines.append(f"| `{name[:70]}` | {calls} | {tot:.3f} | {avg:.3f} | {pct:.1f} |")
+    lines += ["", f"Kernel sources hash: `{source_hash()}`", ""]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+def _per_kernel(rows, counter):
+    out = {}
+    for r in rows:
+        if r["Counter_Name"] != counter:
+            continue
+        out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def traffic(fetch_csv: str, write_csv: str, workload: str, out_prefix: str):
+    fr, wr = _rows(fetch_csv), _rows(write_csv)
+    fk, wk = _per_kernel(fr, "FETCH_SIZE"), _per_kernel(wr, "WRITE_SIZE")
+
+    def copy_value(d):
+        vals = [v for k, vs in d.items() if "copy" in k.lower() or "elementwise" in k.lower()
+                for v in vs if v > 0]
+        return max(vals) if vals else None
+
+    cf, cw = copy_value(fk), copy_value(wk)
+    if not cf or not cw:
+        raise SystemExit("copy calibration kernel not found in the counter files")
+    sf, sw = COPY_BYTES / cf, COPY_BYTES / cw  # bytes per counter unit
+    h = source_hash()
+    for kname, sym in KERNELS.items():
+        f = [v for k, vs in fk.items() if sym in k for v in vs]
+        w = [v for k, vs in wk.items() if sym in k for v in vs]
+        if not f or not w:
+            continue
+        d = {"kernel": kname, "workload": workload, "source_hash": h,
+             "fetch_kib_per_launch": sum(f) / len(f), "write_kib_per_launch": sum(w) / len(w),
+             "copy_fetch_kib": cf, "copy_write_kib": cw,
+             "bytes_per_launch": sum(f) / len(f) * sf + sum(w) / len(w) * sw}
+        path = f"{out_prefix}_{kname}_{workload}.txt"
+        with open(path, "w") as fh:
+            json.dump(d, fh, indent=1)
+        print(path, json.dumps(d))
+
+
+if __name__ == "__main__":
+    cmd = sys.argv[1]
+    if cmd == "drive":
+        drive(*(sys.argv[2:3]))
+    elif cmd == "stats":
+        stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+    elif cmd == "traffic":
+        traffic(*sys.argv[2:6])
+    else:
+        raise SystemExit(__doc__)

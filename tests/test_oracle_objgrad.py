@@ -158,3 +158,12 @@ def test_multi_site_wrapper_matches_single_site():
     for t, r in enumerate([4, 1]):
         f1, gh1, gJ1 = oracle.site_objgrad(msa, r, w, beff, h[r], J[r], 0.01, 0.02)
         assert f[t] == f1 and np.array_equal(gh[t], gh1) and np.array_equal(gJ[t], gJ1)
+
+
+def test_slice_wrapper_matches_full_arrays():
+    msa, w, beff = _toy(12, B=30, N=6, q=4)
+    h, J = random_params(13, 6, 4)
+    sites = [5, 0, 2]
+    f, gh, gJ = oracle.objgrad(msa, w, beff, h, J, 0.01, 0.03, sites=sites)
+    f2, gh2, gJ2 = oracle.objgrad_slices(msa, w, beff, h[sites], J[sites], sites, 0.01, 0.03, nthreads=3)
+    assert np.array_equal(f, f2) and np.array_equal(gh, gh2) and np.array_equal(gJ, gJ2)
