@@ -94,14 +94,18 @@ int plm_reweight(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, int32_t
  *   f_out  double[N]          f_r = B_eff * g_r^reg
  *   gh_out float [N][q]       d f_r / d h_r(s)
  *   gJ_out float [N][N][q][q] d f_r / d J_ri(s,k) at [r][i][k][s]; zero for i == r
- * gh_out / gJ_out may be NULL to skip the gradient.  path is one of
- * PLM_PATH_*.  beff is a device pointer (as written by plm_reweight). */
+ * gh_out / gJ_out may be NULL to skip the gradient (with gJ_out NULL the
+ * scatter kernel is not run at all).  grad_scale (device double[N], may be
+ * NULL) multiplies the gradient rows of site r by grad_scale[r]: the
+ * vector-Jacobian product an automatic-differentiation backward needs.  path
+ * is one of PLM_PATH_*.  beff is a device pointer (as written by
+ * plm_reweight). */
 size_t plm_objgrad_workspace_bytes(int32_t B, int32_t N, int32_t q, int32_t path);
 int plm_objgrad(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, int32_t q,
                 const double *w, const double *beff, const float *h, const float *J,
                 double lambda_h, double lambda_J, const int32_t *sites, int32_t n_sites,
-                int32_t path, void *workspace, size_t workspace_bytes, double *f_out,
-                float *gh_out, float *gJ_out);
+                int32_t path, void *workspace, size_t workspace_bytes,
+                const double *grad_scale, double *f_out, float *gh_out, float *gJ_out);
 
 /* ---- Minimisation of every site (sec. 3.4 step 3) --------------------------
  * One limited-memory BFGS state per site, all sites advanced together on the

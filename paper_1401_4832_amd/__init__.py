@@ -3,9 +3,10 @@ batched L-BFGS fit and coupling scores behind the C ABI of include/plm.h.
 
 Method: Ekeberg, Hartonen & Aurell, arXiv:1401.4832 (sec. 3.4 rundown)."""
 from . import _lib
+from .autograd import PLMObjective, plm_objective
 from .api import (FitOptions, FitResult, context, fit, last_fit_timing, objgrad, reweight, score, sync,
                   workspace)
 from ._lib import PATH_GATHER_FP32, PATH_MFMA_BF16X2, PlmError
 
-__all__ = ["FitOptions", "FitResult", "context", "fit", "last_fit_timing", "objgrad", "reweight", "score", "sync",
+__all__ = ["PLMObjective", "plm_objective", "FitOptions", "FitResult", "context", "fit", "last_fit_timing", "objgrad", "reweight", "score", "sync",
            "workspace", "PATH_GATHER_FP32", "PATH_MFMA_BF16X2", "PlmError"]

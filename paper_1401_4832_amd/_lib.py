@@ -90,7 +90,7 @@ def lib():
             "plm_reweight": (ctypes.c_int, [P, P, I32, I32, I32, D, I32, P, P, P]),
             "plm_objgrad_workspace_bytes": (SZ, [I32, I32, I32, I32]),
             "plm_objgrad": (ctypes.c_int, [P, P, I32, I32, I32, P, P, P, P, D, D, P, I32, I32, P, SZ,
-                                           P, P, P]),
+                                           P, P, P, P]),
             "plm_fit_opts_default": (None, [ctypes.POINTER(FitOpts)]),
             "plm_fit_workspace_bytes": (SZ, [I32, I32, I32, ctypes.POINTER(FitOpts)]),
             "plm_fit": (ctypes.c_int, [P, P, I32, I32, I32, P, P, ctypes.POINTER(FitOpts), P, SZ, P, P,

@@ -83,10 +83,12 @@ def reweight(msa: torch.Tensor, theta: float = 0.8, uniform: bool = False, q: in
 
 
 def objgrad(msa, w, beff, h, J, lambda_h=0.01, lambda_J=0.01, sites=None, grad=True,
-            path=L.PATH_GATHER_FP32):
+            path=L.PATH_GATHER_FP32, grad_scale=None):
     """f float64[N], gh float32[N,q], gJ float32[N,N,q,q] for the listed sites (all if None).
 
-    Rows of unlisted sites are left zero.  f_r = B_eff * g_r^reg."""
+    Rows of unlisted sites are left zero.  f_r = B_eff * g_r^reg.  With
+    grad_scale (float64 [N] on the device) the gradient rows of site r are
+    multiplied by grad_scale[r] inside the library."""
     dev = msa.device
     _dev_tensor(msa, torch.uint8, dev, "msa")
     B, N = msa.shape
@@ -102,6 +104,10 @@ def objgrad(msa, w, beff, h, J, lambda_h=0.01, lambda_J=0.01, sites=None, grad=T
         ns = int(sites.numel())
     else:
         ns = N
+    if grad_scale is not None:
+        _dev_tensor(grad_scale, torch.float64, dev, "grad_scale")
+        if grad_scale.numel() != N:
+            raise ValueError("grad_scale must have N entries")
     f = torch.zeros(N, dtype=torch.float64, device=dev)
     gh = torch.zeros(N, q, dtype=torch.float32, device=dev) if grad else None
     gJ = torch.zeros(N, N, q, q, dtype=torch.float32, device=dev) if grad else None
@@ -110,7 +116,7 @@ def objgrad(msa, w, beff, h, J, lambda_h=0.01, lambda_J=0.01, sites=None, grad=T
     ctx = context(dev)
     _check(L.lib().plm_objgrad(ctx, _ptr(msa), B, N, q, _ptr(w), _ptr(beff), _ptr(h), _ptr(J),
                                float(lambda_h), float(lambda_J), _ptr(sites), ns, path, _ptr(ws),
-                               ws.numel(), _ptr(f), _ptr(gh), _ptr(gJ)), ctx)
+                               ws.numel(), _ptr(grad_scale), _ptr(f), _ptr(gh), _ptr(gJ)), ctx)
     return f, gh, gJ
 
 

@@ -72,6 +72,7 @@ __global__ __launch_bounds__(1024) void objgrad_final_kernel(FinalArgs a) {
   const int q = a.q, N = a.N;
   const size_t qq = (size_t)q * q, Nqq = (size_t)N * qq;
   const double beff = *a.beff;
+  const double sc = a.grad_scale ? a.grad_scale[r] : 1.0;
   double reg = 0.0;
   for (size_t e = threadIdx.x; e < Nqq; e += blockDim.x) {
     const size_t i = e / qq;
@@ -79,7 +80,8 @@ __global__ __launch_bounds__(1024) void objgrad_final_kernel(FinalArgs a) {
     if (i != (size_t)r) reg += a.lambda_Jp * v * v;
     if (a.gJ_out)
       a.gJ_out[(size_t)r * Nqq + e] =
-          (i == (size_t)r) ? 0.f : (float)(a.gJ[(size_t)r * Nqq + e] + 2.0 * beff * a.lambda_Jp * v);
+          (i == (size_t)r) ? 0.f
+                           : (float)(sc * (a.gJ[(size_t)r * Nqq + e] + 2.0 * beff * a.lambda_Jp * v));
   }
   if (threadIdx.x < (unsigned)q) {
     const int s = threadIdx.x;
@@ -88,7 +90,7 @@ __global__ __launch_bounds__(1024) void objgrad_final_kernel(FinalArgs a) {
     if (a.gh_out) {
       double t = 0.0;
       for (int k = 0; k < a.tiles; ++k) t += a.gh_part[((size_t)k * N + r) * kSlot + s];
-      a.gh_out[(size_t)r * q + s] = (float)(t + 2.0 * beff * a.lambda_h * v);
+      a.gh_out[(size_t)r * q + s] = (float)(sc * (t + 2.0 * beff * a.lambda_h * v));
     }
   }
   reg = block_sum_f64(reg, red);

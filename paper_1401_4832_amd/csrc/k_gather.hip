@@ -18,14 +18,19 @@
 
 namespace plm {
 
+// Padded copy of the alignment in chunk-major order: symbol (b, i) at byte
+// ((i / 16) * B_pad + b) * 16 + i % 16, so that the sixteen columns of a chunk
+// for a run of rows are one contiguous block.  Symbols >= q raise the flag.
 __global__ void pad_msa_kernel(const uint8_t* __restrict__ msa, int32_t B, int32_t N, int32_t q,
                                uint8_t* __restrict__ out, int32_t B_pad, int32_t N_pad,
                                int32_t* flag) {
   const size_t total = (size_t)B_pad * N_pad;
+  const size_t per_chunk = (size_t)B_pad * kFwdChunk;
   int bad = 0;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
-    const int32_t b = (int32_t)(e / N_pad), i = (int32_t)(e - (size_t)b * N_pad);
+    const size_t c = e / per_chunk, rem = e - c * per_chunk;
+    const int32_t b = (int32_t)(rem / kFwdChunk), i = (int32_t)(c * kFwdChunk + rem % kFwdChunk);
     uint8_t v = 0;
     if (b < B && i < N) {
       v = msa[(size_t)b * N + i];
@@ -36,12 +41,12 @@ __global__ void pad_msa_kernel(const uint8_t* __restrict__ msa, int32_t B, int32
   if (bad && flag) atomicOr(flag, 1);
 }
 
-hipError_t launch_pad_msa(const uint8_t* msa, int32_t B, int32_t N, int32_t q, uint8_t* msa_pad,
+hipError_t launch_pad_msa(const uint8_t* msa, int32_t B, int32_t N, int32_t q, uint8_t* msa_cm,
                           int32_t B_pad, int32_t N_pad, int32_t* flag_dev, hipStream_t st) {
   const size_t total = (size_t)B_pad * N_pad;
   int blocks = (int)((total + 255) / 256);
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(pad_msa_kernel, dim3(blocks), dim3(256), 0, st, msa, B, N, q, msa_pad, B_pad,
+  hipLaunchKernelGGL(pad_msa_kernel, dim3(blocks), dim3(256), 0, st, msa, B, N, q, msa_cm, B_pad,
                      N_pad, flag_dev);
   return hipGetLastError();
 }
@@ -54,7 +59,9 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(EvalArgs a) {
   __shared__ float lds[kFwdChunk * kQMax * kRowF];  // 86 KB: J_r for 16 columns, 3 copies per row
   __shared__ uint4 sgl[tileSeq];                    // symbols of the tile's rows for those columns
   __shared__ double red[kFwdWaves * 64];
-  const int idx = blockIdx.y;
+  // sites vary fastest across the grid, so that the blocks resident at one time
+  // share a tile's symbols in L2
+  const int idx = blockIdx.x;
   const int nact = a.n_active ? *a.n_active : a.n_active_host;
   if (idx >= nact) return;
   const int r = a.sites ? a.sites[idx] : idx;
@@ -63,7 +70,7 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(EvalArgs a) {
   const int slot = lane / kSlot, s = lane - slot * kSlot;
   const int slotA = slot < kSlots ? slot : kSlots - 1;  // lane 63 shadows slot 2 for addressing
   const bool act = (slot < kSlots) && (s < q);
-  const int tile0 = blockIdx.x * tileSeq;
+  const int tile0 = blockIdx.y * tileSeq;
   const int tw = wid * (NB * kSlots) + slotA;  // tile row of row j: tw + 3j
   const int bw = tile0 + tw;
 
@@ -88,7 +95,7 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(EvalArgs a) {
       row[ss + 2 * kSlot] = v;
     }
     for (int e = tid; e < tileSeq; e += kFwdThreads)
-      sgl[e] = *reinterpret_cast<const uint4*>(a.msa_pad + (size_t)(tile0 + e) * a.N_pad + c * kFwdChunk);
+      sgl[e] = *reinterpret_cast<const uint4*>(a.msa_cm + ((size_t)c * a.B_pad + tile0 + e) * kFwdChunk);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
@@ -140,7 +147,7 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(EvalArgs a) {
       }
       sum = __shfl(sum, sbase, 64);
       const float lse = m + logf(sum);
-      const int sr = a.msa_pad[(size_t)b * a.N_pad + r];
+      const int sr = a.msa_cm[((size_t)(r / kFwdChunk) * a.B_pad + b) * kFwdChunk + r % kFwdChunk];
       const double wb = (slot < kSlots && b < a.B) ? a.w[b] : 0.0;
       const float P = ex / sum;
       const float Rv = act ? (float)wb * (P - (s == sr ? 1.f : 0.f)) : 0.f;
@@ -150,20 +157,20 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(EvalArgs a) {
     }
   }
   const double ftot = block_sum_f64(facc, red);
-  if (tid == 0) a.f_part[(size_t)blockIdx.x * N + r] = ftot;
+  if (tid == 0) a.f_part[(size_t)blockIdx.y * N + r] = ftot;
   red[wid * 64 + lane] = (slot < kSlots) ? ghacc : 0.0;
   __syncthreads();
   if (tid < kSlot) {
     double t = 0.0;
     for (int w = 0; w < kFwdWaves; ++w)
       for (int c = 0; c < kSlots; ++c) t += red[w * 64 + c * kSlot + tid];
-    a.gh_part[((size_t)blockIdx.x * N + r) * kSlot + tid] = t;
+    a.gh_part[((size_t)blockIdx.y * N + r) * kSlot + tid] = t;
   }
 }
 
 hipError_t launch_forward(const EvalArgs& a, int32_t n_sites_grid, int32_t nb, hipStream_t st) {
   const int tiles = (a.B + forward_tile_seqs(nb) - 1) / forward_tile_seqs(nb);
-  dim3 grid(tiles, n_sites_grid);
+  dim3 grid(n_sites_grid, tiles);
   switch (nb) {
     case 16: hipLaunchKernelGGL(fwd_kernel<16>, grid, dim3(kFwdThreads), 0, st, a); break;
     case 32: hipLaunchKernelGGL(fwd_kernel<32>, grid, dim3(kFwdThreads), 0, st, a); break;
@@ -177,8 +184,8 @@ hipError_t launch_forward(const EvalArgs& a, int32_t n_sites_grid, int32_t nb, h
 // done once per alignment.  Entry = (chunk-local row << 8) | symbol; the row
 // field is then directly the byte offset of the row in the LDS residual tile
 // (rows of 64 floats = 256 bytes), and the low byte the symbol.
-__global__ __launch_bounds__(256) void chunk_sort_kernel(const uint8_t* __restrict__ msa_pad,
-                                                         int32_t B3, int32_t N, int32_t N_pad,
+__global__ __launch_bounds__(256) void chunk_sort_kernel(const uint8_t* __restrict__ msa_cm,
+                                                         int32_t B3, int32_t B_pad, int32_t N,
                                                          int32_t q, uint16_t* __restrict__ sorted) {
   __shared__ uint16_t cnt[256][kQMax + 1];
   const int c = blockIdx.x, i = blockIdx.y * 256 + threadIdx.x;
@@ -186,7 +193,8 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const uint8_t* __restri
   const int b0 = c * kBwdSeqChunk, n = min(kBwdSeqChunk, B3 - b0);
   uint16_t* ct = cnt[threadIdx.x];
   for (int k = 0; k <= kQMax; ++k) ct[k] = 0;
-  for (int t = 0; t < n; ++t) ct[msa_pad[(size_t)(b0 + t) * N_pad + i]]++;
+  const uint8_t* col = msa_cm + (size_t)(i / kFwdChunk) * B_pad * kFwdChunk + i % kFwdChunk;
+  for (int t = 0; t < n; ++t) ct[col[(size_t)(b0 + t) * kFwdChunk]]++;
   int run = 0;
   for (int k = 0; k < q; ++k) {
     const int v = ct[k];
@@ -195,16 +203,16 @@ __global__ __launch_bounds__(256) void chunk_sort_kernel(const uint8_t* __restri
   }
   uint16_t* out = sorted + ((size_t)c * N + i) * kBwdSeqChunk;
   for (int t = 0; t < n; ++t) {
-    const int k = msa_pad[(size_t)(b0 + t) * N_pad + i];
+    const int k = col[(size_t)(b0 + t) * kFwdChunk];
     out[ct[k]++] = (uint16_t)((t << 8) | k);
   }
 }
 
-hipError_t launch_chunk_sort(const uint8_t* msa_pad, int32_t B3, int32_t N, int32_t N_pad, int32_t q,
+hipError_t launch_chunk_sort(const uint8_t* msa_cm, int32_t B3, int32_t B_pad, int32_t N, int32_t q,
                              uint16_t* sorted, hipStream_t st) {
   const int nchunks = (B3 + kBwdSeqChunk - 1) / kBwdSeqChunk;
-  hipLaunchKernelGGL(chunk_sort_kernel, dim3(nchunks, (N + 255) / 256), dim3(256), 0, st, msa_pad,
-                     B3, N, N_pad, q, sorted);
+  hipLaunchKernelGGL(chunk_sort_kernel, dim3(nchunks, (N + 255) / 256), dim3(256), 0, st, msa_cm,
+                     B3, B_pad, N, q, sorted);
   return hipGetLastError();
 }
 
@@ -230,12 +238,12 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_kernel(EvalArgs a) {
   float* Rs = reinterpret_cast<float*>(arena);
   uint16_t* ent = reinterpret_cast<uint16_t*>(arena + kRsBytes);
   float* seg = reinterpret_cast<float*>(arena + kRsBytes + kEntBytes);
-  const int idx = blockIdx.y;
+  const int idx = blockIdx.x;  // sites fastest: resident blocks share a column group's entries
   const int nact = a.n_active ? *a.n_active : a.n_active_host;
   if (idx >= nact) return;
   const int r = a.sites ? a.sites[idx] : idx;
   const int q = a.q, N = a.N, qq = q * q;
-  const int i0 = blockIdx.x * kBwdPos;
+  const int i0 = blockIdx.y * kBwdPos;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int slot = lane / kSlot, s = lane - slot * kSlot;
   const int slotA = slot < kSlots ? slot : kSlots - 1;  // lane 63 shadows lane 42 and never writes
@@ -332,7 +340,7 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_kernel(EvalArgs a) {
 }
 
 hipError_t launch_backward(const EvalArgs& a, int32_t n_sites_grid, hipStream_t st) {
-  dim3 grid((a.N + kBwdPos - 1) / kBwdPos, n_sites_grid);
+  dim3 grid(n_sites_grid, (a.N + kBwdPos - 1) / kBwdPos);
   hipLaunchKernelGGL(bwd_kernel, grid, dim3(kBwdThreads), 0, st, a);
   return hipGetLastError();
 }

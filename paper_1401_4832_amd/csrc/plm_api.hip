@@ -56,7 +56,7 @@ struct Bump {
 size_t rup(size_t x, size_t m) { return (x + m - 1) / m * m; }
 
 struct EvalBufs {
-  uint8_t* msa_pad;
+  uint8_t* msa_cm;
   float* R;
   double* f_part;
   double* gh_part;
@@ -70,7 +70,7 @@ void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
   e.N_pad = (int32_t)rup(N, kFwdChunk);
   e.B3 = (int32_t)rup(B, 3);
   e.tiles_max = (B + forward_tile_seqs(16) - 1) / forward_tile_seqs(16);
-  e.msa_pad = bp.take<uint8_t>((size_t)e.B_pad * e.N_pad);
+  e.msa_cm = bp.take<uint8_t>((size_t)e.B_pad * e.N_pad);
   e.R = bp.take<float>((size_t)N * e.B3 * kSlot);
   e.f_part = bp.take<double>((size_t)e.tiles_max * N);
   e.gh_part = bp.take<double>((size_t)e.tiles_max * N * kSlot);
@@ -247,7 +247,8 @@ size_t plm_objgrad_workspace_bytes(int32_t B, int32_t N, int32_t q, int32_t path
 int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
                 const double* beff, const float* h, const float* J, double lambda_h,
                 double lambda_J, const int32_t* sites, int32_t n_sites, int32_t path, void* ws,
-                size_t ws_bytes, double* f_out, float* gh_out, float* gJ_out) {
+                size_t ws_bytes, const double* grad_scale, double* f_out, float* gh_out,
+                float* gJ_out) {
   if (!c) return PLM_E_INVALID;
   if (!msa || !w || !beff || !h || !J || !f_out) return set_err(c, PLM_E_INVALID, "null pointer");
   int rc = check_sizes(c, B, N, q);
@@ -267,11 +268,12 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
   HIPCHK(c, launch_check_f64(w, (size_t)B, c->pin_dev, c->stream));
   HIPCHK(c, launch_check_f32(h, (size_t)N * q, c->pin_dev, c->stream));
   HIPCHK(c, launch_check_f32(J, (size_t)N * N * q * q, c->pin_dev, c->stream));
-  HIPCHK(c, launch_pad_msa(msa, B, N, q, e.msa_pad, e.B_pad, e.N_pad, c->pin_dev, c->stream));
-  HIPCHK(c, launch_chunk_sort(e.msa_pad, e.B3, N, e.N_pad, q, e.sorted, c->stream));
+  if (grad_scale) HIPCHK(c, launch_check_f64(grad_scale, (size_t)N, c->pin_dev, c->stream));
+  HIPCHK(c, launch_pad_msa(msa, B, N, q, e.msa_cm, e.B_pad, e.N_pad, c->pin_dev, c->stream));
+  HIPCHK(c, launch_chunk_sort(e.msa_cm, e.B3, e.B_pad, N, q, e.sorted, c->stream));
   const int32_t nb = pick_nb(B, 0);
   EvalArgs a;
-  a.msa_pad = e.msa_pad;
+  a.msa_cm = e.msa_cm;
   a.B = B; a.B3 = e.B3; a.B_pad = e.B_pad; a.N = N; a.N_pad = e.N_pad; a.q = q;
   a.w = w; a.h = h; a.J = J;
   a.sites = sites; a.n_active = nullptr; a.n_active_host = n_sites;
@@ -279,11 +281,11 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
   a.sorted = e.sorted;
   a.tiles = (B + forward_tile_seqs(nb) - 1) / forward_tile_seqs(nb);
   HIPCHK(c, launch_forward(a, n_sites, nb, c->stream));
-  HIPCHK(c, launch_backward(a, n_sites, c->stream));
+  if (gJ_out) HIPCHK(c, launch_backward(a, n_sites, c->stream));
   FinalArgs fa;
   fa.N = N; fa.q = q; fa.tiles = a.tiles; fa.lambda_h = lambda_h; fa.lambda_Jp = 0.5 * lambda_J;
   fa.beff = beff; fa.h = h; fa.J = J; fa.sites = sites;
-  fa.f_part = e.f_part; fa.gh_part = e.gh_part; fa.gJ = e.gJ;
+  fa.f_part = e.f_part; fa.gh_part = e.gh_part; fa.gJ = e.gJ; fa.grad_scale = grad_scale;
   fa.f_out = f_out; fa.gh_out = gh_out; fa.gJ_out = gJ_out;
   HIPCHK(c, launch_objgrad_final(fa, n_sites, c->stream));
   return PLM_OK;
@@ -348,8 +350,8 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
 
   HIPCHK(c, launch_check_f64(w, (size_t)B, c->pin_dev, st));
   HIPCHK(c, launch_check_f32(h_io, (size_t)N * q, c->pin_dev, st));
-  HIPCHK(c, launch_pad_msa(msa, B, N, q, f.ev.msa_pad, f.ev.B_pad, f.ev.N_pad, c->pin_dev, st));
-  HIPCHK(c, launch_chunk_sort(f.ev.msa_pad, f.ev.B3, N, f.ev.N_pad, q, f.ev.sorted, st));
+  HIPCHK(c, launch_pad_msa(msa, B, N, q, f.ev.msa_cm, f.ev.B_pad, f.ev.N_pad, c->pin_dev, st));
+  HIPCHK(c, launch_chunk_sort(f.ev.msa_cm, f.ev.B3, f.ev.B_pad, N, q, f.ev.sorted, st));
   HIPCHK(c, launch_init_fit(N, q, h_io, J_io, f.Th, f.TJ, f.st, f.sites, f.n_active, phase_host_dev, st));
   HIPCHK(c, launch_check_f32(J_io, (size_t)N * N * q * q, c->pin_dev, st));
   HIPCHK(c, launch_zero_u64(f.site_evals, st));
@@ -359,7 +361,7 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
 
   const int32_t nb = pick_nb(B, o->tile_seqs);
   EvalArgs a;
-  a.msa_pad = f.ev.msa_pad;
+  a.msa_cm = f.ev.msa_cm;
   a.B = B; a.B3 = f.ev.B3; a.B_pad = f.ev.B_pad; a.N = N; a.N_pad = f.ev.N_pad; a.q = q;
   a.w = w; a.h = f.Th; a.J = f.TJ;
   a.sites = f.sites; a.n_active = f.n_active; a.n_active_host = N;

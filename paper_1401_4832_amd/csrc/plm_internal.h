@@ -54,7 +54,7 @@ enum { PH_INIT = 0, PH_LS = 1, PH_DONE = 2 };
 
 // Everything the evaluation kernels need about one alignment.
 struct EvalArgs {
-  const uint8_t* msa_pad;  // [B_pad][N_pad] symbols, zero padded
+  const uint8_t* msa_cm;   // padded symbols, chunk-major: (b, i) at ((i/16)*B_pad + b)*16 + i%16
   int32_t B, B3, B_pad, N, N_pad, q;
   const double* w;         // [B]
   const float* h;          // [N][q]  (trial point)
@@ -107,6 +107,7 @@ struct FinalArgs {
   const double* f_part;
   const double* gh_part;
   const double* gJ;
+  const double* grad_scale;  // nullable per-site gradient multiplier
   double* f_out;
   float* gh_out;
   float* gJ_out;
@@ -128,11 +129,11 @@ __device__ inline double block_sum_f64(double v, double* red) {
 }
 
 // Host-side launchers -------------------------------------------------------
-hipError_t launch_pad_msa(const uint8_t* msa, int32_t B, int32_t N, int32_t q, uint8_t* msa_pad,
+hipError_t launch_pad_msa(const uint8_t* msa, int32_t B, int32_t N, int32_t q, uint8_t* msa_cm,
                           int32_t B_pad, int32_t N_pad, int32_t* flag_dev, hipStream_t st);
 hipError_t launch_forward(const EvalArgs& a, int32_t n_sites_grid, int32_t nb, hipStream_t st);
 hipError_t launch_backward(const EvalArgs& a, int32_t n_sites_grid, hipStream_t st);
-hipError_t launch_chunk_sort(const uint8_t* msa_pad, int32_t B3, int32_t N, int32_t N_pad, int32_t q,
+hipError_t launch_chunk_sort(const uint8_t* msa_cm, int32_t B3, int32_t B_pad, int32_t N, int32_t q,
                              uint16_t* sorted, hipStream_t st);
 int32_t forward_tile_seqs(int32_t nb);
 hipError_t launch_lbfgs(const LbfgsArgs& a, int32_t nblocks, hipStream_t st);
