@@ -56,9 +56,15 @@ extern "C" {
 #define PLM_E_HIP -5         /* a HIP runtime error; plm_last_error() has the text */
 #define PLM_E_UNSUPPORTED -6 /* device is not gfx950, or an option not built */
 
-/* Objective/gradient evaluation paths. */
-#define PLM_PATH_GATHER_FP32 0 /* LDS gather/scatter, FP32 arithmetic, FP64 reductions */
-#define PLM_PATH_MFMA_BF16X2 1 /* one-hot BF16 MFMA contraction, hi/lo split operands */
+/* Objective/gradient evaluation paths.  All reduce objectives and gradients
+ * over sequences in FP64 and keep the optimiser in FP64. */
+#define PLM_PATH_GATHER_FP32 0 /* energies by LDS gather, coupling gradient by a symbol-sorted
+                                  LDS scatter; FP32 arithmetic */
+#define PLM_PATH_MFMA_BF16X2 1 /* energies and coupling gradient as one-hot BF16 MFMA products
+                                  with hi/lo-split couplings and residuals (precision path) */
+#define PLM_PATH_GATHER_MFMA_FP32 2 /* energies by LDS gather; coupling gradient as a one-hot
+                                  MFMA product with residuals split into three BF16 pieces,
+                                  which carry FP32's 24-bit significand */
 
 typedef struct plm_ctx plm_ctx;
 

@@ -254,7 +254,7 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
   int rc = check_sizes(c, B, N, q);
   if (rc) return rc;
   if (!(lambda_h >= 0.0) || !(lambda_J >= 0.0)) return set_err(c, PLM_E_INVALID, "negative lambda");
-  if (path != PLM_PATH_GATHER_FP32)
+  if (path != PLM_PATH_GATHER_FP32 && path != PLM_PATH_GATHER_MFMA_FP32)
     return set_err(c, PLM_E_UNSUPPORTED, "evaluation path %d is not available", path);
   if (!sites) n_sites = N;
   if (n_sites < 1 || n_sites > N) return set_err(c, PLM_E_INVALID, "n_sites out of range");
@@ -281,7 +281,12 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
   a.sorted = e.sorted;
   a.tiles = (B + forward_tile_seqs(nb) - 1) / forward_tile_seqs(nb);
   HIPCHK(c, launch_forward(a, n_sites, nb, c->stream));
-  if (gJ_out) HIPCHK(c, launch_backward(a, n_sites, c->stream));
+  if (gJ_out) {
+    if (path == PLM_PATH_GATHER_MFMA_FP32)
+      HIPCHK(c, launch_backward_mfma(a, n_sites, 3, c->stream));
+    else
+      HIPCHK(c, launch_backward(a, n_sites, c->stream));
+  }
   FinalArgs fa;
   fa.N = N; fa.q = q; fa.tiles = a.tiles; fa.lambda_h = lambda_h; fa.lambda_Jp = 0.5 * lambda_J;
   fa.beff = beff; fa.h = h; fa.J = J; fa.sites = sites;
@@ -329,7 +334,7 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
   if (!(o->lambda_h >= 0.0) || !(o->lambda_J >= 0.0) || !(o->tol >= 0.0) || o->max_iter < 1 ||
       o->lbfgs_m < 1 || o->lbfgs_m > kMMax || o->max_linesearch < 1)
     return set_err(c, PLM_E_INVALID, "invalid fit options");
-  if (o->path != PLM_PATH_GATHER_FP32)
+  if (o->path != PLM_PATH_GATHER_FP32 && o->path != PLM_PATH_GATHER_MFMA_FP32)
     return set_err(c, PLM_E_UNSUPPORTED, "evaluation path %d is not available", o->path);
   const size_t need = plm_fit_workspace_bytes(B, N, q, o);
   rc = check_ws(c, ws, ws_bytes, need);
@@ -395,7 +400,8 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
       L1.site_offset = r;
       for (int64_t it = 0; it < cap; ++it) {
         HIPCHK(c, launch_forward(a1, 1, nb, st));
-        HIPCHK(c, launch_backward(a1, 1, st));
+        HIPCHK(c, o->path == PLM_PATH_GATHER_MFMA_FP32 ? launch_backward_mfma(a1, 1, 3, st)
+                                                      : launch_backward(a1, 1, st));
         HIPCHK(c, launch_lbfgs(L1, 1, st));
         HIPCHK(c, hipStreamSynchronize(st));
         if (phase_host[r] == PH_DONE) break;
@@ -410,7 +416,9 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
       hipError_t e = mark(0);
       if (e == hipSuccess) e = launch_forward(a, N, nb, st);
       if (e == hipSuccess) e = mark(1);
-      if (e == hipSuccess) e = launch_backward(a, N, st);
+      if (e == hipSuccess)
+        e = o->path == PLM_PATH_GATHER_MFMA_FP32 ? launch_backward_mfma(a, N, 3, st)
+                                                 : launch_backward(a, N, st);
       if (e == hipSuccess) e = mark(2);
       if (e == hipSuccess) e = launch_lbfgs(L, N, st);
       if (e == hipSuccess) e = mark(3);

@@ -133,6 +133,8 @@ hipError_t launch_pad_msa(const uint8_t* msa, int32_t B, int32_t N, int32_t q, u
                           int32_t B_pad, int32_t N_pad, int32_t* flag_dev, hipStream_t st);
 hipError_t launch_forward(const EvalArgs& a, int32_t n_sites_grid, int32_t nb, hipStream_t st);
 hipError_t launch_backward(const EvalArgs& a, int32_t n_sites_grid, hipStream_t st);
+hipError_t launch_backward_mfma(const EvalArgs& a, int32_t n_sites_grid, int32_t npieces,
+                                hipStream_t st);
 hipError_t launch_chunk_sort(const uint8_t* msa_cm, int32_t B3, int32_t B_pad, int32_t N, int32_t q,
                              uint16_t* sorted, hipStream_t st);
 int32_t forward_tile_seqs(int32_t nb);

@@ -57,10 +57,11 @@ def test_fit_small_all_sites(plm):
     np.testing.assert_allclose(cfn.cpu().numpy(), cfn_o, rtol=1e-9, atol=1e-12)
 
 
-def test_fit_gapped_sampled_sites(plm):
-    print("[case] fit potts_n120_b5000_gaps sampled sites", flush=True)
+@pytest.mark.parametrize("path", [0, 2])
+def test_fit_gapped_sampled_sites(plm, path):
+    print(f"[case] fit potts_n120_b5000_gaps sampled sites path={path}", flush=True)
     s = synth.workload("potts_n120_b5000_gaps")
-    opts = plm.FitOptions(tol=1e-6)
+    opts = plm.FitOptions(tol=1e-6, path=path)
     sites = [0, 1, 37, 60, 88, 119]
     res, err, cert, _ = _fit_case(plm, s, False, opts, sites)
     assert all(st["status"] == "converged" for st in res.stats), res.stats[:3]

@@ -84,13 +84,16 @@ def test_reweight_uniform(plm):
 
 
 # ----------------------------------------------------------- objective/grad
-def _objgrad_case(plm, msa, w_o, beff_o, h, J, lh=0.01, lJ=0.01, sites=None):
+PATHS = [0, 2]  # gather/scatter FP32; gather forward + three-piece MFMA coupling gradient
+
+
+def _objgrad_case(plm, msa, w_o, beff_o, h, J, lh=0.01, lJ=0.01, sites=None, path=0):
     B, N = msa.shape
     q = h.shape[1]
     w = _to(w_o)
     beff = _to(np.array([beff_o]))
     f, gh, gJ = plm.objgrad(_to(msa), w, beff, _to(h.astype(np.float32)), _to(J.astype(np.float32)),
-                            lh, lJ, sites=sites)
+                            lh, lJ, sites=sites, path=path)
     plm.sync(DEV)
     Jz = J.astype(np.float32).astype(np.float64)
     for r in range(N):
@@ -106,28 +109,30 @@ def _objgrad_case(plm, msa, w_o, beff_o, h, J, lh=0.01, lJ=0.01, sites=None):
     return frel, gerr, gJ
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("B,N,q", [(500, 40, 21), (1, 2, 21), (7, 17, 21), (3001, 33, 21), (800, 25, 3),
-                                   (1537, 49, 11), (4000, 70, 21)])
-def test_objgrad_random_point(plm, B, N, q):
-    _note(f"objgrad random B={B} N={N} q={q}")
+                                   (1537, 49, 11), (4000, 70, 21), (700, 97, 21)])
+def test_objgrad_random_point(plm, B, N, q, path):
+    _note(f"objgrad random B={B} N={N} q={q} path={path}")
     rng = np.random.default_rng(B * 7 + N)
     msa = rng.integers(0, q, size=(B, N), dtype=np.uint8)
     w_o = rng.uniform(0.2, 1.0, size=B)
     beff_o = float(np.sum(w_o))
     h, J = random_params(B + q, N, q, 0.3, 0.2)
-    frel, gerr, gJ = _objgrad_case(plm, msa, w_o, beff_o, h, J)
+    frel, gerr, gJ = _objgrad_case(plm, msa, w_o, beff_o, h, J, path=path)
     assert frel <= 1e-5, frel
     assert gerr <= 2e-6, gerr
     for r in range(N):
         assert np.all(gJ[r, r] == 0)
 
 
-def test_objgrad_workload_gapped(plm):
+@pytest.mark.parametrize("path", PATHS)
+def test_objgrad_workload_gapped(plm, path):
     s = synth.workload("potts_n120_b5000_gaps")
-    _note("objgrad potts_n120_b5000_gaps")
+    _note(f"objgrad potts_n120_b5000_gaps path={path}")
     m_o, w_o, beff_o = oracle.reweight(s.msa, theta=0.8)
     h, J = random_params(3, s.N, 21, 0.1, 0.1)
-    frel, gerr, _ = _objgrad_case(plm, s.msa, w_o, beff_o, h, J, sites=[0, 5, 60, 119])
+    frel, gerr, _ = _objgrad_case(plm, s.msa, w_o, beff_o, h, J, sites=[0, 5, 60, 119], path=path)
     assert frel <= 1e-5 and gerr <= 2e-6, (frel, gerr)
 
 
@@ -141,15 +146,16 @@ def test_objgrad_at_origin_is_beff_log_q(plm):
     np.testing.assert_allclose(f.cpu().numpy(), 500 * np.log(21.0), rtol=1e-7)
 
 
-def test_objgrad_deterministic(plm):
+@pytest.mark.parametrize("path", PATHS)
+def test_objgrad_deterministic(plm, path):
     rng = np.random.default_rng(9)
     msa = rng.integers(0, 21, size=(2000, 30), dtype=np.uint8)
     w = _to(np.ones(2000))
     beff = _to(np.array([2000.0]))
     h, J = random_params(10, 30, 21)
     ht, Jt = _to(h.astype(np.float32)), _to(J.astype(np.float32))
-    a = plm.objgrad(_to(msa), w, beff, ht, Jt)
-    b = plm.objgrad(_to(msa), w, beff, ht, Jt)
+    a = plm.objgrad(_to(msa), w, beff, ht, Jt, path=path)
+    b = plm.objgrad(_to(msa), w, beff, ht, Jt, path=path)
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2])
 
 
