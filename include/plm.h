@@ -57,14 +57,19 @@ extern "C" {
 #define PLM_E_UNSUPPORTED -6 /* device is not gfx950, or an option not built */
 
 /* Objective/gradient evaluation paths.  All reduce objectives and gradients
- * over sequences in FP64 and keep the optimiser in FP64. */
+ * over sequences in FP64 and keep the optimiser in FP64.  The one-hot matrix
+ * X[b][(i,k)] = [sigma_i^b = k] is exact in BF16; the MFMA paths split the
+ * other operand (the couplings W_r[(i,k)][s] = J_ri(s,k) in the forward, the
+ * residuals R_b(s) in the backward) into BF16 pieces and accumulate in FP32. */
 #define PLM_PATH_GATHER_FP32 0 /* energies by LDS gather, coupling gradient by a symbol-sorted
                                   LDS scatter; FP32 arithmetic */
-#define PLM_PATH_MFMA_BF16X2 1 /* energies and coupling gradient as one-hot BF16 MFMA products
-                                  with hi/lo-split couplings and residuals (precision path) */
-#define PLM_PATH_GATHER_MFMA_FP32 2 /* energies by LDS gather; coupling gradient as a one-hot
-                                  MFMA product with residuals split into three BF16 pieces,
-                                  which carry FP32's 24-bit significand */
+#define PLM_PATH_MFMA_BF16X2 1 /* both directions as MFMA products with hi/lo (two-piece)
+                                  operands: 16 significant bits, relative error <= 2^-16 per
+                                  coupling and residual (precision/speed trade-off) */
+#define PLM_PATH_GATHER_MFMA_FP32 2 /* energies by LDS gather; coupling gradient as an MFMA
+                                  product with three-piece residuals (24 significant bits, the
+                                  FP32 significand) */
+#define PLM_PATH_MFMA_FP32 3   /* both directions as MFMA products with three-piece operands */
 
 typedef struct plm_ctx plm_ctx;
 

@@ -6,7 +6,9 @@ from . import _lib
 from .autograd import PLMObjective, plm_objective
 from .api import (FitOptions, FitResult, context, fit, last_fit_timing, objgrad, reweight, score, sync,
                   workspace)
-from ._lib import PATH_GATHER_FP32, PATH_GATHER_MFMA_FP32, PATH_MFMA_BF16X2, PlmError
+from ._lib import (PATH_GATHER_FP32, PATH_GATHER_MFMA_FP32, PATH_MFMA_BF16X2, PATH_MFMA_FP32,
+                   PlmError)
 
 __all__ = ["PLMObjective", "plm_objective", "FitOptions", "FitResult", "context", "fit", "last_fit_timing", "objgrad", "reweight", "score", "sync",
-           "workspace", "PATH_GATHER_FP32", "PATH_GATHER_MFMA_FP32", "PATH_MFMA_BF16X2", "PlmError"]
+           "workspace", "PATH_GATHER_FP32", "PATH_GATHER_MFMA_FP32", "PATH_MFMA_BF16X2",
+           "PATH_MFMA_FP32", "PlmError"]

@@ -19,6 +19,7 @@ PLM_E_UNSUPPORTED = -6
 PATH_GATHER_FP32 = 0
 PATH_MFMA_BF16X2 = 1
 PATH_GATHER_MFMA_FP32 = 2
+PATH_MFMA_FP32 = 3
 
 SITE_STATUS = {0: "converged", 1: "maxiter", 2: "linesearch", 3: "nonfinite"}
 

@@ -9,6 +9,13 @@
 // piece is multiplied on v_mfma_f32_32x32x16_bf16 with FP32 accumulation,
 // folded into FP64 every 256 rows.
 //
+// One block = one site x up to 768 rows (i,k) (36 columns at q = 21), all
+// sequences, in 256-sequence chunks.  A chunk's residual pieces and symbols are
+// staged in LDS (double-buffered); the global loads of chunk c+2 are issued
+// before the matrix work on chunk c so that their latency is hidden.  Blocks
+// are ordered so that the column blocks of one site run on one XCD and share
+// its L2 copy of R_r.
+//
 // Fragment layouts of v_mfma_f32_32x32x16_bf16 (verified on the device): A
 // lane l holds row l % 32, inner indices 8 (l / 32) + 0..7; B lane l holds
 // column l % 32, the same inner indices; D lane l register j holds row
@@ -22,12 +29,18 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int kMWaves = 8;
 constexpr int kMThreads = kMWaves * 64;
-constexpr int kMRowBlocks = 4;                 // 32-row blocks per wave
-constexpr int kMPos = 48;                      // columns per block: 48 * 21 <= 8 * 4 * 32 rows
-constexpr int kMChunk = 256;                   // alignment rows per staged chunk (16 steps of 16)
-constexpr int kMSteps = kMChunk / 16;
+constexpr int kMRB = 3;                          // 32-row blocks per wave
+constexpr int kMRows = kMWaves * kMRB * 32;      // 768 rows (i,k) per block
+constexpr int kMPosMax = 48;                     // alignment columns per block at most
+constexpr int kMChunk = 256;                     // sequences per staged chunk
+constexpr int kMSteps = kMChunk / 16;            // MFMA steps per chunk
+constexpr int kSigPitch = kMChunk + 16;          // LDS bytes per column (padding spreads banks)
+constexpr int kBfPiece = kMSteps * 2 * 32 * 8;   // BF16 entries of one piece of one chunk
+constexpr int kRUnits = (kMChunk / 8) * kSlot;   // (8-sequence group, state) units per chunk
 
-__device__ inline uint32_t f2bf(float f) {     // round to nearest even (finite inputs)
+int32_t mfma_block_positions(int32_t q) { return min(kMPosMax, kMRows / q); }
+
+__device__ inline uint32_t f2bf(float f) {  // round to nearest even (finite inputs)
   uint32_t u = __float_as_uint(f);
   u += 0x7fffu + ((u >> 16) & 1u);
   return u >> 16;
@@ -39,9 +52,9 @@ __device__ inline bf16x8 onehot8(uint2 s8, uint32_t kk) {
   uint32_t w[2] = {s8.x, s8.y}, r[4];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const uint32_t x = w[h] ^ kk;                                    // zero byte where equal
-    const uint32_t nz = ((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x;       // bit 7 set where not equal
-    const uint32_t m = (nz & 0x80808080u) ^ 0x80808080u;             // 0x80 where equal
+    const uint32_t x = w[h] ^ kk;                               // zero byte where equal
+    const uint32_t nz = ((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x;  // bit 7 set where not equal
+    const uint32_t m = (nz & 0x80808080u) ^ 0x80808080u;        // 0x80 where equal
     // bytes (m0, 0, m1, 0) and (m2, 0, m3, 0), times 0x7f: 0x80 * 0x7f = 0x3f80
     r[2 * h] = __builtin_amdgcn_perm(0u, m, 0x0c010c00u) * 0x7fu;
     r[2 * h + 1] = __builtin_amdgcn_perm(0u, m, 0x0c030c02u) * 0x7fu;
@@ -50,115 +63,191 @@ __device__ inline bf16x8 onehot8(uint2 s8, uint32_t kk) {
   return __builtin_bit_cast(bf16x8, v);
 }
 
+// Position-major copy of the padded alignment: msaT[i * B_pad + b].
+__global__ void transpose_msa_kernel(const uint8_t* __restrict__ msa_cm, int32_t B_pad,
+                                     int32_t N_pad, uint8_t* __restrict__ msaT) {
+  const size_t groups = (size_t)B_pad / 16;
+  const size_t total = (size_t)N_pad * groups;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int32_t i = (int32_t)(e / groups);
+    const size_t b0 = (e - (size_t)i * groups) * 16;
+    const uint8_t* src = msa_cm + ((size_t)(i / kFwdChunk) * B_pad + b0) * kFwdChunk + i % kFwdChunk;
+    uint32_t w[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      w[t] = (uint32_t)src[(4 * t) * kFwdChunk] | ((uint32_t)src[(4 * t + 1) * kFwdChunk] << 8) |
+             ((uint32_t)src[(4 * t + 2) * kFwdChunk] << 16) |
+             ((uint32_t)src[(4 * t + 3) * kFwdChunk] << 24);
+    }
+    *reinterpret_cast<uint4*>(msaT + (size_t)i * B_pad + b0) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+hipError_t launch_transpose_msa(const uint8_t* msa_cm, int32_t B_pad, int32_t N_pad, uint8_t* msaT,
+                                hipStream_t st) {
+  const size_t total = (size_t)N_pad * (B_pad / 16);
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(transpose_msa_kernel, dim3(blocks), dim3(256), 0, st, msa_cm, B_pad, N_pad,
+                     msaT);
+  return hipGetLastError();
+}
+
 template <int NP>
-__global__ __launch_bounds__(kMThreads) void bwd_mfma_kernel(EvalArgs a) {
-  // B fragments of the residual pieces: [piece][step][half][column][8 rows]
-  __shared__ __attribute__((aligned(16))) uint16_t Bf[NP * kMSteps * 2 * 32 * 8];
-  __shared__ __attribute__((aligned(16))) uint8_t sig[kMPos * kMChunk];  // [column][row] symbols
-  const int idx = blockIdx.x;  // sites fastest
+__global__ __launch_bounds__(kMThreads) void bwd_mfma_kernel(EvalArgs a, int32_t npos_blk,
+                                                             int32_t ncb, int32_t xcd_map) {
+  // B fragments of the residual pieces: [buffer][piece][step][half][column][8 sequences]
+  __shared__ __attribute__((aligned(16))) uint16_t Bf[2][NP * kBfPiece];
+  // symbols of the block's columns: [buffer][column][sequence]
+  __shared__ __attribute__((aligned(16))) uint8_t sig[2][kMPosMax * kSigPitch];
+
+  // workgroups are dealt to the XCDs round-robin; with xcd_map, XCD x takes
+  // the sites x, x + 8, ... and all their column blocks in turn
+  int idx, cb;
+  if (xcd_map) {
+    const int x = blockIdx.x & 7, k = blockIdx.x >> 3;
+    idx = 8 * (k / ncb) + x;
+    cb = k % ncb;
+  } else {
+    idx = blockIdx.x / ncb;
+    cb = blockIdx.x % ncb;
+  }
   const int nact = a.n_active ? *a.n_active : a.n_active_host;
   if (idx >= nact) return;
   const int r = a.sites ? a.sites[idx] : idx;
   const int q = a.q, N = a.N, qq = q * q;
-  const int i0 = blockIdx.y * kMPos;
-  const int npos = min(kMPos, N - i0);
+  const int i0 = cb * npos_blk;
+  const int npos = min(npos_blk, N - i0);
   const int nrows = npos * q;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
 
-  // this lane's A-fragment row in each of its row blocks
-  int arow_col[kMRowBlocks];
-  uint32_t arow_kk[kMRowBlocks];
-  bool arow_ok[kMRowBlocks];
+  // this lane's A-fragment row in each of its row blocks; rows past the end
+  // compare against 0xff, which no symbol equals, so their one-hot is zero
+  int arow_off[kMRB];
+  uint32_t arow_kk[kMRB];
 #pragma unroll
-  for (int m = 0; m < kMRowBlocks; ++m) {
-    const int rho = (wid * kMRowBlocks + m) * 32 + l32;
-    arow_ok[m] = rho < nrows;
-    const int rr = arow_ok[m] ? rho : 0;
-    arow_col[m] = rr / q;
-    arow_kk[m] = (uint32_t)(rr % q) * 0x01010101u;
+  for (int m = 0; m < kMRB; ++m) {
+    const int rho = (wid * kMRB + m) * 32 + l32;
+    const bool ok = rho < nrows;
+    arow_off[m] = ok ? (rho / q) * kSigPitch : 0;
+    arow_kk[m] = ok ? (uint32_t)(rho % q) * 0x01010101u : 0xffffffffu;
   }
-  const bool wave_live = wid * kMRowBlocks * 32 < nrows;
+  const bool wave_live = wid * kMRB * 32 < nrows;
 
-  for (int e = tid; e < NP * kMSteps * 2 * 32 * 8; e += kMThreads) Bf[e] = 0;
-  floatx16 acc[kMRowBlocks];
-  double acc64[kMRowBlocks][16];
+  for (int e = tid; e < 2 * NP * kBfPiece / 8; e += kMThreads)
+    reinterpret_cast<uint4*>(&Bf[0][0])[e] = make_uint4(0, 0, 0, 0);
+
+  const float* Rr = a.R + (size_t)r * a.B3 * kSlot;
+  const int nchunks = (a.B3 + kMChunk - 1) / kMChunk;
+  const int nsig = npos_blk * (kMChunk / 16);
+
+  float rv[2][8];
+  uint4 sv[2];
+  auto load = [&](int c) {
+    const int bc = c * kMChunk;
 #pragma unroll
-  for (int m = 0; m < kMRowBlocks; ++m)
+    for (int k = 0; k < 2; ++k) {
+      const int u = tid + k * kMThreads;
+      const int g = u / kSlot, s = u - g * kSlot;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int row = bc + g * 8 + j;
+        rv[k][j] = (u < kRUnits && row < a.B3) ? Rr[(size_t)row * kSlot + s] : 0.f;
+      }
+      const int e = tid + k * kMThreads;
+      const int pos = e >> 4, part = e & 15;
+      sv[k] = make_uint4(0, 0, 0, 0);
+      if (e < nsig && i0 + pos < N)
+        sv[k] = *reinterpret_cast<const uint4*>(a.msaT + (size_t)(i0 + pos) * a.B_pad + bc + part * 16);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int u = tid + k * kMThreads;
+      if (u < kRUnits) {
+        const int g = u / kSlot, s = u - g * kSlot;
+        uint32_t hw[NP][4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          float v0 = rv[k][2 * jj], v1 = rv[k][2 * jj + 1];
+#pragma unroll
+          for (int p = 0; p < NP; ++p) {
+            const uint32_t h0 = f2bf(v0), h1 = f2bf(v1);
+            hw[p][jj] = h0 | (h1 << 16);
+            v0 -= bf2f(h0);
+            v1 -= bf2f(h1);
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+          *reinterpret_cast<uint4*>(&Bf[buf][p * kBfPiece + (g * 32 + s) * 8]) =
+              make_uint4(hw[p][0], hw[p][1], hw[p][2], hw[p][3]);
+      }
+      const int e = tid + k * kMThreads;
+      if (e < nsig)
+        *reinterpret_cast<uint4*>(&sig[buf][(e >> 4) * kSigPitch + (e & 15) * 16]) = sv[k];
+    }
+  };
+
+  floatx16 acc[kMRB];
+  double acc64[kMRB][16];
+#pragma unroll
+  for (int m = 0; m < kMRB; ++m)
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       acc[m][j] = 0.f;
       acc64[m][j] = 0.0;
     }
 
-  const float* Rr = a.R + (size_t)r * a.B3 * kSlot;
-  const int nchunks = (a.B3 + kMChunk - 1) / kMChunk;
-  const int c16_0 = i0 / kFwdChunk, nc16 = a.N_pad / kFwdChunk;
+  load(0);
+  __syncthreads();  // zero fill of the unused fragment columns is complete
+  store(0);
+  if (nchunks > 1) load(1);
+  __syncthreads();
   for (int c = 0; c < nchunks; ++c) {
-    const int bc = c * kMChunk, n = min(kMChunk, a.B3 - bc);
-    __syncthreads();
-    // residual pieces, transposed into the B-fragment layout (columns >= 21 stay zero)
-    for (int e = tid; e < kMChunk * kSlot; e += kMThreads) {
-      const int b = e / kSlot, s = e - b * kSlot;
-      const float v = b < n ? Rr[(size_t)(bc + b) * kSlot + s] : 0.f;
-      const int off = (((b >> 4) * 2 + ((b >> 3) & 1)) * 32 + s) * 8 + (b & 7);
-      uint32_t hi = f2bf(v);
-      Bf[off] = (uint16_t)hi;
-      float rem = v - bf2f(hi);
-#pragma unroll
-      for (int p = 1; p < NP; ++p) {
-        const uint32_t pc = f2bf(rem);
-        Bf[p * (kMSteps * 2 * 32 * 8) + off] = (uint16_t)pc;
-        rem -= bf2f(pc);
-      }
-    }
-    // symbols of the block's columns, transposed to [column][row]
-    for (int e = tid; e < kMChunk * 3; e += kMThreads) {
-      const int b = e / 3, g = e - b * 3, c16 = c16_0 + g;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (b < n && c16 < nc16) v = *reinterpret_cast<const uint4*>(a.msa_cm + ((size_t)c16 * a.B_pad + bc + b) * kFwdChunk);
-      const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int p = 0; p < 16; ++p) sig[(g * 16 + p) * kMChunk + b] = (uint8_t)(wv[p >> 2] >> (8 * (p & 3)));
-    }
-    __syncthreads();
+    const int buf = c & 1;
     if (wave_live) {
+      const uint16_t* bfb = &Bf[buf][((half * 32) + l32) * 8];
+      const uint8_t* sgb = &sig[buf][half * 8];
 #pragma unroll 2
       for (int t = 0; t < kMSteps; ++t) {
         bf16x8 bp[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p)
-          bp[p] = *reinterpret_cast<const bf16x8*>(
-              &Bf[p * (kMSteps * 2 * 32 * 8) + ((t * 2 + half) * 32 + l32) * 8]);
-        bf16x8 av[kMRowBlocks];
+          bp[p] = *reinterpret_cast<const bf16x8*>(bfb + p * kBfPiece + t * (2 * 32 * 8));
+        bf16x8 av[kMRB];
 #pragma unroll
-        for (int m = 0; m < kMRowBlocks; ++m) {
-          const uint2 s8 = *reinterpret_cast<const uint2*>(&sig[arow_col[m] * kMChunk + t * 16 + half * 8]);
-          av[m] = onehot8(s8, arow_kk[m]);
-          if (!arow_ok[m]) av[m] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
-        }
+        for (int m = 0; m < kMRB; ++m)
+          av[m] = onehot8(*reinterpret_cast<const uint2*>(sgb + arow_off[m] + t * 16), arow_kk[m]);
         // the row blocks are independent accumulation chains
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
-          for (int m = 0; m < kMRowBlocks; ++m)
+          for (int m = 0; m < kMRB; ++m)
             acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[m], bp[p], acc[m], 0, 0, 0);
       }
 #pragma unroll
-      for (int m = 0; m < kMRowBlocks; ++m)
+      for (int m = 0; m < kMRB; ++m)
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           acc64[m][j] += (double)acc[m][j];
           acc[m][j] = 0.f;
         }
     }
+    // the other buffer was last read before the previous barrier
+    if (c + 1 < nchunks) store(buf ^ 1);
+    if (c + 2 < nchunks) load(c + 2);
+    __syncthreads();
   }
   if (!wave_live) return;
 #pragma unroll
-  for (int m = 0; m < kMRowBlocks; ++m)
+  for (int m = 0; m < kMRB; ++m)
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const int row = (wid * kMRowBlocks + m) * 32 + 8 * (j >> 2) + 4 * half + (j & 3);
+      const int row = (wid * kMRB + m) * 32 + 8 * (j >> 2) + 4 * half + (j & 3);
       if (row < nrows && l32 < q) {
         const int i = i0 + row / q, k = row % q;
         a.gJ[((size_t)r * N + i) * qq + (size_t)k * q + l32] = (i == r) ? 0.0 : acc64[m][j];
@@ -166,13 +255,224 @@ __global__ __launch_bounds__(kMThreads) void bwd_mfma_kernel(EvalArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- forward
+// E_b(s) = h_r(s) + sum_i J_ri(s, sigma_i^b) (eq. condpfinal) as the product
+// of the one-hot X[b][(i,k)] with W_r[(i,k)][s] = J_ri(s,k) (i != r), the
+// couplings split into NP BF16 pieces.  One block = one site x 1024 sequences
+// (8 waves x 4 row blocks of 32); the inner index runs over eight alignment
+// columns per staged chunk, ordered (k-range, column, k within the range) with
+// q padded to 24, so that all lanes of a step test the same k-range.  The
+// log-sum-exp, objective term, residual R_b(s) and the h-gradient partials
+// follow in the epilogue, in the same output buffers as the gather forward.
+constexpr int kFRB = 4;                            // row blocks per wave
+constexpr int kFRows = kMWaves * kFRB * 32;        // 1024 sequences per block
+constexpr int kFPos = 8;                           // alignment columns per chunk
+constexpr int kFGroups = kFPos * 3;                // 8-wide inner-index groups per chunk
+constexpr int kFSteps = kFGroups / 2;              // 12 MFMA steps per chunk
+constexpr int kFPiece = kFGroups * 32 * 8;         // BF16 entries of one piece of one chunk
+
+int32_t mfma_forward_tile_seqs() { return kFRows; }
+
+// one-hot of sigma against the eight states kb..kb+7 (d = sigma - kb, unsigned)
+__device__ inline bf16x8 onehot_range(uint32_t d) {
+  const uint32_t v = (d & 1u) ? 0x3f800000u : 0x00003f80u;
+  const uint32_t w = d >> 1;
+  uint4 r = make_uint4(w == 0 ? v : 0u, w == 1 ? v : 0u, w == 2 ? v : 0u, w == 3 ? v : 0u);
+  return __builtin_bit_cast(bf16x8, r);
+}
+
+template <int NP>
+__global__ __launch_bounds__(kMThreads) void fwd_mfma_kernel(EvalArgs a, int32_t ntiles,
+                                                             int32_t xcd_map) {
+  // W fragments: [buffer][piece][group][column s][8 inner indices]
+  __shared__ __attribute__((aligned(16))) uint16_t Wf[2][NP * kFPiece];
+  // the tile's symbols for the chunk's eight columns: [buffer][sequence][column]
+  __shared__ __attribute__((aligned(16))) uint8_t sgl[2][kFRows * kFPos];
+  __shared__ double red[kMWaves * 64];
+
+  int idx, tile;
+  if (xcd_map) {
+    const int x = blockIdx.x & 7, k = blockIdx.x >> 3;
+    idx = 8 * (k / ntiles) + x;
+    tile = k % ntiles;
+  } else {
+    idx = blockIdx.x / ntiles;
+    tile = blockIdx.x % ntiles;
+  }
+  const int nact = a.n_active ? *a.n_active : a.n_active_host;
+  if (idx >= nact) return;
+  const int r = a.sites ? a.sites[idx] : idx;
+  const int q = a.q, N = a.N, qq = q * q;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int half = lane >> 5, l32 = lane & 31;
+  const int tile0 = tile * kFRows;
+
+  for (int e = tid; e < 2 * NP * kFPiece / 8; e += kMThreads)
+    reinterpret_cast<uint4*>(&Wf[0][0])[e] = make_uint4(0, 0, 0, 0);
+
+  const float* Jr = a.J + (size_t)r * N * qq;
+  const int nunits = kFGroups * q;  // (group, state) units, at most 504
+  const int nchunks = (N + kFPos - 1) / kFPos;
+  float wv[8];
+  uint2 sv[2];
+  auto load = [&](int c) {
+    const int i0 = c * kFPos;
+    const int u = tid;
+    const int g = u / q, s = u - g * q;
+    const int kg = g / kFPos, i = i0 + (g - kg * kFPos);
+    const bool uok = u < nunits && i < N && i != r;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = kg * 8 + j;
+      wv[j] = (uok && k < q) ? Jr[((size_t)i * q + k) * q + s] : 0.f;
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int row = tid + t * kMThreads;
+      sv[t] = *reinterpret_cast<const uint2*>(
+          a.msa_cm + ((size_t)(i0 / kFwdChunk) * a.B_pad + tile0 + row) * kFwdChunk + (i0 % kFwdChunk));
+    }
+  };
+  auto store = [&](int buf) {
+    if (tid < nunits) {
+      const int g = tid / q, s = tid - g * q;
+      uint32_t hw[NP][4];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        float v0 = wv[2 * jj], v1 = wv[2 * jj + 1];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const uint32_t h0 = f2bf(v0), h1 = f2bf(v1);
+          hw[p][jj] = h0 | (h1 << 16);
+          v0 -= bf2f(h0);
+          v1 -= bf2f(h1);
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        *reinterpret_cast<uint4*>(&Wf[buf][p * kFPiece + (g * 32 + s) * 8]) =
+            make_uint4(hw[p][0], hw[p][1], hw[p][2], hw[p][3]);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      *reinterpret_cast<uint2*>(&sgl[buf][(tid + t * kMThreads) * kFPos]) = sv[t];
+  };
+
+  floatx16 acc[kFRB];
+#pragma unroll
+  for (int m = 0; m < kFRB; ++m)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[m][j] = 0.f;
+
+  load(0);
+  __syncthreads();
+  store(0);
+  if (nchunks > 1) load(1);
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    // this lane's eight symbols per row block; odd lanes-halves take the odd columns
+    uint32_t sym[kFRB][2];
+#pragma unroll
+    for (int m = 0; m < kFRB; ++m) {
+      const uint2 s8 = *reinterpret_cast<const uint2*>(&sgl[buf][((wid * kFRB + m) * 32 + l32) * kFPos]);
+      const uint64_t v = ((uint64_t)s8.y << 32 | s8.x) >> (8 * half);
+      sym[m][0] = (uint32_t)v;
+      sym[m][1] = (uint32_t)(v >> 32);
+    }
+    const uint16_t* wfb = &Wf[buf][(half * 32 + l32) * 8];
+#pragma unroll
+    for (int t = 0; t < kFSteps; ++t) {
+      // group 2t + half = (k-range t / 4, column 2 (t % 4) + half)
+      const int kb = (t / 4) * 8;
+      const int sh = 16 * (t % 4);
+      bf16x8 bp[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        bp[p] = *reinterpret_cast<const bf16x8*>(wfb + p * kFPiece + t * (2 * 32 * 8));
+      bf16x8 av[kFRB];
+#pragma unroll
+      for (int m = 0; m < kFRB; ++m) {
+        const uint32_t sg = (sh < 32 ? sym[m][0] >> sh : sym[m][1] >> (sh - 32)) & 0xffu;
+        av[m] = onehot_range(sg - (uint32_t)kb);
+      }
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int m = 0; m < kFRB; ++m)
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[m], bp[p], acc[m], 0, 0, 0);
+    }
+    if (c + 1 < nchunks) store(buf ^ 1);
+    if (c + 2 < nchunks) load(c + 2);
+    __syncthreads();
+  }
+
+  // epilogue: rows of D are sequences, columns (lanes of a 32-lane half) states
+  const bool col_ok = l32 < q;
+  const float hv = col_ok ? a.h[r * q + l32] : 0.f;
+  double facc = 0.0, ghacc = 0.0;
+#pragma unroll
+  for (int m = 0; m < kFRB; ++m)
+#pragma unroll 4
+    for (int j = 0; j < 16; ++j) {
+      const int b = tile0 + (wid * kFRB + m) * 32 + 8 * (j >> 2) + 4 * half + (j & 3);
+      const float e = col_ok ? acc[m][j] + hv : -INFINITY;
+      float mx = e;
+#pragma unroll
+      for (int d = 16; d > 0; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d, 32));
+      const float ex = col_ok ? expf(e - mx) : 0.f;
+      float sum = ex;
+#pragma unroll
+      for (int d = 16; d > 0; d >>= 1) sum += __shfl_xor(sum, d, 32);
+      const float lse = mx + logf(sum);
+      const int sr = a.msa_cm[((size_t)(r / kFwdChunk) * a.B_pad + b) * kFwdChunk + r % kFwdChunk];
+      const double wb = b < a.B ? a.w[b] : 0.0;
+      const float P = ex / sum;
+      const float Rv = col_ok ? (float)wb * (P - (l32 == sr ? 1.f : 0.f)) : 0.f;
+      if (col_ok && l32 == sr) facc += wb * (double)(lse - e);
+      ghacc += (double)Rv;
+      if (col_ok && b < a.B3) a.R[((size_t)r * a.B3 + b) * kSlot + l32] = Rv;
+    }
+  const double ftot = block_sum_f64(facc, red);
+  if (tid == 0) a.f_part[(size_t)tile * N + r] = ftot;
+  ghacc += __shfl_xor(ghacc, 32, 64);
+  if (half == 0) red[wid * 32 + l32] = ghacc;
+  __syncthreads();
+  if (tid < q) {
+    double t = 0.0;
+    for (int w = 0; w < kMWaves; ++w) t += red[w * 32 + tid];
+    a.gh_part[((size_t)tile * N + r) * kSlot + tid] = t;
+  }
+}
+
+hipError_t launch_forward_mfma(const EvalArgs& a, int32_t n_sites_grid, int32_t npieces,
+                               hipStream_t st) {
+  if (a.q > kQMax || a.q < 1) return hipErrorInvalidValue;
+  const int ntiles = (a.B + kFRows - 1) / kFRows;
+  const int xcd_map = n_sites_grid >= 8 ? 1 : 0;
+  const int nblk = xcd_map ? 8 * ntiles * ((n_sites_grid + 7) / 8) : n_sites_grid * ntiles;
+  if (npieces == 3)
+    hipLaunchKernelGGL(fwd_mfma_kernel<3>, dim3(nblk), dim3(kMThreads), 0, st, a, ntiles, xcd_map);
+  else if (npieces == 2)
+    hipLaunchKernelGGL(fwd_mfma_kernel<2>, dim3(nblk), dim3(kMThreads), 0, st, a, ntiles, xcd_map);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t launch_backward_mfma(const EvalArgs& a, int32_t n_sites_grid, int32_t npieces,
                                 hipStream_t st) {
-  dim3 grid(n_sites_grid, (a.N + kMPos - 1) / kMPos);
+  if (a.q > 32 || a.q < 1) return hipErrorInvalidValue;
+  const int npos_blk = mfma_block_positions(a.q);
+  const int ncb = (a.N + npos_blk - 1) / npos_blk;
+  const int xcd_map = n_sites_grid >= 8 ? 1 : 0;
+  const int nblk = xcd_map ? 8 * ncb * ((n_sites_grid + 7) / 8) : n_sites_grid * ncb;
   if (npieces == 3)
-    hipLaunchKernelGGL(bwd_mfma_kernel<3>, grid, dim3(kMThreads), 0, st, a);
+    hipLaunchKernelGGL(bwd_mfma_kernel<3>, dim3(nblk), dim3(kMThreads), 0, st, a, npos_blk, ncb,
+                       xcd_map);
   else if (npieces == 2)
-    hipLaunchKernelGGL(bwd_mfma_kernel<2>, grid, dim3(kMThreads), 0, st, a);
+    hipLaunchKernelGGL(bwd_mfma_kernel<2>, dim3(nblk), dim3(kMThreads), 0, st, a, npos_blk, ncb,
+                       xcd_map);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -57,6 +57,7 @@ size_t rup(size_t x, size_t m) { return (x + m - 1) / m * m; }
 
 struct EvalBufs {
   uint8_t* msa_cm;
+  uint8_t* msaT;
   float* R;
   double* f_part;
   double* gh_part;
@@ -71,6 +72,7 @@ void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
   e.B3 = (int32_t)rup(B, 3);
   e.tiles_max = (B + forward_tile_seqs(16) - 1) / forward_tile_seqs(16);
   e.msa_cm = bp.take<uint8_t>((size_t)e.B_pad * e.N_pad);
+  e.msaT = bp.take<uint8_t>((size_t)e.B_pad * e.N_pad);
   e.R = bp.take<float>((size_t)N * e.B3 * kSlot);
   e.f_part = bp.take<double>((size_t)e.tiles_max * N);
   e.gh_part = bp.take<double>((size_t)e.tiles_max * N * kSlot);
@@ -141,6 +143,41 @@ int32_t pick_nb(int32_t B, int32_t tile_seqs) {
   if (B >= 4 * forward_tile_seqs(64)) return 64;
   if (B >= 2 * forward_tile_seqs(32)) return 32;
   return 16;
+}
+
+// Kernels of each evaluation path: 0 = LDS gather forward / sorted scatter
+// backward, n > 0 = one-hot MFMA product with n BF16 pieces.
+struct PathSpec {
+  int fwd_np, bwd_np;
+};
+
+bool path_spec(int32_t path, PathSpec* p) {
+  switch (path) {
+    case PLM_PATH_GATHER_FP32: *p = {0, 0}; return true;
+    case PLM_PATH_MFMA_BF16X2: *p = {2, 2}; return true;
+    case PLM_PATH_GATHER_MFMA_FP32: *p = {0, 3}; return true;
+    case PLM_PATH_MFMA_FP32: *p = {3, 3}; return true;
+    default: return false;
+  }
+}
+
+int32_t eval_tiles(const PathSpec& p, int32_t B, int32_t nb) {
+  const int32_t t = p.fwd_np ? mfma_forward_tile_seqs() : forward_tile_seqs(nb);
+  return (B + t - 1) / t;
+}
+
+hipError_t eval_prepare(const PathSpec& p, const EvalArgs& a, uint8_t* msaT, uint16_t* sorted,
+                        hipStream_t st) {
+  if (p.bwd_np) return launch_transpose_msa(a.msa_cm, a.B_pad, a.N_pad, msaT, st);
+  return launch_chunk_sort(a.msa_cm, a.B3, a.B_pad, a.N, a.q, sorted, st);
+}
+
+hipError_t eval_forward(const PathSpec& p, const EvalArgs& a, int32_t n, int32_t nb, hipStream_t st) {
+  return p.fwd_np ? launch_forward_mfma(a, n, p.fwd_np, st) : launch_forward(a, n, nb, st);
+}
+
+hipError_t eval_backward(const PathSpec& p, const EvalArgs& a, int32_t n, hipStream_t st) {
+  return p.bwd_np ? launch_backward_mfma(a, n, p.bwd_np, st) : launch_backward(a, n, st);
 }
 
 int flags_status(plm_ctx* c) {
@@ -254,7 +291,8 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
   int rc = check_sizes(c, B, N, q);
   if (rc) return rc;
   if (!(lambda_h >= 0.0) || !(lambda_J >= 0.0)) return set_err(c, PLM_E_INVALID, "negative lambda");
-  if (path != PLM_PATH_GATHER_FP32 && path != PLM_PATH_GATHER_MFMA_FP32)
+  PathSpec ps;
+  if (!path_spec(path, &ps))
     return set_err(c, PLM_E_UNSUPPORTED, "evaluation path %d is not available", path);
   if (!sites) n_sites = N;
   if (n_sites < 1 || n_sites > N) return set_err(c, PLM_E_INVALID, "n_sites out of range");
@@ -270,22 +308,20 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
   HIPCHK(c, launch_check_f32(J, (size_t)N * N * q * q, c->pin_dev, c->stream));
   if (grad_scale) HIPCHK(c, launch_check_f64(grad_scale, (size_t)N, c->pin_dev, c->stream));
   HIPCHK(c, launch_pad_msa(msa, B, N, q, e.msa_cm, e.B_pad, e.N_pad, c->pin_dev, c->stream));
-  HIPCHK(c, launch_chunk_sort(e.msa_cm, e.B3, e.B_pad, N, q, e.sorted, c->stream));
   const int32_t nb = pick_nb(B, 0);
   EvalArgs a;
   a.msa_cm = e.msa_cm;
+  a.msaT = e.msaT;
   a.B = B; a.B3 = e.B3; a.B_pad = e.B_pad; a.N = N; a.N_pad = e.N_pad; a.q = q;
   a.w = w; a.h = h; a.J = J;
   a.sites = sites; a.n_active = nullptr; a.n_active_host = n_sites;
   a.R = e.R; a.f_part = e.f_part; a.gh_part = e.gh_part; a.gJ = e.gJ;
   a.sorted = e.sorted;
-  a.tiles = (B + forward_tile_seqs(nb) - 1) / forward_tile_seqs(nb);
-  HIPCHK(c, launch_forward(a, n_sites, nb, c->stream));
+  a.tiles = eval_tiles(ps, B, nb);
+  HIPCHK(c, eval_forward(ps, a, n_sites, nb, c->stream));
   if (gJ_out) {
-    if (path == PLM_PATH_GATHER_MFMA_FP32)
-      HIPCHK(c, launch_backward_mfma(a, n_sites, 3, c->stream));
-    else
-      HIPCHK(c, launch_backward(a, n_sites, c->stream));
+    HIPCHK(c, eval_prepare(ps, a, e.msaT, e.sorted, c->stream));
+    HIPCHK(c, eval_backward(ps, a, n_sites, c->stream));
   }
   FinalArgs fa;
   fa.N = N; fa.q = q; fa.tiles = a.tiles; fa.lambda_h = lambda_h; fa.lambda_Jp = 0.5 * lambda_J;
@@ -334,7 +370,8 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
   if (!(o->lambda_h >= 0.0) || !(o->lambda_J >= 0.0) || !(o->tol >= 0.0) || o->max_iter < 1 ||
       o->lbfgs_m < 1 || o->lbfgs_m > kMMax || o->max_linesearch < 1)
     return set_err(c, PLM_E_INVALID, "invalid fit options");
-  if (o->path != PLM_PATH_GATHER_FP32 && o->path != PLM_PATH_GATHER_MFMA_FP32)
+  PathSpec ps;
+  if (!path_spec(o->path, &ps))
     return set_err(c, PLM_E_UNSUPPORTED, "evaluation path %d is not available", o->path);
   const size_t need = plm_fit_workspace_bytes(B, N, q, o);
   rc = check_ws(c, ws, ws_bytes, need);
@@ -356,7 +393,6 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
   HIPCHK(c, launch_check_f64(w, (size_t)B, c->pin_dev, st));
   HIPCHK(c, launch_check_f32(h_io, (size_t)N * q, c->pin_dev, st));
   HIPCHK(c, launch_pad_msa(msa, B, N, q, f.ev.msa_cm, f.ev.B_pad, f.ev.N_pad, c->pin_dev, st));
-  HIPCHK(c, launch_chunk_sort(f.ev.msa_cm, f.ev.B3, f.ev.B_pad, N, q, f.ev.sorted, st));
   HIPCHK(c, launch_init_fit(N, q, h_io, J_io, f.Th, f.TJ, f.st, f.sites, f.n_active, phase_host_dev, st));
   HIPCHK(c, launch_check_f32(J_io, (size_t)N * N * q * q, c->pin_dev, st));
   HIPCHK(c, launch_zero_u64(f.site_evals, st));
@@ -367,12 +403,14 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
   const int32_t nb = pick_nb(B, o->tile_seqs);
   EvalArgs a;
   a.msa_cm = f.ev.msa_cm;
+  a.msaT = f.ev.msaT;
   a.B = B; a.B3 = f.ev.B3; a.B_pad = f.ev.B_pad; a.N = N; a.N_pad = f.ev.N_pad; a.q = q;
   a.w = w; a.h = f.Th; a.J = f.TJ;
   a.sites = f.sites; a.n_active = f.n_active; a.n_active_host = N;
   a.R = f.ev.R; a.f_part = f.ev.f_part; a.gh_part = f.ev.gh_part; a.gJ = f.ev.gJ;
   a.sorted = f.ev.sorted;
-  a.tiles = (B + forward_tile_seqs(nb) - 1) / forward_tile_seqs(nb);
+  a.tiles = eval_tiles(ps, B, nb);
+  HIPCHK(c, eval_prepare(ps, a, f.ev.msaT, f.ev.sorted, st));
 
   LbfgsArgs L;
   L.N = N; L.q = q; L.m = o->lbfgs_m; L.max_iter = o->max_iter; L.max_ls = o->max_linesearch;
@@ -399,9 +437,8 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
       LbfgsArgs L1 = L;
       L1.site_offset = r;
       for (int64_t it = 0; it < cap; ++it) {
-        HIPCHK(c, launch_forward(a1, 1, nb, st));
-        HIPCHK(c, o->path == PLM_PATH_GATHER_MFMA_FP32 ? launch_backward_mfma(a1, 1, 3, st)
-                                                      : launch_backward(a1, 1, st));
+        HIPCHK(c, eval_forward(ps, a1, 1, nb, st));
+        HIPCHK(c, eval_backward(ps, a1, 1, st));
         HIPCHK(c, launch_lbfgs(L1, 1, st));
         HIPCHK(c, hipStreamSynchronize(st));
         if (phase_host[r] == PH_DONE) break;
@@ -414,11 +451,9 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
     auto mark = [&](int k) -> hipError_t { return timed ? hipEventRecord(c->ev[k], st) : hipSuccess; };
     auto enqueue = [&]() -> hipError_t {
       hipError_t e = mark(0);
-      if (e == hipSuccess) e = launch_forward(a, N, nb, st);
+      if (e == hipSuccess) e = eval_forward(ps, a, N, nb, st);
       if (e == hipSuccess) e = mark(1);
-      if (e == hipSuccess)
-        e = o->path == PLM_PATH_GATHER_MFMA_FP32 ? launch_backward_mfma(a, N, 3, st)
-                                                 : launch_backward(a, N, st);
+      if (e == hipSuccess) e = eval_backward(ps, a, N, st);
       if (e == hipSuccess) e = mark(2);
       if (e == hipSuccess) e = launch_lbfgs(L, N, st);
       if (e == hipSuccess) e = mark(3);

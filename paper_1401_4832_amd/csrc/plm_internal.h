@@ -55,6 +55,7 @@ enum { PH_INIT = 0, PH_LS = 1, PH_DONE = 2 };
 // Everything the evaluation kernels need about one alignment.
 struct EvalArgs {
   const uint8_t* msa_cm;   // padded symbols, chunk-major: (b, i) at ((i/16)*B_pad + b)*16 + i%16
+  const uint8_t* msaT;     // padded symbols, position-major: (b, i) at i*B_pad + b (MFMA paths)
   int32_t B, B3, B_pad, N, N_pad, q;
   const double* w;         // [B]
   const float* h;          // [N][q]  (trial point)
@@ -133,6 +134,11 @@ hipError_t launch_pad_msa(const uint8_t* msa, int32_t B, int32_t N, int32_t q, u
                           int32_t B_pad, int32_t N_pad, int32_t* flag_dev, hipStream_t st);
 hipError_t launch_forward(const EvalArgs& a, int32_t n_sites_grid, int32_t nb, hipStream_t st);
 hipError_t launch_backward(const EvalArgs& a, int32_t n_sites_grid, hipStream_t st);
+hipError_t launch_transpose_msa(const uint8_t* msa_cm, int32_t B_pad, int32_t N_pad, uint8_t* msaT,
+                                hipStream_t st);
+int32_t mfma_forward_tile_seqs();
+hipError_t launch_forward_mfma(const EvalArgs& a, int32_t n_sites_grid, int32_t npieces,
+                               hipStream_t st);
 hipError_t launch_backward_mfma(const EvalArgs& a, int32_t n_sites_grid, int32_t npieces,
                                 hipStream_t st);
 hipError_t launch_chunk_sort(const uint8_t* msa_cm, int32_t B3, int32_t B_pad, int32_t N, int32_t q,

@@ -84,10 +84,11 @@ def test_reweight_uniform(plm):
 
 
 # ----------------------------------------------------------- objective/grad
-PATHS = [0, 2]  # gather/scatter FP32; gather forward + three-piece MFMA coupling gradient
+# FP32-faithful paths: gather/scatter; gather + three-piece MFMA gradient; three-piece MFMA both ways
+PATHS = [0, 2, 3]
 
 
-def _objgrad_case(plm, msa, w_o, beff_o, h, J, lh=0.01, lJ=0.01, sites=None, path=0):
+def _objgrad_case(plm, msa, w_o, beff_o, h, J, lh=0.01, lJ=0.01, sites=None, path=0, fabs=False):
     B, N = msa.shape
     q = h.shape[1]
     w = _to(w_o)
@@ -106,7 +107,48 @@ def _objgrad_case(plm, msa, w_o, beff_o, h, J, lh=0.01, lJ=0.01, sites=None, pat
     gJ = gJ.cpu().numpy()[idx]
     frel = np.max(np.abs(f - fo) / np.abs(fo))
     gerr = max(np.max(np.abs(gJ - gJo)), np.max(np.abs(gh - gho))) / beff_o
+    if fabs:
+        return np.max(np.abs(f - fo)) / beff_o, gerr, gJ
     return frel, gerr, gJ
+
+
+def _hilo_bounds(msa, h, J, sites):
+    """Error bounds of the two-piece (hi/lo BF16) path, from its arithmetic.
+
+    hi + lo represents each coupling and residual to 16 significant bits, so
+    |dJ| <= 2^-16 |J| and |dR| <= 2^-16 |R| <= 2^-16 w_b.  An energy then moves
+    by at most eps_E = 2^-16 max_b sum_i max_s |J_ri(s, sigma_i^b)|; the
+    log-partition function by at most eps_E, each probability by a factor
+    exp(+-2 eps_E).  Hence, on the B_eff-normalised scale,
+    |dg| <= 2 eps_E + 2^-16 per gradient entry and |df| <= 2 eps_E.  The FP32
+    accumulation bounds of the other paths are added on top."""
+    u = 2.0 ** -16
+    Jf = np.abs(J.astype(np.float32).astype(np.float64))
+    epsE = 0.0
+    for r in sites:
+        # max over s of |J_ri(s, k)|, indexed by (i, k): layout [i][k][s]
+        mx = Jf[r].max(axis=2)
+        mx[r] = 0
+        per_b = mx[np.arange(msa.shape[1])[None, :], msa.astype(np.int64)].sum(axis=1)
+        epsE = max(epsE, u * float(per_b.max()))
+    return 2 * epsE, 2 * epsE + u
+
+
+@pytest.mark.parametrize("B,N,q", [(500, 40, 21), (7, 17, 21), (3001, 33, 21), (1537, 49, 11), (700, 97, 21)])
+def test_objgrad_hilo_path_within_derived_bound(plm, B, N, q):
+    _note(f"objgrad hi/lo B={B} N={N} q={q}")
+    rng = np.random.default_rng(B * 7 + N)
+    msa = rng.integers(0, q, size=(B, N), dtype=np.uint8)
+    w_o = rng.uniform(0.2, 1.0, size=B)
+    beff_o = float(np.sum(w_o))
+    h, J = random_params(B + q, N, q, 0.3, 0.2)
+    fb, gb = _hilo_bounds(msa, h, J, range(N))
+    ferr, gerr, gJ = _objgrad_case(plm, msa, w_o, beff_o, h, J, path=1, fabs=True)
+    print(f"  hi/lo errors: f {ferr:.2e} (bound {fb:.2e}), grad {gerr:.2e} (bound {gb:.2e})")
+    assert gerr <= gb + 2e-6, (gerr, gb)
+    assert ferr <= fb + 1e-5 * np.log(q) * 10, (ferr, fb)
+    for r in range(N):
+        assert np.all(gJ[r, r] == 0)
 
 
 @pytest.mark.parametrize("path", PATHS)
