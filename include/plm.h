@@ -100,7 +100,8 @@ int plm_reweight(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, int32_t
 /* ---- Objective and gradient (sec. 3.4 step 3: eqs. g_regdef2, g_gradh2,
  * g_gradJ2), all listed sites at once ---------------------------------------
  * sites: device int32[n_sites] of distinct site indices, or NULL for all N
- * (then n_sites is ignored).  Outputs are indexed by site; only the rows of
+ * (then n_sites is ignored).  An index outside [0, N) is evaluated as site 0
+ * and reported as PLM_E_INVALID by the next plm_sync.  Outputs are indexed by site; only the rows of
  * listed sites are written:
  *   f_out  double[N]          f_r = B_eff * g_r^reg
  *   gh_out float [N][q]       d f_r / d h_r(s)
@@ -180,6 +181,34 @@ size_t plm_fit_workspace_bytes(int32_t B, int32_t N, int32_t q, const plm_fit_op
 int plm_fit(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, int32_t q,
             const double *w, const double *beff, const plm_fit_opts *opts, void *workspace,
             size_t workspace_bytes, float *h_io, float *J_io, plm_site_stats *stats_out);
+
+/* ---- Ragged batch of alignments --------------------------------------------
+ * Every site of every alignment is minimised as in plm_fit, all alignments
+ * together: each iteration is one launch per kernel over the whole batch
+ * (persistent evaluation kernels draining (alignment, site, tile) work items
+ * from per-XCD queues, largest alignments first), captured once in a hipGraph.
+ * The alignments share q and the options; each brings its own sizes, weights
+ * (plm_reweight per alignment), start point and outputs.  With the forward
+ * tile size fixed (opts->tile_seqs; by default a batch takes the one its
+ * largest alignment would get), results are exactly those plm_fit gives for
+ * each alignment alone: same kernels, same per-item arithmetic, in any work
+ * order.  descs is a HOST array; the pointers in it are device pointers
+ * except stats_out (HOST, N records, may be NULL).  opts->single_site must be
+ * 0.  Returns PLM_W_MAXITER if any site of any alignment hit max_iter. */
+typedef struct {
+  const uint8_t *msa;         /* uint8[B][N] */
+  int32_t B, N;
+  const double *w;            /* double[B] */
+  const double *beff;         /* double[1] */
+  float *h_io;                /* float[N][q] */
+  float *J_io;                /* float[N][N][q][q] */
+  plm_site_stats *stats_out;  /* HOST, N records, may be NULL */
+} plm_msa_desc;
+
+size_t plm_fit_batch_workspace_bytes(const plm_msa_desc *descs, int32_t n_msas, int32_t q,
+                                     const plm_fit_opts *opts);
+int plm_fit_batch(plm_ctx *ctx, const plm_msa_desc *descs, int32_t n_msas, int32_t q,
+                  const plm_fit_opts *opts, void *workspace, size_t workspace_bytes);
 
 /* ---- Scoring (sec. 3.4 steps 4-6) ------------------------------------------
  * For every pair i != j: both estimates are moved to the Ising gauge

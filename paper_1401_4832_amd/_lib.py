@@ -65,6 +65,19 @@ class SiteStats(ctypes.Structure):
     ]
 
 
+class MsaDesc(ctypes.Structure):
+    _fields_ = [
+        ("msa", ctypes.c_void_p),
+        ("B", ctypes.c_int32),
+        ("N", ctypes.c_int32),
+        ("w", ctypes.c_void_p),
+        ("beff", ctypes.c_void_p),
+        ("h_io", ctypes.c_void_p),
+        ("J_io", ctypes.c_void_p),
+        ("stats_out", ctypes.POINTER(SiteStats)),
+    ]
+
+
 class PlmError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libplm status {code}: {msg}")
@@ -99,6 +112,9 @@ def lib():
                                        ctypes.POINTER(SiteStats)]),
             "plm_score": (ctypes.c_int, [P, P, I32, I32, P, P]),
             "plm_fit_last_timing": (ctypes.c_int, [P, ctypes.POINTER(FitTiming)]),
+            "plm_fit_batch_workspace_bytes": (SZ, [ctypes.POINTER(MsaDesc), I32, I32, ctypes.POINTER(FitOpts)]),
+            "plm_fit_batch": (ctypes.c_int, [P, ctypes.POINTER(MsaDesc), I32, I32, ctypes.POINTER(FitOpts),
+                                             P, SZ]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -112,4 +128,5 @@ def exported_symbols():
     """Names declared in include/plm.h that the ABI tests check for."""
     return ["plm_ctx_create", "plm_ctx_destroy", "plm_last_error", "plm_status_string", "plm_sync",
             "plm_reweight", "plm_objgrad_workspace_bytes", "plm_objgrad", "plm_fit_opts_default",
-            "plm_fit_workspace_bytes", "plm_fit", "plm_score", "plm_fit_last_timing"]
+            "plm_fit_workspace_bytes", "plm_fit", "plm_score", "plm_fit_last_timing",
+            "plm_fit_batch_workspace_bytes", "plm_fit_batch"]

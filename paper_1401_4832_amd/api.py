@@ -182,9 +182,51 @@ def fit(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None) -> FitRe
     rc = _check(L.lib().plm_fit(ctx, _ptr(msa), B, N, q, _ptr(w), _ptr(beff), ctypes.byref(co), _ptr(ws),
                                 ws.numel(), _ptr(h), _ptr(J), stats), ctx)
     del ws
-    st = [dict(iterations=s.iterations, evaluations=s.evaluations, status=L.SITE_STATUS.get(s.status, "?"),
-               f=s.f, gnorm=s.gnorm) for s in stats]
-    return FitResult(h, J, st, rc)
+    return FitResult(h, J, _stats_list(stats), rc)
+
+
+def _stats_list(stats):
+    return [dict(iterations=s.iterations, evaluations=s.evaluations, status=L.SITE_STATUS.get(s.status, "?"),
+                 f=s.f, gnorm=s.gnorm) for s in stats]
+
+
+def fit_batch(items, opts: FitOptions | None = None, q: int = 21):
+    """Fit a ragged batch of alignments in one set of launches per iteration.
+
+    items: sequence of (msa, w, beff) or (msa, w, beff, h0, J0) on one device.
+    Returns one FitResult per alignment, in the order given; each equals what
+    fit() gives for that alignment alone."""
+    opts = opts or FitOptions()
+    if not items:
+        raise ValueError("empty batch")
+    dev = items[0][0].device
+    n = len(items)
+    descs = (L.MsaDesc * n)()
+    keep, out = [], []
+    for k, it in enumerate(items):
+        msa, w, beff = it[0], it[1], it[2]
+        _dev_tensor(msa, torch.uint8, dev, f"msa[{k}]")
+        _dev_tensor(w, torch.float64, dev, f"w[{k}]")
+        _dev_tensor(beff, torch.float64, dev, f"beff[{k}]")
+        B, N = msa.shape
+        h = torch.zeros(N, q, dtype=torch.float32, device=dev) if len(it) < 4 else it[3].clone().contiguous()
+        J = torch.zeros(N, N, q, q, dtype=torch.float32, device=dev) if len(it) < 5 else it[4].clone().contiguous()
+        stats = (L.SiteStats * N)()
+        d = descs[k]
+        d.msa, d.B, d.N, d.w, d.beff = msa.data_ptr(), B, N, w.data_ptr(), beff.data_ptr()
+        d.h_io, d.J_io = h.data_ptr(), J.data_ptr()
+        d.stats_out = ctypes.cast(stats, ctypes.POINTER(L.SiteStats))
+        keep.append(stats)
+        out.append((h, J, stats))
+    co = opts.to_c()
+    nbytes = L.lib().plm_fit_batch_workspace_bytes(descs, n, q, ctypes.byref(co))
+    if nbytes == 0:
+        raise L.PlmError(L.PLM_E_INVALID, "invalid sizes or options")
+    ws = workspace(nbytes, dev)
+    ctx = context(dev)
+    rc = _check(L.lib().plm_fit_batch(ctx, descs, n, q, ctypes.byref(co), _ptr(ws), ws.numel()), ctx)
+    del ws
+    return [FitResult(h, J, _stats_list(st), rc) for (h, J, st) in out]
 
 
 def last_fit_timing(device=None) -> dict:

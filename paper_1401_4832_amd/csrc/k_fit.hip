@@ -2,15 +2,17 @@
 // fit initialisation, active-site compaction, the standalone objective /
 // gradient finalisation (adds the l2 terms of eq. g_regdef2 and their
 // derivatives, eqs. g_gradh2 / g_gradJ2), and input checks.
+#include <string.h>
+
 #include "plm_internal.h"
 
 namespace plm {
 
 // Zero the self blocks of the start point, copy it to the trial buffers and
-// reset every site's optimiser state; the active list is all sites.
+// reset every site's optimiser state (one alignment; st and phase_host point
+// at its first site).
 __global__ void init_fit_kernel(int32_t N, int32_t q, float* Xh, float* XJ, float* Th, float* TJ,
-                                SiteState* st, int32_t* sites, int32_t* n_active,
-                                int32_t* phase_host) {
+                                SiteState* st, int32_t* phase_host) {
   const int r = blockIdx.x;
   const size_t qq = (size_t)q * q, Nqq = (size_t)N * qq;
   for (size_t e = threadIdx.x; e < qq; e += blockDim.x) XJ[(size_t)r * Nqq + (size_t)r * qq + e] = 0.f;
@@ -26,26 +28,43 @@ __global__ void init_fit_kernel(int32_t N, int32_t q, float* Xh, float* XJ, floa
     s.gamma = 1.0;
     for (int k = 0; k < kMMax; ++k) s.rho[k] = s.ahist[k] = 0.0;
     st[r] = s;
-    sites[r] = r;
     if (phase_host) phase_host[r] = PH_INIT;
-    if (r == 0) *n_active = N;
   }
 }
 
-// Active list = sites not done, in increasing order; the count also goes to
-// pinned host memory, and the running total of site evaluations is kept.
-__global__ void compact_kernel(int32_t N, const SiteState* st, int32_t* sites, int32_t* n_active,
-                               int32_t* host_count, unsigned long long* site_evals) {
+// Work-item offsets of every alignment from the active-list runs in b.seg,
+// and cleared queue counters (one block; after the runs are written).
+__device__ inline void finish_tables(const BatchArgs& b) {
+  __syncthreads();
+  if (threadIdx.x < 2 * kQueues) b.ctr[threadIdx.x] = 0u;
+  if (threadIdx.x < 2) {
+    const int kind = threadIdx.x;
+    int32_t* off = b.item_off + kind * (b.n_msas + 1);
+    int32_t acc = 0;
+    for (int m = 0; m < b.n_msas; ++m) {
+      off[m] = acc;
+      acc += (b.seg[m + 1] - b.seg[m]) * b.nsub[kind * b.n_msas + m];
+    }
+    off[b.n_msas] = acc;
+  }
+}
+
+// Active list = sites not done, in global order, with the run of each
+// alignment and the work-item tables for the next evaluation; the count also
+// goes to pinned host memory, and the running total of site evaluations (the
+// sites active in the iteration just finished) is kept.
+__global__ void compact_kernel(BatchArgs b, const SiteState* st, int32_t* host_count,
+                               unsigned long long* site_evals) {
   __shared__ int32_t flags[1024];
   __shared__ int32_t base;
   if (threadIdx.x == 0) {
-    *site_evals += (unsigned long long)*n_active;  // the sites evaluated in this iteration
+    if (site_evals) *site_evals += (unsigned long long)*b.n_active;
     base = 0;
   }
   __syncthreads();
-  for (int r0 = 0; r0 < N; r0 += 1024) {
-    const int r = r0 + threadIdx.x;
-    const int act = (r < N && st[r].phase != PH_DONE) ? 1 : 0;
+  for (int g0 = 0; g0 < b.total_sites; g0 += 1024) {
+    const int g = g0 + threadIdx.x;
+    const int act = (g < b.total_sites && st[g].phase != PH_DONE) ? 1 : 0;
     flags[threadIdx.x] = act;
     __syncthreads();
     // inclusive scan (Hillis-Steele) over the 1024 flags
@@ -55,15 +74,43 @@ __global__ void compact_kernel(int32_t N, const SiteState* st, int32_t* sites, i
       flags[threadIdx.x] += v;
       __syncthreads();
     }
-    if (act) sites[base + flags[threadIdx.x] - 1] = r;
+    const int excl = base + flags[threadIdx.x] - act;
+    if (act) b.active[excl] = g;
+    if (g < b.total_sites) {
+      const int m = b.msa_of[g];
+      if (g == b.site_base[m]) b.seg[m] = excl;
+    }
     __syncthreads();
     if (threadIdx.x == 0) base += flags[1023];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    *n_active = base;
+    *b.n_active = base;
+    b.seg[b.n_msas] = base;
     if (host_count) *host_count = base;
   }
+  finish_tables(b);
+}
+
+// Tables of a one-alignment batch over an explicit site list (list[j], or
+// first + j when list is null).  Site indices outside [0, N) are replaced by
+// 0 and raise bit 4 of *flag.
+__global__ void list_tables_kernel(BatchArgs b, const int32_t* list, int32_t first, int32_t n,
+                                   int32_t* flag) {
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    int32_t v = list ? list[j] : first + j;
+    if (v < 0 || v >= b.total_sites) {
+      if (flag) atomicOr(flag, 4);
+      v = 0;
+    }
+    b.active[j] = v;
+  }
+  if (threadIdx.x == 0) {
+    *b.n_active = n;
+    b.seg[0] = 0;
+    b.seg[1] = n;
+  }
+  finish_tables(b);
 }
 
 __global__ __launch_bounds__(1024) void objgrad_final_kernel(FinalArgs a) {
@@ -131,25 +178,56 @@ hipError_t launch_check_f64(const double* p, size_t n, int32_t* flag, hipStream_
   return hipGetLastError();
 }
 
+// Descriptors of alignment m of a batch (one thread block; host data travels
+// as kernel arguments).  lb may be absent (evaluation only).  Alignment 0 also
+// clears the active count and the evaluation counter.
+__global__ void setup_msa_kernel(BatchArgs b, int32_t m, EvalArgs e, LbfgsArgs l, int32_t has_l,
+                                 int32_t base, int32_t N, int32_t nsub_f, int32_t nsub_b,
+                                 unsigned long long* site_evals) {
+  for (int j = threadIdx.x; j < N; j += blockDim.x) const_cast<int32_t*>(b.msa_of)[base + j] = m;
+  if (threadIdx.x == 0) {
+    const_cast<EvalArgs*>(b.ev)[m] = e;
+    if (has_l) const_cast<LbfgsArgs*>(b.lb)[m] = l;
+    int32_t* sb = const_cast<int32_t*>(b.site_base);
+    sb[m] = base;
+    if (m == b.n_msas - 1) sb[b.n_msas] = base + N;
+    int32_t* ns = const_cast<int32_t*>(b.nsub);
+    ns[KIND_FWD * b.n_msas + m] = nsub_f;
+    ns[KIND_BWD * b.n_msas + m] = nsub_b;
+    if (m == 0) {
+      *b.n_active = 0;
+      if (site_evals) *site_evals = 0ull;
+    }
+  }
+}
+
+hipError_t launch_setup_msa(const BatchArgs& b, int32_t m, const EvalArgs& e, const LbfgsArgs* l,
+                            int32_t base, int32_t N, int32_t nsub_f, int32_t nsub_b,
+                            unsigned long long* site_evals, hipStream_t st) {
+  LbfgsArgs lz;
+  if (l) lz = *l; else memset(&lz, 0, sizeof(lz));
+  hipLaunchKernelGGL(setup_msa_kernel, dim3(1), dim3(256), 0, st, b, m, e, lz, l ? 1 : 0, base, N,
+                     nsub_f, nsub_b, site_evals);
+  return hipGetLastError();
+}
+
 hipError_t launch_init_fit(int32_t N, int32_t q, float* Xh, float* XJ, float* Th, float* TJ,
-                           SiteState* st_, int32_t* sites, int32_t* n_active, int32_t* phase_host,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(init_fit_kernel, dim3(N), dim3(1024), 0, st, N, q, Xh, XJ, Th, TJ, st_, sites,
-                     n_active, phase_host);
+                           SiteState* st_, int32_t* phase_host, hipStream_t st) {
+  hipLaunchKernelGGL(init_fit_kernel, dim3(N), dim3(1024), 0, st, N, q, Xh, XJ, Th, TJ, st_, phase_host);
   return hipGetLastError();
 }
 
-hipError_t launch_compact(int32_t N, const SiteState* st_, int32_t* sites, int32_t* n_active,
-                          int32_t* host_count, unsigned long long* site_evals, hipStream_t st) {
-  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, st, N, st_, sites, n_active,
-                     host_count, site_evals);
+hipError_t launch_compact(const BatchArgs& b, const SiteState* st_, int32_t* host_count,
+                          unsigned long long* site_evals, hipStream_t st) {
+  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, st, b, st_, host_count, site_evals);
   return hipGetLastError();
 }
 
-__global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
-hipError_t launch_zero_u64(unsigned long long* p, hipStream_t st) {
-  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, st, p);
+hipError_t launch_list_tables(const BatchArgs& b, const int32_t* list, int32_t first, int32_t n,
+                              int32_t* flag, hipStream_t st) {
+  hipLaunchKernelGGL(list_tables_kernel, dim3(1), dim3(256), 0, st, b, list, first, n, flag);
   return hipGetLastError();
 }
+
 
 }  // namespace plm

@@ -53,24 +53,19 @@ hipError_t launch_pad_msa(const uint8_t* msa, int32_t B, int32_t N, int32_t q, u
 
 int32_t forward_tile_seqs(int32_t nb) { return kFwdWaves * kSlots * nb; }
 
+// One forward work item: site r x sequence tile `tile` of one alignment.
+// lds: 86 KB (J_r for 16 columns, 3 copies per row); sgl: the tile's symbols
+// for those columns; red: FP64 reduction scratch.
 template <int NB>
-__global__ __launch_bounds__(kFwdThreads) void fwd_kernel(EvalArgs a) {
+__device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, uint4* sgl,
+                                double* red) {
   constexpr int tileSeq = kFwdWaves * kSlots * NB;
-  __shared__ float lds[kFwdChunk * kQMax * kRowF];  // 86 KB: J_r for 16 columns, 3 copies per row
-  __shared__ uint4 sgl[tileSeq];                    // symbols of the tile's rows for those columns
-  __shared__ double red[kFwdWaves * 64];
-  // sites vary fastest across the grid, so that the blocks resident at one time
-  // share a tile's symbols in L2
-  const int idx = blockIdx.x;
-  const int nact = a.n_active ? *a.n_active : a.n_active_host;
-  if (idx >= nact) return;
-  const int r = a.sites ? a.sites[idx] : idx;
   const int q = a.q, N = a.N, qq = q * q;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = item_tid(), lane = tid & 63, wid = tid >> 6;
   const int slot = lane / kSlot, s = lane - slot * kSlot;
   const int slotA = slot < kSlots ? slot : kSlots - 1;  // lane 63 shadows slot 2 for addressing
   const bool act = (slot < kSlots) && (s < q);
-  const int tile0 = blockIdx.y * tileSeq;
+  const int tile0 = tile * tileSeq;
   const int tw = wid * (NB * kSlots) + slotA;  // tile row of row j: tw + 3j
   const int bw = tile0 + tw;
 
@@ -88,14 +83,14 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(EvalArgs a) {
     for (int e = tid; e < kFwdChunk * qq; e += kFwdThreads) {
       const int p = e / qq, rem = e - p * qq, k = rem / q, ss = rem - k * q;
       const int i = c * kFwdChunk + p;
-      const float v = (i < N && i != r) ? a.J[Jr + (size_t)i * qq + rem] : 0.f;
+      const float v = (i < N && i != r) ? gmem(a.J)[Jr + (size_t)i * qq + rem] : 0.f;
       float* row = lds + (p * q + k) * kRowF;
       row[ss] = v;
       row[ss + kSlot] = v;
       row[ss + 2 * kSlot] = v;
     }
     for (int e = tid; e < tileSeq; e += kFwdThreads)
-      sgl[e] = *reinterpret_cast<const uint4*>(a.msa_cm + ((size_t)c * a.B_pad + tile0 + e) * kFwdChunk);
+      sgl[e] = gload_u4(a.msa_cm + ((size_t)c * a.B_pad + tile0 + e) * kFwdChunk);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
@@ -153,31 +148,62 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(EvalArgs a) {
       const float Rv = act ? (float)wb * (P - (s == sr ? 1.f : 0.f)) : 0.f;
       if (act && s == sr) facc += wb * (double)(lse - e);
       ghacc += (double)Rv;
-      if (slot < kSlots && b < a.B3) a.R[((size_t)r * a.B3 + b) * kSlot + s] = Rv;
+      if (slot < kSlots && b < a.B3) gmem_w(a.R)[((size_t)r * a.B3 + b) * kSlot + s] = Rv;
     }
   }
   const double ftot = block_sum_f64(facc, red);
-  if (tid == 0) a.f_part[(size_t)blockIdx.y * N + r] = ftot;
+  if (tid == 0) a.f_part[(size_t)tile * N + r] = ftot;
   red[wid * 64 + lane] = (slot < kSlots) ? ghacc : 0.0;
   __syncthreads();
   if (tid < kSlot) {
     double t = 0.0;
     for (int w = 0; w < kFwdWaves; ++w)
       for (int c = 0; c < kSlots; ++c) t += red[w * 64 + c * kSlot + tid];
-    a.gh_part[((size_t)blockIdx.y * N + r) * kSlot + tid] = t;
+    a.gh_part[((size_t)tile * N + r) * kSlot + tid] = t;
   }
 }
 
-hipError_t launch_forward(const EvalArgs& a, int32_t n_sites_grid, int32_t nb, hipStream_t st) {
-  const int tiles = (a.B + forward_tile_seqs(nb) - 1) / forward_tile_seqs(nb);
-  dim3 grid(n_sites_grid, tiles);
+// Persistent forward kernel: drains the forward work items of the batch.
+template <int NB>
+__global__ __launch_bounds__(kFwdThreads) void fwd_kernel(BatchArgs b) {
+  __shared__ float lds[kFwdChunk * kQMax * kRowF];
+  __shared__ uint4 sgl[kFwdWaves * kSlots * NB];
+  __shared__ double red[kFwdWaves * 64];
+  __shared__ int32_t item_s;
+  int32_t qi = 0;
+  const int32_t total = total_items(b, KIND_FWD);
+  for (;;) {
+    if (threadIdx.x == 0) item_s = next_item(b.ctr + KIND_FWD * kQueues, total, qi);
+    __syncthreads();
+    const int32_t t = __builtin_amdgcn_readfirstlane(item_s);
+    if (t < 0) break;
+    const Item it = decode_item(b, KIND_FWD, t);
+    const EvalArgs a = load_uniform(b.ev + it.m);
+    fwd_item<NB>(a, it.r, it.sub, lds, sgl, red);
+    __syncthreads();
+  }
+}
+
+hipError_t launch_forward(const BatchArgs& b, int32_t nb, int32_t nblocks, hipStream_t st) {
   switch (nb) {
-    case 16: hipLaunchKernelGGL(fwd_kernel<16>, grid, dim3(kFwdThreads), 0, st, a); break;
-    case 32: hipLaunchKernelGGL(fwd_kernel<32>, grid, dim3(kFwdThreads), 0, st, a); break;
-    case 64: hipLaunchKernelGGL(fwd_kernel<64>, grid, dim3(kFwdThreads), 0, st, a); break;
+    case 16: hipLaunchKernelGGL(fwd_kernel<16>, dim3(nblocks), dim3(kFwdThreads), 0, st, b); break;
+    case 32: hipLaunchKernelGGL(fwd_kernel<32>, dim3(nblocks), dim3(kFwdThreads), 0, st, b); break;
+    case 64: hipLaunchKernelGGL(fwd_kernel<64>, dim3(nblocks), dim3(kFwdThreads), 0, st, b); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+int32_t forward_resident_blocks(int32_t nb) {
+  int per = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (nb) {
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<16>, kFwdThreads, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<32>, kFwdThreads, 0); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<64>, kFwdThreads, 0); break;
+    default: break;
+  }
+  return (e == hipSuccess && per > 0) ? per : 1;
 }
 
 // Stable counting sort of each chunk's rows by their symbol at each column,
@@ -224,27 +250,24 @@ hipError_t launch_chunk_sort(const uint8_t* msa_cm, int32_t B3, int32_t B_pad, i
 // changes and is stored (plain store, no read-back) into the column's slot for
 // that symbol; after the chunk every lane folds its 21 slots into FP64
 // registers and clears them.  No two lanes ever write the same LDS word.
-__global__ __launch_bounds__(kBwdThreads) void bwd_kernel(EvalArgs a) {
-  // one LDS arena: residual rows first (so a row's byte offset is its address)
-  // Pitches chosen so that the three slots of a wave, which work on three
-  // consecutive columns, hit disjoint LDS banks: 200 entries (100 dwords) per
-  // column, and 469 = 7 * 64 + 21 floats per column of group sums.
-  constexpr int kEntPitch = kBwdSeqChunk + 8;
-  constexpr int kSegPitch = 7 * 64 + kSlot;
-  constexpr int kRsBytes = kBwdSeqChunk * kRowF * 4;              // 48 KB
-  constexpr int kEntBytes = kBwdPos * kEntPitch * 2;              // 19 KB
-  constexpr int kSegBytes = kBwdPos * kSegPitch * 4;              // 88 KB
-  __shared__ __attribute__((aligned(16))) char arena[kRsBytes + kEntBytes + kSegBytes];
+// One LDS arena: residual rows first (so a row's byte offset is its address).
+// Pitches chosen so that the three slots of a wave, which work on three
+// consecutive columns, hit disjoint LDS banks: 200 entries (100 dwords) per
+// column, and 469 = 7 * 64 + 21 floats per column of group sums.
+constexpr int kEntPitch = kBwdSeqChunk + 8;
+constexpr int kSegPitch = 7 * 64 + kSlot;
+constexpr int kRsBytes = kBwdSeqChunk * kRowF * 4;              // 48 KB
+constexpr int kEntBytes = kBwdPos * kEntPitch * 2;              // 19 KB
+constexpr int kSegBytes = kBwdPos * kSegPitch * 4;              // 88 KB
+
+// One backward work item: site r x the 48 alignment columns of block cb.
+__device__ inline void bwd_item(const EvalArgs& a, int r, int cb, char* arena) {
   float* Rs = reinterpret_cast<float*>(arena);
   uint16_t* ent = reinterpret_cast<uint16_t*>(arena + kRsBytes);
   float* seg = reinterpret_cast<float*>(arena + kRsBytes + kEntBytes);
-  const int idx = blockIdx.x;  // sites fastest: resident blocks share a column group's entries
-  const int nact = a.n_active ? *a.n_active : a.n_active_host;
-  if (idx >= nact) return;
-  const int r = a.sites ? a.sites[idx] : idx;
   const int q = a.q, N = a.N, qq = q * q;
-  const int i0 = blockIdx.y * kBwdPos;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int i0 = cb * kBwdPos;
+  const int tid = item_tid(), lane = tid & 63, wid = tid >> 6;
   const int slot = lane / kSlot, s = lane - slot * kSlot;
   const int slotA = slot < kSlots ? slot : kSlots - 1;  // lane 63 shadows lane 42 and never writes
   const int pl = wid * kSlots + slotA;                   // this lane's column within the block
@@ -261,7 +284,7 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_kernel(EvalArgs a) {
   const uint16_t* myent = ent + pl * kEntPitch;
 
   const int nchunks = (a.B3 + kBwdSeqChunk - 1) / kBwdSeqChunk;
-  const float* Rr = a.R + (size_t)r * a.B3 * kSlot;
+  const auto Rr = gmem(a.R + (size_t)r * a.B3 * kSlot);
   for (int c = 0; c < nchunks; ++c) {
     const int bc = c * kBwdSeqChunk, n = min(kBwdSeqChunk, a.B3 - bc);
     __syncthreads();
@@ -275,11 +298,11 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_kernel(EvalArgs a) {
     }
     {
       constexpr int kV = kBwdSeqChunk / 8, kVP = kEntPitch / 8;   // uint4 per column: data, pitch
-      const uint4* src = reinterpret_cast<const uint4*>(a.sorted + ((size_t)c * N + i0) * kBwdSeqChunk);
+      const uint16_t* src = a.sorted + ((size_t)c * N + i0) * kBwdSeqChunk;
       uint4* dst = reinterpret_cast<uint4*>(ent);
       for (int e = tid; e < kBwdPos * kV; e += kBwdThreads) {
         const int col = e / kV, x = e - col * kV;
-        dst[col * kVP + x] = col < npos ? src[e] : make_uint4(0, 0, 0, 0);
+        dst[col * kVP + x] = col < npos ? gload_u4(src + 8 * (size_t)e) : make_uint4(0, 0, 0, 0);
       }
     }
     __syncthreads();
@@ -339,9 +362,34 @@ __global__ __launch_bounds__(kBwdThreads) void bwd_kernel(EvalArgs a) {
   }
 }
 
-hipError_t launch_backward(const EvalArgs& a, int32_t n_sites_grid, hipStream_t st) {
-  dim3 grid(n_sites_grid, (a.N + kBwdPos - 1) / kBwdPos);
-  hipLaunchKernelGGL(bwd_kernel, grid, dim3(kBwdThreads), 0, st, a);
+// Persistent backward kernel: drains the backward work items of the batch.
+__global__ __launch_bounds__(kBwdThreads) void bwd_kernel(BatchArgs b) {
+  __shared__ __attribute__((aligned(16))) char arena[kRsBytes + kEntBytes + kSegBytes];
+  __shared__ int32_t item_s;
+  int32_t qi = 0;
+  const int32_t total = total_items(b, KIND_BWD);
+  for (;;) {
+    if (threadIdx.x == 0) item_s = next_item(b.ctr + KIND_BWD * kQueues, total, qi);
+    __syncthreads();
+    const int32_t t = __builtin_amdgcn_readfirstlane(item_s);
+    if (t < 0) break;
+    const Item it = decode_item(b, KIND_BWD, t);
+    const EvalArgs a = load_uniform(b.ev + it.m);
+    bwd_item(a, it.r, it.sub, arena);
+    __syncthreads();
+  }
+}
+
+int32_t backward_blocks_per_site(int32_t N) { return (N + kBwdPos - 1) / kBwdPos; }
+
+int32_t backward_resident_blocks() {
+  int per = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bwd_kernel, kBwdThreads, 0);
+  return (e == hipSuccess && per > 0) ? per : 1;
+}
+
+hipError_t launch_backward(const BatchArgs& b, int32_t nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(bwd_kernel, dim3(nblocks), dim3(kBwdThreads), 0, st, b);
   return hipGetLastError();
 }
 

@@ -14,12 +14,7 @@
 
 namespace plm {
 
-__global__ __launch_bounds__(1024) void lbfgs_kernel(LbfgsArgs a) {
-  __shared__ double red[16];
-  __shared__ double ghd[kSlot];
-  __shared__ double ahist[kMMax];
-  const int r = a.site_offset + blockIdx.x;
-  if (r >= a.N) return;
+__device__ inline void lbfgs_site(const LbfgsArgs& a, int r, double* red, double* ghd, double* ahist) {
   SiteState* S = a.st + r;
   const int phase = S->phase;
   if (phase == PH_DONE) return;
@@ -43,7 +38,8 @@ __global__ __launch_bounds__(1024) void lbfgs_kernel(LbfgsArgs a) {
     for (int k = 0; k < a.tiles; ++k) fdata += a.f_part[(size_t)k * N + r];
   __syncthreads();
 
-  auto lam = [&](int e) { return e < q ? a.lambda_h : ((e >= self0 && e < self1) ? 0.0 : a.lambda_Jp); };
+  const double lam_h = a.lambda_h, lam_J = a.lambda_Jp;
+  auto lam = [&](int e) -> double { return e < q ? lam_h : ((e >= self0 && e < self1) ? 0.0 : lam_J); };
   auto Tv = [&](int e) -> double { return e < q ? (double)a.Th[h0 + e] : (double)a.TJ[j0 + (e - q)]; };
   auto Xv = [&](int e) -> double { return e < q ? (double)a.Xh[h0 + e] : (double)a.XJ[j0 + (e - q)]; };
   auto gtv = [&](int e) -> double {
@@ -221,8 +217,21 @@ __global__ __launch_bounds__(1024) void lbfgs_kernel(LbfgsArgs a) {
   }
 }
 
-hipError_t launch_lbfgs(const LbfgsArgs& a, int32_t nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(lbfgs_kernel, dim3(nblocks), dim3(1024), 0, st, a);
+// One block per active site of the batch.
+__global__ __launch_bounds__(1024) void lbfgs_kernel(BatchArgs b) {
+  __shared__ double red[16];
+  __shared__ double ghd[kSlot];
+  __shared__ double ahist[kMMax];
+  const int idx = blockIdx.x;
+  if (idx >= *b.n_active) return;
+  const int g = b.active[idx];
+  const int m = b.msa_of[g];
+  const LbfgsArgs a = load_uniform(b.lb + m);
+  lbfgs_site(a, g - b.site_base[m], red, ghd, ahist);
+}
+
+hipError_t launch_lbfgs(const BatchArgs& b, int32_t nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(lbfgs_kernel, dim3(nblocks), dim3(1024), 0, st, b);
   return hipGetLastError();
 }
 

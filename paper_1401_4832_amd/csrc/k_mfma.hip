@@ -38,7 +38,9 @@ constexpr int kSigPitch = kMChunk + 16;          // LDS bytes per column (paddin
 constexpr int kBfPiece = kMSteps * 2 * 32 * 8;   // BF16 entries of one piece of one chunk
 constexpr int kRUnits = (kMChunk / 8) * kSlot;   // (8-sequence group, state) units per chunk
 
-int32_t mfma_block_positions(int32_t q) { return min(kMPosMax, kMRows / q); }
+__host__ __device__ inline int32_t mfma_block_positions(int32_t q) {
+  return kMRows / q < kMPosMax ? kMRows / q : kMPosMax;
+}
 
 __device__ inline uint32_t f2bf(float f) {  // round to nearest even (finite inputs)
   uint32_t u = __float_as_uint(f);
@@ -94,33 +96,18 @@ hipError_t launch_transpose_msa(const uint8_t* msa_cm, int32_t B_pad, int32_t N_
   return hipGetLastError();
 }
 
+// One backward work item: site r x column block cb.  Bf: B fragments of the
+// residual pieces, [buffer][piece][step][half][column][8 sequences]; sig:
+// symbols of the block's columns, [buffer][column][sequence].
 template <int NP>
-__global__ __launch_bounds__(kMThreads) void bwd_mfma_kernel(EvalArgs a, int32_t npos_blk,
-                                                             int32_t ncb, int32_t xcd_map) {
-  // B fragments of the residual pieces: [buffer][piece][step][half][column][8 sequences]
-  __shared__ __attribute__((aligned(16))) uint16_t Bf[2][NP * kBfPiece];
-  // symbols of the block's columns: [buffer][column][sequence]
-  __shared__ __attribute__((aligned(16))) uint8_t sig[2][kMPosMax * kSigPitch];
-
-  // workgroups are dealt to the XCDs round-robin; with xcd_map, XCD x takes
-  // the sites x, x + 8, ... and all their column blocks in turn
-  int idx, cb;
-  if (xcd_map) {
-    const int x = blockIdx.x & 7, k = blockIdx.x >> 3;
-    idx = 8 * (k / ncb) + x;
-    cb = k % ncb;
-  } else {
-    idx = blockIdx.x / ncb;
-    cb = blockIdx.x % ncb;
-  }
-  const int nact = a.n_active ? *a.n_active : a.n_active_host;
-  if (idx >= nact) return;
-  const int r = a.sites ? a.sites[idx] : idx;
+__device__ inline void bwd_mfma_item(const EvalArgs& a, int r, int cb, uint16_t (*Bf)[NP * kBfPiece],
+                                     uint8_t (*sig)[kMPosMax * kSigPitch]) {
+  const int npos_blk = mfma_block_positions(a.q);
   const int q = a.q, N = a.N, qq = q * q;
   const int i0 = cb * npos_blk;
   const int npos = min(npos_blk, N - i0);
   const int nrows = npos * q;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = item_tid(), lane = tid & 63, wid = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
 
   // this lane's A-fragment row in each of its row blocks; rows past the end
@@ -139,7 +126,7 @@ __global__ __launch_bounds__(kMThreads) void bwd_mfma_kernel(EvalArgs a, int32_t
   for (int e = tid; e < 2 * NP * kBfPiece / 8; e += kMThreads)
     reinterpret_cast<uint4*>(&Bf[0][0])[e] = make_uint4(0, 0, 0, 0);
 
-  const float* Rr = a.R + (size_t)r * a.B3 * kSlot;
+  const auto Rr = gmem(a.R + (size_t)r * a.B3 * kSlot);
   const int nchunks = (a.B3 + kMChunk - 1) / kMChunk;
   const int nsig = npos_blk * (kMChunk / 16);
 
@@ -160,7 +147,7 @@ __global__ __launch_bounds__(kMThreads) void bwd_mfma_kernel(EvalArgs a, int32_t
       const int pos = e >> 4, part = e & 15;
       sv[k] = make_uint4(0, 0, 0, 0);
       if (e < nsig && i0 + pos < N)
-        sv[k] = *reinterpret_cast<const uint4*>(a.msaT + (size_t)(i0 + pos) * a.B_pad + bc + part * 16);
+        sv[k] = gload_u4(a.msaT + (size_t)(i0 + pos) * a.B_pad + bc + part * 16);
     }
   };
   auto store = [&](int buf) {
@@ -250,7 +237,7 @@ __global__ __launch_bounds__(kMThreads) void bwd_mfma_kernel(EvalArgs a, int32_t
       const int row = (wid * kMRB + m) * 32 + 8 * (j >> 2) + 4 * half + (j & 3);
       if (row < nrows && l32 < q) {
         const int i = i0 + row / q, k = row % q;
-        a.gJ[((size_t)r * N + i) * qq + (size_t)k * q + l32] = (i == r) ? 0.0 : acc64[m][j];
+        gmem_w(a.gJ)[((size_t)r * N + i) * qq + (size_t)k * q + l32] = (i == r) ? 0.0 : acc64[m][j];
       }
     }
 }
@@ -281,36 +268,22 @@ __device__ inline bf16x8 onehot_range(uint32_t d) {
   return __builtin_bit_cast(bf16x8, r);
 }
 
+// One forward work item: site r x sequence tile `tile`.  Wf: W fragments,
+// [buffer][piece][group][column s][8 inner indices]; sgl: the tile's symbols
+// for the chunk's eight columns, [buffer][sequence][column].
 template <int NP>
-__global__ __launch_bounds__(kMThreads) void fwd_mfma_kernel(EvalArgs a, int32_t ntiles,
-                                                             int32_t xcd_map) {
-  // W fragments: [buffer][piece][group][column s][8 inner indices]
-  __shared__ __attribute__((aligned(16))) uint16_t Wf[2][NP * kFPiece];
-  // the tile's symbols for the chunk's eight columns: [buffer][sequence][column]
-  __shared__ __attribute__((aligned(16))) uint8_t sgl[2][kFRows * kFPos];
-  __shared__ double red[kMWaves * 64];
-
-  int idx, tile;
-  if (xcd_map) {
-    const int x = blockIdx.x & 7, k = blockIdx.x >> 3;
-    idx = 8 * (k / ntiles) + x;
-    tile = k % ntiles;
-  } else {
-    idx = blockIdx.x / ntiles;
-    tile = blockIdx.x % ntiles;
-  }
-  const int nact = a.n_active ? *a.n_active : a.n_active_host;
-  if (idx >= nact) return;
-  const int r = a.sites ? a.sites[idx] : idx;
+__device__ inline void fwd_mfma_item(const EvalArgs& a, int r, int tile, uint16_t (*Wf)[NP * kFPiece],
+                                     uint8_t (*sgl)[kFRows * kFPos], double* red) {
   const int q = a.q, N = a.N, qq = q * q;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = item_tid(), lane = tid & 63, wid = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
   const int tile0 = tile * kFRows;
 
   for (int e = tid; e < 2 * NP * kFPiece / 8; e += kMThreads)
     reinterpret_cast<uint4*>(&Wf[0][0])[e] = make_uint4(0, 0, 0, 0);
 
-  const float* Jr = a.J + (size_t)r * N * qq;
+  const auto Jr = gmem(a.J + (size_t)r * N * qq);
+  const auto msa_cm = gmem(a.msa_cm);
   const int nunits = kFGroups * q;  // (group, state) units, at most 504
   const int nchunks = (N + kFPos - 1) / kFPos;
   float wv[8];
@@ -329,8 +302,8 @@ __global__ __launch_bounds__(kMThreads) void fwd_mfma_kernel(EvalArgs a, int32_t
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int row = tid + t * kMThreads;
-      sv[t] = *reinterpret_cast<const uint2*>(
-          a.msa_cm + ((size_t)(i0 / kFwdChunk) * a.B_pad + tile0 + row) * kFwdChunk + (i0 % kFwdChunk));
+      sv[t] = gload_u2(a.msa_cm + ((size_t)(i0 / kFwdChunk) * a.B_pad + tile0 + row) * kFwdChunk +
+                       (i0 % kFwdChunk));
     }
   };
   auto store = [&](int buf) {
@@ -425,13 +398,13 @@ __global__ __launch_bounds__(kMThreads) void fwd_mfma_kernel(EvalArgs a, int32_t
 #pragma unroll
       for (int d = 16; d > 0; d >>= 1) sum += __shfl_xor(sum, d, 32);
       const float lse = mx + logf(sum);
-      const int sr = a.msa_cm[((size_t)(r / kFwdChunk) * a.B_pad + b) * kFwdChunk + r % kFwdChunk];
-      const double wb = b < a.B ? a.w[b] : 0.0;
+      const int sr = msa_cm[((size_t)(r / kFwdChunk) * a.B_pad + b) * kFwdChunk + r % kFwdChunk];
+      const double wb = b < a.B ? gmem(a.w)[b] : 0.0;
       const float P = ex / sum;
       const float Rv = col_ok ? (float)wb * (P - (l32 == sr ? 1.f : 0.f)) : 0.f;
       if (col_ok && l32 == sr) facc += wb * (double)(lse - e);
       ghacc += (double)Rv;
-      if (col_ok && b < a.B3) a.R[((size_t)r * a.B3 + b) * kSlot + l32] = Rv;
+      if (col_ok && b < a.B3) gmem_w(a.R)[((size_t)r * a.B3 + b) * kSlot + l32] = Rv;
     }
   const double ftot = block_sum_f64(facc, red);
   if (tid == 0) a.f_part[(size_t)tile * N + r] = ftot;
@@ -445,37 +418,82 @@ __global__ __launch_bounds__(kMThreads) void fwd_mfma_kernel(EvalArgs a, int32_t
   }
 }
 
-hipError_t launch_forward_mfma(const EvalArgs& a, int32_t n_sites_grid, int32_t npieces,
-                               hipStream_t st) {
-  if (a.q > kQMax || a.q < 1) return hipErrorInvalidValue;
-  const int ntiles = (a.B + kFRows - 1) / kFRows;
-  const int xcd_map = n_sites_grid >= 8 ? 1 : 0;
-  const int nblk = xcd_map ? 8 * ntiles * ((n_sites_grid + 7) / 8) : n_sites_grid * ntiles;
+template <int NP>
+__global__ __launch_bounds__(kMThreads) void fwd_mfma_kernel(BatchArgs b) {
+  __shared__ __attribute__((aligned(16))) uint16_t Wf[2][NP * kFPiece];
+  __shared__ __attribute__((aligned(16))) uint8_t sgl[2][kFRows * kFPos];
+  __shared__ double red[kMWaves * 64];
+  __shared__ int32_t item_s;
+  int32_t qi = 0;
+  const int32_t total = total_items(b, KIND_FWD);
+  for (;;) {
+    if (threadIdx.x == 0) item_s = next_item(b.ctr + KIND_FWD * kQueues, total, qi);
+    __syncthreads();
+    const int32_t t = __builtin_amdgcn_readfirstlane(item_s);
+    if (t < 0) break;
+    const Item it = decode_item(b, KIND_FWD, t);
+    const EvalArgs a = load_uniform(b.ev + it.m);
+    fwd_mfma_item<NP>(a, it.r, it.sub, Wf, sgl, red);
+    __syncthreads();
+  }
+}
+
+hipError_t launch_forward_mfma(const BatchArgs& b, int32_t npieces, int32_t nblocks, hipStream_t st) {
   if (npieces == 3)
-    hipLaunchKernelGGL(fwd_mfma_kernel<3>, dim3(nblk), dim3(kMThreads), 0, st, a, ntiles, xcd_map);
+    hipLaunchKernelGGL(fwd_mfma_kernel<3>, dim3(nblocks), dim3(kMThreads), 0, st, b);
   else if (npieces == 2)
-    hipLaunchKernelGGL(fwd_mfma_kernel<2>, dim3(nblk), dim3(kMThreads), 0, st, a, ntiles, xcd_map);
+    hipLaunchKernelGGL(fwd_mfma_kernel<2>, dim3(nblocks), dim3(kMThreads), 0, st, b);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_backward_mfma(const EvalArgs& a, int32_t n_sites_grid, int32_t npieces,
-                                hipStream_t st) {
-  if (a.q > 32 || a.q < 1) return hipErrorInvalidValue;
-  const int npos_blk = mfma_block_positions(a.q);
-  const int ncb = (a.N + npos_blk - 1) / npos_blk;
-  const int xcd_map = n_sites_grid >= 8 ? 1 : 0;
-  const int nblk = xcd_map ? 8 * ncb * ((n_sites_grid + 7) / 8) : n_sites_grid * ncb;
+
+template <int NP>
+__global__ __launch_bounds__(kMThreads) void bwd_mfma_kernel(BatchArgs b) {
+  __shared__ __attribute__((aligned(16))) uint16_t Bf[2][NP * kBfPiece];
+  __shared__ __attribute__((aligned(16))) uint8_t sig[2][kMPosMax * kSigPitch];
+  __shared__ int32_t item_s;
+  int32_t qi = 0;
+  const int32_t total = total_items(b, KIND_BWD);
+  for (;;) {
+    if (threadIdx.x == 0) item_s = next_item(b.ctr + KIND_BWD * kQueues, total, qi);
+    __syncthreads();
+    const int32_t t = __builtin_amdgcn_readfirstlane(item_s);
+    if (t < 0) break;
+    const Item it = decode_item(b, KIND_BWD, t);
+    const EvalArgs a = load_uniform(b.ev + it.m);
+    bwd_mfma_item<NP>(a, it.r, it.sub, Bf, sig);
+    __syncthreads();
+  }
+}
+
+int32_t mfma_backward_blocks_per_site(int32_t N, int32_t q) {
+  const int32_t p = mfma_block_positions(q);
+  return (N + p - 1) / p;
+}
+
+hipError_t launch_backward_mfma(const BatchArgs& b, int32_t npieces, int32_t nblocks, hipStream_t st) {
   if (npieces == 3)
-    hipLaunchKernelGGL(bwd_mfma_kernel<3>, dim3(nblk), dim3(kMThreads), 0, st, a, npos_blk, ncb,
-                       xcd_map);
+    hipLaunchKernelGGL(bwd_mfma_kernel<3>, dim3(nblocks), dim3(kMThreads), 0, st, b);
   else if (npieces == 2)
-    hipLaunchKernelGGL(bwd_mfma_kernel<2>, dim3(nblk), dim3(kMThreads), 0, st, a, npos_blk, ncb,
-                       xcd_map);
+    hipLaunchKernelGGL(bwd_mfma_kernel<2>, dim3(nblocks), dim3(kMThreads), 0, st, b);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+// resident blocks per CU of the persistent MFMA kernels: kind 0 forward, 1 backward
+int32_t mfma_resident_blocks(int32_t kind, int32_t npieces) {
+  int per = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (kind == KIND_FWD)
+    e = npieces == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_mfma_kernel<3>, kMThreads, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_mfma_kernel<2>, kMThreads, 0);
+  else
+    e = npieces == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bwd_mfma_kernel<3>, kMThreads, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bwd_mfma_kernel<2>, kMThreads, 0);
+  return (e == hipSuccess && per > 0) ? per : 1;
 }
 
 }  // namespace plm

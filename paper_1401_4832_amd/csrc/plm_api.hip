@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "plm_internal.h"
@@ -20,6 +21,7 @@ struct plm_ctx {
   hipStream_t fit_stream;  // private stream of the synchronous fit (graph capture needs one)
   hipEvent_t ev[5];        // kernel timing marks of the fit iteration
   plm_fit_timing timing;   // of the last timed fit
+  int32_t ncu;             // compute units of the device
 };
 
 namespace {
@@ -81,14 +83,11 @@ void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
   e.sorted = bp.take<uint16_t>((size_t)e.nchunks * N * kBwdSeqChunk);
 }
 
+// per-alignment optimiser buffers
 struct FitBufs {
   EvalBufs ev;
   float *Th, *TJ;
   double *Gh, *GJ, *Dh, *DJ, *Sh, *SJ, *Yh, *YJ;
-  SiteState* st;
-  int32_t* sites;
-  int32_t* n_active;
-  unsigned long long* site_evals;
 };
 
 void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, FitBufs& f) {
@@ -104,10 +103,48 @@ void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, FitBufs& f
   f.SJ = bp.take<double>(NNqq * m);
   f.Yh = bp.take<double>(Nq * m);
   f.YJ = bp.take<double>(NNqq * m);
-  f.st = bp.take<SiteState>(N);
-  f.sites = bp.take<int32_t>(N);
-  f.n_active = bp.take<int32_t>(1);
-  f.site_evals = bp.take<unsigned long long>(1);
+}
+
+// device tables of a batch (BatchArgs points into them)
+struct Tables {
+  EvalArgs* ev;
+  LbfgsArgs* lb;
+  int32_t *site_base, *msa_of, *active, *n_active, *seg, *item_off, *nsub;
+  uint32_t* ctr;
+  SiteState* st;
+  unsigned long long* site_evals;
+};
+
+void layout_tables(Bump& bp, int32_t n_msas, int32_t total, bool fit, Tables& t) {
+  t.ev = bp.take<EvalArgs>(n_msas);
+  t.lb = fit ? bp.take<LbfgsArgs>(n_msas) : nullptr;
+  t.site_base = bp.take<int32_t>(n_msas + 1);
+  t.msa_of = bp.take<int32_t>(total);
+  t.active = bp.take<int32_t>(total);
+  t.n_active = bp.take<int32_t>(1);
+  t.seg = bp.take<int32_t>(n_msas + 1);
+  t.item_off = bp.take<int32_t>(2 * (n_msas + 1));
+  t.nsub = bp.take<int32_t>(2 * n_msas);
+  t.ctr = bp.take<uint32_t>(2 * kQueues);
+  t.st = fit ? bp.take<SiteState>(total) : nullptr;
+  t.site_evals = bp.take<unsigned long long>(1);
+}
+
+BatchArgs batch_args(const Tables& t, int32_t n_msas, int32_t total) {
+  BatchArgs b;
+  b.ev = t.ev;
+  b.lb = t.lb;
+  b.n_msas = n_msas;
+  b.total_sites = total;
+  b.site_base = t.site_base;
+  b.msa_of = t.msa_of;
+  b.active = t.active;
+  b.n_active = t.n_active;
+  b.seg = t.seg;
+  b.item_off = t.item_off;
+  b.nsub = t.nsub;
+  b.ctr = t.ctr;
+  return b;
 }
 
 int check_sizes(plm_ctx* c, int32_t B, int32_t N, int32_t q) {
@@ -166,18 +203,49 @@ int32_t eval_tiles(const PathSpec& p, int32_t B, int32_t nb) {
   return (B + t - 1) / t;
 }
 
+int32_t eval_bwd_blocks(const PathSpec& p, int32_t N, int32_t q) {
+  return p.bwd_np ? mfma_backward_blocks_per_site(N, q) : backward_blocks_per_site(N);
+}
+
 hipError_t eval_prepare(const PathSpec& p, const EvalArgs& a, uint8_t* msaT, uint16_t* sorted,
                         hipStream_t st) {
   if (p.bwd_np) return launch_transpose_msa(a.msa_cm, a.B_pad, a.N_pad, msaT, st);
   return launch_chunk_sort(a.msa_cm, a.B3, a.B_pad, a.N, a.q, sorted, st);
 }
 
-hipError_t eval_forward(const PathSpec& p, const EvalArgs& a, int32_t n, int32_t nb, hipStream_t st) {
-  return p.fwd_np ? launch_forward_mfma(a, n, p.fwd_np, st) : launch_forward(a, n, nb, st);
+// persistent grids: resident blocks of each kernel on the whole device
+struct Grids {
+  int32_t fwd, bwd;
+};
+
+Grids eval_grids(const plm_ctx* c, const PathSpec& p, int32_t nb) {
+  Grids g;
+  g.fwd = c->ncu * (p.fwd_np ? mfma_resident_blocks(KIND_FWD, p.fwd_np) : forward_resident_blocks(nb));
+  g.bwd = c->ncu * (p.bwd_np ? mfma_resident_blocks(KIND_BWD, p.bwd_np) : backward_resident_blocks());
+  return g;
 }
 
-hipError_t eval_backward(const PathSpec& p, const EvalArgs& a, int32_t n, hipStream_t st) {
-  return p.bwd_np ? launch_backward_mfma(a, n, p.bwd_np, st) : launch_backward(a, n, st);
+hipError_t eval_forward(const PathSpec& p, const BatchArgs& b, int32_t nb, const Grids& g,
+                        hipStream_t st) {
+  return p.fwd_np ? launch_forward_mfma(b, p.fwd_np, g.fwd, st) : launch_forward(b, nb, g.fwd, st);
+}
+
+hipError_t eval_backward(const PathSpec& p, const BatchArgs& b, const Grids& g, hipStream_t st) {
+  return p.bwd_np ? launch_backward_mfma(b, p.bwd_np, g.bwd, st) : launch_backward(b, g.bwd, st);
+}
+
+EvalArgs eval_args(const EvalBufs& e, const uint8_t* msa_unused, int32_t B, int32_t N, int32_t q,
+                   const double* w, const float* h, const float* J, int32_t tiles) {
+  (void)msa_unused;
+  EvalArgs a;
+  a.msa_cm = e.msa_cm;
+  a.msaT = e.msaT;
+  a.B = B; a.B3 = e.B3; a.B_pad = e.B_pad; a.N = N; a.N_pad = e.N_pad; a.q = q;
+  a.w = w; a.h = h; a.J = J;
+  a.R = e.R; a.f_part = e.f_part; a.gh_part = e.gh_part; a.gJ = e.gJ;
+  a.tiles = tiles;
+  a.sorted = e.sorted;
+  return a;
 }
 
 int flags_status(plm_ctx* c) {
@@ -189,6 +257,10 @@ int flags_status(plm_ctx* c) {
   if (f & 2) {
     c->pin[0] = 0;
     return set_err(c, PLM_E_NONFINITE, "non-finite value in an input array");
+  }
+  if (f & 4) {
+    c->pin[0] = 0;
+    return set_err(c, PLM_E_INVALID, "site index outside [0, N)");
   }
   return PLM_OK;
 }
@@ -223,6 +295,7 @@ int plm_ctx_create(plm_ctx** out, int device, void* hip_stream) {
   if (strncmp(p.gcnArchName, "gfx950", 6) != 0) return PLM_E_UNSUPPORTED;
   plm_ctx* c = new plm_ctx();
   c->device = device;
+  c->ncu = p.multiProcessorCount > 0 ? p.multiProcessorCount : 1;
   c->stream = (hipStream_t)hip_stream;
   c->err[0] = 0;
   c->pin = nullptr;
@@ -278,6 +351,8 @@ size_t plm_objgrad_workspace_bytes(int32_t B, int32_t N, int32_t q, int32_t path
   Bump bp{nullptr, 0};
   EvalBufs e;
   layout_eval(bp, B, N, q, e);
+  Tables t;
+  layout_tables(bp, 1, N, false, t);
   return rup(bp.off, 256);
 }
 
@@ -303,29 +378,28 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
   Bump bp{(char*)ws, 0};
   EvalBufs e;
   layout_eval(bp, B, N, q, e);
+  Tables t;
+  layout_tables(bp, 1, N, false, t);
+  const BatchArgs b = batch_args(t, 1, N);
   HIPCHK(c, launch_check_f64(w, (size_t)B, c->pin_dev, c->stream));
   HIPCHK(c, launch_check_f32(h, (size_t)N * q, c->pin_dev, c->stream));
   HIPCHK(c, launch_check_f32(J, (size_t)N * N * q * q, c->pin_dev, c->stream));
   if (grad_scale) HIPCHK(c, launch_check_f64(grad_scale, (size_t)N, c->pin_dev, c->stream));
   HIPCHK(c, launch_pad_msa(msa, B, N, q, e.msa_cm, e.B_pad, e.N_pad, c->pin_dev, c->stream));
   const int32_t nb = pick_nb(B, 0);
-  EvalArgs a;
-  a.msa_cm = e.msa_cm;
-  a.msaT = e.msaT;
-  a.B = B; a.B3 = e.B3; a.B_pad = e.B_pad; a.N = N; a.N_pad = e.N_pad; a.q = q;
-  a.w = w; a.h = h; a.J = J;
-  a.sites = sites; a.n_active = nullptr; a.n_active_host = n_sites;
-  a.R = e.R; a.f_part = e.f_part; a.gh_part = e.gh_part; a.gJ = e.gJ;
-  a.sorted = e.sorted;
-  a.tiles = eval_tiles(ps, B, nb);
-  HIPCHK(c, eval_forward(ps, a, n_sites, nb, c->stream));
+  const EvalArgs a = eval_args(e, msa, B, N, q, w, h, J, eval_tiles(ps, B, nb));
+  HIPCHK(c, launch_setup_msa(b, 0, a, nullptr, 0, N, a.tiles, eval_bwd_blocks(ps, N, q), nullptr,
+                             c->stream));
+  HIPCHK(c, launch_list_tables(b, sites, 0, n_sites, c->pin_dev, c->stream));
+  const Grids g = eval_grids(c, ps, nb);
+  HIPCHK(c, eval_forward(ps, b, nb, g, c->stream));
   if (gJ_out) {
     HIPCHK(c, eval_prepare(ps, a, e.msaT, e.sorted, c->stream));
-    HIPCHK(c, eval_backward(ps, a, n_sites, c->stream));
+    HIPCHK(c, eval_backward(ps, b, g, c->stream));
   }
   FinalArgs fa;
   fa.N = N; fa.q = q; fa.tiles = a.tiles; fa.lambda_h = lambda_h; fa.lambda_Jp = 0.5 * lambda_J;
-  fa.beff = beff; fa.h = h; fa.J = J; fa.sites = sites;
+  fa.beff = beff; fa.h = h; fa.J = J; fa.sites = t.active;  // the checked site list
   fa.f_part = e.f_part; fa.gh_part = e.gh_part; fa.gJ = e.gJ; fa.grad_scale = grad_scale;
   fa.f_out = f_out; fa.gh_out = gh_out; fa.gJ_out = gJ_out;
   HIPCHK(c, launch_objgrad_final(fa, n_sites, c->stream));
@@ -350,96 +424,126 @@ void plm_fit_opts_default(plm_fit_opts* o) {
   o->timing = 0;
 }
 
-size_t plm_fit_workspace_bytes(int32_t B, int32_t N, int32_t q, const plm_fit_opts* o) {
-  if (B < 1 || N < 2 || q < 2 || q > kQMax || !o) return 0;
-  const int m = o->lbfgs_m;
-  if (m < 1 || m > kMMax) return 0;
-  Bump bp{nullptr, 0};
-  FitBufs f;
-  layout_fit(bp, B, N, q, m, f);
+}  // extern "C"
+
+namespace {
+
+bool fit_opts_ok(const plm_fit_opts* o) {
+  return o->lambda_h >= 0.0 && o->lambda_J >= 0.0 && o->tol >= 0.0 && o->max_iter >= 1 &&
+         o->lbfgs_m >= 1 && o->lbfgs_m <= kMMax && o->max_linesearch >= 1;
+}
+
+// Alignments in batch order: decreasing evaluation cost B * N^2, ties by index.
+std::vector<int32_t> batch_order(const plm_msa_desc* d, int32_t n) {
+  std::vector<int32_t> ord(n);
+  for (int32_t k = 0; k < n; ++k) ord[k] = k;
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+    return (double)d[x].B * d[x].N * d[x].N > (double)d[y].B * d[y].N * d[y].N;
+  });
+  return ord;
+}
+
+size_t fit_layout(const plm_msa_desc* d, int32_t n, int32_t q, const plm_fit_opts* o, char* base,
+                  std::vector<FitBufs>* bufs, Tables* t) {
+  const std::vector<int32_t> ord = batch_order(d, n);
+  Bump bp{base, 0};
+  int32_t total = 0;
+  if (bufs) bufs->resize(n);
+  for (int32_t k = 0; k < n; ++k) {
+    const plm_msa_desc& m = d[ord[k]];
+    FitBufs f;
+    layout_fit(bp, m.B, m.N, q, o->lbfgs_m, f);
+    if (bufs) (*bufs)[k] = f;
+    total += m.N;
+  }
+  Tables tt;
+  layout_tables(bp, n, total, true, tt);
+  if (t) *t = tt;
   return rup(bp.off, 256);
 }
 
-int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
-            const double* beff, const plm_fit_opts* o, void* ws, size_t ws_bytes, float* h_io,
-            float* J_io, plm_site_stats* stats_out) {
-  if (!c) return PLM_E_INVALID;
-  if (!msa || !w || !beff || !o || !h_io || !J_io) return set_err(c, PLM_E_INVALID, "null pointer");
-  int rc = check_sizes(c, B, N, q);
-  if (rc) return rc;
-  if (!(o->lambda_h >= 0.0) || !(o->lambda_J >= 0.0) || !(o->tol >= 0.0) || o->max_iter < 1 ||
-      o->lbfgs_m < 1 || o->lbfgs_m > kMMax || o->max_linesearch < 1)
-    return set_err(c, PLM_E_INVALID, "invalid fit options");
+// The fit of a batch of alignments (plm_fit is a batch of one).
+int run_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_fit_opts* o,
+            void* ws, size_t ws_bytes) {
+  if (!fit_opts_ok(o)) return set_err(c, PLM_E_INVALID, "invalid fit options");
   PathSpec ps;
   if (!path_spec(o->path, &ps))
     return set_err(c, PLM_E_UNSUPPORTED, "evaluation path %d is not available", o->path);
-  const size_t need = plm_fit_workspace_bytes(B, N, q, o);
-  rc = check_ws(c, ws, ws_bytes, need);
+  if (o->single_site && n != 1)
+    return set_err(c, PLM_E_INVALID, "the single-site path takes one alignment");
+  int32_t total = 0, Bmax = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    const plm_msa_desc& m = d[k];
+    if (!m.msa || !m.w || !m.beff || !m.h_io || !m.J_io)
+      return set_err(c, PLM_E_INVALID, "null pointer in alignment %d", k);
+    int rc = check_sizes(c, m.B, m.N, q);
+    if (rc) return rc;
+    total += m.N;
+    if (m.B > Bmax) Bmax = m.B;
+  }
+  const size_t need = fit_layout(d, n, q, o, nullptr, nullptr, nullptr);
+  int rc = check_ws(c, ws, ws_bytes, need);
   if (rc) return rc;
   HIPCHK(c, hipSetDevice(c->device));
-  rc = ensure_pin(c, 2 + (size_t)N);
+  rc = ensure_pin(c, 2 + (size_t)total);
   if (rc) return rc;
   int32_t* phase_host_dev = c->pin_dev + 2;
   volatile int32_t* phase_host = c->pin + 2;
-  Bump bp{(char*)ws, 0};
-  FitBufs f;
-  layout_fit(bp, B, N, q, o->lbfgs_m, f);
+  std::vector<FitBufs> fb;
+  Tables t;
+  fit_layout(d, n, q, o, (char*)ws, &fb, &t);
+  const std::vector<int32_t> ord = batch_order(d, n);
+  const BatchArgs b = batch_args(t, n, total);
   // the fit runs on the context's private stream once the caller's stream has
   // delivered its inputs, and returns after the private stream has finished
   HIPCHK(c, hipStreamSynchronize(c->stream));
   hipStream_t st = c->fit_stream;
-  c->pin[1] = N;
+  c->pin[1] = total;
 
-  HIPCHK(c, launch_check_f64(w, (size_t)B, c->pin_dev, st));
-  HIPCHK(c, launch_check_f32(h_io, (size_t)N * q, c->pin_dev, st));
-  HIPCHK(c, launch_pad_msa(msa, B, N, q, f.ev.msa_cm, f.ev.B_pad, f.ev.N_pad, c->pin_dev, st));
-  HIPCHK(c, launch_init_fit(N, q, h_io, J_io, f.Th, f.TJ, f.st, f.sites, f.n_active, phase_host_dev, st));
-  HIPCHK(c, launch_check_f32(J_io, (size_t)N * N * q * q, c->pin_dev, st));
-  HIPCHK(c, launch_zero_u64(f.site_evals, st));
+  const int32_t nb = pick_nb(Bmax, o->tile_seqs);
+  std::vector<int32_t> base(n + 1, 0);
+  for (int32_t k = 0; k < n; ++k) {
+    const plm_msa_desc& m = d[ord[k]];
+    const FitBufs& f = fb[k];
+    base[k + 1] = base[k] + m.N;
+    HIPCHK(c, launch_check_f64(m.w, (size_t)m.B, c->pin_dev, st));
+    HIPCHK(c, launch_check_f32(m.h_io, (size_t)m.N * q, c->pin_dev, st));
+    HIPCHK(c, launch_pad_msa(m.msa, m.B, m.N, q, f.ev.msa_cm, f.ev.B_pad, f.ev.N_pad, c->pin_dev, st));
+    HIPCHK(c, launch_init_fit(m.N, q, m.h_io, m.J_io, f.Th, f.TJ, t.st + base[k], phase_host_dev + base[k], st));
+    HIPCHK(c, launch_check_f32(m.J_io, (size_t)m.N * m.N * q * q, c->pin_dev, st));
+    const EvalArgs a = eval_args(f.ev, m.msa, m.B, m.N, q, m.w, f.Th, f.TJ, eval_tiles(ps, m.B, nb));
+    HIPCHK(c, eval_prepare(ps, a, f.ev.msaT, f.ev.sorted, st));
+    LbfgsArgs L;
+    L.N = m.N; L.q = q; L.m = o->lbfgs_m; L.max_iter = o->max_iter; L.max_ls = o->max_linesearch;
+    L.tiles = a.tiles; L.tol = o->tol; L.lambda_h = o->lambda_h; L.lambda_Jp = 0.5 * o->lambda_J;
+    L.c1 = 1e-4;
+    L.noise = 1e-7;  // relative rounding noise allowed in the FP32 objective
+    L.beff = m.beff;
+    L.Xh = m.h_io; L.XJ = m.J_io; L.Th = f.Th; L.TJ = f.TJ;
+    L.Gh = f.Gh; L.GJ = f.GJ; L.Dh = f.Dh; L.DJ = f.DJ;
+    L.Sh = f.Sh; L.SJ = f.SJ; L.Yh = f.Yh; L.YJ = f.YJ;
+    L.f_part = f.ev.f_part; L.gh_part = f.ev.gh_part; L.gJ = f.ev.gJ;
+    L.st = t.st + base[k];
+    L.phase_host = phase_host_dev + base[k];
+    HIPCHK(c, launch_setup_msa(b, k, a, &L, base[k], m.N, a.tiles, eval_bwd_blocks(ps, m.N, q),
+                               t.site_evals, st));
+  }
+  HIPCHK(c, launch_compact(b, t.st, nullptr, nullptr, st));  // every site active
   HIPCHK(c, hipStreamSynchronize(st));
   rc = flags_status(c);
   if (rc) return rc;
-
-  const int32_t nb = pick_nb(B, o->tile_seqs);
-  EvalArgs a;
-  a.msa_cm = f.ev.msa_cm;
-  a.msaT = f.ev.msaT;
-  a.B = B; a.B3 = f.ev.B3; a.B_pad = f.ev.B_pad; a.N = N; a.N_pad = f.ev.N_pad; a.q = q;
-  a.w = w; a.h = f.Th; a.J = f.TJ;
-  a.sites = f.sites; a.n_active = f.n_active; a.n_active_host = N;
-  a.R = f.ev.R; a.f_part = f.ev.f_part; a.gh_part = f.ev.gh_part; a.gJ = f.ev.gJ;
-  a.sorted = f.ev.sorted;
-  a.tiles = eval_tiles(ps, B, nb);
-  HIPCHK(c, eval_prepare(ps, a, f.ev.msaT, f.ev.sorted, st));
-
-  LbfgsArgs L;
-  L.N = N; L.q = q; L.m = o->lbfgs_m; L.max_iter = o->max_iter; L.max_ls = o->max_linesearch;
-  L.tiles = a.tiles; L.tol = o->tol; L.lambda_h = o->lambda_h; L.lambda_Jp = 0.5 * o->lambda_J;
-  L.c1 = 1e-4;
-  L.noise = 1e-7;  // relative rounding noise allowed in the FP32 objective
-  L.beff = beff;
-  L.Xh = h_io; L.XJ = J_io; L.Th = f.Th; L.TJ = f.TJ;
-  L.Gh = f.Gh; L.GJ = f.GJ; L.Dh = f.Dh; L.DJ = f.DJ;
-  L.Sh = f.Sh; L.SJ = f.SJ; L.Yh = f.Yh; L.YJ = f.YJ;
-  L.f_part = f.ev.f_part; L.gh_part = f.ev.gh_part; L.gJ = f.ev.gJ;
-  L.st = f.st; L.phase_host = phase_host_dev; L.site_offset = 0;
+  const Grids g = eval_grids(c, ps, nb);
 
   const int64_t cap = (int64_t)o->max_iter * (o->max_linesearch + 2) + 16;
   if (o->single_site) {
-    // the plain path: one site at a time, each launch sized for one site, the
-    // host waiting for every iteration
-    EvalArgs a1 = a;
-    a1.n_active = nullptr;
-    a1.n_active_host = 1;
-    const int32_t nsites = (o->site_limit > 0 && o->site_limit < N) ? o->site_limit : N;
+    // the plain path: one site at a time, the host waiting for every iteration
+    const int32_t nsites = (o->site_limit > 0 && o->site_limit < total) ? o->site_limit : total;
     for (int32_t r = 0; r < nsites; ++r) {
-      a1.sites = f.sites + r;  // sites[r] == r after initialisation
-      LbfgsArgs L1 = L;
-      L1.site_offset = r;
       for (int64_t it = 0; it < cap; ++it) {
-        HIPCHK(c, eval_forward(ps, a1, 1, nb, st));
-        HIPCHK(c, eval_backward(ps, a1, 1, st));
-        HIPCHK(c, launch_lbfgs(L1, 1, st));
+        HIPCHK(c, launch_list_tables(b, nullptr, r, 1, nullptr, st));
+        HIPCHK(c, eval_forward(ps, b, nb, g, st));
+        HIPCHK(c, eval_backward(ps, b, g, st));
+        HIPCHK(c, launch_lbfgs(b, 1, st));
         HIPCHK(c, hipStreamSynchronize(st));
         if (phase_host[r] == PH_DONE) break;
       }
@@ -451,13 +555,13 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
     auto mark = [&](int k) -> hipError_t { return timed ? hipEventRecord(c->ev[k], st) : hipSuccess; };
     auto enqueue = [&]() -> hipError_t {
       hipError_t e = mark(0);
-      if (e == hipSuccess) e = eval_forward(ps, a, N, nb, st);
+      if (e == hipSuccess) e = eval_forward(ps, b, nb, g, st);
       if (e == hipSuccess) e = mark(1);
-      if (e == hipSuccess) e = eval_backward(ps, a, N, st);
+      if (e == hipSuccess) e = eval_backward(ps, b, g, st);
       if (e == hipSuccess) e = mark(2);
-      if (e == hipSuccess) e = launch_lbfgs(L, N, st);
+      if (e == hipSuccess) e = launch_lbfgs(b, total, st);
       if (e == hipSuccess) e = mark(3);
-      if (e == hipSuccess) e = launch_compact(N, f.st, f.sites, f.n_active, c->pin_dev + 1, f.site_evals, st);
+      if (e == hipSuccess) e = launch_compact(b, t.st, c->pin_dev + 1, t.site_evals, st);
       return e;
     };
     plm_fit_timing tm;
@@ -506,7 +610,7 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
     }
     if (timed) {
       unsigned long long se = 0;
-      (void)hipMemcpy(&se, f.site_evals, sizeof(se), hipMemcpyDeviceToHost);
+      (void)hipMemcpy(&se, t.site_evals, sizeof(se), hipMemcpyDeviceToHost);
       tm.site_evals = (int64_t)se;
       tm.total_ms = tm.forward_ms + tm.backward_ms + tm.lbfgs_ms;
       c->timing = tm;
@@ -518,22 +622,71 @@ int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, con
   HIPCHK(c, hipStreamSynchronize(st));
   rc = flags_status(c);
   if (rc) return rc;
-  std::vector<SiteState> hs(N);
-  HIPCHK(c, hipMemcpy(hs.data(), f.st, sizeof(SiteState) * N, hipMemcpyDeviceToHost));
+  std::vector<SiteState> hs(total);
+  HIPCHK(c, hipMemcpy(hs.data(), t.st, sizeof(SiteState) * total, hipMemcpyDeviceToHost));
   int any_max = 0;
-  for (int32_t r = 0; r < N; ++r) {
-    int status = hs[r].phase == PH_DONE ? hs[r].status : PLM_SITE_MAXITER;
-    if (status == PLM_SITE_MAXITER) any_max = 1;
-    if (stats_out) {
-      stats_out[r].iterations = hs[r].iter;
-      stats_out[r].evaluations = hs[r].evals;
-      stats_out[r].status = status;
-      stats_out[r].pad = 0;
-      stats_out[r].f = hs[r].f;
-      stats_out[r].gnorm = hs[r].gnorm;
+  for (int32_t k = 0; k < n; ++k) {
+    const plm_msa_desc& m = d[ord[k]];
+    for (int32_t r = 0; r < m.N; ++r) {
+      const SiteState& S = hs[base[k] + r];
+      int status = S.phase == PH_DONE ? S.status : PLM_SITE_MAXITER;
+      if (status == PLM_SITE_MAXITER) any_max = 1;
+      if (m.stats_out) {
+        m.stats_out[r].iterations = S.iter;
+        m.stats_out[r].evaluations = S.evals;
+        m.stats_out[r].status = status;
+        m.stats_out[r].pad = 0;
+        m.stats_out[r].f = S.f;
+        m.stats_out[r].gnorm = S.gnorm;
+      }
     }
   }
   return any_max ? PLM_W_MAXITER : PLM_OK;
+}
+
+plm_msa_desc single_desc(const uint8_t* msa, int32_t B, int32_t N, const double* w, const double* beff,
+                         float* h_io, float* J_io, plm_site_stats* stats_out) {
+  plm_msa_desc d;
+  d.msa = msa; d.B = B; d.N = N; d.w = w; d.beff = beff; d.h_io = h_io; d.J_io = J_io;
+  d.stats_out = stats_out;
+  return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t plm_fit_workspace_bytes(int32_t B, int32_t N, int32_t q, const plm_fit_opts* o) {
+  if (B < 1 || N < 2 || q < 2 || q > kQMax || !o) return 0;
+  if (o->lbfgs_m < 1 || o->lbfgs_m > kMMax) return 0;
+  const plm_msa_desc d = single_desc(nullptr, B, N, nullptr, nullptr, nullptr, nullptr, nullptr);
+  return fit_layout(&d, 1, q, o, nullptr, nullptr, nullptr);
+}
+
+int plm_fit(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
+            const double* beff, const plm_fit_opts* o, void* ws, size_t ws_bytes, float* h_io,
+            float* J_io, plm_site_stats* stats_out) {
+  if (!c) return PLM_E_INVALID;
+  if (!msa || !w || !beff || !o || !h_io || !J_io) return set_err(c, PLM_E_INVALID, "null pointer");
+  const plm_msa_desc d = single_desc(msa, B, N, w, beff, h_io, J_io, stats_out);
+  return run_fit(c, &d, 1, q, o, ws, ws_bytes);
+}
+
+size_t plm_fit_batch_workspace_bytes(const plm_msa_desc* descs, int32_t n_msas, int32_t q,
+                                     const plm_fit_opts* o) {
+  if (!descs || n_msas < 1 || !o || q < 2 || q > kQMax) return 0;
+  if (o->lbfgs_m < 1 || o->lbfgs_m > kMMax) return 0;
+  for (int32_t k = 0; k < n_msas; ++k)
+    if (descs[k].B < 1 || descs[k].N < 2) return 0;
+  return fit_layout(descs, n_msas, q, o, nullptr, nullptr, nullptr);
+}
+
+int plm_fit_batch(plm_ctx* c, const plm_msa_desc* descs, int32_t n_msas, int32_t q,
+                  const plm_fit_opts* o, void* ws, size_t ws_bytes) {
+  if (!c) return PLM_E_INVALID;
+  if (!descs || !o || n_msas < 1) return set_err(c, PLM_E_INVALID, "null pointer or empty batch");
+  if (o->single_site) return set_err(c, PLM_E_INVALID, "single_site is not available for batches");
+  return run_fit(c, descs, n_msas, q, o, ws, ws_bytes);
 }
 
 int plm_fit_last_timing(const plm_ctx* c, plm_fit_timing* out) {

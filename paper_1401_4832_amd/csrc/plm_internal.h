@@ -60,9 +60,6 @@ struct EvalArgs {
   const double* w;         // [B]
   const float* h;          // [N][q]  (trial point)
   const float* J;          // [N][N][q][q]
-  const int32_t* sites;    // active site list
-  const int32_t* n_active; // device count (nullable: then n_active_host)
-  int32_t n_active_host;
   float* R;                // [N][B3][21] residuals w_b (P_b(s) - [sigma_r = s])
   double* f_part;          // [tiles][N]
   double* gh_part;         // [tiles][N][21]
@@ -94,7 +91,6 @@ struct LbfgsArgs {
   const double* gJ;       // [N][N][q][q] data part
   SiteState* st;
   int32_t* phase_host;    // pinned mirror of each site's phase (nullable)
-  int32_t site_offset;    // block b handles site site_offset + b
 };
 
 // Arguments of the standalone objective/gradient finalisation.
@@ -114,6 +110,119 @@ struct FinalArgs {
   float* gJ_out;
 };
 
+// A batch of alignments evaluated together (a single alignment is a batch of
+// one).  Sites of all alignments get global ids, alignment by alignment in the
+// batch order (largest cost first); the active list keeps that order.  Each
+// evaluation kernel is persistent: its blocks drain work items (alignment,
+// site, tile) from kQueues queues, each a contiguous range of the item order.
+constexpr int kQueues = 8;
+enum { KIND_FWD = 0, KIND_BWD = 1 };
+
+struct BatchArgs {
+  const EvalArgs* ev;        // [n_msas] evaluation descriptors (device)
+  const LbfgsArgs* lb;       // [n_msas] optimiser descriptors (device; fit only)
+  int32_t n_msas, total_sites;
+  const int32_t* site_base;  // [n_msas + 1] first global site id of each alignment
+  const int32_t* msa_of;     // [total_sites] alignment of each global site
+  int32_t* active;           // [total_sites] active global site ids
+  int32_t* n_active;         // device count of active sites
+  int32_t* seg;              // [n_msas + 1] start of each alignment's run in the active list
+  int32_t* item_off;         // [2][n_msas + 1] work-item offsets (forward, backward)
+  const int32_t* nsub;       // [2][n_msas] work items per site (forward tiles, backward blocks)
+  uint32_t* ctr;             // [2][kQueues] queue counters, cleared when the tables are built
+};
+
+struct Item {
+  int32_t m, g, r, sub;
+};
+
+// Next work item of a persistent block (call from one thread).  The block
+// starts on queue blockIdx % kQueues -- under round-robin dispatch, the queue
+// of its XCD, so that consecutive items of one site share that XCD's L2 --
+// and moves to the following queues when its own is empty.  qi counts the
+// queues finished; -1 is returned once all are empty, so every block exits.
+__device__ inline int32_t next_item(uint32_t* ctr, int32_t total, int32_t& qi) {
+  while (qi < kQueues) {
+    const int32_t x = (int32_t)((blockIdx.x + (uint32_t)qi) % kQueues);
+    const int32_t lo = (int32_t)(((int64_t)total * x) / kQueues);
+    const int32_t hi = (int32_t)(((int64_t)total * (x + 1)) / kQueues);
+    if (lo < hi) {
+      const int32_t k = (int32_t)atomicAdd(&ctr[x], 1u);
+      if (lo + k < hi) return lo + k;
+    }
+    ++qi;
+  }
+  return -1;
+}
+
+// A descriptor read by a whole block, moved into scalar registers (every
+// 32-bit word through readfirstlane), so that its fields cost no VGPRs.
+template <class T>
+__device__ inline T load_uniform(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "descriptor size");
+  T out;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(p);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+  return out;
+}
+
+// A device pointer seen as global memory (descriptors loaded from memory lose
+// the address space of their pointers; global loads can then address with a
+// scalar base and a 32-bit lane offset).
+template <class T>
+__device__ inline const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ inline __attribute__((address_space(1))) T* gmem_w(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+__device__ inline uint4 gload_u4(const void* p) {
+  const u32x4_t v = *(const __attribute__((address_space(1))) u32x4_t*)p;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ inline uint2 gload_u2(const void* p) {
+  const u32x2_t v = *(const __attribute__((address_space(1))) u32x2_t*)p;
+  return make_uint2(v.x, v.y);
+}
+
+// threadIdx.x, opaque to the optimiser: the item bodies of the persistent
+// kernels derive their per-lane offsets from it, so that those are recomputed
+// per item instead of being hoisted out of the item loop (where they would
+// occupy registers for the whole kernel).
+__device__ inline int item_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+__device__ inline int32_t total_items(const BatchArgs& b, int kind) {
+  return b.item_off[kind * (b.n_msas + 1) + b.n_msas];
+}
+
+__device__ inline Item decode_item(const BatchArgs& b, int kind, int32_t t) {
+  const int32_t* off = b.item_off + kind * (b.n_msas + 1);
+  int32_t lo = 0, hi = b.n_msas - 1;  // last alignment whose first item is <= t
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  Item it;
+  it.m = lo;
+  const int32_t ns = b.nsub[kind * b.n_msas + lo];
+  const int32_t loc = t - off[lo];
+  const int32_t j = loc / ns;
+  it.sub = loc - j * ns;
+  it.g = b.active[b.seg[lo] + j];
+  it.r = it.g - b.site_base[lo];
+  return it;
+}
+
 // Device helpers ----------------------------------------------------------
 __device__ inline double block_sum_f64(double v, double* red) {
   // deterministic: fixed shuffle tree per wave, then waves summed in order
@@ -130,33 +239,41 @@ __device__ inline double block_sum_f64(double v, double* red) {
 }
 
 // Host-side launchers -------------------------------------------------------
+// The evaluation and optimiser kernels are persistent / per-site over a batch;
+// nblocks is the grid (resident blocks for the persistent kernels).
 hipError_t launch_pad_msa(const uint8_t* msa, int32_t B, int32_t N, int32_t q, uint8_t* msa_cm,
                           int32_t B_pad, int32_t N_pad, int32_t* flag_dev, hipStream_t st);
-hipError_t launch_forward(const EvalArgs& a, int32_t n_sites_grid, int32_t nb, hipStream_t st);
-hipError_t launch_backward(const EvalArgs& a, int32_t n_sites_grid, hipStream_t st);
 hipError_t launch_transpose_msa(const uint8_t* msa_cm, int32_t B_pad, int32_t N_pad, uint8_t* msaT,
-                                hipStream_t st);
-int32_t mfma_forward_tile_seqs();
-hipError_t launch_forward_mfma(const EvalArgs& a, int32_t n_sites_grid, int32_t npieces,
-                               hipStream_t st);
-hipError_t launch_backward_mfma(const EvalArgs& a, int32_t n_sites_grid, int32_t npieces,
                                 hipStream_t st);
 hipError_t launch_chunk_sort(const uint8_t* msa_cm, int32_t B3, int32_t B_pad, int32_t N, int32_t q,
                              uint16_t* sorted, hipStream_t st);
 int32_t forward_tile_seqs(int32_t nb);
-hipError_t launch_lbfgs(const LbfgsArgs& a, int32_t nblocks, hipStream_t st);
+int32_t forward_resident_blocks(int32_t nb);
+hipError_t launch_forward(const BatchArgs& b, int32_t nb, int32_t nblocks, hipStream_t st);
+int32_t backward_blocks_per_site(int32_t N);
+int32_t backward_resident_blocks();
+hipError_t launch_backward(const BatchArgs& b, int32_t nblocks, hipStream_t st);
+int32_t mfma_forward_tile_seqs();
+int32_t mfma_backward_blocks_per_site(int32_t N, int32_t q);
+int32_t mfma_resident_blocks(int32_t kind, int32_t npieces);
+hipError_t launch_forward_mfma(const BatchArgs& b, int32_t npieces, int32_t nblocks, hipStream_t st);
+hipError_t launch_backward_mfma(const BatchArgs& b, int32_t npieces, int32_t nblocks, hipStream_t st);
+hipError_t launch_lbfgs(const BatchArgs& b, int32_t nblocks, hipStream_t st);
+hipError_t launch_compact(const BatchArgs& b, const SiteState* st_, int32_t* host_count,
+                          unsigned long long* site_evals, hipStream_t st);
+hipError_t launch_list_tables(const BatchArgs& b, const int32_t* list, int32_t first, int32_t n,
+                              int32_t* flag, hipStream_t st);
+hipError_t launch_setup_msa(const BatchArgs& b, int32_t m, const EvalArgs& e, const LbfgsArgs* l,
+                            int32_t base, int32_t N, int32_t nsub_f, int32_t nsub_b,
+                            unsigned long long* site_evals, hipStream_t st);
+hipError_t launch_init_fit(int32_t N, int32_t q, float* Xh, float* XJ, float* Th, float* TJ,
+                           SiteState* st_, int32_t* phase_host, hipStream_t st);
 hipError_t launch_reweight(const uint8_t* msa, int32_t B, int32_t N, int32_t q, double theta,
-                           int32_t uniform, int32_t* m, double* w, double* beff, int32_t* flag,
-                           hipStream_t st);
+                           int32_t uniform, int32_t* m_out, double* w_out, double* beff_out,
+                           int32_t* flag_dev, hipStream_t st);
 hipError_t launch_score(const float* J, int32_t N, int32_t q, double* fn, double* cfn, hipStream_t st);
 hipError_t launch_objgrad_final(const FinalArgs& a, int32_t nsites, hipStream_t st);
 hipError_t launch_check_f32(const float* p, size_t n, int32_t* flag, hipStream_t st);
 hipError_t launch_check_f64(const double* p, size_t n, int32_t* flag, hipStream_t st);
-hipError_t launch_init_fit(int32_t N, int32_t q, float* Xh, float* XJ, float* Th, float* TJ,
-                           SiteState* st_, int32_t* sites, int32_t* n_active, int32_t* phase_host,
-                           hipStream_t st);
-hipError_t launch_compact(int32_t N, const SiteState* st_, int32_t* sites, int32_t* n_active,
-                          int32_t* host_count, unsigned long long* site_evals, hipStream_t st);
-hipError_t launch_zero_u64(unsigned long long* p, hipStream_t st);
 
 }  // namespace plm

@@ -1,0 +1,84 @@
+"""Ragged batches of alignments (plm_fit_batch): one set of launches per
+iteration for all sites of all alignments.
+
+Each alignment's result must be bit-identical to plm_fit on that alignment
+alone (same kernels and per-item arithmetic; the forward tile size is fixed
+so that both use the same tiles), and sampled sites must meet the fit bar of
+the single-alignment tests against the FP64 oracle (couplings within 1e-4,
+strong-convexity certificate)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def plm():
+    import paper_1401_4832_amd as plm
+    return plm
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    # 5 alignments, N in [10, 60], B in [200, 2500]: several tiles, ragged tails
+    return synth.ragged_set(count=5, seed=11, n_range=(10, 60), b_range=(200, 2500), burnin=200,
+                            thin=2, cache=False)
+
+
+def _prep(plm, s):
+    msa = torch.from_numpy(s.msa).to(DEV)
+    m, w, beff = plm.reweight(msa, theta=0.8)
+    return msa, w, beff
+
+
+@pytest.mark.parametrize("path", [0, 2, 3])
+def test_batch_equals_single_alignment_fits(plm, ragged, path):
+    print(f"[case] batch vs single fits path={path} sizes={[s.msa.shape for s in ragged]}", flush=True)
+    items = [_prep(plm, s) for s in ragged]
+    opts = plm.FitOptions(tol=1e-6, path=path, tile_seqs=16)
+    res = plm.fit_batch(items, opts)
+    assert len(res) == len(items)
+    for k, ((msa, w, beff), r) in enumerate(zip(items, res)):
+        one = plm.fit(msa, w, beff, opts)
+        assert torch.equal(one.h, r.h) and torch.equal(one.J, r.J), k
+        assert [x["evaluations"] for x in one.stats] == [x["evaluations"] for x in r.stats], k
+        assert all(x["status"] == "converged" for x in r.stats), k
+
+
+def test_batch_sampled_sites_match_oracle(plm, ragged):
+    print("[case] batch vs oracle on sampled sites", flush=True)
+    items = [_prep(plm, s) for s in ragged]
+    opts = plm.FitOptions(tol=1e-6, path=2)
+    res = plm.fit_batch(items, opts)
+    mu = 2 * min(opts.lambda_h, 0.5 * opts.lambda_J)
+    for k in (0, 3):
+        s = ragged[k]
+        N = s.msa.shape[1]
+        sites = [0, N // 2, N - 1]
+        m_o, w_o, beff_o = oracle.reweight(s.msa, theta=0.8)
+        h_o, J_o, _ = oracle.fit(s.msa, w_o, beff_o, opts.lambda_h, opts.lambda_J, sites=sites, tol=1e-8)
+        h = res[k].h.cpu().numpy().astype(np.float64)
+        J = res[k].J.cpu().numpy().astype(np.float64)
+        for t, r in enumerate(sites):
+            err = max(np.max(np.abs(J[r] - J_o[t])), np.max(np.abs(h[r] - h_o[t])))
+            assert err <= 1e-4, (k, r, err)
+            f, gh, gJ = oracle.site_objgrad(s.msa, r, w_o, beff_o, h[r], J[r], opts.lambda_h, opts.lambda_J)
+            gn = np.sqrt(np.sum(gh ** 2) + np.sum(gJ ** 2)) / beff_o
+            assert gn / mu <= 1e-3, (k, r, gn)
+
+
+def test_batch_of_one_and_errors(plm, ragged):
+    msa, w, beff = _prep(plm, ragged[1])
+    opts = plm.FitOptions(tol=1e-6, tile_seqs=16)
+    a = plm.fit(msa, w, beff, opts)
+    (b,) = plm.fit_batch([(msa, w, beff)], opts)
+    assert torch.equal(a.J, b.J) and torch.equal(a.h, b.h)
+    with pytest.raises(plm.PlmError):
+        plm.fit_batch([(msa, w, beff)], plm.FitOptions(single_site=True))
+    with pytest.raises(ValueError):
+        plm.fit_batch([], opts)
