@@ -4,6 +4,8 @@ One step = reweighting (0.8 identity) + the all-sites batched L-BFGS fit to
 ||grad g_r^reg||_2 <= 1e-6 (every per-site objective+gradient evaluation on the
 GPU) + Ising-gauge/FN/APC scoring, on a seeded synthetic planted-Potts
 alignment of N = 500 columns and B = 50000 rows (q = 21), resident in HBM.
+`--workload ragged16` runs the ragged batch instead: 16 alignments with N in
+[60, 300] and B in [2000, 30000], fitted together by plm_fit_batch.
 
 metric: objective+gradient updates per second, one update being one
 (site r, sequence b, column i, state s) term of the energy sums -- B*N*q per
@@ -13,7 +15,10 @@ single-site GPU path (one site per launch, eager, host sync every iteration;
 sampled and extrapolated), per-kernel roofline of the dominant kernel, and the
 FP64 CPU oracle on a bounded sample of the same evaluations.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+The evaluation schedule (path, forward tile) is the autotuner's choice for
+the workload, timed on the device before the warm-up (--path to force one).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload W] [--path auto|0..3]
 """
 from __future__ import annotations
 
@@ -28,8 +33,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+Q = 21
 # one FP32 add per lane per clock: 256 CUs x 64 lanes x 2.4 GHz
 ALU_ADD_PEAK = 256 * 64 * 2.4e9
+# dense BF16 matrix-core peak of the MI355X
+MFMA_BF16_PEAK = 2.5e15
+PATH_NAMES = {0: "gather_fp32", 1: "mfma_bf16x2", 2: "gather_mfma_fp32", 3: "mfma_fp32"}
+# BF16 pieces of the non-one-hot operand, per path: (forward, backward); 0 = LDS gather/scatter
+PATH_PIECES = {0: (0, 0), 1: (2, 2), 2: (0, 3), 3: (3, 3)}
 
 
 def kernel_source_hash() -> str:
@@ -64,8 +75,8 @@ def cpu_baseline(s, w_np, beff, budget_s=12.0):
 
     import oracle
     threads = oracle._threads()
-    hr = np.zeros((threads, 21))
-    Jr = np.zeros((threads, s.N, 21, 21))
+    hr = np.zeros((threads, Q))
+    Jr = np.zeros((threads, s.N, Q, Q))
     done = 0
     t = time.perf_counter()
     while True:
@@ -75,10 +86,17 @@ def cpu_baseline(s, w_np, beff, budget_s=12.0):
         dt = time.perf_counter() - t
         if dt >= budget_s:
             break
-    units = done * s.B * s.N * 21
+    units = done * s.B * s.N * Q
     return {"value": units / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} site objective+gradient evaluations ({threads} threads, one site per "
-                      f"thread per round) of the N={s.N}, B={s.B} workload at h=J=0, FP64, {dt:.1f} s"}
+                      f"thread per round) of the N={s.N}, B={s.B} alignment at h=J=0, FP64, {dt:.1f} s"}
+
+
+def load_sets(name: str):
+    import synth
+    if name == "ragged16":
+        return synth.ragged_set(16)
+    return [synth.workload(name)]
 
 
 def main():
@@ -87,6 +105,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="potts_n500_b50000")
+    ap.add_argument("--path", default="auto", help="auto (autotuner) or an evaluation path 0..3")
+    ap.add_argument("--tile-seqs", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--plain-sites", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
@@ -103,12 +123,13 @@ def main():
     import torch
 
     import paper_1401_4832_amd as plm
-    import synth
 
     dev = torch.device("cuda:0")
-    s = synth.workload(args.workload)
-    print(f"[bench] workload {args.workload} N={s.N} B={s.B}", file=sys.stderr, flush=True)
-    msa = torch.from_numpy(s.msa).to(dev)
+    sets = load_sets(args.workload)
+    ragged = len(sets) > 1
+    print(f"[bench] workload {args.workload}: " + ", ".join(f"N={s.N} B={s.B}" for s in sets),
+          file=sys.stderr, flush=True)
+    msas = [torch.from_numpy(s.msa).to(dev) for s in sets]
     torch.cuda.synchronize()
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -117,14 +138,32 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    opts = plm.FitOptions(tol=args.tol, timing=True)
+    def weights():
+        return [plm.reweight(m, theta=0.8) for m in msas]
+
+    # the schedule: the autotuner's choice for this workload (outside the timed region)
+    tuned = None
+    if args.path == "auto":
+        items = [(m, w, beff) for m, (_, w, beff) in zip(msas, weights())]
+        t = time.perf_counter()
+        tuned = plm.autotune.choose(items, plm.FitOptions(tol=args.tol), Q)
+        print(f"[bench] schedule path={tuned['path']} tile_seqs={tuned['tile_seqs']} "
+              f"({time.perf_counter() - t:.1f} s to choose)", file=sys.stderr, flush=True)
+        path, tile = int(tuned["path"]), int(tuned["tile_seqs"])
+    else:
+        path, tile = int(args.path), args.tile_seqs
+    opts = plm.FitOptions(tol=args.tol, path=path, tile_seqs=tile, timing=True)
 
     def step():
-        m, w, beff = plm.reweight(msa, theta=0.8)
-        res = plm.fit(msa, w, beff, opts)
-        fn, cfn = plm.score(res.J)
+        ws = weights()
+        if ragged:
+            res = plm.fit_batch([(m, w, beff) for m, (_, w, beff) in zip(msas, ws)], opts)
+        else:
+            _, w, beff = ws[0]
+            res = [plm.fit(msas[0], w, beff, opts)]
+        cfn = [plm.score(r.J)[1] for r in res]
         torch.cuda.synchronize()
-        return w, beff, res, cfn
+        return ws, res, cfn
 
     for k in range(args.warmup):
         t = time.perf_counter()
@@ -144,50 +183,72 @@ def main():
         tm = plm.last_fit_timing(dev)
         for key in kt:
             kt[key] += tm[key]
+        ws, res, _ = last
+        units = sum(sum(st["evaluations"] for st in r.stats) * s.B * s.N * Q for r, s in zip(res, sets))
         tot_time += dt
-        tot_units += tm["site_evals"] * s.B * s.N * 21
+        tot_units += units
         print(f"[bench] step {k} {dt:.2f} s, site evals {tm['site_evals']}, "
               f"fwd {tm['forward_ms']:.0f} ms bwd {tm['backward_ms']:.0f} ms lbfgs {tm['lbfgs_ms']:.0f} ms",
               file=sys.stderr, flush=True)
-    w, beff, res, cfn = last
+    ws, res, cfn = last
     statuses = {}
-    for st in res.stats:
-        statuses[st["status"]] = statuses.get(st["status"], 0) + 1
-    gmax = max(st["gnorm"] for st in res.stats)
+    for r in res:
+        for st in r.stats:
+            statuses[st["status"]] = statuses.get(st["status"], 0) + 1
+    gmax = max(st["gnorm"] for r in res for st in r.stats)
     mu = 2 * min(0.01, 0.005)
 
     # dominant kernel: the one with the largest share of device time
     shares = {"backward": kt["backward_ms"], "forward": kt["forward_ms"], "lbfgs": kt["lbfgs_ms"]}
     dom = max(shares, key=shares.get)
-    adds = kt["site_evals"] * s.B * s.N * 21  # one FP32 add per update in either kernel
+    units_all = tot_units  # over the timed steps, like the kernel times
     roofline = None
     if dom in ("backward", "forward"):
+        np_dom = PATH_PIECES[path][0 if dom == "forward" else 1]
         t_dom = shares[dom] * 1e-3
-        achieved = adds / t_dom / 1e12
-        tb = measured_traffic(dom, args.workload)
-        roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_ADD_PEAK / 1e12, "unit": "TFLOP/s",
-                    "frac": achieved * 1e12 / ALU_ADD_PEAK, "traffic": tb,
-                    "kernel": dom, "launches": kt["iterations"],
-                    "avg_launch_ms": shares[dom] / max(1, kt["iterations"])}
+        if np_dom:
+            # dense matrix-core flops of the one-hot product: q MACs per unit and piece
+            flops = units_all * 2 * Q * np_dom
+            kname = f"{dom}_mfma"
+            roofline = {"bound": "mfma", "achieved": flops / t_dom / 1e12, "peak": MFMA_BF16_PEAK / 1e12,
+                        "unit": "TFLOP/s", "frac": flops / t_dom / MFMA_BF16_PEAK,
+                        "flops_per_unit": 2 * Q * np_dom}
+        else:
+            kname = dom
+            adds = units_all  # one FP32 add per update in the gather or the scatter
+            roofline = {"bound": "alu", "achieved": adds / t_dom / 1e12, "peak": ALU_ADD_PEAK / 1e12,
+                        "unit": "TFLOP/s", "frac": adds / t_dom / ALU_ADD_PEAK, "flops_per_unit": 1}
+        roofline.update({"traffic": measured_traffic(kname, args.workload), "kernel": kname,
+                         "launches": kt["iterations"], "avg_launch_ms": shares[dom] / max(1, kt["iterations"])})
 
     plain = None
-    if not args.no_plain:
-        po = plm.FitOptions(tol=args.tol, single_site=True, site_limit=args.plain_sites)
+    if not args.no_plain and not ragged:
+        _, w, beff = ws[0]
+        po = plm.FitOptions(tol=args.tol, path=path, tile_seqs=tile, single_site=True, site_limit=args.plain_sites)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        plm.fit(msa, w, beff, po)
+        plm.fit(msas[0], w, beff, po)
         torch.cuda.synchronize()
         dtp = time.perf_counter() - t
-        est = dtp / args.plain_sites * s.N
+        est = dtp / args.plain_sites * sets[0].N
         plain = {"sites_sampled": args.plain_sites, "seconds_sampled": dtp,
                  "time_to_fit_s_extrapolated": est,
                  "speedup_batched_vs_plain": est / (tot_time / args.steps)}
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(s, w.cpu().numpy(), float(beff.item()))
+        k = max(range(len(sets)), key=lambda j: sets[j].B * sets[j].N ** 2)
+        _, w, beff = ws[k]
+        cpu = cpu_baseline(sets[k], w.cpu().numpy(), float(beff.item()))
 
     ms_per_step = tot_time / args.steps * 1e3
+    if ragged:
+        cfg = {"workload": args.workload, "alignments": len(sets), "N": [s.N for s in sets],
+               "B": [s.B for s in sets]}
+    else:
+        cfg = {"workload": args.workload, "N": sets[0].N, "B": sets[0].B}
+    cfg.update({"q": Q, "theta": 0.8, "lambda_h": 0.01, "lambda_J": 0.01, "tol": args.tol,
+                "path": PATH_NAMES[path], "tile_seqs": tile, "schedule": "autotuned" if tuned else "fixed"})
     line = {
         "metric": "plm objective+gradient updates/s (B*N^2*q, active sites) and time-to-fit at <=1e-4 vs plain",
         "value": tot_units / tot_time,
@@ -199,10 +260,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (FP64 reductions and optimiser)",
+        "dtype": "f32 (FP64 reductions and optimiser)" if path != 1 else "bf16x2 operands, f32 accumulate",
         "data": "synthetic planted-Potts alignment (seeded Gibbs sampling)",
-        "config": {"workload": args.workload, "N": s.N, "B": s.B, "q": 21, "theta": 0.8,
-                   "lambda_h": 0.01, "lambda_J": 0.01, "tol": args.tol, "path": "gather_fp32"},
+        "config": cfg,
         "time_to_fit_s": ms_per_step / 1e3,
         "fit": {"site_evals": kt["site_evals"], "iterations": kt["iterations"], "status": statuses,
                 "max_gnorm": gmax, "coupling_error_bound_l2": gmax / mu},
@@ -211,6 +271,8 @@ def main():
         "plain_single_site": plain,
         "cpu_baseline": cpu,
     }
+    if tuned:
+        line["tuning"] = {"candidates": tuned.get("candidates", [])}
     print(json.dumps(line))
 
 

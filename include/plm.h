@@ -210,6 +210,27 @@ size_t plm_fit_batch_workspace_bytes(const plm_msa_desc *descs, int32_t n_msas, 
 int plm_fit_batch(plm_ctx *ctx, const plm_msa_desc *descs, int32_t n_msas, int32_t q,
                   const plm_fit_opts *opts, void *workspace, size_t workspace_bytes);
 
+/* ---- Autotuning ---------------------------------------------------------------
+ * Times one all-sites objective+gradient evaluation of the batch (descs as in
+ * plm_fit_batch, evaluated at each alignment's (h_io, J_io), whose diagonal
+ * blocks are zeroed) for every candidate schedule: each evaluation path
+ * (PLM_PATH_MFMA_BF16X2 only if fp32_only == 0) and, for the paths with the
+ * LDS-gather forward, forward tiles of 16, 32 and 64 rows per wave.  Writes
+ * up to max_out results, fastest first, and their number to *n_out; out[0]'s
+ * path and tile_seqs are the schedule to put into plm_fit_opts.  Each time is
+ * the shortest of three runs after one warm-up (HIP events on the fit's
+ * stream).  Workspace: plm_fit_batch_workspace_bytes.  The choice depends on
+ * the device's timing, so it is the caller's to cache (per size bucket). */
+typedef struct {
+  int32_t path;       /* PLM_PATH_* */
+  int32_t tile_seqs;  /* forward tile rows per wave; 0 for the MFMA forward */
+  double eval_ms;     /* one all-sites evaluation, forward and backward */
+} plm_tune_result;
+
+int plm_tune(plm_ctx *ctx, const plm_msa_desc *descs, int32_t n_msas, int32_t q,
+             const plm_fit_opts *opts, int32_t fp32_only, void *workspace, size_t workspace_bytes,
+             plm_tune_result *out, int32_t max_out, int32_t *n_out);
+
 /* ---- Scoring (sec. 3.4 steps 4-6) ------------------------------------------
  * For every pair i != j: both estimates are moved to the Ising gauge
  * (eq. gauge_change2: subtract row and column means over all q states, add

@@ -78,6 +78,14 @@ class MsaDesc(ctypes.Structure):
     ]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [
+        ("path", ctypes.c_int32),
+        ("tile_seqs", ctypes.c_int32),
+        ("eval_ms", ctypes.c_double),
+    ]
+
+
 class PlmError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libplm status {code}: {msg}")
@@ -115,6 +123,8 @@ def lib():
             "plm_fit_batch_workspace_bytes": (SZ, [ctypes.POINTER(MsaDesc), I32, I32, ctypes.POINTER(FitOpts)]),
             "plm_fit_batch": (ctypes.c_int, [P, ctypes.POINTER(MsaDesc), I32, I32, ctypes.POINTER(FitOpts),
                                              P, SZ]),
+            "plm_tune": (ctypes.c_int, [P, ctypes.POINTER(MsaDesc), I32, I32, ctypes.POINTER(FitOpts), I32, P,
+                                        SZ, ctypes.POINTER(TuneResult), I32, ctypes.POINTER(I32)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -129,4 +139,4 @@ def exported_symbols():
     return ["plm_ctx_create", "plm_ctx_destroy", "plm_last_error", "plm_status_string", "plm_sync",
             "plm_reweight", "plm_objgrad_workspace_bytes", "plm_objgrad", "plm_fit_opts_default",
             "plm_fit_workspace_bytes", "plm_fit", "plm_score", "plm_fit_last_timing",
-            "plm_fit_batch_workspace_bytes", "plm_fit_batch"]
+            "plm_fit_batch_workspace_bytes", "plm_fit_batch", "plm_tune"]

@@ -135,6 +135,8 @@ class FitOptions:
     tile_seqs: int = 0
     site_limit: int = 0
     timing: bool = False
+    # pick path and tile_seqs with the autotuner (cached per size bucket)
+    autotune: bool = False
 
     def to_c(self) -> L.FitOpts:
         o = L.FitOpts()
@@ -164,6 +166,9 @@ class FitResult:
 def fit(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None) -> FitResult:
     """Minimise every site's g_r^reg (sec. 3.4 step 3) from (h0, J0) (zeros by default)."""
     opts = opts or FitOptions()
+    if opts.autotune and not opts.single_site:
+        from . import autotune
+        opts = autotune.tuned_options([(msa, w, beff)], opts, 21 if h0 is None else h0.shape[1])
     dev = msa.device
     _dev_tensor(msa, torch.uint8, dev, "msa")
     B, N = msa.shape
@@ -190,19 +195,12 @@ def _stats_list(stats):
                  f=s.f, gnorm=s.gnorm) for s in stats]
 
 
-def fit_batch(items, opts: FitOptions | None = None, q: int = 21):
-    """Fit a ragged batch of alignments in one set of launches per iteration.
-
-    items: sequence of (msa, w, beff) or (msa, w, beff, h0, J0) on one device.
-    Returns one FitResult per alignment, in the order given; each equals what
-    fit() gives for that alignment alone."""
-    opts = opts or FitOptions()
-    if not items:
-        raise ValueError("empty batch")
+def _batch_descs(items, q):
+    """C descriptors of a batch; returns (descs, [(h, J, stats)])."""
     dev = items[0][0].device
     n = len(items)
     descs = (L.MsaDesc * n)()
-    keep, out = [], []
+    out = []
     for k, it in enumerate(items):
         msa, w, beff = it[0], it[1], it[2]
         _dev_tensor(msa, torch.uint8, dev, f"msa[{k}]")
@@ -216,8 +214,25 @@ def fit_batch(items, opts: FitOptions | None = None, q: int = 21):
         d.msa, d.B, d.N, d.w, d.beff = msa.data_ptr(), B, N, w.data_ptr(), beff.data_ptr()
         d.h_io, d.J_io = h.data_ptr(), J.data_ptr()
         d.stats_out = ctypes.cast(stats, ctypes.POINTER(L.SiteStats))
-        keep.append(stats)
         out.append((h, J, stats))
+    return descs, out
+
+
+def fit_batch(items, opts: FitOptions | None = None, q: int = 21):
+    """Fit a ragged batch of alignments in one set of launches per iteration.
+
+    items: sequence of (msa, w, beff) or (msa, w, beff, h0, J0) on one device.
+    Returns one FitResult per alignment, in the order given; each equals what
+    fit() gives for that alignment alone (with the same tile_seqs)."""
+    opts = opts or FitOptions()
+    if not items:
+        raise ValueError("empty batch")
+    if opts.autotune:
+        from . import autotune
+        opts = autotune.tuned_options(items, opts, q)
+    dev = items[0][0].device
+    n = len(items)
+    descs, out = _batch_descs(items, q)
     co = opts.to_c()
     nbytes = L.lib().plm_fit_batch_workspace_bytes(descs, n, q, ctypes.byref(co))
     if nbytes == 0:
@@ -227,6 +242,30 @@ def fit_batch(items, opts: FitOptions | None = None, q: int = 21):
     rc = _check(L.lib().plm_fit_batch(ctx, descs, n, q, ctypes.byref(co), _ptr(ws), ws.numel()), ctx)
     del ws
     return [FitResult(h, J, _stats_list(st), rc) for (h, J, st) in out]
+
+
+def tune(items, opts: FitOptions | None = None, q: int = 21, fp32_only: bool = True) -> list:
+    """Time every candidate schedule on the batch (plm_tune); fastest first."""
+    opts = opts or FitOptions()
+    if not items:
+        raise ValueError("empty batch")
+    dev = items[0][0].device
+    descs, _ = _batch_descs(items, q)
+    co = opts.to_c()
+    co.single_site = 0
+    n = len(items)
+    nbytes = L.lib().plm_fit_batch_workspace_bytes(descs, n, q, ctypes.byref(co))
+    if nbytes == 0:
+        raise L.PlmError(L.PLM_E_INVALID, "invalid sizes or options")
+    ws = workspace(nbytes, dev)
+    res = (L.TuneResult * 16)()
+    nout = ctypes.c_int32(0)
+    ctx = context(dev)
+    _check(L.lib().plm_tune(ctx, descs, n, q, ctypes.byref(co), int(bool(fp32_only)), _ptr(ws), ws.numel(),
+                            res, 16, ctypes.byref(nout)), ctx)
+    del ws
+    return [dict(path=res[k].path, tile_seqs=res[k].tile_seqs, eval_ms=res[k].eval_ms)
+            for k in range(nout.value)]
 
 
 def last_fit_timing(device=None) -> dict:

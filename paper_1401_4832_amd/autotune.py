@@ -1,0 +1,81 @@
+"""Cache of the autotuner's choices: the fastest evaluation schedule (path and
+forward tile size) per size bucket of a batch.
+
+The timing itself runs in the library (plm_tune: every candidate schedule on
+the caller's own alignments, HIP events on the device).  This module keys the
+result by device, q, precision class and the (N, B) bucket of every alignment
+-- ceil(log2 N), ceil(log2 B) -- and keeps it in a JSON file
+($PLM_TUNE_CACHE, else ~/.cache/paper_1401_4832_amd/tune.json), so that later
+fits of similar sizes reuse it without timing again."""
+from __future__ import annotations
+
+import dataclasses
+import json
+import math
+import os
+
+import torch
+
+from . import api
+
+
+def cache_path() -> str:
+    return os.environ.get("PLM_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_1401_4832_amd", "tune.json"))
+
+
+def bucket(N: int, B: int) -> tuple:
+    return (int(math.ceil(math.log2(max(N, 2)))), int(math.ceil(math.log2(max(B, 2)))))
+
+
+def _arch(dev) -> str:
+    return getattr(torch.cuda.get_device_properties(dev), "gcnArchName", "gpu").split(":")[0]
+
+
+def key(items, q: int, fp32_only: bool) -> str:
+    arch = _arch(items[0][0].device)
+    bs = sorted(bucket(int(it[0].shape[1]), int(it[0].shape[0])) for it in items)
+    return f"{arch}|q{q}|{'fp32' if fp32_only else 'any'}|" + ",".join(f"{n}x{b}" for n, b in bs)
+
+
+def load(path: str | None = None) -> dict:
+    path = path or cache_path()
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def store(d: dict, path: str | None = None) -> None:
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = f"{path}.tmp{os.getpid()}"
+    with open(tmp, "w") as fh:
+        json.dump(d, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def choose(items, opts=None, q: int = 21, fp32_only: bool = True, path: str | None = None,
+           retune: bool = False) -> dict:
+    """The cached schedule for this batch's bucket, timing the candidates on
+    the batch itself on a miss (or when retune is set)."""
+    opts = opts or api.FitOptions()
+    k = key(items, q, fp32_only)
+    d = load(path)
+    if not retune and k in d:
+        return d[k]
+    res = api.tune(items, opts, q, fp32_only)
+    entry = dict(path=res[0]["path"], tile_seqs=res[0]["tile_seqs"], eval_ms=res[0]["eval_ms"],
+                 candidates=res)
+    d = load(path)  # re-read: another process may have written meanwhile
+    d[k] = entry
+    store(d, path)
+    return entry
+
+
+def tuned_options(items, opts, q: int = 21):
+    """opts with path and tile_seqs taken from the tuner (autotune cleared)."""
+    ch = choose(items, opts, q)
+    return dataclasses.replace(opts, path=int(ch["path"]), tile_seqs=int(ch["tile_seqs"]), autotune=False)

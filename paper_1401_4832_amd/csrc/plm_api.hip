@@ -462,9 +462,22 @@ size_t fit_layout(const plm_msa_desc* d, int32_t n, int32_t q, const plm_fit_opt
   return rup(bp.off, 256);
 }
 
-// The fit of a batch of alignments (plm_fit is a batch of one).
-int run_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_fit_opts* o,
-            void* ws, size_t ws_bytes) {
+// Everything the iteration needs once a batch is set up on the device.
+struct Prep {
+  PathSpec ps;
+  int32_t nb, total;
+  Grids g;
+  Tables t;
+  BatchArgs b;
+  std::vector<int32_t> ord, base;
+  hipStream_t st;
+};
+
+// Validate, lay out the workspace, and set up every alignment of the batch on
+// the context's private stream: padded symbols, trial point, optimiser states,
+// descriptors, and the tables with every site active.  Synchronous.
+int prepare_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_fit_opts* o,
+                void* ws, size_t ws_bytes, Prep* P) {
   if (!fit_opts_ok(o)) return set_err(c, PLM_E_INVALID, "invalid fit options");
   PathSpec ps;
   if (!path_spec(o->path, &ps))
@@ -488,7 +501,6 @@ int run_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_f
   rc = ensure_pin(c, 2 + (size_t)total);
   if (rc) return rc;
   int32_t* phase_host_dev = c->pin_dev + 2;
-  volatile int32_t* phase_host = c->pin + 2;
   std::vector<FitBufs> fb;
   Tables t;
   fit_layout(d, n, q, o, (char*)ws, &fb, &t);
@@ -532,7 +544,33 @@ int run_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_f
   HIPCHK(c, hipStreamSynchronize(st));
   rc = flags_status(c);
   if (rc) return rc;
-  const Grids g = eval_grids(c, ps, nb);
+  P->ps = ps;
+  P->nb = nb;
+  P->total = total;
+  P->g = eval_grids(c, ps, nb);
+  P->t = t;
+  P->b = b;
+  P->ord = ord;
+  P->base = base;
+  P->st = st;
+  return PLM_OK;
+}
+
+// The fit of a batch of alignments (plm_fit is a batch of one).
+int run_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_fit_opts* o,
+            void* ws, size_t ws_bytes) {
+  Prep P;
+  int rc = prepare_fit(c, d, n, q, o, ws, ws_bytes, &P);
+  if (rc) return rc;
+  const PathSpec& ps = P.ps;
+  const int32_t nb = P.nb, total = P.total;
+  const Grids& g = P.g;
+  const Tables& t = P.t;
+  const BatchArgs& b = P.b;
+  const std::vector<int32_t>& ord = P.ord;
+  const std::vector<int32_t>& base = P.base;
+  hipStream_t st = P.st;
+  volatile int32_t* phase_host = c->pin + 2;
 
   const int64_t cap = (int64_t)o->max_iter * (o->max_linesearch + 2) + 16;
   if (o->single_site) {
@@ -687,6 +725,65 @@ int plm_fit_batch(plm_ctx* c, const plm_msa_desc* descs, int32_t n_msas, int32_t
   if (!descs || !o || n_msas < 1) return set_err(c, PLM_E_INVALID, "null pointer or empty batch");
   if (o->single_site) return set_err(c, PLM_E_INVALID, "single_site is not available for batches");
   return run_fit(c, descs, n_msas, q, o, ws, ws_bytes);
+}
+
+int plm_tune(plm_ctx* c, const plm_msa_desc* descs, int32_t n_msas, int32_t q, const plm_fit_opts* o,
+             int32_t fp32_only, void* ws, size_t ws_bytes, plm_tune_result* out, int32_t max_out,
+             int32_t* n_out) {
+  if (!c) return PLM_E_INVALID;
+  if (!descs || !o || n_msas < 1 || !out || max_out < 1 || !n_out)
+    return set_err(c, PLM_E_INVALID, "null pointer or empty batch");
+  if (o->single_site) return set_err(c, PLM_E_INVALID, "single_site cannot be tuned");
+  struct Cand {
+    int32_t path, tile;
+  };
+  std::vector<Cand> cands;
+  const int32_t paths[] = {PLM_PATH_GATHER_MFMA_FP32, PLM_PATH_GATHER_FP32, PLM_PATH_MFMA_FP32,
+                           PLM_PATH_MFMA_BF16X2};
+  for (int32_t p : paths) {
+    if (fp32_only && p == PLM_PATH_MFMA_BF16X2) continue;
+    PathSpec ps;
+    path_spec(p, &ps);
+    if (ps.fwd_np) {
+      cands.push_back({p, 0});
+    } else {
+      for (int32_t tl : {16, 32, 64}) cands.push_back({p, tl});
+    }
+  }
+  std::vector<plm_tune_result> res;
+  for (const Cand& cd : cands) {
+    plm_fit_opts oc = *o;
+    oc.path = cd.path;
+    oc.tile_seqs = cd.tile;
+    oc.single_site = 0;
+    Prep P;
+    int rc = prepare_fit(c, descs, n_msas, q, &oc, ws, ws_bytes, &P);
+    if (rc) return rc;
+    // one untimed and three timed all-sites evaluations; the shortest counts
+    float best = 1e30f;
+    for (int rep = 0; rep < 4; ++rep) {
+      HIPCHK(c, launch_compact(P.b, P.t.st, nullptr, nullptr, P.st));  // clears the queues
+      HIPCHK(c, hipEventRecord(c->ev[0], P.st));
+      HIPCHK(c, eval_forward(P.ps, P.b, P.nb, P.g, P.st));
+      HIPCHK(c, eval_backward(P.ps, P.b, P.g, P.st));
+      HIPCHK(c, hipEventRecord(c->ev[1], P.st));
+      HIPCHK(c, hipStreamSynchronize(P.st));
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+      if (rep > 0 && ms < best) best = ms;
+    }
+    plm_tune_result r;
+    r.path = cd.path;
+    r.tile_seqs = cd.tile == 0 ? 0 : pick_nb(0, cd.tile);
+    r.eval_ms = best;
+    res.push_back(r);
+  }
+  std::stable_sort(res.begin(), res.end(),
+                   [](const plm_tune_result& x, const plm_tune_result& y) { return x.eval_ms < y.eval_ms; });
+  const int32_t k = (int32_t)res.size() < max_out ? (int32_t)res.size() : max_out;
+  for (int32_t j = 0; j < k; ++j) out[j] = res[j];
+  *n_out = k;
+  return PLM_OK;
 }
 
 int plm_fit_last_timing(const plm_ctx* c, plm_fit_timing* out) {

@@ -1,9 +1,10 @@
 """Profiling helpers for the benchmark's roofline numbers.
 
-python -m paper_1401_4832_amd.profiling drive [workload]
-    one reweight + one all-sites objective/gradient evaluation on the workload,
-    then a 1 GiB device-to-device copy (the calibration kernel for the HBM
-    byte counters); the program rocprofv3 runs for kernel traces and counters.
+python -m paper_1401_4832_amd.profiling drive [workload] [path]
+    one reweight + one all-sites objective/gradient evaluation on the workload
+    (evaluation path 2 unless given), then a 1 GiB device-to-device copy (the
+    calibration kernel for the HBM byte counters); the program rocprofv3 runs
+    for kernel traces and counters.
 python -m paper_1401_4832_amd.profiling stats <kernel_stats.csv> <out.md> <command...>
     short markdown summary of a rocprofv3 --stats kernel table.
 python -m paper_1401_4832_amd.profiling traffic <fetch.csv> <write.csv> <workload> <out_prefix>
@@ -22,8 +23,8 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 1 << 30
-KERNELS = {"forward": "fwd_kernel", "backward": "bwd_kernel", "lbfgs": "lbfgs_kernel",
-           "reweight": "identity_kernel"}
+KERNELS = {"forward": "fwd_kernel", "backward": "bwd_kernel", "forward_mfma": "fwd_mfma_kernel",
+           "backward_mfma": "bwd_mfma_kernel", "lbfgs": "lbfgs_kernel", "reweight": "identity_kernel"}
 
 
 def source_hash() -> str:
@@ -34,7 +35,7 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def drive(workload: str = "potts_n500_b50000"):
+def drive(workload: str = "potts_n500_b50000", path: str = "2"):
     sys.path.insert(0, ROOT)
     import numpy as np
     import torch
@@ -49,7 +50,7 @@ def drive(workload: str = "potts_n500_b50000"):
     rng = np.random.default_rng(0)
     h = torch.from_numpy((0.1 * rng.standard_normal((N, q))).astype(np.float32)).to(dev)
     J = torch.from_numpy((0.1 * rng.standard_normal((N, N, q, q))).astype(np.float32)).to(dev)
-    f, gh, gJ = plm.objgrad(msa, w, beff, h, J)
+    f, gh, gJ = plm.objgrad(msa, w, beff, h, J, path=int(path))
     plm.sync(dev)
     del gJ, J
     a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -122,7 +123,7 @@ def traffic(fetch_csv: str, write_csv: str, workload: str, out_prefix: str):
 if __name__ == "__main__":
     cmd = sys.argv[1]
     if cmd == "drive":
-        drive(*(sys.argv[2:3]))
+        drive(*(sys.argv[2:4]))
     elif cmd == "stats":
         stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
     elif cmd == "traffic":

@@ -1,0 +1,51 @@
+"""Autotuner cache logic on the CPU: buckets, keys, the JSON store, and that a
+cached choice is used without timing again."""
+import dataclasses
+
+import pytest
+import torch
+
+from paper_1401_4832_amd import api, autotune
+
+
+def test_bucket_edges():
+    assert autotune.bucket(40, 500) == (6, 9)
+    assert autotune.bucket(64, 512) == (6, 9)
+    assert autotune.bucket(65, 513) == (7, 10)
+    assert autotune.bucket(2, 1) == (1, 1)
+
+
+def test_key_is_order_free_and_separates_classes(monkeypatch):
+    monkeypatch.setattr(autotune, "_arch", lambda dev: "gfx950")
+    a = torch.zeros(500, 40, dtype=torch.uint8)
+    b = torch.zeros(5000, 120, dtype=torch.uint8)
+    k1 = autotune.key([(a,), (b,)], 21, True)
+    k2 = autotune.key([(b,), (a,)], 21, True)
+    assert k1 == k2 == "gfx950|q21|fp32|6x9,7x13"
+    assert autotune.key([(a,)], 21, False) != autotune.key([(a,)], 21, True)
+
+
+def test_store_load_roundtrip_and_cached_choice(monkeypatch, tmp_path):
+    path = str(tmp_path / "sub" / "tune.json")
+    monkeypatch.setattr(autotune, "_arch", lambda dev: "gfx950")
+    a = torch.zeros(500, 40, dtype=torch.uint8)
+    k = autotune.key([(a,)], 21, True)
+    autotune.store({k: dict(path=2, tile_seqs=32, eval_ms=1.5, candidates=[])}, path)
+    assert autotune.load(path)[k]["tile_seqs"] == 32
+
+    def no_timing(*args, **kw):
+        raise AssertionError("a cached bucket must not be timed again")
+    monkeypatch.setattr(api, "tune", no_timing)
+    ch = autotune.choose([(a,)], api.FitOptions(), 21, True, path=path)
+    assert (ch["path"], ch["tile_seqs"]) == (2, 32)
+    monkeypatch.setenv("PLM_TUNE_CACHE", path)
+    o = autotune.tuned_options([(a,)], api.FitOptions(autotune=True, path=0), 21)
+    assert (o.path, o.tile_seqs, o.autotune) == (2, 32, False)
+    assert dataclasses.replace(o, path=0).path == 0
+
+
+def test_load_tolerates_missing_and_corrupt_files(tmp_path):
+    assert autotune.load(str(tmp_path / "none.json")) == {}
+    bad = tmp_path / "bad.json"
+    bad.write_text("{not json")
+    assert autotune.load(str(bad)) == {}

@@ -82,3 +82,20 @@ def test_batch_of_one_and_errors(plm, ragged):
         plm.fit_batch([(msa, w, beff)], plm.FitOptions(single_site=True))
     with pytest.raises(ValueError):
         plm.fit_batch([], opts)
+
+
+def test_tuner_times_every_candidate_and_autotuned_fit_converges(plm, ragged, tmp_path, monkeypatch):
+    print("[case] autotune on the ragged batch", flush=True)
+    monkeypatch.setenv("PLM_TUNE_CACHE", str(tmp_path / "tune.json"))
+    items = [_prep(plm, s) for s in ragged]
+    res = plm.tune(items, plm.FitOptions(), fp32_only=True)
+    # paths 2 and 0 with three forward tiles each, path 3 with the MFMA forward
+    assert len(res) == 7
+    assert sorted((r["path"], r["tile_seqs"]) for r in res) == sorted(
+        [(2, 16), (2, 32), (2, 64), (0, 16), (0, 32), (0, 64), (3, 0)])
+    assert all(r["eval_ms"] > 0 for r in res)
+    assert [r["eval_ms"] for r in res] == sorted(r["eval_ms"] for r in res)
+    out = plm.fit_batch(items, plm.FitOptions(tol=1e-6, autotune=True))
+    assert all(x["status"] == "converged" for r in out for x in r.stats)
+    ch = plm.autotune.choose(items)  # now cached
+    assert (ch["path"], ch["tile_seqs"]) in [(r["path"], r["tile_seqs"]) for r in res]
