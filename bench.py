@@ -18,7 +18,7 @@ FP64 CPU oracle on a bounded sample of the same evaluations.
 The evaluation schedule (path, forward tile) is the autotuner's choice for
 the workload, timed on the device before the warm-up (--path to force one).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload W] [--path auto|0..3]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload W] [--path auto|0..4]
 """
 from __future__ import annotations
 
@@ -38,9 +38,10 @@ Q = 21
 ALU_ADD_PEAK = 256 * 64 * 2.4e9
 # dense BF16 matrix-core peak of the MI355X
 MFMA_BF16_PEAK = 2.5e15
-PATH_NAMES = {0: "gather_fp32", 1: "mfma_bf16x2", 2: "gather_mfma_fp32", 3: "mfma_fp32"}
-# BF16 pieces of the non-one-hot operand, per path: (forward, backward); 0 = LDS gather/scatter
-PATH_PIECES = {0: (0, 0), 1: (2, 2), 2: (0, 3), 3: (3, 3)}
+PATH_NAMES = {0: "gather_fp32", 1: "mfma_bf16x2", 2: "gather_mfma_fp32", 3: "mfma_fp32",
+              4: "gather_mfma_f16x2"}
+# 16-bit pieces of the non-one-hot operand, per path: (forward, backward); 0 = LDS gather/scatter
+PATH_PIECES = {0: (0, 0), 1: (2, 2), 2: (0, 3), 3: (3, 3), 4: (0, 2)}
 
 
 def kernel_source_hash() -> str:
@@ -105,7 +106,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="potts_n500_b50000")
-    ap.add_argument("--path", default="auto", help="auto (autotuner) or an evaluation path 0..3")
+    ap.add_argument("--path", default="auto", help="auto (autotuner) or an evaluation path 0..4")
     ap.add_argument("--tile-seqs", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--plain-sites", type=int, default=4)
@@ -210,6 +211,7 @@ def main():
             # dense matrix-core flops of the one-hot product: q MACs per unit and piece
             flops = units_all * 2 * Q * np_dom
             kname = f"{dom}_mfma"
+            # BF16 and FP16 dense matrix-core peaks are the same on this chip
             roofline = {"bound": "mfma", "achieved": flops / t_dom / 1e12, "peak": MFMA_BF16_PEAK / 1e12,
                         "unit": "TFLOP/s", "frac": flops / t_dom / MFMA_BF16_PEAK,
                         "flops_per_unit": 2 * Q * np_dom}
@@ -260,7 +262,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (FP64 reductions and optimiser)" if path != 1 else "bf16x2 operands, f32 accumulate",
+        "dtype": {1: "bf16x2 operands, f32 accumulate", 4: "f32 forward, f16x2 gradient operands (22-bit), "
+                  "FP64 reductions and optimiser"}.get(path, "f32 (FP64 reductions and optimiser)"),
         "data": "synthetic planted-Potts alignment (seeded Gibbs sampling)",
         "config": cfg,
         "time_to_fit_s": ms_per_step / 1e3,

@@ -70,6 +70,10 @@ extern "C" {
                                   product with three-piece residuals (24 significant bits, the
                                   FP32 significand) */
 #define PLM_PATH_MFMA_FP32 3   /* both directions as MFMA products with three-piece operands */
+#define PLM_PATH_GATHER_MFMA_F16X2 4 /* energies by LDS gather; coupling gradient as an MFMA
+                                  product with FP16 hi/lo pieces of R * 2^12 (22 significant
+                                  bits: |dR| <= 2^-22 |R|; the scaling keeps the low piece out
+                                  of the FP16 subnormal range) */
 
 typedef struct plm_ctx plm_ctx;
 

@@ -7,9 +7,9 @@ from .autograd import PLMObjective, plm_objective
 from . import autotune
 from .api import (FitOptions, FitResult, context, fit, fit_batch, last_fit_timing, objgrad, reweight, score,
                   sync, tune, workspace)
-from ._lib import (PATH_GATHER_FP32, PATH_GATHER_MFMA_FP32, PATH_MFMA_BF16X2, PATH_MFMA_FP32,
-                   PlmError)
+from ._lib import (PATH_GATHER_FP32, PATH_GATHER_MFMA_F16X2, PATH_GATHER_MFMA_FP32, PATH_MFMA_BF16X2,
+                   PATH_MFMA_FP32, PlmError)
 
 __all__ = ["PLMObjective", "plm_objective", "FitOptions", "FitResult", "context", "fit", "fit_batch",
            "last_fit_timing", "objgrad", "reweight", "score", "sync", "tune", "autotune", "workspace", "PATH_GATHER_FP32", "PATH_GATHER_MFMA_FP32", "PATH_MFMA_BF16X2",
-           "PATH_MFMA_FP32", "PlmError"]
+           "PATH_MFMA_FP32", "PATH_GATHER_MFMA_F16X2", "PlmError"]

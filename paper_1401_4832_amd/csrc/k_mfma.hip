@@ -25,7 +25,14 @@
 namespace plm {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// FP16 pieces of the residuals are taken of R * 2^12 (|R| <= 1, so no
+// overflow, and the low piece stays clear of the FP16 subnormal range); the
+// FP64 sums are scaled back by 2^-12, exactly.
+constexpr float kF16Scale = 4096.f;
+constexpr double kF16Unscale = 1.0 / 4096.0;
 
 constexpr int kMWaves = 8;
 constexpr int kMThreads = kMWaves * 64;
@@ -49,20 +56,21 @@ __device__ inline uint32_t f2bf(float f) {  // round to nearest even (finite inp
 }
 __device__ inline float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
 
-// one-hot of 8 symbols against k: BF16 1.0 (0x3f80) where sigma == k, else 0
-__device__ inline bf16x8 onehot8(uint2 s8, uint32_t kk) {
+// one-hot of 8 symbols against k: 1.0 where sigma == k, else 0, as eight
+// 16-bit words (BF16 1.0 = 0x3f80 = 0x80 * 0x7f, FP16 1.0 = 0x3c00 = 0x80 * 0x78)
+template <uint32_t kOneMul>
+__device__ inline uint4 onehot8_bits(uint2 s8, uint32_t kk) {
   uint32_t w[2] = {s8.x, s8.y}, r[4];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const uint32_t x = w[h] ^ kk;                               // zero byte where equal
     const uint32_t nz = ((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x;  // bit 7 set where not equal
     const uint32_t m = (nz & 0x80808080u) ^ 0x80808080u;        // 0x80 where equal
-    // bytes (m0, 0, m1, 0) and (m2, 0, m3, 0), times 0x7f: 0x80 * 0x7f = 0x3f80
-    r[2 * h] = __builtin_amdgcn_perm(0u, m, 0x0c010c00u) * 0x7fu;
-    r[2 * h + 1] = __builtin_amdgcn_perm(0u, m, 0x0c030c02u) * 0x7fu;
+    // bytes (m0, 0, m1, 0) and (m2, 0, m3, 0), times the multiplier
+    r[2 * h] = __builtin_amdgcn_perm(0u, m, 0x0c010c00u) * kOneMul;
+    r[2 * h + 1] = __builtin_amdgcn_perm(0u, m, 0x0c030c02u) * kOneMul;
   }
-  uint4 v = make_uint4(r[0], r[1], r[2], r[3]);
-  return __builtin_bit_cast(bf16x8, v);
+  return make_uint4(r[0], r[1], r[2], r[3]);
 }
 
 // Position-major copy of the padded alignment: msaT[i * B_pad + b].
@@ -99,7 +107,9 @@ hipError_t launch_transpose_msa(const uint8_t* msa_cm, int32_t B_pad, int32_t N_
 // One backward work item: site r x column block cb.  Bf: B fragments of the
 // residual pieces, [buffer][piece][step][half][column][8 sequences]; sig:
 // symbols of the block's columns, [buffer][column][sequence].
-template <int NP>
+// F16: FP16 hi/lo pieces of R * 2^12 (v_mfma_f32_32x32x16_f16) instead of
+// BF16 pieces (v_mfma_f32_32x32x16_bf16).
+template <int NP, bool F16>
 __device__ inline void bwd_mfma_item(const EvalArgs& a, int r, int cb, uint16_t (*Bf)[NP * kBfPiece],
                                      uint8_t (*sig)[kMPosMax * kSigPitch]) {
   const int npos_blk = mfma_block_positions(a.q);
@@ -160,12 +170,24 @@ __device__ inline void bwd_mfma_item(const EvalArgs& a, int r, int cb, uint16_t 
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
           float v0 = rv[k][2 * jj], v1 = rv[k][2 * jj + 1];
+          if (F16) {
+            v0 *= kF16Scale;
+            v1 *= kF16Scale;
+          }
 #pragma unroll
           for (int p = 0; p < NP; ++p) {
-            const uint32_t h0 = f2bf(v0), h1 = f2bf(v1);
-            hw[p][jj] = h0 | (h1 << 16);
-            v0 -= bf2f(h0);
-            v1 -= bf2f(h1);
+            if (F16) {
+              const _Float16 h0 = (_Float16)v0, h1 = (_Float16)v1;
+              hw[p][jj] = (uint32_t)__builtin_bit_cast(uint16_t, h0) |
+                          ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+              v0 -= (float)h0;
+              v1 -= (float)h1;
+            } else {
+              const uint32_t h0 = f2bf(v0), h1 = f2bf(v1);
+              hw[p][jj] = h0 | (h1 << 16);
+              v0 -= bf2f(h0);
+              v1 -= bf2f(h1);
+            }
           }
         }
 #pragma unroll
@@ -201,20 +223,27 @@ __device__ inline void bwd_mfma_item(const EvalArgs& a, int r, int cb, uint16_t 
       const uint8_t* sgb = &sig[buf][half * 8];
 #pragma unroll 2
       for (int t = 0; t < kMSteps; ++t) {
-        bf16x8 bp[NP];
+        uint4 bp[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p)
-          bp[p] = *reinterpret_cast<const bf16x8*>(bfb + p * kBfPiece + t * (2 * 32 * 8));
-        bf16x8 av[kMRB];
+          bp[p] = *reinterpret_cast<const uint4*>(bfb + p * kBfPiece + t * (2 * 32 * 8));
+        uint4 av[kMRB];
 #pragma unroll
         for (int m = 0; m < kMRB; ++m)
-          av[m] = onehot8(*reinterpret_cast<const uint2*>(sgb + arow_off[m] + t * 16), arow_kk[m]);
+          av[m] = onehot8_bits<F16 ? 0x78u : 0x7fu>(
+              *reinterpret_cast<const uint2*>(sgb + arow_off[m] + t * 16), arow_kk[m]);
         // the row blocks are independent accumulation chains
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
-          for (int m = 0; m < kMRB; ++m)
-            acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[m], bp[p], acc[m], 0, 0, 0);
+          for (int m = 0; m < kMRB; ++m) {
+            if (F16)
+              acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, av[m]),
+                                                              __builtin_bit_cast(f16x8, bp[p]), acc[m], 0, 0, 0);
+            else
+              acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[m]),
+                                                               __builtin_bit_cast(bf16x8, bp[p]), acc[m], 0, 0, 0);
+          }
       }
 #pragma unroll
       for (int m = 0; m < kMRB; ++m)
@@ -237,7 +266,8 @@ __device__ inline void bwd_mfma_item(const EvalArgs& a, int r, int cb, uint16_t 
       const int row = (wid * kMRB + m) * 32 + 8 * (j >> 2) + 4 * half + (j & 3);
       if (row < nrows && l32 < q) {
         const int i = i0 + row / q, k = row % q;
-        gmem_w(a.gJ)[((size_t)r * N + i) * qq + (size_t)k * q + l32] = (i == r) ? 0.0 : acc64[m][j];
+        gmem_w(a.gJ)[((size_t)r * N + i) * qq + (size_t)k * q + l32] =
+            (i == r) ? 0.0 : (F16 ? acc64[m][j] * kF16Unscale : acc64[m][j]);
       }
     }
 }
@@ -449,7 +479,7 @@ hipError_t launch_forward_mfma(const BatchArgs& b, int32_t npieces, int32_t nblo
 }
 
 
-template <int NP>
+template <int NP, bool F16>
 __global__ __launch_bounds__(kMThreads) void bwd_mfma_kernel(BatchArgs b) {
   __shared__ __attribute__((aligned(16))) uint16_t Bf[2][NP * kBfPiece];
   __shared__ __attribute__((aligned(16))) uint8_t sig[2][kMPosMax * kSigPitch];
@@ -463,7 +493,7 @@ __global__ __launch_bounds__(kMThreads) void bwd_mfma_kernel(BatchArgs b) {
     if (t < 0) break;
     const Item it = decode_item(b, KIND_BWD, t);
     const EvalArgs a = load_uniform(b.ev + it.m);
-    bwd_mfma_item<NP>(a, it.r, it.sub, Bf, sig);
+    bwd_mfma_item<NP, F16>(a, it.r, it.sub, Bf, sig);
     __syncthreads();
   }
 }
@@ -473,11 +503,14 @@ int32_t mfma_backward_blocks_per_site(int32_t N, int32_t q) {
   return (N + p - 1) / p;
 }
 
-hipError_t launch_backward_mfma(const BatchArgs& b, int32_t npieces, int32_t nblocks, hipStream_t st) {
-  if (npieces == 3)
-    hipLaunchKernelGGL(bwd_mfma_kernel<3>, dim3(nblocks), dim3(kMThreads), 0, st, b);
-  else if (npieces == 2)
-    hipLaunchKernelGGL(bwd_mfma_kernel<2>, dim3(nblocks), dim3(kMThreads), 0, st, b);
+hipError_t launch_backward_mfma(const BatchArgs& b, int32_t npieces, int32_t f16, int32_t nblocks,
+                                hipStream_t st) {
+  if (f16 && npieces == 2)
+    hipLaunchKernelGGL((bwd_mfma_kernel<2, true>), dim3(nblocks), dim3(kMThreads), 0, st, b);
+  else if (!f16 && npieces == 3)
+    hipLaunchKernelGGL((bwd_mfma_kernel<3, false>), dim3(nblocks), dim3(kMThreads), 0, st, b);
+  else if (!f16 && npieces == 2)
+    hipLaunchKernelGGL((bwd_mfma_kernel<2, false>), dim3(nblocks), dim3(kMThreads), 0, st, b);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -491,8 +524,8 @@ int32_t mfma_resident_blocks(int32_t kind, int32_t npieces) {
     e = npieces == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_mfma_kernel<3>, kMThreads, 0)
                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_mfma_kernel<2>, kMThreads, 0);
   else
-    e = npieces == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bwd_mfma_kernel<3>, kMThreads, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bwd_mfma_kernel<2>, kMThreads, 0);
+    e = npieces == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bwd_mfma_kernel<3, false>, kMThreads, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bwd_mfma_kernel<2, true>, kMThreads, 0);
   return (e == hipSuccess && per > 0) ? per : 1;
 }
 

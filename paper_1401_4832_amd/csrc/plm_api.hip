@@ -186,14 +186,16 @@ int32_t pick_nb(int32_t B, int32_t tile_seqs) {
 // backward, n > 0 = one-hot MFMA product with n BF16 pieces.
 struct PathSpec {
   int fwd_np, bwd_np;
+  int bwd_f16;  // gradient pieces in FP16 (of R * 2^12) instead of BF16
 };
 
 bool path_spec(int32_t path, PathSpec* p) {
   switch (path) {
-    case PLM_PATH_GATHER_FP32: *p = {0, 0}; return true;
-    case PLM_PATH_MFMA_BF16X2: *p = {2, 2}; return true;
-    case PLM_PATH_GATHER_MFMA_FP32: *p = {0, 3}; return true;
-    case PLM_PATH_MFMA_FP32: *p = {3, 3}; return true;
+    case PLM_PATH_GATHER_FP32: *p = {0, 0, 0}; return true;
+    case PLM_PATH_MFMA_BF16X2: *p = {2, 2, 0}; return true;
+    case PLM_PATH_GATHER_MFMA_FP32: *p = {0, 3, 0}; return true;
+    case PLM_PATH_MFMA_FP32: *p = {3, 3, 0}; return true;
+    case PLM_PATH_GATHER_MFMA_F16X2: *p = {0, 2, 1}; return true;
     default: return false;
   }
 }
@@ -231,7 +233,7 @@ hipError_t eval_forward(const PathSpec& p, const BatchArgs& b, int32_t nb, const
 }
 
 hipError_t eval_backward(const PathSpec& p, const BatchArgs& b, const Grids& g, hipStream_t st) {
-  return p.bwd_np ? launch_backward_mfma(b, p.bwd_np, g.bwd, st) : launch_backward(b, g.bwd, st);
+  return p.bwd_np ? launch_backward_mfma(b, p.bwd_np, p.bwd_f16, g.bwd, st) : launch_backward(b, g.bwd, st);
 }
 
 EvalArgs eval_args(const EvalBufs& e, const uint8_t* msa_unused, int32_t B, int32_t N, int32_t q,
@@ -738,8 +740,8 @@ int plm_tune(plm_ctx* c, const plm_msa_desc* descs, int32_t n_msas, int32_t q, c
     int32_t path, tile;
   };
   std::vector<Cand> cands;
-  const int32_t paths[] = {PLM_PATH_GATHER_MFMA_FP32, PLM_PATH_GATHER_FP32, PLM_PATH_MFMA_FP32,
-                           PLM_PATH_MFMA_BF16X2};
+  const int32_t paths[] = {PLM_PATH_GATHER_MFMA_F16X2, PLM_PATH_GATHER_MFMA_FP32, PLM_PATH_GATHER_FP32,
+                           PLM_PATH_MFMA_FP32, PLM_PATH_MFMA_BF16X2};
   for (int32_t p : paths) {
     if (fp32_only && p == PLM_PATH_MFMA_BF16X2) continue;
     PathSpec ps;

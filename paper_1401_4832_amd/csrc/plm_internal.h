@@ -257,7 +257,8 @@ int32_t mfma_forward_tile_seqs();
 int32_t mfma_backward_blocks_per_site(int32_t N, int32_t q);
 int32_t mfma_resident_blocks(int32_t kind, int32_t npieces);
 hipError_t launch_forward_mfma(const BatchArgs& b, int32_t npieces, int32_t nblocks, hipStream_t st);
-hipError_t launch_backward_mfma(const BatchArgs& b, int32_t npieces, int32_t nblocks, hipStream_t st);
+hipError_t launch_backward_mfma(const BatchArgs& b, int32_t npieces, int32_t f16, int32_t nblocks,
+                                hipStream_t st);
 hipError_t launch_lbfgs(const BatchArgs& b, int32_t nblocks, hipStream_t st);
 hipError_t launch_compact(const BatchArgs& b, const SiteState* st_, int32_t* host_count,
                           unsigned long long* site_evals, hipStream_t st);
