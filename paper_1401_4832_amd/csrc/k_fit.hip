@@ -26,7 +26,6 @@ __global__ void init_fit_kernel(int32_t N, int32_t q, float* Xh, float* XJ, floa
     s.iter = s.evals = s.ls_count = s.head = s.stored = s.pad = 0;
     s.f = s.gnorm = s.alpha = s.gtd = 0.0;
     s.gamma = 1.0;
-    for (int k = 0; k < kMMax; ++k) s.rho[k] = s.ahist[k] = 0.0;
     st[r] = s;
     if (phase_host) phase_host[r] = PH_INIT;
   }

@@ -6,19 +6,81 @@
 // trial point (objective partials from the forward kernel, FP64 gradient data
 // part from the backward kernel), adds the l2 terms in FP64, takes the line
 // search decision (sufficient decrease with backtracking by safeguarded
-// quadratic interpolation), and on acceptance stores the curvature pair,
-// runs the two-loop recursion and writes the next trial point.  All dot
-// products and the history are FP64; the iterate is kept at FP32-representable
-// values so that the evaluated point and the stored point are the same.
+// quadratic interpolation), and on acceptance stores the curvature pair and
+// writes the next trial point.  All dot products, the history and the small
+// matrices are FP64; the iterate is kept at FP32-representable values so that
+// the evaluated point and the stored point are the same.
+//
+// The search direction d = -H g uses the compact representation of the
+// limited-memory inverse Hessian (Byrd, Nocedal and Schnabel, 1994), which
+// gives the same direction as the two-loop recursion: with the n stored pairs
+// in chronological order, R = upper triangle of S^T Y, D = its diagonal and
+// gamma the scaling of the newest pair,
+//   H g = gamma g + S q1 - gamma Y t,   R t = S^T g,
+//   R^T q1 = (D + gamma Y^T Y) t - gamma Y^T g.
+// S^T Y and Y^T Y are kept per site and gain one column per accepted pair, so
+// an accepted step streams the history twice (one pass of dot products, one
+// pass forming d) instead of the 2m passes of the two-loop recursion.  The
+// history has m + 1 slots, so that a candidate pair can be written before the
+// curvature test decides whether it is kept.
 #include "plm_internal.h"
 
 namespace plm {
 
-__device__ inline void lbfgs_site(const LbfgsArgs& a, int r, double* red, double* ghd, double* ahist) {
+constexpr int kLbThreads = 1024;
+constexpr int kLbWaves = kLbThreads / 64;
+constexpr int kGroupA = 4;  // stored pairs whose dot products ride on the acceptance pass
+constexpr int kGroupB = 4;  // stored pairs per further dot-product pass
+constexpr int kVecMax = 4 * kGroupB;
+constexpr int kSlotsMax = kMMax + 1;
+
+struct LbShared {
+  double red[kLbWaves * kVecMax];
+  double vec[kVecMax];
+  double ghd[kSlot];
+  double Rm[kMMax * kMMax];   // S^T Y and Y^T Y of the stored pairs, chronological order
+  double YYm[kMMax * kMMax];
+  double cs[kMMax];           // direction coefficients of s and y, chronological order
+  double cy[kMMax];
+  double tv[kMMax];
+  double p1[kSlotsMax];       // s_j . g and y_j . g of the stored pairs, newest first
+  double p2[kSlotsMax];
+  double colS[kSlotsMax];     // s_j . y_cand and y_j . y_cand, newest first
+  double colY[kSlotsMax];
+  double cand[4];             // candidate pair: s.y, y.y, s.g, y.g
+  int32_t ord[kMMax];         // slots of the stored pairs, oldest first
+};
+
+// Block sums of NV per-thread FP64 values (fixed order: a shuffle tree per
+// wave, then the waves in order); every thread gets the sums.
+template <int NV>
+__device__ inline void block_sum_vec(double (&v)[NV], LbShared& sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh.red[wid * NV + k] = v[k];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double t = 0.0;
+    for (int w = 0; w < kLbWaves; ++w) t += sh.red[w * NV + threadIdx.x];
+    sh.vec[threadIdx.x] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = sh.vec[k];
+  __syncthreads();
+}
+
+__device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, double* red) {
   SiteState* S = a.st + r;
   const int phase = S->phase;
   if (phase == PH_DONE) return;
-  const int q = a.q, N = a.N, m = a.m;
+  const int q = a.q, N = a.N, m = a.m, M = m + 1;  // M history slots
   const size_t Nqq = (size_t)N * q * q;
   const int P = q + (int)Nqq;
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -26,12 +88,14 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, double* red, double
   const double ib = 1.0 / beff;
   const size_t h0 = (size_t)r * q, j0 = (size_t)r * Nqq;
   const int self0 = q + r * q * q, self1 = self0 + q * q;  // self block range in e
+  double* StY = a.small + (size_t)r * 2 * M * M;            // [M][M] s_i . y_j by slot
+  double* YtY = StY + (size_t)M * M;                         // [M][M] y_i . y_j by slot
 
   // ---- gather the evaluation at the trial point ----
   if (tid < q) {
     double t = 0.0;
     for (int k = 0; k < a.tiles; ++k) t += a.gh_part[((size_t)k * N + r) * kSlot + tid];
-    ghd[tid] = t;
+    sh.ghd[tid] = t;
   }
   double fdata = 0.0;
   if (tid == 0)
@@ -43,23 +107,24 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, double* red, double
   auto Tv = [&](int e) -> double { return e < q ? (double)a.Th[h0 + e] : (double)a.TJ[j0 + (e - q)]; };
   auto Xv = [&](int e) -> double { return e < q ? (double)a.Xh[h0 + e] : (double)a.XJ[j0 + (e - q)]; };
   auto gtv = [&](int e) -> double {
-    const double d = e < q ? ghd[e] : a.gJ[j0 + (e - q)];
+    const double d = e < q ? sh.ghd[e] : a.gJ[j0 + (e - q)];
     return d * ib + 2.0 * lam(e) * Tv(e);
   };
   auto Gv = [&](int e) -> double { return e < q ? a.Gh[h0 + e] : a.GJ[j0 + (e - q)]; };
   auto Dp = [&](int e) -> double* { return e < q ? a.Dh + h0 + e : a.DJ + j0 + (e - q); };
   auto Gp = [&](int e) -> double* { return e < q ? a.Gh + h0 + e : a.GJ + j0 + (e - q); };
-  auto Sv = [&](int k, int e) -> double* {
+  auto Sp = [&](int k, int e) -> double* {
     return e < q ? a.Sh + ((size_t)k * N) * q + h0 + e : a.SJ + (size_t)k * N * Nqq + j0 + (e - q);
   };
-  auto Yv = [&](int k, int e) -> double* {
+  auto Yp = [&](int k, int e) -> double* {
     return e < q ? a.Yh + ((size_t)k * N) * q + h0 + e : a.YJ + (size_t)k * N * Nqq + j0 + (e - q);
   };
+  auto storeT = [&](int e, double v) {
+    const float f = (float)v;
+    if (e < q) a.Th[h0 + e] = f; else a.TJ[j0 + (e - q)] = (e >= self0 && e < self1) ? 0.f : f;
+  };
   auto writeT = [&](double alpha) {
-    for (int e = tid; e < P; e += nth) {
-      const float v = (float)(Xv(e) + alpha * *Dp(e));
-      if (e < q) a.Th[h0 + e] = v; else a.TJ[j0 + (e - q)] = (e >= self0 && e < self1) ? 0.f : v;
-    }
+    for (int e = tid; e < P; e += nth) storeT(e, Xv(e) + alpha * *Dp(e));
   };
 
   double reg = 0.0, gg = 0.0;
@@ -89,28 +154,107 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, double* red, double
   } else if (phase == PH_INIT ||
              (finite && ft <= f + a.c1 * alpha * gtd + a.noise * fabs(f))) {
     // accept the trial point (the first evaluation is the start point itself);
-    // sufficient decrease allows for the rounding noise of the FP32 evaluation
-    double sy = 0.0, yy = 0.0;
-    const bool pair = (phase != PH_INIT) && m > 0;
+    // sufficient decrease allows for the rounding noise of the FP32 evaluation.
+    // One pass: gradient, candidate pair (s, y) into the free slot `head`, and
+    // the dot products of the newest stored pairs with y and g.
+    const bool pair = phase != PH_INIT;
+    const int nA = min(stored, kGroupA);
+    double acc[4 + 4 * kGroupA];
+#pragma unroll
+    for (int k = 0; k < 4 + 4 * kGroupA; ++k) acc[k] = 0.0;
     for (int e = tid; e < P; e += nth) {
       const double g = gtv(e);
       if (pair) {
         const double sv = Tv(e) - Xv(e), yv = g - Gv(e);
-        *Sv(head, e) = sv;
-        *Yv(head, e) = yv;
-        sy += sv * yv;
-        yy += yv * yv;
+        *Sp(head, e) = sv;
+        *Yp(head, e) = yv;
+        acc[0] += sv * yv;
+        acc[1] += yv * yv;
+        acc[2] += sv * g;
+        acc[3] += yv * g;
+#pragma unroll
+        for (int j = 0; j < kGroupA; ++j)
+          if (j < nA) {
+            const int k = (head - 1 - j + 2 * M) % M;
+            const double s_ = *Sp(k, e), y_ = *Yp(k, e);
+            acc[4 + 4 * j] += s_ * yv;
+            acc[5 + 4 * j] += y_ * yv;
+            acc[6 + 4 * j] += s_ * g;
+            acc[7 + 4 * j] += y_ * g;
+          }
       }
       *Gp(e) = g;
       if (e < q) a.Xh[h0 + e] = a.Th[h0 + e]; else a.XJ[j0 + (e - q)] = a.TJ[j0 + (e - q)];
     }
     if (pair) {
-      sy = block_sum_f64(sy, red);
-      yy = block_sum_f64(yy, red);
+      block_sum_vec(acc, sh);
+      if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sh.cand[k] = acc[k];
+#pragma unroll
+        for (int j = 0; j < kGroupA; ++j)
+          if (j < nA) {
+            sh.colS[j] = acc[4 + 4 * j];
+            sh.colY[j] = acc[5 + 4 * j];
+            sh.p1[j] = acc[6 + 4 * j];
+            sh.p2[j] = acc[7 + 4 * j];
+          }
+      }
+      // the older stored pairs, kGroupB at a time (g and y from the buffers
+      // this thread has just written)
+      for (int jg = kGroupA; jg < stored; jg += kGroupB) {
+        double bcc[4 * kGroupB];
+#pragma unroll
+        for (int k = 0; k < 4 * kGroupB; ++k) bcc[k] = 0.0;
+        const int nB = min(kGroupB, stored - jg);
+        for (int e = tid; e < P; e += nth) {
+          const double g = Gv(e), yv = *Yp(head, e);
+#pragma unroll
+          for (int j = 0; j < kGroupB; ++j)
+            if (j < nB) {
+              const int k = (head - 1 - (jg + j) + 2 * M) % M;
+              const double s_ = *Sp(k, e), y_ = *Yp(k, e);
+              bcc[4 * j] += s_ * yv;
+              bcc[4 * j + 1] += y_ * yv;
+              bcc[4 * j + 2] += s_ * g;
+              bcc[4 * j + 3] += y_ * g;
+            }
+        }
+        block_sum_vec(bcc, sh);
+        if (tid == 0)
+#pragma unroll
+          for (int j = 0; j < kGroupB; ++j)
+            if (j < nB) {
+              sh.colS[jg + j] = bcc[4 * j];
+              sh.colY[jg + j] = bcc[4 * j + 1];
+              sh.p1[jg + j] = bcc[4 * j + 2];
+              sh.p2[jg + j] = bcc[4 * j + 3];
+            }
+      }
+      __syncthreads();
+      const double sy = sh.cand[0], yy = sh.cand[1];
       if (sy > 0.0 && yy > 0.0) {
-        if (tid == 0) S->rho[head] = 1.0 / sy;
+        // keep the candidate: its column of S^T Y and its row/column of Y^T Y;
+        // it becomes the newest pair (index 0 of the newest-first lists)
+        if (tid == 0) {
+          const int c = head;
+          for (int j = 0; j < stored; ++j) {
+            const int k = (head - 1 - j + 2 * M) % M;
+            StY[k * M + c] = sh.colS[j];
+            YtY[k * M + c] = sh.colY[j];
+            YtY[c * M + k] = sh.colY[j];
+          }
+          StY[c * M + c] = sy;
+          YtY[c * M + c] = yy;
+          for (int j = min(stored, m - 1); j > 0; --j) {
+            sh.p1[j] = sh.p1[j - 1];
+            sh.p2[j] = sh.p2[j - 1];
+          }
+          sh.p1[0] = sh.cand[2];
+          sh.p2[0] = sh.cand[3];
+        }
         gamma = sy / yy;
-        head = (head + 1) % m;
+        head = (head + 1) % M;
         if (stored < m) ++stored;
       }
     }
@@ -156,34 +300,56 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, double* red, double
   }
 
   if (dir == QUASI_NEWTON) {
+    // the compact form over the n stored pairs, in chronological order
+    const int n = stored;
     __syncthreads();
-    // two-loop recursion d = -H g over the stored pairs, newest first
-    for (int e = tid; e < P; e += nth) *Dp(e) = -Gv(e);
-    for (int t = 0; t < stored; ++t) {
-      const int k = (head - 1 - t + 2 * m) % m;
-      double dot = 0.0;
-      for (int e = tid; e < P; e += nth) dot += *Sv(k, e) * *Dp(e);
-      dot = block_sum_f64(dot, red);
-      const double ak = S->rho[k] * dot;
-      if (tid == 0) ahist[t] = ak;
-      for (int e = tid; e < P; e += nth) *Dp(e) -= ak * *Yv(k, e);
+    if (tid < n) sh.ord[tid] = (head - n + tid + 2 * M) % M;
+    __syncthreads();
+    for (int e = tid; e < n * n; e += nth) {
+      const int i = e / n, j = e - i * n;
+      sh.Rm[e] = i <= j ? StY[sh.ord[i] * M + sh.ord[j]] : 0.0;
+      sh.YYm[e] = YtY[sh.ord[i] * M + sh.ord[j]];
     }
-    for (int e = tid; e < P; e += nth) *Dp(e) *= gamma;
-    for (int t = stored - 1; t >= 0; --t) {
-      const int k = (head - 1 - t + 2 * m) % m;
-      double dot = 0.0;
-      for (int e = tid; e < P; e += nth) dot += *Yv(k, e) * *Dp(e);
-      dot = block_sum_f64(dot, red);  // its barriers also publish ahist
-      const double bk = S->rho[k] * dot;
-      const double ck = ahist[t] - bk;
-      for (int e = tid; e < P; e += nth) *Dp(e) += ck * *Sv(k, e);
+    __syncthreads();
+    if (tid == 0) {
+      // R t = S^T g (back substitution); p1, p2 are newest first
+      for (int i = n - 1; i >= 0; --i) {
+        double x = sh.p1[n - 1 - i];
+        for (int l = i + 1; l < n; ++l) x -= sh.Rm[i * n + l] * sh.tv[l];
+        sh.tv[i] = x / sh.Rm[i * n + i];
+      }
+      // R^T q1 = D t + gamma Y^T Y t - gamma Y^T g (forward substitution), q1 in cs
+      for (int i = 0; i < n; ++i) {
+        double yyt = 0.0;
+        for (int l = 0; l < n; ++l) yyt += sh.YYm[i * n + l] * sh.tv[l];
+        double x = sh.Rm[i * n + i] * sh.tv[i] + gamma * (yyt - sh.p2[n - 1 - i]);
+        for (int l = 0; l < i; ++l) x -= sh.Rm[l * n + i] * sh.cs[l];
+        sh.cs[i] = x / sh.Rm[i * n + i];
+      }
+      // d = -gamma g - S q1 + gamma Y t
+      for (int i = 0; i < n; ++i) {
+        sh.cs[i] = -sh.cs[i];
+        sh.cy[i] = gamma * sh.tv[i];
+      }
     }
+    __syncthreads();
     double dg = 0.0;
-    for (int e = tid; e < P; e += nth) dg += *Dp(e) * Gv(e);
+    for (int e = tid; e < P; e += nth) {
+      const double g = Gv(e);
+      double d = -gamma * g;
+      for (int i = 0; i < n; ++i) {
+        const int k = sh.ord[i];
+        d += sh.cs[i] * *Sp(k, e) + sh.cy[i] * *Yp(k, e);
+      }
+      *Dp(e) = d;
+      storeT(e, Xv(e) + d);  // trial point at alpha = 1
+      dg += d * g;
+    }
     dg = block_sum_f64(dg, red);
     if (dg < 0.0) {
       gtd = dg;
       alpha = 1.0;
+      move = false;  // already written
     } else {
       dir = STEEPEST;  // not a descent direction
     }
@@ -218,20 +384,19 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, double* red, double
 }
 
 // One block per active site of the batch.
-__global__ __launch_bounds__(1024) void lbfgs_kernel(BatchArgs b) {
+__global__ __launch_bounds__(kLbThreads) void lbfgs_kernel(BatchArgs b) {
+  __shared__ LbShared sh;
   __shared__ double red[16];
-  __shared__ double ghd[kSlot];
-  __shared__ double ahist[kMMax];
   const int idx = blockIdx.x;
   if (idx >= *b.n_active) return;
   const int g = b.active[idx];
   const int m = b.msa_of[g];
   const LbfgsArgs a = load_uniform(b.lb + m);
-  lbfgs_site(a, g - b.site_base[m], red, ghd, ahist);
+  lbfgs_site(a, g - b.site_base[m], sh, red);
 }
 
 hipError_t launch_lbfgs(const BatchArgs& b, int32_t nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(lbfgs_kernel, dim3(nblocks), dim3(1024), 0, st, b);
+  hipLaunchKernelGGL(lbfgs_kernel, dim3(nblocks), dim3(kLbThreads), 0, st, b);
   return hipGetLastError();
 }
 

@@ -56,22 +56,26 @@ __device__ inline uint32_t f2bf(float f) {  // round to nearest even (finite inp
 }
 __device__ inline float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
 
-// one-hot of 8 symbols against k: 1.0 where sigma == k, else 0, as eight
-// 16-bit words (BF16 1.0 = 0x3f80 = 0x80 * 0x7f, FP16 1.0 = 0x3c00 = 0x80 * 0x78)
-template <uint32_t kOneMul>
-__device__ inline uint4 onehot8_bits(uint2 s8, uint32_t kk) {
+// One-hot of 8 symbols against k as eight 16-bit words: 2.0 where sigma == k,
+// else 0 (0x4000 is 2.0 in both BF16 and FP16; the factor 2 is removed,
+// exactly, when the sums are written).  Symbols and k are below 32, so the
+// bytes of x = sigma ^ k are below 32 and x + 0x3f never carries out of a
+// byte: bit 6 of a byte of x + 0x3f3f3f3f is clear exactly where sigma == k.
+// Rows past the end use k = 31, which no symbol (< q <= 21) equals.
+__device__ inline uint4 onehot8_x2(uint2 s8, uint32_t kk) {
   uint32_t w[2] = {s8.x, s8.y}, r[4];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const uint32_t x = w[h] ^ kk;                               // zero byte where equal
-    const uint32_t nz = ((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x;  // bit 7 set where not equal
-    const uint32_t m = (nz & 0x80808080u) ^ 0x80808080u;        // 0x80 where equal
-    // bytes (m0, 0, m1, 0) and (m2, 0, m3, 0), times the multiplier
-    r[2 * h] = __builtin_amdgcn_perm(0u, m, 0x0c010c00u) * kOneMul;
-    r[2 * h + 1] = __builtin_amdgcn_perm(0u, m, 0x0c030c02u) * kOneMul;
+    const uint32_t nz = (w[h] ^ kk) + 0x3f3f3f3fu;
+    const uint32_t m = ~nz & 0x40404040u;  // 0x40 in the bytes where sigma == k
+    // bytes (0, m0, 0, m1) and (0, m2, 0, m3): words 0x4000 or 0
+    r[2 * h] = __builtin_amdgcn_perm(0u, m, 0x010c000cu);
+    r[2 * h + 1] = __builtin_amdgcn_perm(0u, m, 0x030c020cu);
   }
   return make_uint4(r[0], r[1], r[2], r[3]);
 }
+
+constexpr double kOneHotUnscale = 0.5;  // the one-hot value is 2
 
 // Position-major copy of the padded alignment: msaT[i * B_pad + b].
 __global__ void transpose_msa_kernel(const uint8_t* __restrict__ msa_cm, int32_t B_pad,
@@ -121,7 +125,7 @@ __device__ inline void bwd_mfma_item(const EvalArgs& a, int r, int cb, uint16_t 
   const int half = lane >> 5, l32 = lane & 31;
 
   // this lane's A-fragment row in each of its row blocks; rows past the end
-  // compare against 0xff, which no symbol equals, so their one-hot is zero
+  // compare against 31, which no symbol equals, so their one-hot is zero
   int arow_off[kMRB];
   uint32_t arow_kk[kMRB];
 #pragma unroll
@@ -129,7 +133,7 @@ __device__ inline void bwd_mfma_item(const EvalArgs& a, int r, int cb, uint16_t 
     const int rho = (wid * kMRB + m) * 32 + l32;
     const bool ok = rho < nrows;
     arow_off[m] = ok ? (rho / q) * kSigPitch : 0;
-    arow_kk[m] = ok ? (uint32_t)(rho % q) * 0x01010101u : 0xffffffffu;
+    arow_kk[m] = (ok ? (uint32_t)(rho % q) : 31u) * 0x01010101u;
   }
   const bool wave_live = wid * kMRB * 32 < nrows;
 
@@ -230,8 +234,7 @@ __device__ inline void bwd_mfma_item(const EvalArgs& a, int r, int cb, uint16_t 
         uint4 av[kMRB];
 #pragma unroll
         for (int m = 0; m < kMRB; ++m)
-          av[m] = onehot8_bits<F16 ? 0x78u : 0x7fu>(
-              *reinterpret_cast<const uint2*>(sgb + arow_off[m] + t * 16), arow_kk[m]);
+          av[m] = onehot8_x2(*reinterpret_cast<const uint2*>(sgb + arow_off[m] + t * 16), arow_kk[m]);
         // the row blocks are independent accumulation chains
 #pragma unroll
         for (int p = 0; p < NP; ++p)
@@ -267,7 +270,7 @@ __device__ inline void bwd_mfma_item(const EvalArgs& a, int r, int cb, uint16_t 
       if (row < nrows && l32 < q) {
         const int i = i0 + row / q, k = row % q;
         gmem_w(a.gJ)[((size_t)r * N + i) * qq + (size_t)k * q + l32] =
-            (i == r) ? 0.0 : (F16 ? acc64[m][j] * kF16Unscale : acc64[m][j]);
+            (i == r) ? 0.0 : acc64[m][j] * (F16 ? kF16Unscale * kOneHotUnscale : kOneHotUnscale);
       }
     }
 }

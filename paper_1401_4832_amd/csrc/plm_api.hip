@@ -87,7 +87,7 @@ void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
 struct FitBufs {
   EvalBufs ev;
   float *Th, *TJ;
-  double *Gh, *GJ, *Dh, *DJ, *Sh, *SJ, *Yh, *YJ;
+  double *Gh, *GJ, *Dh, *DJ, *Sh, *SJ, *Yh, *YJ, *small;
 };
 
 void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, FitBufs& f) {
@@ -99,10 +99,11 @@ void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, FitBufs& f
   f.GJ = bp.take<double>(NNqq);
   f.Dh = bp.take<double>(Nq);
   f.DJ = bp.take<double>(NNqq);
-  f.Sh = bp.take<double>(Nq * m);
-  f.SJ = bp.take<double>(NNqq * m);
-  f.Yh = bp.take<double>(Nq * m);
-  f.YJ = bp.take<double>(NNqq * m);
+  f.Sh = bp.take<double>(Nq * (m + 1));
+  f.SJ = bp.take<double>(NNqq * (m + 1));
+  f.Yh = bp.take<double>(Nq * (m + 1));
+  f.YJ = bp.take<double>(NNqq * (m + 1));
+  f.small = bp.take<double>((size_t)N * 2 * (m + 1) * (m + 1));
 }
 
 // device tables of a batch (BatchArgs points into them)
@@ -535,7 +536,7 @@ int prepare_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const p
     L.beff = m.beff;
     L.Xh = m.h_io; L.XJ = m.J_io; L.Th = f.Th; L.TJ = f.TJ;
     L.Gh = f.Gh; L.GJ = f.GJ; L.Dh = f.Dh; L.DJ = f.DJ;
-    L.Sh = f.Sh; L.SJ = f.SJ; L.Yh = f.Yh; L.YJ = f.YJ;
+    L.Sh = f.Sh; L.SJ = f.SJ; L.Yh = f.Yh; L.YJ = f.YJ; L.small = f.small;
     L.f_part = f.ev.f_part; L.gh_part = f.ev.gh_part; L.gJ = f.ev.gJ;
     L.st = t.st + base[k];
     L.phase_host = phase_host_dev + base[k];

@@ -46,8 +46,6 @@ struct SiteState {
   double alpha;        // step of the pending trial point
   double gtd;          // g' d at the current point
   double gamma;        // initial inverse-Hessian scale
-  double rho[kMMax];
-  double ahist[kMMax];
 };
 
 enum { PH_INIT = 0, PH_LS = 1, PH_DONE = 2 };
@@ -82,10 +80,11 @@ struct LbfgsArgs {
   double* GJ;
   double* Dh;
   double* DJ;
-  double* Sh;  // [m][N][q]
-  double* SJ;  // [m][N][N q q]
+  double* Sh;  // [m+1][N][q] history slots (one spare for the candidate pair)
+  double* SJ;  // [m+1][N][N q q]
   double* Yh;
   double* YJ;
+  double* small;  // [N][2][m+1][m+1] S^T Y and Y^T Y by slot
   const double* f_part;   // [tiles][N]
   const double* gh_part;  // [tiles][N][21]
   const double* gJ;       // [N][N][q][q] data part
