@@ -53,11 +53,22 @@ hipError_t launch_pad_msa(const uint8_t* msa, int32_t B, int32_t N, int32_t q, u
 
 int32_t forward_tile_seqs(int32_t nb) { return kFwdWaves * kSlots * nb; }
 
+// J chunk of the gather forward: kFwdPos columns of kQMax rows of 64 floats;
+// the same LDS later parks 16 energies per lane (16 waves x 16 x 64 floats).
+constexpr int kFwdPos = 8;
+constexpr int kPosBytes = kQMax * kRowF * 4;  // 5376
+static_assert((kFwdPos - 1) * kPosBytes + 20 * 256 + 255 < 65536, "LDS offsets fit the immediate field");
+constexpr int kFwdJFloats = kFwdPos * kQMax * kRowF;
+constexpr int kFwdParkFloats = kFwdWaves * 16 * 64;
+constexpr int kFwdLdsFloats = kFwdJFloats > kFwdParkFloats ? kFwdJFloats : kFwdParkFloats;
+
 // One forward work item: site r x sequence tile `tile` of one alignment.
-// lds: 86 KB (J_r for 16 columns, 3 copies per row); sgl: the tile's symbols
-// for those columns; red: FP64 reduction scratch.
+// lds: J_r for kFwdPos columns, 3 copies per row, with a fixed pitch of kQMax
+// rows per column so that a column's offset is a compile-time constant (and
+// later the parked energies); sgl: the tile's symbols for those columns; red:
+// FP64 reduction scratch.
 template <int NB>
-__device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, uint4* sgl,
+__device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, uint2* sgl,
                                 double* red) {
   constexpr int tileSeq = kFwdWaves * kSlots * NB;
   const int q = a.q, N = a.N, qq = q * q;
@@ -75,36 +86,72 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
   for (int j = 0; j < NB; ++j) E[j] = hv;
 
   const size_t Jr = (size_t)r * N * qq;
-  const int nchunks = a.N_pad / kFwdChunk;
+  const int nchunks = (N + kFwdPos - 1) / kFwdPos;
   const char* L = reinterpret_cast<const char*>(lds);
+  // LDS byte address of row (p, sigma), this lane's word: p * kPosBytes (an
+  // immediate offset) + sigma * 256 + 4 * lane, where the last two are one
+  // byte permute: byte 0 = 4 * lane (< 256), byte 1 = the symbol byte
   const uint32_t lane4 = 4u * lane;
-  for (int c = 0; c < nchunks; ++c) {
-    __syncthreads();
-    for (int e = tid; e < kFwdChunk * qq; e += kFwdThreads) {
-      const int p = e / qq, rem = e - p * qq, k = rem / q, ss = rem - k * q;
-      const int i = c * kFwdChunk + p;
-      const float v = (i < N && i != r) ? gmem(a.J)[Jr + (size_t)i * qq + rem] : 0.f;
-      float* row = lds + (p * q + k) * kRowF;
-      row[ss] = v;
-      row[ss + kSlot] = v;
-      row[ss + 2 * kSlot] = v;
+  // the next chunk's couplings and symbols travel in registers while the
+  // current chunk is gathered
+  constexpr int kJPer = (kFwdPos * kQMax * kQMax + kFwdThreads - 1) / kFwdThreads;
+  constexpr int kSPer = (tileSeq + kFwdThreads - 1) / kFwdThreads;
+  float jv[kJPer];
+  uint2 sv[kSPer];
+  auto load = [&](int c) {
+#pragma unroll
+    for (int k = 0; k < kJPer; ++k) {
+      const int e = tid + k * kFwdThreads;
+      const int p = e / qq, rem = e - p * qq;
+      const int i = c * kFwdPos + p;
+      jv[k] = (e < kFwdPos * qq && i < N && i != r) ? gmem(a.J)[Jr + (size_t)i * qq + rem] : 0.f;
     }
-    for (int e = tid; e < tileSeq; e += kFwdThreads)
-      sgl[e] = gload_u4(a.msa_cm + ((size_t)c * a.B_pad + tile0 + e) * kFwdChunk);
+#pragma unroll
+    for (int k = 0; k < kSPer; ++k) {
+      const int e = tid + k * kFwdThreads;
+      if (e < tileSeq)
+        sv[k] = gload_u2(a.msa_cm + ((size_t)(c >> 1) * a.B_pad + tile0 + e) * kFwdChunk + 8 * (c & 1));
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int k = 0; k < kJPer; ++k) {
+      const int e = tid + k * kFwdThreads;
+      if (e < kFwdPos * qq) {
+        const int p = e / qq, rem = e - p * qq, kk = rem / q, ss = rem - kk * q;
+        float* row = lds + (p * kQMax + kk) * kRowF;
+        row[ss] = jv[k];
+        row[ss + kSlot] = jv[k];
+        row[ss + 2 * kSlot] = jv[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kSPer; ++k) {
+      const int e = tid + k * kFwdThreads;
+      if (e < tileSeq) sgl[e] = sv[k];
+    }
+  };
+  load(0);
+  for (int c = 0; c < nchunks; ++c) {
+    __syncthreads();  // every wave is done with the previous chunk
+    store();
     __syncthreads();
+    if (c + 1 < nchunks) load(c + 1);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const uint4 sg = sgl[tw + 3 * j];
-      float acc = E[j];
+      const uint2 sg = sgl[tw + 3 * j];
+      // two accumulation chains (even and odd columns)
+      float acc0 = E[j], acc1 = 0.f;
 #pragma unroll
-      for (int p = 0; p < kFwdChunk; ++p) {
-        const uint32_t word = p < 4 ? sg.x : p < 8 ? sg.y : p < 12 ? sg.z : sg.w;
-        const uint32_t sig = (word >> (8 * (p & 3))) & 0xffu;
-        // row (p, sig) of 64 floats = 256 bytes; the lane's column is fixed
-        const uint32_t off = (uint32_t)(p * q) * 256u + lane4 + (sig << 8);
-        acc += *reinterpret_cast<const float*>(L + off);
+      for (int p = 0; p < kFwdPos; ++p) {
+        const uint32_t word = p < 4 ? sg.x : sg.y;
+        const uint32_t addr = __builtin_amdgcn_perm(lane4, word, 0x0c0c0004u | ((uint32_t)(p & 3) << 8));
+        const float v = *reinterpret_cast<const float*>(L + addr + p * kPosBytes);
+        if (p == 1) acc1 = v;
+        else if (p & 1) acc1 += v;
+        else acc0 += v;
       }
-      E[j] = acc;
+      E[j] = acc0 + acc1;
       // keep one row's loads in flight at a time, so rows do not pile up in registers
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -166,8 +213,8 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
 // Persistent forward kernel: drains the forward work items of the batch.
 template <int NB>
 __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(BatchArgs b) {
-  __shared__ float lds[kFwdChunk * kQMax * kRowF];
-  __shared__ uint4 sgl[kFwdWaves * kSlots * NB];
+  __shared__ float lds[kFwdLdsFloats];
+  __shared__ uint2 sgl[kFwdWaves * kSlots * NB];
   __shared__ double red[kFwdWaves * 64];
   __shared__ int32_t item_s;
   int32_t qi = 0;
