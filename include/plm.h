@@ -246,6 +246,59 @@ int plm_tune(plm_ctx *ctx, const plm_msa_desc *descs, int32_t n_msas, int32_t q,
 int plm_score(plm_ctx *ctx, const float *J, int32_t N, int32_t q, double *fn_out,
               double *cfn_out);
 
+/* ---- Score variants (sec. 7) and contact evaluation (sec. 6) ----------------
+ * The alternatives the paper tried besides the CFN score: other combinations
+ * of the two Ising-gauge estimates (elementwise min or max instead of the
+ * average of eq. average2), other norms (an l_p norm, the sum of |J|^p to
+ * the power 1/p; the Burkoff divergence of eqs. burkoffscore1/burkoffscore2,
+ * D_ij = sum P ln(P / (f_i f_j)) with P proportional to f_i(k) f_j(l)
+ * exp(J*_ij(k,l)), computed on the combined Ising-gauge couplings), the gap
+ * state (q-1) left out of the sums, and the average-sum correction of eq.
+ * corr_normsum (S = FN - FN_i: - FN_:j + FN_::) or none instead of the APC.
+ * plm_score is plm_score_ex with the defaults below. */
+#define PLM_COMBINE_AVG 0
+#define PLM_COMBINE_MIN 1
+#define PLM_COMBINE_MAX 2
+#define PLM_NORM_FROB 0
+#define PLM_NORM_LP 1
+#define PLM_NORM_BURKOFF 2
+#define PLM_CORR_APC 0
+#define PLM_CORR_NONE 1
+#define PLM_CORR_ASC 2
+
+typedef struct {
+  int32_t combine;      /* PLM_COMBINE_*; default AVG */
+  int32_t norm;         /* PLM_NORM_*; default FROB */
+  double p;             /* exponent of PLM_NORM_LP (> 0); default 2 */
+  int32_t exclude_gap;  /* 1: sums over states 0..q-2 only; default 0 */
+  int32_t correction;   /* PLM_CORR_*; default APC */
+  int32_t reserved[4];
+} plm_score_opts;
+
+void plm_score_opts_default(plm_score_opts *opts);
+
+/* Reweighted single-site frequencies f_i(k) = sum_b w_b [sigma_i^b = k] / B_eff
+ * (device double[N][q]), as the Burkoff score needs them.  All pointers device. */
+int plm_frequencies(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, int32_t q,
+                    const double *w, const double *beff, double *f_out);
+
+/* raw_out: the uncorrected pair scores, corrected_out: after the correction;
+ * both device double[N][N], symmetric, zero diagonal.  freq (device
+ * double[N][q], from plm_frequencies) is required for PLM_NORM_BURKOFF and
+ * ignored otherwise. */
+int plm_score_ex(plm_ctx *ctx, const float *J, int32_t N, int32_t q, const plm_score_opts *opts,
+                 const double *freq, double *raw_out, double *corrected_out);
+
+/* True-positive rate of the strongest predicted contacts (sec. 6): the pairs
+ * i < j with j - i >= min_sep are ranked by decreasing score (ties by i, then
+ * j), and tpr_out[k] is the fraction of true contacts among the k + 1 first.
+ * score: device double[N][N]; contacts: device uint8[N][N] (nonzero = contact,
+ * read at [i][j] for i < j).  tpr_out: HOST double[kmax]; *n_out receives the
+ * number written (min(kmax, number of pairs)).  Synchronises the context's
+ * stream. */
+int plm_contact_tpr(plm_ctx *ctx, const double *score, int32_t N, const uint8_t *contacts,
+                    int32_t min_sep, int32_t kmax, double *tpr_out, int32_t *n_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -87,6 +87,22 @@ class TuneResult(ctypes.Structure):
     ]
 
 
+class ScoreOpts(ctypes.Structure):
+    _fields_ = [
+        ("combine", ctypes.c_int32),
+        ("norm", ctypes.c_int32),
+        ("p", ctypes.c_double),
+        ("exclude_gap", ctypes.c_int32),
+        ("correction", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
+    ]
+
+
+COMBINE = {"avg": 0, "min": 1, "max": 2}
+NORM = {"frob": 0, "lp": 1, "burkoff": 2}
+CORRECTION = {"apc": 0, "none": 1, "asc": 2}
+
+
 class PlmError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libplm status {code}: {msg}")
@@ -124,6 +140,10 @@ def lib():
             "plm_fit_batch_workspace_bytes": (SZ, [ctypes.POINTER(MsaDesc), I32, I32, ctypes.POINTER(FitOpts)]),
             "plm_fit_batch": (ctypes.c_int, [P, ctypes.POINTER(MsaDesc), I32, I32, ctypes.POINTER(FitOpts),
                                              P, SZ]),
+            "plm_score_opts_default": (None, [ctypes.POINTER(ScoreOpts)]),
+            "plm_frequencies": (ctypes.c_int, [P, P, I32, I32, I32, P, P, P]),
+            "plm_score_ex": (ctypes.c_int, [P, P, I32, I32, ctypes.POINTER(ScoreOpts), P, P, P]),
+            "plm_contact_tpr": (ctypes.c_int, [P, P, I32, P, I32, I32, P, ctypes.POINTER(I32)]),
             "plm_tune": (ctypes.c_int, [P, ctypes.POINTER(MsaDesc), I32, I32, ctypes.POINTER(FitOpts), I32, P,
                                         SZ, ctypes.POINTER(TuneResult), I32, ctypes.POINTER(I32)]),
         }
@@ -140,4 +160,5 @@ def exported_symbols():
     return ["plm_ctx_create", "plm_ctx_destroy", "plm_last_error", "plm_status_string", "plm_sync",
             "plm_reweight", "plm_objgrad_workspace_bytes", "plm_objgrad", "plm_fit_opts_default",
             "plm_fit_workspace_bytes", "plm_fit", "plm_score", "plm_fit_last_timing",
-            "plm_fit_batch_workspace_bytes", "plm_fit_batch", "plm_tune"]
+            "plm_fit_batch_workspace_bytes", "plm_fit_batch", "plm_tune", "plm_score_opts_default",
+            "plm_frequencies", "plm_score_ex", "plm_contact_tpr"]

@@ -277,13 +277,64 @@ def last_fit_timing(device=None) -> dict:
                 total_ms=t.total_ms, iterations=int(t.iterations), site_evals=int(t.site_evals))
 
 
-def score(J: torch.Tensor):
-    """(FN, CFN) float64 [N, N] (sec. 3.4 steps 4-6)."""
+def score(J: torch.Tensor, combine: str = "avg", norm: str = "frob", p: float = 2.0,
+          exclude_gap: bool = False, correction: str = "apc", freq: torch.Tensor | None = None):
+    """(raw, corrected) float64 [N, N] pair scores (sec. 3.4 steps 4-6).
+
+    The defaults give the paper's score: Frobenius norm of the averaged
+    Ising-gauge couplings (FN) and its average-product correction (CFN).  The
+    options select the variants of sec. 7: combine "avg" | "min" | "max",
+    norm "frob" | "lp" (exponent p) | "burkoff" (needs freq, see
+    frequencies()), exclude_gap, correction "apc" | "none" | "asc"."""
     dev = J.device
     _dev_tensor(J, torch.float32, dev, "J")
     N, _, q, _ = J.shape
-    fn = torch.empty(N, N, dtype=torch.float64, device=dev)
-    cfn = torch.empty(N, N, dtype=torch.float64, device=dev)
+    raw = torch.empty(N, N, dtype=torch.float64, device=dev)
+    cor = torch.empty(N, N, dtype=torch.float64, device=dev)
     ctx = context(dev)
-    _check(L.lib().plm_score(ctx, _ptr(J), N, q, _ptr(fn), _ptr(cfn)), ctx)
-    return fn, cfn
+    default = (combine, norm, exclude_gap, correction) == ("avg", "frob", False, "apc")
+    if default:
+        _check(L.lib().plm_score(ctx, _ptr(J), N, q, _ptr(raw), _ptr(cor)), ctx)
+        return raw, cor
+    o = L.ScoreOpts()
+    L.lib().plm_score_opts_default(ctypes.byref(o))
+    o.combine = L.COMBINE[combine]
+    o.norm = L.NORM[norm]
+    o.p = float(p)
+    o.exclude_gap = int(bool(exclude_gap))
+    o.correction = L.CORRECTION[correction]
+    if freq is not None:
+        _dev_tensor(freq, torch.float64, dev, "freq")
+        if tuple(freq.shape) != (N, q):
+            raise ValueError("freq must be [N, q]")
+    _check(L.lib().plm_score_ex(ctx, _ptr(J), N, q, ctypes.byref(o), _ptr(freq), _ptr(raw), _ptr(cor)), ctx)
+    return raw, cor
+
+
+def frequencies(msa, w, beff, q: int = 21) -> torch.Tensor:
+    """Reweighted single-site frequencies float64 [N, q] on msa's device."""
+    dev = msa.device
+    _dev_tensor(msa, torch.uint8, dev, "msa")
+    _dev_tensor(w, torch.float64, dev, "w")
+    _dev_tensor(beff, torch.float64, dev, "beff")
+    B, N = msa.shape
+    f = torch.empty(N, q, dtype=torch.float64, device=dev)
+    ctx = context(dev)
+    _check(L.lib().plm_frequencies(ctx, _ptr(msa), B, N, q, _ptr(w), _ptr(beff), _ptr(f)), ctx)
+    return f
+
+
+def contact_tpr(scores: torch.Tensor, contacts: torch.Tensor, min_sep: int = 5, kmax: int | None = None):
+    """True-positive rates (numpy float64) of the strongest pairs with j - i >= min_sep."""
+    import numpy as np
+    dev = scores.device
+    _dev_tensor(scores, torch.float64, dev, "scores")
+    N = scores.shape[0]
+    c = contacts.to(device=dev, dtype=torch.uint8).contiguous()
+    kmax = kmax or N * N
+    out = np.zeros(kmax, dtype=np.float64)
+    n = ctypes.c_int32(0)
+    ctx = context(dev)
+    _check(L.lib().plm_contact_tpr(ctx, _ptr(scores), N, _ptr(c), int(min_sep), int(kmax),
+                                   out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)), ctx)
+    return out[:n.value]

@@ -805,4 +805,76 @@ int plm_score(plm_ctx* c, const float* J, int32_t N, int32_t q, double* fn_out, 
   return PLM_OK;
 }
 
+void plm_score_opts_default(plm_score_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->combine = PLM_COMBINE_AVG;
+  o->norm = PLM_NORM_FROB;
+  o->p = 2.0;
+  o->exclude_gap = 0;
+  o->correction = PLM_CORR_APC;
+}
+
+int plm_frequencies(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
+                    const double* beff, double* f_out) {
+  if (!c) return PLM_E_INVALID;
+  if (!msa || !w || !beff || !f_out) return set_err(c, PLM_E_INVALID, "null pointer");
+  int rc = check_sizes(c, B, N, q);
+  if (rc) return rc;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, launch_frequencies(msa, B, N, q, w, beff, f_out, c->stream));
+  return PLM_OK;
+}
+
+int plm_score_ex(plm_ctx* c, const float* J, int32_t N, int32_t q, const plm_score_opts* o,
+                 const double* freq, double* raw_out, double* corrected_out) {
+  if (!c) return PLM_E_INVALID;
+  if (!J || !o || !raw_out || !corrected_out) return set_err(c, PLM_E_INVALID, "null pointer");
+  if (N < 2 || q < 2 || q > kQMax) return set_err(c, PLM_E_INVALID, "unsupported sizes");
+  if (o->combine < PLM_COMBINE_AVG || o->combine > PLM_COMBINE_MAX || o->norm < PLM_NORM_FROB ||
+      o->norm > PLM_NORM_BURKOFF || o->correction < PLM_CORR_APC || o->correction > PLM_CORR_ASC ||
+      (o->norm == PLM_NORM_LP && !(o->p > 0.0)) || (o->exclude_gap && q < 3))
+    return set_err(c, PLM_E_INVALID, "invalid score options");
+  if (o->norm == PLM_NORM_BURKOFF && !freq)
+    return set_err(c, PLM_E_INVALID, "the Burkoff score needs the frequencies");
+  HIPCHK(c, hipSetDevice(c->device));
+  ScoreOpts so;
+  so.combine = o->combine;
+  so.norm = o->norm;
+  so.p = o->p;
+  so.exclude_gap = o->exclude_gap;
+  so.correction = o->correction;
+  HIPCHK(c, launch_score_ex(J, N, q, so, freq, raw_out, corrected_out, c->stream));
+  return PLM_OK;
+}
+
+int plm_contact_tpr(plm_ctx* c, const double* score, int32_t N, const uint8_t* contacts,
+                    int32_t min_sep, int32_t kmax, double* tpr_out, int32_t* n_out) {
+  if (!c) return PLM_E_INVALID;
+  if (!score || !contacts || !tpr_out || !n_out) return set_err(c, PLM_E_INVALID, "null pointer");
+  if (N < 2 || min_sep < 1 || kmax < 1) return set_err(c, PLM_E_INVALID, "invalid sizes");
+  HIPCHK(c, hipSetDevice(c->device));
+  const size_t NN = (size_t)N * N;
+  std::vector<double> S(NN);
+  std::vector<uint8_t> C(NN);
+  HIPCHK(c, hipMemcpyAsync(S.data(), score, NN * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(C.data(), contacts, NN, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<std::pair<int32_t, int32_t>> pairs;
+  for (int32_t i = 0; i < N; ++i)
+    for (int32_t j = i + min_sep; j < N; ++j) pairs.emplace_back(i, j);
+  std::stable_sort(pairs.begin(), pairs.end(), [&](const std::pair<int32_t, int32_t>& x,
+                                                   const std::pair<int32_t, int32_t>& y) {
+    return S[(size_t)x.first * N + x.second] > S[(size_t)y.first * N + y.second];
+  });
+  const int32_t n = (int32_t)pairs.size() < kmax ? (int32_t)pairs.size() : kmax;
+  int64_t hits = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    if (C[(size_t)pairs[k].first * N + pairs[k].second]) ++hits;
+    tpr_out[k] = (double)hits / (double)(k + 1);
+  }
+  *n_out = n;
+  return PLM_OK;
+}
+
 }  // extern "C"

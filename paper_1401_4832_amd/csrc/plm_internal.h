@@ -222,6 +222,13 @@ __device__ inline Item decode_item(const BatchArgs& b, int kind, int32_t t) {
   return it;
 }
 
+// Options of the pair scores (PLM_COMBINE_*, PLM_NORM_*, PLM_CORR_*).
+struct ScoreOpts {
+  int32_t combine, norm;
+  double p;
+  int32_t exclude_gap, correction;
+};
+
 // Device helpers ----------------------------------------------------------
 __device__ inline double block_sum_f64(double v, double* red) {
   // deterministic: fixed shuffle tree per wave, then waves summed in order
@@ -272,6 +279,10 @@ hipError_t launch_reweight(const uint8_t* msa, int32_t B, int32_t N, int32_t q, 
                            int32_t uniform, int32_t* m_out, double* w_out, double* beff_out,
                            int32_t* flag_dev, hipStream_t st);
 hipError_t launch_score(const float* J, int32_t N, int32_t q, double* fn, double* cfn, hipStream_t st);
+hipError_t launch_score_ex(const float* J, int32_t N, int32_t q, const ScoreOpts& o,
+                           const double* freq, double* raw, double* cor, hipStream_t st);
+hipError_t launch_frequencies(const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
+                              const double* beff, double* f, hipStream_t st);
 hipError_t launch_objgrad_final(const FinalArgs& a, int32_t nsites, hipStream_t st);
 hipError_t launch_check_f32(const float* p, size_t n, int32_t* flag, hipStream_t st);
 hipError_t launch_check_f64(const double* p, size_t n, int32_t* flag, hipStream_t st);
