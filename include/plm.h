@@ -299,6 +299,24 @@ int plm_score_ex(plm_ctx *ctx, const float *J, int32_t N, int32_t q, const plm_s
 int plm_contact_tpr(plm_ctx *ctx, const double *score, int32_t N, const uint8_t *contacts,
                     int32_t min_sep, int32_t kmax, double *tpr_out, int32_t *n_out);
 
+/* ---- Alignment ingestion (sec. 4) ------------------------------------------
+ * FASTA or Stockholm text (HOST memory, len bytes) to symbol codes (HOST
+ * uint8[B][N], row-major).  Inserts -- lowercase residues and "." -- are
+ * removed, as for the paper's PFAM alignments.  Codes: A C D E F G H I K L M N
+ * P Q R S T V W Y = 0..19, "-" = 20 (q = 21); B J O U X Z count as gaps; "*"
+ * is skipped; other characters and sequences of unequal aligned length are
+ * errors (PLM_E_INVALID, message in err).  Stockholm: "#" lines are
+ * annotation, "//" ends the alignment, other lines are "name part", parts
+ * of one name concatenated in order.  With codes_out NULL only *B_out and
+ * *N_out are set; otherwise capacity must be at least B * N (else
+ * PLM_E_WORKSPACE).  No context, no device. */
+#define PLM_FORMAT_AUTO 0
+#define PLM_FORMAT_FASTA 1
+#define PLM_FORMAT_STOCKHOLM 2
+
+int plm_parse_alignment(const char *text, size_t len, int32_t format, uint8_t *codes_out,
+                        size_t capacity, int32_t *B_out, int32_t *N_out, char *err, size_t err_len);
+
 #ifdef __cplusplus
 }
 #endif

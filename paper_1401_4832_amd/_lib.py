@@ -98,6 +98,7 @@ class ScoreOpts(ctypes.Structure):
     ]
 
 
+FORMAT = {"auto": 0, "fasta": 1, "stockholm": 2}
 COMBINE = {"avg": 0, "min": 1, "max": 2}
 NORM = {"frob": 0, "lp": 1, "burkoff": 2}
 CORRECTION = {"apc": 0, "none": 1, "asc": 2}
@@ -144,6 +145,8 @@ def lib():
             "plm_frequencies": (ctypes.c_int, [P, P, I32, I32, I32, P, P, P]),
             "plm_score_ex": (ctypes.c_int, [P, P, I32, I32, ctypes.POINTER(ScoreOpts), P, P, P]),
             "plm_contact_tpr": (ctypes.c_int, [P, P, I32, P, I32, I32, P, ctypes.POINTER(I32)]),
+            "plm_parse_alignment": (ctypes.c_int, [ctypes.c_char_p, SZ, I32, P, SZ, ctypes.POINTER(I32),
+                                                   ctypes.POINTER(I32), ctypes.c_char_p, SZ]),
             "plm_tune": (ctypes.c_int, [P, ctypes.POINTER(MsaDesc), I32, I32, ctypes.POINTER(FitOpts), I32, P,
                                         SZ, ctypes.POINTER(TuneResult), I32, ctypes.POINTER(I32)]),
         }
@@ -161,4 +164,4 @@ def exported_symbols():
             "plm_reweight", "plm_objgrad_workspace_bytes", "plm_objgrad", "plm_fit_opts_default",
             "plm_fit_workspace_bytes", "plm_fit", "plm_score", "plm_fit_last_timing",
             "plm_fit_batch_workspace_bytes", "plm_fit_batch", "plm_tune", "plm_score_opts_default",
-            "plm_frequencies", "plm_score_ex", "plm_contact_tpr"]
+            "plm_frequencies", "plm_score_ex", "plm_contact_tpr", "plm_parse_alignment"]

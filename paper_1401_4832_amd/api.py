@@ -338,3 +338,29 @@ def contact_tpr(scores: torch.Tensor, contacts: torch.Tensor, min_sep: int = 5, 
     _check(L.lib().plm_contact_tpr(ctx, _ptr(scores), N, _ptr(c), int(min_sep), int(kmax),
                                    out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)), ctx)
     return out[:n.value]
+
+
+def parse_alignment(text, fmt: str = "auto"):
+    """FASTA or Stockholm text (str or bytes) to a uint8 [B, N] numpy array of
+    codes (A C D E F G H I K L M N P Q R S T V W Y = 0..19, gap = 20), inserts
+    removed (sec. 4).  Host-side; move the result to the device with torch."""
+    import numpy as np
+    data = text.encode() if isinstance(text, str) else bytes(text)
+    B, N = ctypes.c_int32(0), ctypes.c_int32(0)
+    err = ctypes.create_string_buffer(512)
+    rc = L.lib().plm_parse_alignment(data, len(data), L.FORMAT[fmt], None, 0, ctypes.byref(B), ctypes.byref(N),
+                                     err, 512)
+    if rc != 0:
+        raise L.PlmError(rc, err.value.decode())
+    out = np.zeros((B.value, N.value), dtype=np.uint8)
+    rc = L.lib().plm_parse_alignment(data, len(data), L.FORMAT[fmt], out.ctypes.data_as(ctypes.c_void_p),
+                                     out.size, ctypes.byref(B), ctypes.byref(N), err, 512)
+    if rc != 0:
+        raise L.PlmError(rc, err.value.decode())
+    return out
+
+
+def read_alignment(path: str, fmt: str = "auto"):
+    """parse_alignment() of a file."""
+    with open(path, "rb") as fh:
+        return parse_alignment(fh.read(), fmt)
