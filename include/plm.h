@@ -246,6 +246,26 @@ int plm_tune(plm_ctx *ctx, const plm_msa_desc *descs, int32_t n_msas, int32_t q,
 int plm_score(plm_ctx *ctx, const float *J, int32_t N, int32_t q, double *fn_out,
               double *cfn_out);
 
+/* ---- Symmetric pseudolikelihood maximization (eqs. npll_1, l2reg) -----------
+ * The comparison method of the paper (sec. 3.2): one minimisation of
+ * sum_r g_r + lambda_h sum_i ||h_i||^2 + lambda_J sum_{i<j} ||J_ij||^2 (lambda_J
+ * as given, not halved) over all fields and couplings, each J_ij shared by
+ * g_i and g_j.  J_io uses the layout of plm_fit and is made consistent: on
+ * entry the blocks J[r][i], r < i, are the parameters (J[i][r] is overwritten
+ * by their transpose, self blocks by zero); on return J[i][r] is the
+ * transpose of J[r][i].  One L-BFGS over the whole vector (compact form,
+ * lbfgs_m pairs, the line search of plm_fit) until ||grad||_2 <= tol;
+ * stats_out (HOST, one record, may be NULL) describes the whole problem.
+ * The evaluation of each trial point is the all-sites evaluation of plm_fit
+ * (opts->path); every decision is taken on the device and one iteration is
+ * one replay of a captured graph.  Returns PLM_W_MAXITER on the iteration
+ * cap.  plm_fit_last_timing reports its kernel times when opts->timing. */
+size_t plm_fit_symmetric_workspace_bytes(int32_t B, int32_t N, int32_t q, const plm_fit_opts *opts);
+int plm_fit_symmetric(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, int32_t q,
+                      const double *w, const double *beff, const plm_fit_opts *opts,
+                      void *workspace, size_t workspace_bytes, float *h_io, float *J_io,
+                      plm_site_stats *stats_out);
+
 /* ---- Score variants (sec. 7) and contact evaluation (sec. 6) ----------------
  * The alternatives the paper tried besides the CFN score: other combinations
  * of the two Ising-gauge estimates (elementwise min or max instead of the

@@ -147,6 +147,9 @@ def lib():
             "plm_contact_tpr": (ctypes.c_int, [P, P, I32, P, I32, I32, P, ctypes.POINTER(I32)]),
             "plm_parse_alignment": (ctypes.c_int, [ctypes.c_char_p, SZ, I32, P, SZ, ctypes.POINTER(I32),
                                                    ctypes.POINTER(I32), ctypes.c_char_p, SZ]),
+            "plm_fit_symmetric_workspace_bytes": (SZ, [I32, I32, I32, ctypes.POINTER(FitOpts)]),
+            "plm_fit_symmetric": (ctypes.c_int, [P, P, I32, I32, I32, P, P, ctypes.POINTER(FitOpts), P, SZ, P,
+                                                 P, ctypes.POINTER(SiteStats)]),
             "plm_tune": (ctypes.c_int, [P, ctypes.POINTER(MsaDesc), I32, I32, ctypes.POINTER(FitOpts), I32, P,
                                         SZ, ctypes.POINTER(TuneResult), I32, ctypes.POINTER(I32)]),
         }
@@ -164,4 +167,5 @@ def exported_symbols():
             "plm_reweight", "plm_objgrad_workspace_bytes", "plm_objgrad", "plm_fit_opts_default",
             "plm_fit_workspace_bytes", "plm_fit", "plm_score", "plm_fit_last_timing",
             "plm_fit_batch_workspace_bytes", "plm_fit_batch", "plm_tune", "plm_score_opts_default",
-            "plm_frequencies", "plm_score_ex", "plm_contact_tpr", "plm_parse_alignment"]
+            "plm_frequencies", "plm_score_ex", "plm_contact_tpr", "plm_parse_alignment",
+            "plm_fit_symmetric_workspace_bytes", "plm_fit_symmetric"]

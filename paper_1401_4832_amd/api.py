@@ -190,6 +190,34 @@ def fit(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None) -> FitRe
     return FitResult(h, J, _stats_list(stats), rc)
 
 
+def fit_symmetric(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None) -> FitResult:
+    """Symmetric pseudolikelihood maximisation (sec. 3.2, eqs. npll_1 / l2reg):
+    one minimisation of sum_r g_r + lambda_h sum ||h||^2 + lambda_J sum_{i<j} ||J_ij||^2
+    with every J_ij shared by sites i and j.  The start point takes the blocks
+    J0[r][i], r < i (zeros by default); the result holds J[i][r] = J[r][i]
+    with the state axes swapped.  stats holds one record for the whole problem."""
+    opts = opts or FitOptions()
+    dev = msa.device
+    _dev_tensor(msa, torch.uint8, dev, "msa")
+    B, N = msa.shape
+    q = 21 if h0 is None else h0.shape[1]
+    h = torch.zeros(N, q, dtype=torch.float32, device=dev) if h0 is None else h0.clone().contiguous()
+    J = torch.zeros(N, N, q, q, dtype=torch.float32, device=dev) if J0 is None else J0.clone().contiguous()
+    _dev_tensor(w, torch.float64, dev, "w")
+    _dev_tensor(beff, torch.float64, dev, "beff")
+    co = opts.to_c()
+    nbytes = L.lib().plm_fit_symmetric_workspace_bytes(B, N, q, ctypes.byref(co))
+    if nbytes == 0:
+        raise L.PlmError(L.PLM_E_INVALID, "invalid sizes or options")
+    ws = workspace(nbytes, dev)
+    stats = (L.SiteStats * 1)()
+    ctx = context(dev)
+    rc = _check(L.lib().plm_fit_symmetric(ctx, _ptr(msa), B, N, q, _ptr(w), _ptr(beff), ctypes.byref(co),
+                                          _ptr(ws), ws.numel(), _ptr(h), _ptr(J), stats), ctx)
+    del ws
+    return FitResult(h, J, _stats_list(stats), rc)
+
+
 def _stats_list(stats):
     return [dict(iterations=s.iterations, evaluations=s.evaluations, status=L.SITE_STATUS.get(s.status, "?"),
                  f=s.f, gnorm=s.gnorm) for s in stats]

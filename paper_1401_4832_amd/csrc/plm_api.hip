@@ -148,6 +148,38 @@ BatchArgs batch_args(const Tables& t, int32_t n_msas, int32_t total) {
   return b;
 }
 
+// buffers of the symmetric fit
+struct SymBufs {
+  EvalBufs ev;
+  float *Th, *TJ;
+  double *Gh, *GJ, *Dh, *DJ, *Sh, *SJ, *Yh, *YJ, *part, *small;
+  SymCoef* coef;
+  SymState* st;
+  int2* pairs;
+  Tables t;
+};
+
+void layout_sym(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, int32_t nblk, SymBufs& f) {
+  layout_eval(bp, B, N, q, f.ev);
+  const size_t Nq = (size_t)N * q, NNqq = (size_t)N * N * q * q;
+  f.Th = bp.take<float>(Nq);
+  f.TJ = bp.take<float>(NNqq);
+  f.Gh = bp.take<double>(Nq);
+  f.GJ = bp.take<double>(NNqq);
+  f.Dh = bp.take<double>(Nq);
+  f.DJ = bp.take<double>(NNqq);
+  f.Sh = bp.take<double>(Nq * (m + 1));
+  f.SJ = bp.take<double>(NNqq * (m + 1));
+  f.Yh = bp.take<double>(Nq * (m + 1));
+  f.YJ = bp.take<double>(NNqq * (m + 1));
+  f.part = bp.take<double>((size_t)(1 + sym_groups(m)) * nblk * sym_part_stride());
+  f.small = bp.take<double>((size_t)2 * (m + 1) * (m + 1));
+  f.coef = bp.take<SymCoef>(1);
+  f.st = bp.take<SymState>(1);
+  f.pairs = bp.take<int2>((size_t)N * (N - 1) / 2);
+  layout_tables(bp, 1, N, false, f.t);
+}
+
 int check_sizes(plm_ctx* c, int32_t B, int32_t N, int32_t q) {
   if (B < 1 || N < 2 || q < 2 || q > kQMax)
     return set_err(c, PLM_E_INVALID, "unsupported sizes B=%d N=%d q=%d (need B>=1, N>=2, 2<=q<=21)", B,
@@ -803,6 +835,166 @@ int plm_score(plm_ctx* c, const float* J, int32_t N, int32_t q, double* fn_out, 
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, launch_score(J, N, q, fn_out, cfn_out, c->stream));
   return PLM_OK;
+}
+
+size_t plm_fit_symmetric_workspace_bytes(int32_t B, int32_t N, int32_t q, const plm_fit_opts* o) {
+  if (B < 1 || N < 2 || q < 2 || q > kQMax || !o) return 0;
+  if (o->lbfgs_m < 1 || o->lbfgs_m > kMMax) return 0;
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess && p.multiProcessorCount > 0) ncu = p.multiProcessorCount;
+  }
+  Bump bp{nullptr, 0};
+  SymBufs f;
+  layout_sym(bp, B, N, q, o->lbfgs_m, 4 * ncu, f);
+  return rup(bp.off, 256);
+}
+
+int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
+                      const double* beff, const plm_fit_opts* o, void* ws, size_t ws_bytes, float* h_io,
+                      float* J_io, plm_site_stats* stats_out) {
+  if (!c) return PLM_E_INVALID;
+  if (!msa || !w || !beff || !o || !h_io || !J_io) return set_err(c, PLM_E_INVALID, "null pointer");
+  int rc = check_sizes(c, B, N, q);
+  if (rc) return rc;
+  if (!fit_opts_ok(o) || o->single_site) return set_err(c, PLM_E_INVALID, "invalid fit options");
+  PathSpec ps;
+  if (!path_spec(o->path, &ps))
+    return set_err(c, PLM_E_UNSUPPORTED, "evaluation path %d is not available", o->path);
+  HIPCHK(c, hipSetDevice(c->device));
+  const int32_t nblk = 4 * c->ncu;
+  {
+    Bump bq{nullptr, 0};
+    SymBufs fq;
+    layout_sym(bq, B, N, q, o->lbfgs_m, nblk, fq);
+    rc = check_ws(c, ws, ws_bytes, rup(bq.off, 256));
+    if (rc) return rc;
+  }
+  rc = ensure_pin(c, 3);
+  if (rc) return rc;
+  Bump bp{(char*)ws, 0};
+  SymBufs f;
+  layout_sym(bp, B, N, q, o->lbfgs_m, nblk, f);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  hipStream_t st = c->fit_stream;
+  c->pin[2] = 0;
+
+  std::vector<int2> pairs;
+  pairs.reserve((size_t)N * (N - 1) / 2);
+  for (int32_t r = 0; r < N; ++r)
+    for (int32_t i = r + 1; i < N; ++i) pairs.push_back(make_int2(r, i));
+  HIPCHK(c, hipMemcpyAsync(f.pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+
+  const int32_t nb = pick_nb(B, o->tile_seqs);
+  const BatchArgs b = batch_args(f.t, 1, N);
+  HIPCHK(c, launch_check_f64(w, (size_t)B, c->pin_dev, st));
+  HIPCHK(c, launch_check_f32(h_io, (size_t)N * q, c->pin_dev, st));
+  HIPCHK(c, launch_check_f32(J_io, (size_t)N * N * q * q, c->pin_dev, st));
+  HIPCHK(c, launch_pad_msa(msa, B, N, q, f.ev.msa_cm, f.ev.B_pad, f.ev.N_pad, c->pin_dev, st));
+  const EvalArgs a = eval_args(f.ev, msa, B, N, q, w, f.Th, f.TJ, eval_tiles(ps, B, nb));
+  HIPCHK(c, eval_prepare(ps, a, f.ev.msaT, f.ev.sorted, st));
+  HIPCHK(c, launch_setup_msa(b, 0, a, nullptr, 0, N, a.tiles, eval_bwd_blocks(ps, N, q), nullptr, st));
+  HIPCHK(c, launch_list_tables(b, nullptr, 0, N, nullptr, st));
+
+  SymArgs S;
+  S.N = N; S.q = q; S.m = o->lbfgs_m; S.max_iter = o->max_iter; S.max_ls = o->max_linesearch;
+  S.tiles = a.tiles; S.nblk = nblk; S.npairs = (int32_t)pairs.size();
+  S.tol = o->tol; S.lambda_h = o->lambda_h; S.lambda_J = o->lambda_J; S.c1 = 1e-4; S.noise = 1e-7;
+  S.beff = beff;
+  S.Xh = h_io; S.XJ = J_io; S.Th = f.Th; S.TJ = f.TJ;
+  S.Gh = f.Gh; S.GJ = f.GJ; S.Dh = f.Dh; S.DJ = f.DJ;
+  S.Sh = f.Sh; S.SJ = f.SJ; S.Yh = f.Yh; S.YJ = f.YJ;
+  S.f_part = f.ev.f_part; S.gh_part = f.ev.gh_part; S.gJ = f.ev.gJ;
+  S.part = f.part; S.small = f.small; S.coef = f.coef; S.st = f.st; S.pairs = f.pairs;
+  S.done_host = c->pin_dev + 2;
+  HIPCHK(c, launch_sym_init(S, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  rc = flags_status(c);
+  if (rc) return rc;
+  const Grids g = eval_grids(c, ps, nb);
+
+  const bool timed = o->timing != 0;
+  auto mark = [&](int k) -> hipError_t { return timed ? hipEventRecord(c->ev[k], st) : hipSuccess; };
+  auto enqueue = [&]() -> hipError_t {
+    hipError_t e = mark(0);
+    if (e == hipSuccess) e = eval_forward(ps, b, nb, g, st);
+    if (e == hipSuccess) e = mark(1);
+    if (e == hipSuccess) e = eval_backward(ps, b, g, st);
+    if (e == hipSuccess) e = mark(2);
+    if (e == hipSuccess) e = launch_sym_step(S, b, st);
+    if (e == hipSuccess) e = mark(3);
+    return e;
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const bool use_graph = o->use_graph && !timed;
+  if (use_graph) {
+    HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue();
+    hipError_t e2 = hipStreamEndCapture(st, &graph);
+    if (e != hipSuccess) return set_err(c, PLM_E_HIP, "capture: %s", hipGetErrorString(e));
+    HIPCHK(c, e2);
+    HIPCHK(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  }
+  plm_fit_timing tm;
+  memset(&tm, 0, sizeof(tm));
+  const int64_t cap = (int64_t)o->max_iter * (o->max_linesearch + 2) + 16;
+  const int every = timed ? 1 : (o->sync_every > 0 ? o->sync_every : 1);
+  int64_t launched = 0;
+  int err = PLM_OK;
+  while (launched < cap) {
+    for (int k = 0; k < every; ++k, ++launched) {
+      hipError_t e = use_graph ? hipGraphLaunch(exec, st) : enqueue();
+      if (e != hipSuccess) {
+        err = set_err(c, PLM_E_HIP, "iteration launch: %s", hipGetErrorString(e));
+        break;
+      }
+    }
+    if (err) break;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      err = set_err(c, PLM_E_HIP, "sync: %s", hipGetErrorString(e));
+      break;
+    }
+    if (timed) {
+      float t01 = 0.f, t12 = 0.f, t23 = 0.f;
+      if (hipEventElapsedTime(&t01, c->ev[0], c->ev[1]) == hipSuccess &&
+          hipEventElapsedTime(&t12, c->ev[1], c->ev[2]) == hipSuccess &&
+          hipEventElapsedTime(&t23, c->ev[2], c->ev[3]) == hipSuccess) {
+        tm.forward_ms += t01;
+        tm.backward_ms += t12;
+        tm.lbfgs_ms += t23;
+      } else {
+        (void)hipGetLastError();
+      }
+      tm.iterations += 1;
+    }
+    if (((volatile int32_t*)c->pin)[2] == 1) break;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (err) return err;
+  HIPCHK(c, hipStreamSynchronize(st));
+  rc = flags_status(c);
+  if (rc) return rc;
+  SymState hs;
+  HIPCHK(c, hipMemcpy(&hs, f.st, sizeof(hs), hipMemcpyDeviceToHost));
+  if (timed) {
+    tm.site_evals = (int64_t)hs.evals * N;
+    tm.total_ms = tm.forward_ms + tm.backward_ms + tm.lbfgs_ms;
+    c->timing = tm;
+  }
+  const int status = hs.phase == PH_DONE ? hs.status : PLM_SITE_MAXITER;
+  if (stats_out) {
+    stats_out->iterations = hs.iter;
+    stats_out->evaluations = hs.evals;
+    stats_out->status = status;
+    stats_out->pad = 0;
+    stats_out->f = hs.f;
+    stats_out->gnorm = hs.gnorm;
+  }
+  return status == PLM_SITE_MAXITER ? PLM_W_MAXITER : PLM_OK;
 }
 
 void plm_score_opts_default(plm_score_opts* o) {

@@ -222,6 +222,36 @@ __device__ inline Item decode_item(const BatchArgs& b, int kind, int32_t t) {
   return it;
 }
 
+// Symmetric pseudolikelihood maximization: optimiser state and arguments.
+struct SymState {
+  int32_t phase, status, iter, evals, ls_count, head, stored;
+  int32_t accept, pair, dir, move, pad;
+  double f, gnorm, alpha, gtd, gamma;
+};
+
+struct SymCoef {
+  double cs[kMMax], cy[kMMax];            // direction coefficients, chronological order
+  double p1[kMMax + 1], p2[kMMax + 1];    // s_j . g, y_j . g, newest first
+  double colS[kMMax + 1], colY[kMMax + 1];
+  int32_t ord[kMMax];
+  int32_t n;
+};
+
+struct SymArgs {
+  int32_t N, q, m, max_iter, max_ls, tiles, nblk, npairs;
+  double tol, lambda_h, lambda_J, c1, noise;
+  const double* beff;
+  float *Xh, *XJ, *Th, *TJ;  // iterate (caller's h, J) and trial point, couplings mirrored
+  double *Gh, *GJ, *Dh, *DJ, *Sh, *SJ, *Yh, *YJ;  // full-layout vectors, blocks r < i used
+  const double *f_part, *gh_part, *gJ;            // evaluation of the trial point
+  double* part;   // block partial sums
+  double* small;  // [2][m+1][m+1] S^T Y, Y^T Y by slot
+  SymCoef* coef;
+  SymState* st;
+  const int2* pairs;  // [npairs] (r, i), r < i
+  int32_t* done_host;
+};
+
 // Options of the pair scores (PLM_COMBINE_*, PLM_NORM_*, PLM_CORR_*).
 struct ScoreOpts {
   int32_t combine, norm;
@@ -275,6 +305,10 @@ hipError_t launch_setup_msa(const BatchArgs& b, int32_t m, const EvalArgs& e, co
                             unsigned long long* site_evals, hipStream_t st);
 hipError_t launch_init_fit(int32_t N, int32_t q, float* Xh, float* XJ, float* Th, float* TJ,
                            SiteState* st_, int32_t* phase_host, hipStream_t st);
+hipError_t launch_sym_init(const SymArgs& a, hipStream_t st);
+hipError_t launch_sym_step(const SymArgs& a, const BatchArgs& b, hipStream_t st);
+int32_t sym_part_stride();
+int32_t sym_groups(int32_t m);
 hipError_t launch_reweight(const uint8_t* msa, int32_t B, int32_t N, int32_t q, double theta,
                            int32_t uniform, int32_t* m_out, double* w_out, double* beff_out,
                            int32_t* flag_dev, hipStream_t st);

@@ -1,0 +1,147 @@
+"""Symmetric pseudolikelihood maximisation on the GPU (plm_fit_symmetric)
+against the FP64 oracle's minimiser.
+
+F is strongly convex with modulus mu = 2 min(lambda_h, lambda_J) (0.02 at
+the default strengths), so ||theta - theta*|| <= ||grad F(theta)|| / mu.
+The GPU stops at ||grad F|| <= 1e-6 (its FP32 evaluation, over all sites)
+and the oracle below 1e-7, so every field and coupling must agree to about
+1e-4; the certificate is re-checked with the oracle's FP64 gradient at the
+GPU's final point.  The result must also be exactly consistent (J[i][r] is
+J[r][i] transposed, bit for bit; self blocks zero) and satisfy the gauge the
+l2 penalty fixes at the optimum (eq. symmetricgauge) to the accuracy the
+certificate allows."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import symmetric as sym
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def plm():
+    import paper_1401_4832_amd as plm
+    return plm
+
+
+@pytest.fixture(scope="module")
+def small():
+    # B = 700: several forward tiles and a ragged tail at every tile size
+    s = synth.make_msa("sym10", N=10, B=700, npairs=6, seed=41, cache=False, burnin=100, thin=2)
+    m, w, beff = oracle.reweight(s.msa, theta=0.8)
+    h_o, J_o, gn_o = sym.fit(s.msa, w, beff, 0.01, 0.01, q=21)
+    assert gn_o <= 1e-7, gn_o
+    return s, h_o, J_o
+
+
+def _gpu_problem(plm, s):
+    msa = torch.from_numpy(s.msa).to(DEV)
+    m, w, beff = plm.reweight(msa, theta=0.8)
+    return msa, w, beff
+
+
+def _check_consistent(J):
+    N = J.shape[0]
+    for r in range(N):
+        assert np.all(J[r, r] == 0.0), r
+        for i in range(r + 1, N):
+            assert np.array_equal(J[i, r], J[r, i].T), (r, i)
+
+
+def _certificate(s, h, J, lh, lJ):
+    m, w, beff = oracle.reweight(s.msa, theta=0.8)
+    F, gh, gJ = sym.objective(s.msa, w, beff, h, J, lh, lJ)
+    return F, float(np.sqrt(np.sum(gh ** 2) + np.sum(gJ ** 2)))
+
+
+@pytest.mark.parametrize("path", [0, 2, 3, 4])
+def test_symmetric_fit_matches_oracle(plm, small, path):
+    s, h_o, J_o = small
+    print(f"[case] symmetric fit N=10 B=700 path={path}", flush=True)
+    msa, w, beff = _gpu_problem(plm, s)
+    opts = plm.FitOptions(tol=1e-6, path=path)
+    res = plm.fit_symmetric(msa, w, beff, opts)
+    (st,) = res.stats
+    assert st["status"] == "converged", st
+    assert st["gnorm"] <= 1e-6
+    h = res.h.cpu().numpy().astype(np.float64)
+    J = res.J.cpu().numpy().astype(np.float64)
+    _check_consistent(J)
+    err = max(np.max(np.abs(J - J_o)), np.max(np.abs(h - h_o)))
+    assert err <= 1e-4, err
+    F, gn = _certificate(s, h, J, 0.01, 0.01)
+    mu = 2 * 0.01
+    assert gn / mu <= 2e-4, gn
+    assert abs(st["f"] - F) <= 1e-6 * abs(F), (st["f"], F)
+    # gauge at the optimum: lambda_J sum_k J_ri(k, s) = lambda_h h_r(s), sum_s h_r(s) = 0
+    # (both hold exactly at the optimum and move by at most sqrt(q) resp.
+    # lambda_J sqrt(q) + lambda_h times the distance to it)
+    dist = gn / mu
+    for r in range(10):
+        assert abs(h[r].sum()) <= np.sqrt(21) * dist + 1e-7
+        for i in range(10):
+            if i != r:
+                res_ri = np.max(np.abs(0.01 * J[r, i].sum(axis=0) - 0.01 * h[r]))
+                assert res_ri <= (0.01 * np.sqrt(21) + 0.01) * dist + 1e-8, (r, i, res_ri)
+
+
+def test_symmetric_start_point_is_made_consistent(plm, small):
+    # an inconsistent start (random blocks everywhere, self blocks included)
+    # reaches the same unique minimiser; only the blocks r < i are read
+    s, h_o, J_o = small
+    print("[case] symmetric fit from an inconsistent start", flush=True)
+    msa, w, beff = _gpu_problem(plm, s)
+    g = torch.Generator().manual_seed(5)
+    h0 = (0.2 * torch.randn(10, 21, generator=g)).to(DEV)
+    J0 = (0.2 * torch.randn(10, 10, 21, 21, generator=g)).to(DEV)
+    res = plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=1e-6, path=4), h0=h0, J0=J0)
+    assert res.stats[0]["status"] == "converged", res.stats
+    J = res.J.cpu().numpy().astype(np.float64)
+    _check_consistent(J)
+    err = max(np.max(np.abs(J - J_o)), np.max(np.abs(res.h.cpu().numpy() - h_o)))
+    assert err <= 1e-4, err
+    # the caller's tensors are not modified
+    assert not torch.equal(J0, res.J)
+
+
+def test_symmetric_graph_and_eager_are_identical(plm, small):
+    s, _, _ = small
+    print("[case] symmetric graph vs eager", flush=True)
+    msa, w, beff = _gpu_problem(plm, s)
+    a = plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=1e-6, use_graph=True))
+    b = plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=1e-6, use_graph=False, sync_every=3))
+    assert torch.equal(a.J, b.J) and torch.equal(a.h, b.h)
+    assert a.stats == b.stats
+
+
+def test_symmetric_fit_larger_gapped(plm):
+    # N = 24 with 10% forced gaps, on the path the autotuner prefers
+    s = synth.make_msa("sym24", N=24, B=1500, npairs=12, seed=43, gap_p=0.1, cache=False, burnin=100,
+                        thin=2)
+    print("[case] symmetric fit N=24 B=1500 path=4", flush=True)
+    m, w_o, beff_o = oracle.reweight(s.msa, theta=0.8)
+    h_o, J_o, gn_o = sym.fit(s.msa, w_o, beff_o, 0.01, 0.01, q=21)
+    msa, w, beff = _gpu_problem(plm, s)
+    res = plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=1e-6, path=4))
+    assert res.stats[0]["status"] == "converged", res.stats
+    J = res.J.cpu().numpy().astype(np.float64)
+    _check_consistent(J)
+    err = max(np.max(np.abs(J - J_o)), np.max(np.abs(res.h.cpu().numpy() - h_o)))
+    assert err <= 1e-4, err
+
+
+def test_symmetric_errors(plm, small):
+    s, _, _ = small
+    msa, w, beff = _gpu_problem(plm, s)
+    with pytest.raises(plm.PlmError):
+        plm.fit_symmetric(msa, w, beff, plm.FitOptions(single_site=True))
+    with pytest.raises(plm.PlmError):
+        plm.fit_symmetric(msa, w, beff, plm.FitOptions(path=17))
+    bad = msa.clone()
+    bad[3, 2] = 30  # a symbol >= q
+    with pytest.raises(plm.PlmError):
+        plm.fit_symmetric(bad, w, beff, plm.FitOptions())
