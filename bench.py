@@ -6,6 +6,8 @@ GPU) + Ising-gauge/FN/APC scoring, on a seeded synthetic planted-Potts
 alignment of N = 500 columns and B = 50000 rows (q = 21), resident in HBM.
 `--workload ragged16` runs the ragged batch instead: 16 alignments with N in
 [60, 300] and B in [2000, 30000], fitted together by plm_fit_batch.
+`--method symmetric` fits the symmetric pseudolikelihood instead (one
+minimisation over all parameters, plm_fit_symmetric) on the same alignment.
 
 metric: objective+gradient updates per second, one update being one
 (site r, sequence b, column i, state s) term of the energy sums -- B*N*q per
@@ -19,12 +21,11 @@ The evaluation schedule (path, forward tile) is the autotuner's choice for
 the workload, timed on the device before the warm-up (--path to force one).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload W] [--path auto|0..4]
+                       [--method asymmetric|symmetric]
 """
 from __future__ import annotations
 
 import argparse
-import glob
-import hashlib
 import json
 import os
 import sys
@@ -44,14 +45,6 @@ PATH_NAMES = {0: "gather_fp32", 1: "mfma_bf16x2", 2: "gather_mfma_fp32", 3: "mfm
 PATH_PIECES = {0: (0, 0), 1: (2, 2), 2: (0, 3), 3: (3, 3), 4: (0, 2)}
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1401_4832_amd", "csrc", "*"))):
-        with open(p, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(kernel: str, workload: str):
     """Per-launch HBM bytes from the committed PMC summary, if it was taken on
     the current kernel sources (else None)."""
@@ -63,7 +56,8 @@ def measured_traffic(kernel: str, workload: str):
             d = json.load(fh)
     except Exception:
         return None
-    if d.get("source_hash") != kernel_source_hash():
+    from paper_1401_4832_amd.profiling import source_hash
+    if d.get("source_hash") != source_hash(kernel):
         return None
     return d.get("bytes_per_launch")
 
@@ -108,6 +102,7 @@ def main():
     ap.add_argument("--workload", default="potts_n500_b50000")
     ap.add_argument("--path", default="auto", help="auto (autotuner) or an evaluation path 0..4")
     ap.add_argument("--tile-seqs", type=int, default=0)
+    ap.add_argument("--method", default="asymmetric", choices=("asymmetric", "symmetric"))
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--plain-sites", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
@@ -128,6 +123,10 @@ def main():
     dev = torch.device("cuda:0")
     sets = load_sets(args.workload)
     ragged = len(sets) > 1
+    symmetric = args.method == "symmetric"
+    if symmetric and ragged:
+        print("--method symmetric takes a single alignment", file=sys.stderr)
+        sys.exit(2)
     print(f"[bench] workload {args.workload}: " + ", ".join(f"N={s.N} B={s.B}" for s in sets),
           file=sys.stderr, flush=True)
     msas = [torch.from_numpy(s.msa).to(dev) for s in sets]
@@ -159,6 +158,9 @@ def main():
         ws = weights()
         if ragged:
             res = plm.fit_batch([(m, w, beff) for m, (_, w, beff) in zip(msas, ws)], opts)
+        elif symmetric:
+            _, w, beff = ws[0]
+            res = [plm.fit_symmetric(msas[0], w, beff, opts)]
         else:
             _, w, beff = ws[0]
             res = [plm.fit(msas[0], w, beff, opts)]
@@ -185,7 +187,9 @@ def main():
         for key in kt:
             kt[key] += tm[key]
         ws, res, _ = last
-        units = sum(sum(st["evaluations"] for st in r.stats) * s.B * s.N * Q for r, s in zip(res, sets))
+        # one symmetric evaluation covers every site of the alignment
+        per_eval = (lambda s: s.B * s.N * s.N * Q) if symmetric else (lambda s: s.B * s.N * Q)
+        units = sum(sum(st["evaluations"] for st in r.stats) * per_eval(s) for r, s in zip(res, sets))
         tot_time += dt
         tot_units += units
         print(f"[bench] step {k} {dt:.2f} s, site evals {tm['site_evals']}, "
@@ -197,7 +201,7 @@ def main():
         for st in r.stats:
             statuses[st["status"]] = statuses.get(st["status"], 0) + 1
     gmax = max(st["gnorm"] for r in res for st in r.stats)
-    mu = 2 * min(0.01, 0.005)
+    mu = 2 * min(0.01, 0.01 if symmetric else 0.005)
 
     # dominant kernel: the one with the largest share of device time
     shares = {"backward": kt["backward_ms"], "forward": kt["forward_ms"], "lbfgs": kt["lbfgs_ms"]}
@@ -220,11 +224,13 @@ def main():
             adds = units_all  # one FP32 add per update in the gather or the scatter
             roofline = {"bound": "alu", "achieved": adds / t_dom / 1e12, "peak": ALU_ADD_PEAK / 1e12,
                         "unit": "TFLOP/s", "frac": adds / t_dom / ALU_ADD_PEAK, "flops_per_unit": 1}
-        roofline.update({"traffic": measured_traffic(kname, args.workload), "kernel": kname,
+        # (per-launch bytes were counted on the asymmetric fit's evaluations)
+        traffic = None if symmetric else measured_traffic(kname, args.workload)
+        roofline.update({"traffic": traffic, "kernel": kname,
                          "launches": kt["iterations"], "avg_launch_ms": shares[dom] / max(1, kt["iterations"])})
 
     plain = None
-    if not args.no_plain and not ragged:
+    if not args.no_plain and not ragged and not symmetric:
         _, w, beff = ws[0]
         po = plm.FitOptions(tol=args.tol, path=path, tile_seqs=tile, single_site=True, site_limit=args.plain_sites)
         torch.cuda.synchronize()
@@ -250,7 +256,8 @@ def main():
     else:
         cfg = {"workload": args.workload, "N": sets[0].N, "B": sets[0].B}
     cfg.update({"q": Q, "theta": 0.8, "lambda_h": 0.01, "lambda_J": 0.01, "tol": args.tol,
-                "path": PATH_NAMES[path], "tile_seqs": tile, "schedule": "autotuned" if tuned else "fixed"})
+                "path": PATH_NAMES[path], "tile_seqs": tile, "schedule": "autotuned" if tuned else "fixed",
+                "method": args.method})
     line = {
         "metric": "plm objective+gradient updates/s (B*N^2*q, active sites) and time-to-fit at <=1e-4 vs plain",
         "value": tot_units / tot_time,

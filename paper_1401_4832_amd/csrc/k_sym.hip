@@ -74,6 +74,18 @@ __device__ inline void block_partials(double (&v)[NV], double* red, double* out)
   }
 }
 
+// Sum of base[k * stride], k < count, over one wavefront: lane l takes
+// k = l, l + 64, ...; the lanes are combined in a fixed tree.  The value of
+// lane 0 is the result (the other lanes may differ in the last bits).
+__device__ inline double wave_sum_strided(const double* base, int count, int stride) {
+  const int lane = threadIdx.x & 63;
+  double t = 0.0;
+  for (int k = lane; k < count; k += 64) t += base[(size_t)k * stride];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  return t;
+}
+
 // gradient of F at the trial point for one parameter (h entry or block entry)
 __device__ inline double sym_grad(const SymArgs& a, bool is_h, size_t j, size_t jm, double ib) {
   if (is_h) {
@@ -86,29 +98,33 @@ __device__ inline double sym_grad(const SymArgs& a, bool is_h, size_t j, size_t 
 }
 
 __global__ __launch_bounds__(kSymThreads) void sym_eval_kernel(SymArgs a) {
-  __shared__ double red[kSymThreads / 64 * 2];
+  __shared__ double red[kSymThreads / 64 * 3];
   if (a.st->phase == PH_DONE) return;
   const double ib = 1.0 / *a.beff;
-  double v[2] = {0.0, 0.0};  // l2 term, |g|^2
+  double v[3] = {0.0, 0.0, 0.0};  // l2 term, |g|^2, data term (unnormalised)
   for_each_param(a, [&](bool is_h, size_t j, size_t jm) {
     const double t = is_h ? (double)a.Th[j] : (double)a.TJ[j];
     const double g = sym_grad(a, is_h, j, jm, ib);
     v[0] += (is_h ? a.lambda_h : a.lambda_J) * t * t;
     v[1] += g * g;
   });
+  const size_t nf = (size_t)a.tiles * a.N, step = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += step) v[2] += a.f_part[e];
   block_partials(v, red, a.part + (size_t)blockIdx.x * kSymPart);
 }
 
-__global__ void sym_decide_kernel(SymArgs a) {
+__global__ __launch_bounds__(kSymThreads) void sym_decide_kernel(SymArgs a) {
+  __shared__ double tot[3];
   SymState* S = a.st;
-  if (threadIdx.x != 0 || S->phase == PH_DONE) return;
-  double reg = 0.0, gg = 0.0, fdata = 0.0;
-  for (int b = 0; b < a.nblk; ++b) {
-    reg += a.part[(size_t)b * kSymPart];
-    gg += a.part[(size_t)b * kSymPart + 1];
+  if (S->phase == PH_DONE) return;
+  const int wid = threadIdx.x >> 6;
+  if (wid < 3) {
+    const double t = wave_sum_strided(a.part + wid, a.nblk, kSymPart);
+    if ((threadIdx.x & 63) == 0) tot[wid] = t;
   }
-  for (int r = 0; r < a.N; ++r)
-    for (int k = 0; k < a.tiles; ++k) fdata += a.f_part[(size_t)k * a.N + r];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double reg = tot[0], gg = tot[1], fdata = tot[2];
   const double ft = fdata / *a.beff + reg, gnt = sqrt(gg);
   const bool finite = isfinite(ft) && isfinite(gnt);
   S->evals += 1;
@@ -239,36 +255,44 @@ __global__ __launch_bounds__(kSymThreads) void sym_group_kernel(SymArgs a, int32
 }
 
 // Curvature test, small-matrix update and the compact-form coefficients
-// (one thread; n <= 32).
-__global__ void sym_solve_kernel(SymArgs a) {
+// (block sums in parallel, the rest on one thread; n <= 32).
+__global__ __launch_bounds__(kSymThreads) void sym_solve_kernel(SymArgs a) {
+  __shared__ double tot[4 + 4 * kMMax];
+  __shared__ double t[kMMax];
   SymState* S = a.st;
-  if (threadIdx.x != 0 || !S->accept) return;
+  if (!S->accept) return;
   const int m = a.m, M = m + 1;
   SymCoef* C = a.coef;
   double* StY = a.small;
   double* YtY = a.small + (size_t)M * M;
   int stored = S->stored, head = S->head;
   if (S->pair) {
-    double cand[4] = {0, 0, 0, 0};
-    for (int b = 0; b < a.nblk; ++b)
-      for (int k = 0; k < 4; ++k) cand[k] += a.part[(size_t)b * kSymPart + k];
-    // the stored pairs' dot products, newest first
-    for (int j = 0; j < stored; ++j) {
-      const int grp = j < kSymGroup ? 0 : 1 + (j - kSymGroup) / kSymGroup;
-      double acc[4] = {0, 0, 0, 0};
-      if (grp == 0) {
-        for (int b = 0; b < a.nblk; ++b)
-          for (int k = 0; k < 4; ++k) acc[k] += a.part[(size_t)b * kSymPart + 4 + 4 * j + k];
+    // block sums of the candidate's dot products (quantity 0..3) and of the
+    // stored pairs' (4 + 4 j + k, newest first), one wavefront per quantity
+    const int nq = 4 + 4 * stored;
+    for (int qi = threadIdx.x >> 6; qi < nq; qi += kSymThreads / 64) {
+      const double* base;
+      if (qi < 4 + 4 * kSymGroup) {
+        base = a.part + qi;
       } else {
-        const int p = (j - kSymGroup) % kSymGroup;
-        for (int b = 0; b < a.nblk; ++b)
-          for (int k = 0; k < 4; ++k) acc[k] += a.part[((size_t)grp * a.nblk + b) * kSymPart + 4 * p + k];
+        const int j = (qi - 4) >> 2, k = (qi - 4) & 3;
+        const int grp = 1 + (j - kSymGroup) / kSymGroup, p = (j - kSymGroup) % kSymGroup;
+        base = a.part + (size_t)grp * a.nblk * kSymPart + 4 * p + k;
       }
-      C->colS[j] = acc[0];
-      C->colY[j] = acc[1];
-      C->p1[j] = acc[2];
-      C->p2[j] = acc[3];
+      const double v = wave_sum_strided(base, a.nblk, kSymPart);
+      if ((threadIdx.x & 63) == 0) tot[qi] = v;
     }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  if (S->pair) {
+    for (int j = 0; j < stored; ++j) {
+      C->colS[j] = tot[4 + 4 * j];
+      C->colY[j] = tot[5 + 4 * j];
+      C->p1[j] = tot[6 + 4 * j];
+      C->p2[j] = tot[7 + 4 * j];
+    }
+    const double cand[4] = {tot[0], tot[1], tot[2], tot[3]};
     const double sy = cand[0], yy = cand[1];
     if (sy > 0.0 && yy > 0.0) {
       const int c = head;
@@ -304,7 +328,6 @@ __global__ void sym_solve_kernel(SymArgs a) {
   for (int i = 0; i < n; ++i) C->ord[i] = (head - n + i + 2 * M) % M;
   auto R = [&](int i, int j) { return StY[C->ord[i] * M + C->ord[j]]; };
   auto YY = [&](int i, int j) { return YtY[C->ord[i] * M + C->ord[j]]; };
-  double t[kMMax];
   for (int i = n - 1; i >= 0; --i) {
     double x = C->p1[n - 1 - i];
     for (int l = i + 1; l < n; ++l) x -= R(i, l) * t[l];
@@ -364,10 +387,11 @@ __global__ __launch_bounds__(kSymThreads) void sym_direct_kernel(SymArgs a) {
 
 __global__ void sym_check_kernel(SymArgs a) {
   SymState* S = a.st;
-  if (threadIdx.x != 0 || S->phase == PH_DONE) return;
+  if (S->phase == PH_DONE) return;
+  const double dgw = S->dir == SD_QN ? wave_sum_strided(a.part, a.nblk, kSymPart) : 0.0;
+  if (threadIdx.x != 0) return;
   if (S->dir == SD_QN) {
-    double dg = 0.0;
-    for (int b = 0; b < a.nblk; ++b) dg += a.part[(size_t)b * kSymPart];
+    const double dg = dgw;
     if (dg < 0.0) {
       S->gtd = dg;
       S->alpha = 1.0;
@@ -467,11 +491,11 @@ int32_t sym_groups(int32_t m) { return m > kSymGroup ? (m - kSymGroup + kSymGrou
 // One optimiser step after the evaluation of the trial point.
 hipError_t launch_sym_step(const SymArgs& a, const BatchArgs& b, hipStream_t st) {
   hipLaunchKernelGGL(sym_eval_kernel, dim3(a.nblk), dim3(kSymThreads), 0, st, a);
-  hipLaunchKernelGGL(sym_decide_kernel, dim3(1), dim3(64), 0, st, a);
+  hipLaunchKernelGGL(sym_decide_kernel, dim3(1), dim3(kSymThreads), 0, st, a);
   hipLaunchKernelGGL(sym_accept_kernel, dim3(a.nblk), dim3(kSymThreads), 0, st, a);
   for (int g = 0; g < sym_groups(a.m); ++g)
     hipLaunchKernelGGL(sym_group_kernel, dim3(a.nblk), dim3(kSymThreads), 0, st, a, g);
-  hipLaunchKernelGGL(sym_solve_kernel, dim3(1), dim3(64), 0, st, a);
+  hipLaunchKernelGGL(sym_solve_kernel, dim3(1), dim3(kSymThreads), 0, st, a);
   hipLaunchKernelGGL(sym_direct_kernel, dim3(a.nblk), dim3(kSymThreads), 0, st, a);
   hipLaunchKernelGGL(sym_check_kernel, dim3(1), dim3(64), 0, st, a);
   hipLaunchKernelGGL(sym_move_kernel, dim3(a.nblk), dim3(kSymThreads), 0, st, a);

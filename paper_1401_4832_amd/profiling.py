@@ -27,9 +27,19 @@ KERNELS = {"forward": "fwd_kernel", "backward": "bwd_kernel", "forward_mfma": "f
            "backward_mfma": "bwd_mfma_kernel", "lbfgs": "lbfgs_kernel", "reweight": "identity_kernel"}
 
 
-def source_hash() -> str:
+# the source files each profiled kernel is compiled from
+KERNEL_SOURCES = {"forward": ("k_gather.hip", "plm_internal.h"), "backward": ("k_gather.hip", "plm_internal.h"),
+                  "forward_mfma": ("k_mfma.hip", "plm_internal.h"), "backward_mfma": ("k_mfma.hip", "plm_internal.h"),
+                  "lbfgs": ("k_lbfgs.hip", "plm_internal.h"), "reweight": ("k_reweight.hip", "plm_internal.h")}
+
+
+def source_hash(kernel: str | None = None) -> str:
+    """Hash of the kernel's source files (of every library source without a kernel)."""
+    csrc = os.path.join(ROOT, "paper_1401_4832_amd", "csrc")
+    files = ([os.path.join(csrc, f) for f in KERNEL_SOURCES[kernel]] if kernel
+             else sorted(glob.glob(os.path.join(csrc, "*"))))
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1401_4832_amd", "csrc", "*"))):
+    for p in files:
         with open(p, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -104,8 +114,8 @@ def traffic(fetch_csv: str, write_csv: str, workload: str, out_prefix: str):
     if not cf or not cw:
         raise SystemExit("copy calibration kernel not found in the counter files")
     sf, sw = COPY_BYTES / cf, COPY_BYTES / cw  # bytes per counter unit
-    h = source_hash()
     for kname, sym in KERNELS.items():
+        h = source_hash(kname)
         f = [v for k, vs in fk.items() if sym in k for v in vs]
         w = [v for k, vs in wk.items() if sym in k for v in vs]
         if not f or not w:
