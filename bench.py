@@ -8,6 +8,8 @@ alignment of N = 500 columns and B = 50000 rows (q = 21), resident in HBM.
 [60, 300] and B in [2000, 30000], fitted together by plm_fit_batch.
 `--method symmetric` fits the symmetric pseudolikelihood instead (one
 minimisation over all parameters, plm_fit_symmetric) on the same alignment.
+`--init mf` starts the fit from the mean-field estimate (plm_mf_init, inside
+the timed step) instead of the origin.
 
 metric: objective+gradient updates per second, one update being one
 (site r, sequence b, column i, state s) term of the energy sums -- B*N*q per
@@ -21,7 +23,7 @@ The evaluation schedule (path, forward tile) is the autotuner's choice for
 the workload, timed on the device before the warm-up (--path to force one).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload W] [--path auto|0..4]
-                       [--method asymmetric|symmetric]
+                       [--method asymmetric|symmetric] [--init zero|mf]
 """
 from __future__ import annotations
 
@@ -103,6 +105,8 @@ def main():
     ap.add_argument("--path", default="auto", help="auto (autotuner) or an evaluation path 0..4")
     ap.add_argument("--tile-seqs", type=int, default=0)
     ap.add_argument("--method", default="asymmetric", choices=("asymmetric", "symmetric"))
+    ap.add_argument("--init", default="zero", choices=("zero", "mf"))
+    ap.add_argument("--pseudocount", type=float, default=0.5)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--plain-sites", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
@@ -124,6 +128,10 @@ def main():
     sets = load_sets(args.workload)
     ragged = len(sets) > 1
     symmetric = args.method == "symmetric"
+    mf_start = args.init == "mf"
+    if mf_start and ragged:
+        print("--init mf takes a single alignment", file=sys.stderr)
+        sys.exit(2)
     if symmetric and ragged:
         print("--method symmetric takes a single alignment", file=sys.stderr)
         sys.exit(2)
@@ -154,16 +162,30 @@ def main():
         path, tile = int(args.path), args.tile_seqs
     opts = plm.FitOptions(tol=args.tol, path=path, tile_seqs=tile, timing=True)
 
+    mf_ms = []
+
+    def start_point(w, beff):
+        if not mf_start:
+            return None, None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h0, J0 = plm.mf_init(msas[0], w, beff, pseudocount=args.pseudocount, q=Q)
+        torch.cuda.synchronize()
+        mf_ms.append((time.perf_counter() - t0) * 1e3)
+        return h0, J0
+
     def step():
         ws = weights()
         if ragged:
             res = plm.fit_batch([(m, w, beff) for m, (_, w, beff) in zip(msas, ws)], opts)
         elif symmetric:
             _, w, beff = ws[0]
-            res = [plm.fit_symmetric(msas[0], w, beff, opts)]
+            h0, J0 = start_point(w, beff)
+            res = [plm.fit_symmetric(msas[0], w, beff, opts, h0=h0, J0=J0)]
         else:
             _, w, beff = ws[0]
-            res = [plm.fit(msas[0], w, beff, opts)]
+            h0, J0 = start_point(w, beff)
+            res = [plm.fit(msas[0], w, beff, opts, h0=h0, J0=J0)]
         cfn = [plm.score(r.J)[1] for r in res]
         torch.cuda.synchronize()
         return ws, res, cfn
@@ -230,7 +252,7 @@ def main():
                          "launches": kt["iterations"], "avg_launch_ms": shares[dom] / max(1, kt["iterations"])})
 
     plain = None
-    if not args.no_plain and not ragged and not symmetric:
+    if not args.no_plain and not ragged and not symmetric and not mf_start:
         _, w, beff = ws[0]
         po = plm.FitOptions(tol=args.tol, path=path, tile_seqs=tile, single_site=True, site_limit=args.plain_sites)
         torch.cuda.synchronize()
@@ -257,7 +279,9 @@ def main():
         cfg = {"workload": args.workload, "N": sets[0].N, "B": sets[0].B}
     cfg.update({"q": Q, "theta": 0.8, "lambda_h": 0.01, "lambda_J": 0.01, "tol": args.tol,
                 "path": PATH_NAMES[path], "tile_seqs": tile, "schedule": "autotuned" if tuned else "fixed",
-                "method": args.method})
+                "method": args.method, "init": args.init})
+    if mf_start:
+        cfg["pseudocount"] = args.pseudocount
     line = {
         "metric": "plm objective+gradient updates/s (B*N^2*q, active sites) and time-to-fit at <=1e-4 vs plain",
         "value": tot_units / tot_time,
@@ -277,6 +301,7 @@ def main():
         "fit": {"site_evals": kt["site_evals"], "iterations": kt["iterations"], "status": statuses,
                 "max_gnorm": gmax, "coupling_error_bound_l2": gmax / mu},
         "kernel_ms": {k: kt[k] for k in ("forward_ms", "backward_ms", "lbfgs_ms")},
+        "mf_init_ms": (sum(mf_ms[-args.steps:]) / args.steps) if mf_start else None,
         "roofline": roofline,
         "plain_single_site": plain,
         "cpu_baseline": cpu,

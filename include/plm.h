@@ -266,6 +266,29 @@ int plm_fit_symmetric(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, in
                       void *workspace, size_t workspace_bytes, float *h_io, float *J_io,
                       plm_site_stats *stats_out);
 
+/* ---- Mean-field starting guess (sec. 2, sec. 7) ------------------------------
+ * Couplings from the inverse of the connected correlation matrix
+ * c_ij(k,l) = f_ij(k,l) - f_i(k) f_j(l) over the states k, l < q-1 (the last
+ * state, the gap, is the reference), with reweighted frequencies mixed with
+ * a uniform pseudocount of weight `pseudocount` in [0, 1]:
+ *   f_i = (1-p) F_i/B_eff + p/q,  f_ij = (1-p) F_ij/B_eff + p/q^2 (i != j),
+ *   f_ii(k,l) = f_i(k)[k = l],  J_ij(k,l) = -(C^-1)_{(i,k),(j,l)},
+ *   h_i(k) = ln(f_i(k)/f_i(q-1)) - sum_{j != i} sum_{l < q-1} J_ij(k,l) f_j(l),
+ * reference-state couplings and fields zero.  Outputs (DEVICE, caller-owned):
+ * h_out [N][q], J_out [N][N][q][q] in the layout of plm_fit (both estimates
+ * of a pair equal, self blocks zero), usable as plm_fit's start point.  All
+ * arithmetic in FP64 (frequencies summed in a fixed order; C inverted in
+ * place by block Gauss-Jordan on the device), results rounded to FP32.
+ * Workspace: plm_mf_init_workspace_bytes (dominated by C: (N(q-1))^2 doubles,
+ * rounded up to 64-row blocks).  Synchronous on the context stream.
+ * PLM_E_SYMBOL for a symbol >= q; PLM_E_NONFINITE if C is not positive
+ * definite or a reference-state frequency is zero (possible only with
+ * pseudocount 0 and an unused state). */
+size_t plm_mf_init_workspace_bytes(int32_t B, int32_t N, int32_t q);
+int plm_mf_init(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, int32_t q, const double *w,
+                const double *beff, double pseudocount, void *workspace, size_t workspace_bytes,
+                float *h_out, float *J_out);
+
 /* ---- Score variants (sec. 7) and contact evaluation (sec. 6) ----------------
  * The alternatives the paper tried besides the CFN score: other combinations
  * of the two Ising-gauge estimates (elementwise min or max instead of the

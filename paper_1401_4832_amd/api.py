@@ -218,6 +218,29 @@ def fit_symmetric(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None
     return FitResult(h, J, _stats_list(stats), rc)
 
 
+def mf_init(msa, w, beff, pseudocount: float = 0.5, q: int = 21):
+    """Mean-field starting guess (h [N, q], J [N, N, q, q] float32): couplings
+    from the inverse of the pseudocount-regularised connected correlation
+    matrix (sec. 2), gap as reference state, in the layout of fit(); pass them
+    as fit(..., h0=h, J0=J)."""
+    dev = msa.device
+    _dev_tensor(msa, torch.uint8, dev, "msa")
+    _dev_tensor(w, torch.float64, dev, "w")
+    _dev_tensor(beff, torch.float64, dev, "beff")
+    B, N = msa.shape
+    nbytes = L.lib().plm_mf_init_workspace_bytes(B, N, q)
+    if nbytes == 0:
+        raise L.PlmError(L.PLM_E_INVALID, "invalid sizes")
+    h = torch.empty(N, q, dtype=torch.float32, device=dev)
+    J = torch.empty(N, N, q, q, dtype=torch.float32, device=dev)
+    ws = workspace(nbytes, dev)
+    ctx = context(dev)
+    _check(L.lib().plm_mf_init(ctx, _ptr(msa), B, N, q, _ptr(w), _ptr(beff), float(pseudocount), _ptr(ws),
+                               ws.numel(), _ptr(h), _ptr(J)), ctx)
+    del ws
+    return h, J
+
+
 def _stats_list(stats):
     return [dict(iterations=s.iterations, evaluations=s.evaluations, status=L.SITE_STATUS.get(s.status, "?"),
                  f=s.f, gnorm=s.gnorm) for s in stats]

@@ -297,6 +297,11 @@ int flags_status(plm_ctx* c) {
     c->pin[0] = 0;
     return set_err(c, PLM_E_INVALID, "site index outside [0, N)");
   }
+  if (f & 8) {
+    c->pin[0] = 0;
+    return set_err(c, PLM_E_NONFINITE,
+                   "a zero frequency or a correlation matrix that is not positive definite (raise the pseudocount)");
+  }
   return PLM_OK;
 }
 
@@ -835,6 +840,45 @@ int plm_score(plm_ctx* c, const float* J, int32_t N, int32_t q, double* fn_out, 
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, launch_score(J, N, q, fn_out, cfn_out, c->stream));
   return PLM_OK;
+}
+
+size_t plm_mf_init_workspace_bytes(int32_t B, int32_t N, int32_t q) {
+  if (B < 1 || N < 2 || q < 2 || q > kQMax) return 0;
+  const size_t tile = (size_t)mf_tile();
+  const size_t n = (size_t)N * (q - 1), n_pad = (n + tile - 1) / tile * tile;
+  Bump bp{nullptr, 0};
+  bp.take<int32_t>((size_t)N * B);
+  bp.take<int32_t>((size_t)N * (q + 1));
+  bp.take<double>((size_t)N * q);
+  bp.take<double>(n_pad * n_pad);
+  return rup(bp.off, 256);
+}
+
+int plm_mf_init(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
+                const double* beff, double pseudocount, void* ws, size_t ws_bytes, float* h_out, float* J_out) {
+  if (!c) return PLM_E_INVALID;
+  if (!msa || !w || !beff || !h_out || !J_out) return set_err(c, PLM_E_INVALID, "null pointer");
+  int rc = check_sizes(c, B, N, q);
+  if (rc) return rc;
+  if (!(pseudocount >= 0.0 && pseudocount <= 1.0)) return set_err(c, PLM_E_INVALID, "pseudocount outside [0, 1]");
+  rc = check_ws(c, ws, ws_bytes, plm_mf_init_workspace_bytes(B, N, q));
+  if (rc) return rc;
+  HIPCHK(c, hipSetDevice(c->device));
+  const int32_t tile = mf_tile();
+  const int32_t n = N * (q - 1), n_pad = (n + tile - 1) / tile * tile;
+  Bump bp{(char*)ws, 0};
+  int32_t* order = bp.take<int32_t>((size_t)N * B);
+  int32_t* start = bp.take<int32_t>((size_t)N * (q + 1));
+  double* fi = bp.take<double>((size_t)N * q);
+  double* C = bp.take<double>((size_t)n_pad * n_pad);
+  hipStream_t st = c->stream;
+  HIPCHK(c, launch_check_f64(w, (size_t)B, c->pin_dev, st));
+  HIPCHK(c, launch_mf_frequencies(msa, B, N, q, w, beff, pseudocount, order, start, fi, c->pin_dev, st));
+  HIPCHK(c, launch_mf_correlation(msa, order, start, w, beff, fi, B, N, q, pseudocount, C, n_pad, st));
+  HIPCHK(c, launch_mf_invert(C, n_pad, c->pin_dev, st));
+  HIPCHK(c, launch_mf_output(C, n_pad, fi, N, q, h_out, J_out, c->pin_dev, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  return flags_status(c);
 }
 
 size_t plm_fit_symmetric_workspace_bytes(int32_t B, int32_t N, int32_t q, const plm_fit_opts* o) {

@@ -309,6 +309,18 @@ hipError_t launch_sym_init(const SymArgs& a, hipStream_t st);
 hipError_t launch_sym_step(const SymArgs& a, const BatchArgs& b, hipStream_t st);
 int32_t sym_part_stride();
 int32_t sym_groups(int32_t m);
+
+// mean-field starting guess
+int32_t mf_tile();
+hipError_t launch_mf_frequencies(const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
+                                 const double* beff, double lam, int32_t* order, int32_t* start, double* fi,
+                                 int32_t* flag, hipStream_t st);
+hipError_t launch_mf_correlation(const uint8_t* msa, const int32_t* order, const int32_t* start, const double* w,
+                                 const double* beff, const double* fi, int32_t B, int32_t N, int32_t q,
+                                 double lam, double* C, int32_t n_pad, hipStream_t st);
+hipError_t launch_mf_invert(double* C, int32_t n_pad, int32_t* flag, hipStream_t st);
+hipError_t launch_mf_output(const double* Cinv, int32_t n_pad, const double* fi, int32_t N, int32_t q, float* h,
+                            float* J, int32_t* flag, hipStream_t st);
 hipError_t launch_reweight(const uint8_t* msa, int32_t B, int32_t N, int32_t q, double theta,
                            int32_t uniform, int32_t* m_out, double* w_out, double* beff_out,
                            int32_t* flag_dev, hipStream_t st);
