@@ -31,18 +31,20 @@ __global__ void init_fit_kernel(int32_t N, int32_t q, float* Xh, float* XJ, floa
   }
 }
 
-// Work-item offsets of every alignment from the active-list runs in b.seg,
-// and cleared queue counters (one block; after the runs are written).
+// Work-item offsets of every alignment from the active-list runs in b.seg
+// (an item covers kind_group consecutive sites of a run), and cleared queue
+// counters (one block; after the runs are written).
 __device__ inline void finish_tables(const BatchArgs& b) {
   __syncthreads();
   if (threadIdx.x < 2 * kQueues) b.ctr[threadIdx.x] = 0u;
   if (threadIdx.x < 2) {
     const int kind = threadIdx.x;
     int32_t* off = b.item_off + kind * (b.n_msas + 1);
+    const int32_t grp = kind_group(b, kind);
     int32_t acc = 0;
     for (int m = 0; m < b.n_msas; ++m) {
       off[m] = acc;
-      acc += (b.seg[m + 1] - b.seg[m]) * b.nsub[kind * b.n_msas + m];
+      acc += (b.seg[m + 1] - b.seg[m] + grp - 1) / grp * b.nsub[kind * b.n_msas + m];
     }
     off[b.n_msas] = acc;
   }

@@ -195,7 +195,21 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
       const float Rv = act ? (float)wb * (P - (s == sr ? 1.f : 0.f)) : 0.f;
       if (act && s == sr) facc += wb * (double)(lse - e);
       ghacc += (double)Rv;
-      if (slot < kSlots && b < a.B3) gmem_w(a.R)[((size_t)r * a.B3 + b) * kSlot + s] = Rv;
+      if (a.rfrag) {
+        // FP16 hi/lo pieces of R * 2^12 in the grouped gradient's fragment
+        // order, for every row of the tile (zero past B)
+        if (slot < kSlots) {
+          const float v = Rv * kRfScale;
+          const _Float16 hi = (_Float16)v;
+          const _Float16 lo = (_Float16)(v - (float)hi);
+          auto Rf = gmem_w(reinterpret_cast<uint16_t*>(a.R));
+          const size_t ix = rfrag_index(r, a.B_pad >> 8, b, s);
+          Rf[ix] = __builtin_bit_cast(uint16_t, hi);
+          Rf[ix + kRfPieceWords] = __builtin_bit_cast(uint16_t, lo);
+        }
+      } else if (slot < kSlots && b < a.B3) {
+        gmem_w(a.R)[((size_t)r * a.B3 + b) * kSlot + s] = Rv;
+      }
     }
   }
   const double ftot = block_sum_f64(facc, red);

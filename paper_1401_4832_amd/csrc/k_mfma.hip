@@ -501,6 +501,217 @@ __global__ __launch_bounds__(kMThreads) void bwd_mfma_kernel(BatchArgs b) {
   }
 }
 
+// ---------------------------------------------- grouped FP16 hi/lo gradient
+// The gradient of three sites at once: X^T [R_r0 | R_r1 | R_r2], the 63
+// residual columns of the group filling two 32-column MFMA tiles (the single-
+// site product leaves 11 of its 32 columns empty), so every one-hot A
+// fragment feeds four products (two tiles x two pieces).  The residuals come
+// from the forward already split (FP16 hi/lo of R * 2^12, fragment order) and
+// are copied global -> LDS by the load unit (16 bytes per lane, no registers,
+// no conversion), double-buffered one 256-sequence chunk ahead.  One block =
+// three sites x 512 rows (i, k) (24 columns at q = 21): 8 waves x 2 row blocks
+// of 32 rows; FP32 accumulators folded into FP64 every chunk, as in the
+// single-site kernel, so every output is summed in the same order.
+constexpr int kGWaves = 8;
+constexpr int kGThreads = kGWaves * 64;
+constexpr int kGRB = 2;                          // 32-row blocks per wave
+constexpr int kGT = 2;                           // 32-column tiles (63 residual columns)
+constexpr int kGRows = kGWaves * kGRB * 32;      // 512
+constexpr int kGPosMax = 32;                     // alignment columns per block at most
+constexpr int kGSiteWords = kRfChunkBytes / 2;   // one site's chunk in 16-bit words
+
+__host__ __device__ inline int32_t g3_block_positions(int32_t q) {
+  return kGRows / q < kGPosMax ? kGRows / q : kGPosMax;
+}
+
+// The two chunk buffers are separate LDS arrays so that the compiler can tell
+// the copy into one from the reads of the other (otherwise it waits for the
+// copy before every read).
+__device__ inline void g3_item(const BatchArgs& bt, const EvalArgs& a, const Item& it, uint16_t* Rf0,
+                               uint16_t* Rf1, uint8_t* sig0, uint8_t* sig1) {
+  const int npos_blk = g3_block_positions(a.q);
+  const int q = a.q, N = a.N, qq = q * q;
+  const int i0 = it.sub * npos_blk;
+  const int npos = min(npos_blk, N - i0);
+  const int nrows = npos * q;
+  const int tid = item_tid(), lane = tid & 63, wid = tid >> 6;
+  const int half = lane >> 5, l32 = lane & 31;
+  const int cnt = it.cnt;
+  int32_t rs[kG3Sites];
+#pragma unroll
+  for (int g = 0; g < kG3Sites; ++g)
+    rs[g] = g < cnt ? bt.active[it.first + g] - bt.site_base[it.m] : it.r;
+
+  int arow_off[kGRB];
+  uint32_t arow_kk[kGRB];
+#pragma unroll
+  for (int m = 0; m < kGRB; ++m) {
+    const int rho = (wid * kGRB + m) * 32 + l32;
+    const bool ok = rho < nrows;
+    arow_off[m] = ok ? (rho / q) * kSigPitch : 0;
+    arow_kk[m] = (ok ? (uint32_t)(rho % q) : 31u) * 0x01010101u;
+  }
+  const bool wave_live = wid * kGRB * 32 < nrows;
+  // this lane's B-fragment column in each tile: residual column 32 T + l32 =
+  // (site, state); column 63 reads a valid word of site 2 and is never written out
+  uint32_t boff[kGT];
+#pragma unroll
+  for (int T = 0; T < kGT; ++T) {
+    const int col = min(32 * T + l32, 3 * kSlot - 1);
+    const int g = col / kSlot, sidx = col - g * kSlot;
+    boff[T] = (uint32_t)(g * kRfChunkBytes + half * (kSlot * 16) + sidx * 16);
+  }
+
+  const int nchunks = (a.B3 + kMChunk - 1) / kMChunk;
+  const int nch_site = a.B_pad >> 8;
+  const int nsig = npos_blk * (kMChunk / 16);
+  // global -> LDS copy of the group's residual chunk c: 21 x 1 KB per site
+  auto fetch_r = [&](int c, uint16_t* dst) {
+    const int ninst = cnt * (kRfChunkBytes / 1024);
+    for (int k = wid; k < ninst; k += kGWaves) {
+      const int g = k / (kRfChunkBytes / 1024), part = k - g * (kRfChunkBytes / 1024);
+      const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
+      const char* src = reinterpret_cast<const char*>(a.R) +
+                        ((size_t)rg * nch_site + c) * kRfChunkBytes + part * 1024 + lane * 16;
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
+                                       (void __attribute__((address_space(3)))*)(
+                                           reinterpret_cast<char*>(dst) + g * kRfChunkBytes + part * 1024),
+                                       16, 0, 0);
+    }
+  };
+  uint4 sv;
+  auto load_sig = [&](int c) {
+    const int bc = c * kMChunk;
+    const int pos = tid >> 4, part = tid & 15;
+    sv = make_uint4(0, 0, 0, 0);
+    if (tid < nsig && i0 + pos < N) sv = gload_u4(a.msaT + (size_t)(i0 + pos) * a.B_pad + bc + part * 16);
+  };
+  auto store_sig = [&](uint8_t* dst) {
+    if (tid < nsig) *reinterpret_cast<uint4*>(dst + (tid >> 4) * kSigPitch + (tid & 15) * 16) = sv;
+  };
+
+  floatx16 acc[kGRB][kGT];
+  double acc64[kGRB][kGT][16];
+#pragma unroll
+  for (int m = 0; m < kGRB; ++m)
+#pragma unroll
+    for (int T = 0; T < kGT; ++T)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        acc[m][T][j] = 0.f;
+        acc64[m][T][j] = 0.0;
+      }
+
+  // chunk c from (cur, scur) while chunk c + 1 is copied into (nxt, snxt)
+  auto chunk = [&](int c, const uint16_t* cur, uint16_t* nxt, const uint8_t* scur, uint8_t* snxt) {
+    // the next buffers were last read before the previous barrier
+    if (c + 1 < nchunks) {
+      fetch_r(c + 1, nxt);
+      store_sig(snxt);
+    }
+    if (c + 2 < nchunks) load_sig(c + 2);
+    if (wave_live) {
+      const char* rb = reinterpret_cast<const char*>(cur);
+      const uint8_t* sgb = scur + half * 8;
+#pragma unroll 2
+      for (int t = 0; t < kMSteps; ++t) {
+        uint4 av[kGRB];
+#pragma unroll
+        for (int m = 0; m < kGRB; ++m)
+          av[m] = onehot8_x2(*reinterpret_cast<const uint2*>(sgb + arow_off[m] + t * 16), arow_kk[m]);
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int T = 0; T < kGT; ++T) {
+            const uint4 bp = *reinterpret_cast<const uint4*>(rb + boff[T] + (p * 16 + t) * (2 * kSlot * 16));
+#pragma unroll
+            for (int m = 0; m < kGRB; ++m)
+              acc[m][T] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, av[m]),
+                                                                 __builtin_bit_cast(f16x8, bp), acc[m][T], 0, 0, 0);
+          }
+      }
+#pragma unroll
+      for (int m = 0; m < kGRB; ++m)
+#pragma unroll
+        for (int T = 0; T < kGT; ++T)
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            acc64[m][T][j] += (double)acc[m][T][j];
+            acc[m][T][j] = 0.f;
+          }
+    }
+    // this wave's copies of chunk c + 1 (and the symbols of c + 2) have landed
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  };
+
+  fetch_r(0, Rf0);
+  load_sig(0);
+  store_sig(sig0);
+  if (nchunks > 1) load_sig(1);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int c = 0; c < nchunks; c += 2) {
+    chunk(c, Rf0, Rf1, sig0, sig1);
+    if (c + 1 < nchunks) chunk(c + 1, Rf1, Rf0, sig1, sig0);
+  }
+  if (!wave_live) return;
+#pragma unroll
+  for (int T = 0; T < kGT; ++T) {
+    const int col = 32 * T + l32;
+    const int g = col / kSlot, sidx = col - g * kSlot;
+    if (g >= cnt || sidx >= q) continue;
+    const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
+#pragma unroll
+    for (int m = 0; m < kGRB; ++m)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int row = (wid * kGRB + m) * 32 + 8 * (j >> 2) + 4 * half + (j & 3);
+        if (row < nrows) {
+          const int i = i0 + row / q, k = row % q;
+          gmem_w(a.gJ)[((size_t)rg * N + i) * qq + (size_t)k * q + sidx] =
+              (i == rg) ? 0.0 : acc64[m][T][j] * ((double)(1.0f / kRfScale) * kOneHotUnscale);
+        }
+      }
+  }
+}
+
+__global__ __launch_bounds__(kGThreads) void bwd_g3_kernel(BatchArgs b) {
+  __shared__ __attribute__((aligned(16))) uint16_t Rf0[kG3Sites * kGSiteWords];
+  __shared__ __attribute__((aligned(16))) uint16_t Rf1[kG3Sites * kGSiteWords];
+  __shared__ __attribute__((aligned(16))) uint8_t sig0[kGPosMax * kSigPitch];
+  __shared__ __attribute__((aligned(16))) uint8_t sig1[kGPosMax * kSigPitch];
+  __shared__ int32_t item_s;
+  int32_t qi = 0;
+  const int32_t total = total_items(b, KIND_BWD);
+  for (;;) {
+    if (threadIdx.x == 0) item_s = next_item(b.ctr + KIND_BWD * kQueues, total, qi);
+    __syncthreads();
+    const int32_t t = __builtin_amdgcn_readfirstlane(item_s);
+    if (t < 0) break;
+    const Item it = decode_item(b, KIND_BWD, t);
+    const EvalArgs a = load_uniform(b.ev + it.m);
+    g3_item(b, a, it, Rf0, Rf1, sig0, sig1);
+    __syncthreads();
+  }
+}
+
+int32_t g3_backward_blocks_per_site(int32_t N, int32_t q) {
+  const int32_t p = g3_block_positions(q);
+  return (N + p - 1) / p;
+}
+
+int32_t g3_resident_blocks() {
+  int per = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bwd_g3_kernel, kGThreads, 0);
+  return (e == hipSuccess && per > 0) ? per : 1;
+}
+
+hipError_t launch_backward_g3(const BatchArgs& b, int32_t nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(bwd_g3_kernel, dim3(nblocks), dim3(kGThreads), 0, st, b);
+  return hipGetLastError();
+}
+
 int32_t mfma_backward_blocks_per_site(int32_t N, int32_t q) {
   const int32_t p = mfma_block_positions(q);
   return (N + p - 1) / p;

@@ -445,8 +445,9 @@ __global__ void sym_finish_kernel(SymArgs a, BatchArgs b) {
     b.seg[0] = 0;
     b.seg[1] = n;
     for (int kind = 0; kind < 2; ++kind) {
+      const int grp = kind_group(b, kind);
       b.item_off[kind * 2] = 0;
-      b.item_off[kind * 2 + 1] = n * b.nsub[kind];
+      b.item_off[kind * 2 + 1] = (n + grp - 1) / grp * b.nsub[kind];
     }
     if (a.done_host) *a.done_host = S->phase == PH_DONE ? 1 : 0;
   }

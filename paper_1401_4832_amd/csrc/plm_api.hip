@@ -75,7 +75,8 @@ void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
   e.tiles_max = (B + forward_tile_seqs(16) - 1) / forward_tile_seqs(16);
   e.msa_cm = bp.take<uint8_t>((size_t)e.B_pad * e.N_pad);
   e.msaT = bp.take<uint8_t>((size_t)e.B_pad * e.N_pad);
-  e.R = bp.take<float>((size_t)N * e.B3 * kSlot);
+  // FP32 rows [B3][21], or the fragment-order FP16 pieces over B_pad rows
+  e.R = bp.take<float>((size_t)N * e.B_pad * kSlot);
   e.f_part = bp.take<double>((size_t)e.tiles_max * N);
   e.gh_part = bp.take<double>((size_t)e.tiles_max * N * kSlot);
   e.gJ = bp.take<double>((size_t)N * N * q * q);
@@ -131,7 +132,7 @@ void layout_tables(Bump& bp, int32_t n_msas, int32_t total, bool fit, Tables& t)
   t.site_evals = bp.take<unsigned long long>(1);
 }
 
-BatchArgs batch_args(const Tables& t, int32_t n_msas, int32_t total) {
+BatchArgs batch_args(const Tables& t, int32_t n_msas, int32_t total, int32_t group) {
   BatchArgs b;
   b.ev = t.ev;
   b.lb = t.lb;
@@ -145,6 +146,7 @@ BatchArgs batch_args(const Tables& t, int32_t n_msas, int32_t total) {
   b.item_off = t.item_off;
   b.nsub = t.nsub;
   b.ctr = t.ctr;
+  b.bwd_group = group;
   return b;
 }
 
@@ -220,15 +222,19 @@ int32_t pick_nb(int32_t B, int32_t tile_seqs) {
 struct PathSpec {
   int fwd_np, bwd_np;
   int bwd_f16;  // gradient pieces in FP16 (of R * 2^12) instead of BF16
+  int bwd_g3;   // grouped gradient: three sites per item, R split by the forward
 };
+
+// sites per gradient work item
+int32_t bwd_group(const PathSpec& p) { return p.bwd_g3 ? kG3Sites : 1; }
 
 bool path_spec(int32_t path, PathSpec* p) {
   switch (path) {
-    case PLM_PATH_GATHER_FP32: *p = {0, 0, 0}; return true;
-    case PLM_PATH_MFMA_BF16X2: *p = {2, 2, 0}; return true;
-    case PLM_PATH_GATHER_MFMA_FP32: *p = {0, 3, 0}; return true;
-    case PLM_PATH_MFMA_FP32: *p = {3, 3, 0}; return true;
-    case PLM_PATH_GATHER_MFMA_F16X2: *p = {0, 2, 1}; return true;
+    case PLM_PATH_GATHER_FP32: *p = {0, 0, 0, 0}; return true;
+    case PLM_PATH_MFMA_BF16X2: *p = {2, 2, 0, 0}; return true;
+    case PLM_PATH_GATHER_MFMA_FP32: *p = {0, 3, 0, 0}; return true;
+    case PLM_PATH_MFMA_FP32: *p = {3, 3, 0, 0}; return true;
+    case PLM_PATH_GATHER_MFMA_F16X2: *p = {0, 2, 1, 1}; return true;
     default: return false;
   }
 }
@@ -239,6 +245,7 @@ int32_t eval_tiles(const PathSpec& p, int32_t B, int32_t nb) {
 }
 
 int32_t eval_bwd_blocks(const PathSpec& p, int32_t N, int32_t q) {
+  if (p.bwd_g3) return g3_backward_blocks_per_site(N, q);
   return p.bwd_np ? mfma_backward_blocks_per_site(N, q) : backward_blocks_per_site(N);
 }
 
@@ -256,7 +263,9 @@ struct Grids {
 Grids eval_grids(const plm_ctx* c, const PathSpec& p, int32_t nb) {
   Grids g;
   g.fwd = c->ncu * (p.fwd_np ? mfma_resident_blocks(KIND_FWD, p.fwd_np) : forward_resident_blocks(nb));
-  g.bwd = c->ncu * (p.bwd_np ? mfma_resident_blocks(KIND_BWD, p.bwd_np) : backward_resident_blocks());
+  g.bwd = c->ncu * (p.bwd_g3   ? g3_resident_blocks()
+                    : p.bwd_np ? mfma_resident_blocks(KIND_BWD, p.bwd_np)
+                               : backward_resident_blocks());
   return g;
 }
 
@@ -266,11 +275,12 @@ hipError_t eval_forward(const PathSpec& p, const BatchArgs& b, int32_t nb, const
 }
 
 hipError_t eval_backward(const PathSpec& p, const BatchArgs& b, const Grids& g, hipStream_t st) {
+  if (p.bwd_g3) return launch_backward_g3(b, g.bwd, st);
   return p.bwd_np ? launch_backward_mfma(b, p.bwd_np, p.bwd_f16, g.bwd, st) : launch_backward(b, g.bwd, st);
 }
 
 EvalArgs eval_args(const EvalBufs& e, const uint8_t* msa_unused, int32_t B, int32_t N, int32_t q,
-                   const double* w, const float* h, const float* J, int32_t tiles) {
+                   const double* w, const float* h, const float* J, int32_t tiles, const PathSpec& ps) {
   (void)msa_unused;
   EvalArgs a;
   a.msa_cm = e.msa_cm;
@@ -279,6 +289,7 @@ EvalArgs eval_args(const EvalBufs& e, const uint8_t* msa_unused, int32_t B, int3
   a.w = w; a.h = h; a.J = J;
   a.R = e.R; a.f_part = e.f_part; a.gh_part = e.gh_part; a.gJ = e.gJ;
   a.tiles = tiles;
+  a.rfrag = ps.bwd_g3;
   a.sorted = e.sorted;
   return a;
 }
@@ -420,14 +431,14 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
   layout_eval(bp, B, N, q, e);
   Tables t;
   layout_tables(bp, 1, N, false, t);
-  const BatchArgs b = batch_args(t, 1, N);
+  const BatchArgs b = batch_args(t, 1, N, bwd_group(ps));
   HIPCHK(c, launch_check_f64(w, (size_t)B, c->pin_dev, c->stream));
   HIPCHK(c, launch_check_f32(h, (size_t)N * q, c->pin_dev, c->stream));
   HIPCHK(c, launch_check_f32(J, (size_t)N * N * q * q, c->pin_dev, c->stream));
   if (grad_scale) HIPCHK(c, launch_check_f64(grad_scale, (size_t)N, c->pin_dev, c->stream));
   HIPCHK(c, launch_pad_msa(msa, B, N, q, e.msa_cm, e.B_pad, e.N_pad, c->pin_dev, c->stream));
   const int32_t nb = pick_nb(B, 0);
-  const EvalArgs a = eval_args(e, msa, B, N, q, w, h, J, eval_tiles(ps, B, nb));
+  const EvalArgs a = eval_args(e, msa, B, N, q, w, h, J, eval_tiles(ps, B, nb), ps);
   HIPCHK(c, launch_setup_msa(b, 0, a, nullptr, 0, N, a.tiles, eval_bwd_blocks(ps, N, q), nullptr,
                              c->stream));
   HIPCHK(c, launch_list_tables(b, sites, 0, n_sites, c->pin_dev, c->stream));
@@ -545,7 +556,7 @@ int prepare_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const p
   Tables t;
   fit_layout(d, n, q, o, (char*)ws, &fb, &t);
   const std::vector<int32_t> ord = batch_order(d, n);
-  const BatchArgs b = batch_args(t, n, total);
+  const BatchArgs b = batch_args(t, n, total, bwd_group(ps));
   // the fit runs on the context's private stream once the caller's stream has
   // delivered its inputs, and returns after the private stream has finished
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -563,7 +574,7 @@ int prepare_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const p
     HIPCHK(c, launch_pad_msa(m.msa, m.B, m.N, q, f.ev.msa_cm, f.ev.B_pad, f.ev.N_pad, c->pin_dev, st));
     HIPCHK(c, launch_init_fit(m.N, q, m.h_io, m.J_io, f.Th, f.TJ, t.st + base[k], phase_host_dev + base[k], st));
     HIPCHK(c, launch_check_f32(m.J_io, (size_t)m.N * m.N * q * q, c->pin_dev, st));
-    const EvalArgs a = eval_args(f.ev, m.msa, m.B, m.N, q, m.w, f.Th, f.TJ, eval_tiles(ps, m.B, nb));
+    const EvalArgs a = eval_args(f.ev, m.msa, m.B, m.N, q, m.w, f.Th, f.TJ, eval_tiles(ps, m.B, nb), ps);
     HIPCHK(c, eval_prepare(ps, a, f.ev.msaT, f.ev.sorted, st));
     LbfgsArgs L;
     L.N = m.N; L.q = q; L.m = o->lbfgs_m; L.max_iter = o->max_iter; L.max_ls = o->max_linesearch;
@@ -931,12 +942,12 @@ int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int3
   HIPCHK(c, hipMemcpyAsync(f.pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice, st));
 
   const int32_t nb = pick_nb(B, o->tile_seqs);
-  const BatchArgs b = batch_args(f.t, 1, N);
+  const BatchArgs b = batch_args(f.t, 1, N, bwd_group(ps));
   HIPCHK(c, launch_check_f64(w, (size_t)B, c->pin_dev, st));
   HIPCHK(c, launch_check_f32(h_io, (size_t)N * q, c->pin_dev, st));
   HIPCHK(c, launch_check_f32(J_io, (size_t)N * N * q * q, c->pin_dev, st));
   HIPCHK(c, launch_pad_msa(msa, B, N, q, f.ev.msa_cm, f.ev.B_pad, f.ev.N_pad, c->pin_dev, st));
-  const EvalArgs a = eval_args(f.ev, msa, B, N, q, w, f.Th, f.TJ, eval_tiles(ps, B, nb));
+  const EvalArgs a = eval_args(f.ev, msa, B, N, q, w, f.Th, f.TJ, eval_tiles(ps, B, nb), ps);
   HIPCHK(c, eval_prepare(ps, a, f.ev.msaT, f.ev.sorted, st));
   HIPCHK(c, launch_setup_msa(b, 0, a, nullptr, 0, N, a.tiles, eval_bwd_blocks(ps, N, q), nullptr, st));
   HIPCHK(c, launch_list_tables(b, nullptr, 0, N, nullptr, st));

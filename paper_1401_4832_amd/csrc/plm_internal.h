@@ -63,8 +63,23 @@ struct EvalArgs {
   double* gh_part;         // [tiles][N][21]
   double* gJ;              // [N][N][q][q] data part of d f / d J (FP64)
   int32_t tiles;
+  int32_t rfrag;           // 1: R is stored as FP16 pieces in gradient-fragment order (see below)
   const uint16_t* sorted;  // [nchunks][N][kBwdSeqChunk]: (row << 8) | symbol, rows sorted by symbol
 };
+
+// Residuals in gradient-fragment order (rfrag = 1): R_b(s) * kRfScale split
+// into FP16 hi and lo pieces, stored per site as [chunk of 256 sequences]
+// [piece][step of 16][half of 8][state 0..20][sequence 0..7] (16-bit words):
+// each (chunk, site) is 21504 contiguous bytes, copied into LDS as is by the
+// grouped MFMA gradient.  Covers B_pad rows per site.
+constexpr float kRfScale = 4096.f;
+constexpr int kRfChunk = 256;
+constexpr int kRfPieceWords = 16 * 2 * kSlot * 8;          // 5376
+constexpr int kRfChunkBytes = 2 * kRfPieceWords * 2;       // 21504
+__device__ inline size_t rfrag_index(int32_t r, int32_t nch, int32_t b, int32_t s) {
+  const size_t c = (size_t)r * nch + (b >> 8);
+  return ((((c * 2) * 16 + ((b >> 4) & 15)) * 2 + ((b >> 3) & 1)) * kSlot + s) * 8 + (b & 7);
+}
 
 
 // Arguments of the optimiser kernel (one block per site).
@@ -129,10 +144,18 @@ struct BatchArgs {
   int32_t* item_off;         // [2][n_msas + 1] work-item offsets (forward, backward)
   const int32_t* nsub;       // [2][n_msas] work items per site (forward tiles, backward blocks)
   uint32_t* ctr;             // [2][kQueues] queue counters, cleared when the tables are built
+  int32_t bwd_group;         // sites per gradient work item (consecutive in the active list)
 };
 
+// sites per work item of a kind
+__host__ __device__ inline int32_t kind_group(const BatchArgs& b, int kind) {
+  return kind == KIND_BWD ? b.bwd_group : 1;
+}
+
+// g, r: the first site of the item; first: its position in the active list;
+// cnt: the item's sites (active[first .. first + cnt), one alignment)
 struct Item {
-  int32_t m, g, r, sub;
+  int32_t m, g, r, sub, first, cnt;
 };
 
 // Next work item of a persistent block (call from one thread).  The block
@@ -214,10 +237,13 @@ __device__ inline Item decode_item(const BatchArgs& b, int kind, int32_t t) {
   Item it;
   it.m = lo;
   const int32_t ns = b.nsub[kind * b.n_msas + lo];
+  const int32_t grp = kind_group(b, kind);
   const int32_t loc = t - off[lo];
   const int32_t j = loc / ns;
   it.sub = loc - j * ns;
-  it.g = b.active[b.seg[lo] + j];
+  it.first = b.seg[lo] + j * grp;
+  it.cnt = min(grp, b.seg[lo + 1] - it.first);
+  it.g = b.active[it.first];
   it.r = it.g - b.site_base[lo];
   return it;
 }
@@ -292,6 +318,11 @@ hipError_t launch_backward(const BatchArgs& b, int32_t nblocks, hipStream_t st);
 int32_t mfma_forward_tile_seqs();
 int32_t mfma_backward_blocks_per_site(int32_t N, int32_t q);
 int32_t mfma_resident_blocks(int32_t kind, int32_t npieces);
+// grouped FP16 hi/lo MFMA gradient (three sites per item, R in fragment order)
+constexpr int kG3Sites = 3;
+int32_t g3_backward_blocks_per_site(int32_t N, int32_t q);
+int32_t g3_resident_blocks();
+hipError_t launch_backward_g3(const BatchArgs& b, int32_t nblocks, hipStream_t st);
 hipError_t launch_forward_mfma(const BatchArgs& b, int32_t npieces, int32_t nblocks, hipStream_t st);
 hipError_t launch_backward_mfma(const BatchArgs& b, int32_t npieces, int32_t f16, int32_t nblocks,
                                 hipStream_t st);
