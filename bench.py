@@ -236,7 +236,8 @@ def main():
         if np_dom:
             # dense matrix-core flops of the one-hot product: q MACs per unit and piece
             flops = units_all * 2 * Q * np_dom
-            kname = f"{dom}_mfma"
+            # path 4's gradient is the grouped three-site kernel
+            kname = "backward_g3" if (dom == "backward" and path == 4) else f"{dom}_mfma"
             # BF16 and FP16 dense matrix-core peaks are the same on this chip
             roofline = {"bound": "mfma", "achieved": flops / t_dom / 1e12, "peak": MFMA_BF16_PEAK / 1e12,
                         "unit": "TFLOP/s", "frac": flops / t_dom / MFMA_BF16_PEAK,

@@ -292,6 +292,7 @@ constexpr int kFSteps = kFGroups / 2;              // 12 MFMA steps per chunk
 constexpr int kFPiece = kFGroups * 32 * 8;         // BF16 entries of one piece of one chunk
 
 int32_t mfma_forward_tile_seqs() { return kFRows; }
+static_assert(kBPadUnit % kFRows == 0, "row padding covers the MFMA forward tiles");
 
 // one-hot of sigma against the eight states kb..kb+7 (d = sigma - kb, unsigned)
 __device__ inline bf16x8 onehot_range(uint32_t d) {
@@ -694,6 +695,25 @@ __global__ __launch_bounds__(kGThreads) void bwd_g3_kernel(BatchArgs b) {
     g3_item(b, a, it, Rf0, Rf1, sig0, sig1);
     __syncthreads();
   }
+}
+
+__global__ void rfrag_tail_zero_kernel(uint4* R, int32_t N, int32_t nch_site, int32_t c0, int32_t c1) {
+  const int64_t per = (int64_t)(c1 - c0) * (kRfChunkBytes / 16);
+  const int64_t total = per * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / per, k = e - r * per;
+    R[(r * nch_site + c0) * (kRfChunkBytes / 16) + k] = make_uint4(0, 0, 0, 0);
+  }
+}
+
+hipError_t launch_rfrag_tail_zero(float* R, int32_t N, int32_t B, int32_t B3, int32_t B_pad, hipStream_t st) {
+  const int32_t c0 = B >> 8, c1 = (B3 + 255) >> 8;
+  if (c0 >= c1) return hipSuccess;
+  const int64_t total = (int64_t)(c1 - c0) * (kRfChunkBytes / 16) * N;
+  const int blocks = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+  hipLaunchKernelGGL(rfrag_tail_zero_kernel, dim3(blocks), dim3(256), 0, st, reinterpret_cast<uint4*>(R), N,
+                     B_pad >> 8, c0, c1);
+  return hipGetLastError();
 }
 
 int32_t g3_backward_blocks_per_site(int32_t N, int32_t q) {

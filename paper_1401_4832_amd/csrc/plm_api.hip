@@ -69,7 +69,7 @@ struct EvalBufs {
 };
 
 void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
-  e.B_pad = (int32_t)rup(B, forward_tile_seqs(64));
+  e.B_pad = (int32_t)rup(B, kBPadUnit);
   e.N_pad = (int32_t)rup(N, kFwdChunk);
   e.B3 = (int32_t)rup(B, 3);
   e.tiles_max = (B + forward_tile_seqs(16) - 1) / forward_tile_seqs(16);
@@ -249,8 +249,14 @@ int32_t eval_bwd_blocks(const PathSpec& p, int32_t N, int32_t q) {
   return p.bwd_np ? mfma_backward_blocks_per_site(N, q) : backward_blocks_per_site(N);
 }
 
+// Once per alignment, before the first forward: the gradient path's symbol
+// copy (and, for the grouped gradient, the residual rows no forward tile writes).
 hipError_t eval_prepare(const PathSpec& p, const EvalArgs& a, uint8_t* msaT, uint16_t* sorted,
                         hipStream_t st) {
+  if (p.bwd_g3) {
+    const hipError_t e = launch_rfrag_tail_zero(a.R, a.N, a.B, a.B3, a.B_pad, st);
+    if (e != hipSuccess) return e;
+  }
   if (p.bwd_np) return launch_transpose_msa(a.msa_cm, a.B_pad, a.N_pad, msaT, st);
   return launch_chunk_sort(a.msa_cm, a.B3, a.B_pad, a.N, a.q, sorted, st);
 }
@@ -443,11 +449,9 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
                              c->stream));
   HIPCHK(c, launch_list_tables(b, sites, 0, n_sites, c->pin_dev, c->stream));
   const Grids g = eval_grids(c, ps, nb);
+  if (gJ_out) HIPCHK(c, eval_prepare(ps, a, e.msaT, e.sorted, c->stream));
   HIPCHK(c, eval_forward(ps, b, nb, g, c->stream));
-  if (gJ_out) {
-    HIPCHK(c, eval_prepare(ps, a, e.msaT, e.sorted, c->stream));
-    HIPCHK(c, eval_backward(ps, b, g, c->stream));
-  }
+  if (gJ_out) HIPCHK(c, eval_backward(ps, b, g, c->stream));
   FinalArgs fa;
   fa.N = N; fa.q = q; fa.tiles = a.tiles; fa.lambda_h = lambda_h; fa.lambda_Jp = 0.5 * lambda_J;
   fa.beff = beff; fa.h = h; fa.J = J; fa.sites = t.active;  // the checked site list

@@ -19,9 +19,14 @@ constexpr int kRowF = 64;
 constexpr int kQMax = 21;
 constexpr int kMMax = 32;  // L-BFGS history cap
 
-// Forward kernel: 16 waves, 16 alignment columns staged per LDS chunk.
-constexpr int kFwdWaves = 16;
+// Forward kernel: 8 waves, 16 alignment columns per symbol chunk.
+constexpr int kFwdWaves = 8;
 constexpr int kFwdThreads = kFwdWaves * 64;
+// Row padding of every alignment: a multiple of every forward tile (the
+// gather tiles of 16, 32 or 64 rows per wave and the 1024-row MFMA tile) and
+// of the 256-row gradient chunk, so that no tile or chunk reads past it.
+constexpr int kBPadUnit = 3072;
+static_assert(kBPadUnit % (kFwdWaves * kSlots * 64) == 0 && kBPadUnit % 256 == 0, "row padding");
 constexpr int kFwdChunk = 16;
 // Backward kernel: 16 waves; the three slots of a wave own three different
 // alignment columns (48 per block).  Sequences are processed in chunks of 192
@@ -323,6 +328,10 @@ constexpr int kG3Sites = 3;
 int32_t g3_backward_blocks_per_site(int32_t N, int32_t q);
 int32_t g3_resident_blocks();
 hipError_t launch_backward_g3(const BatchArgs& b, int32_t nblocks, hipStream_t st);
+// zero the fragment-order residual rows [B rounded down to 256, B3 rounded up
+// to 256) of every site: the forward writes only the rows of its tiles, and the
+// last gradient chunk may reach past them
+hipError_t launch_rfrag_tail_zero(float* R, int32_t N, int32_t B, int32_t B3, int32_t B_pad, hipStream_t st);
 hipError_t launch_forward_mfma(const BatchArgs& b, int32_t npieces, int32_t nblocks, hipStream_t st);
 hipError_t launch_backward_mfma(const BatchArgs& b, int32_t npieces, int32_t f16, int32_t nblocks,
                                 hipStream_t st);
