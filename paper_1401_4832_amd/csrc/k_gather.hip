@@ -81,7 +81,7 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
   const int bw = tile0 + tw;
 
   float E[NB];
-  const float hv = act ? a.h[r * q + s] : 0.f;
+  const float hv = act ? gmem(a.h)[r * q + s] : 0.f;
 #pragma unroll
   for (int j = 0; j < NB; ++j) E[j] = hv;
 
@@ -189,8 +189,8 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
       }
       sum = __shfl(sum, sbase, 64);
       const float lse = m + logf(sum);
-      const int sr = a.msa_cm[((size_t)(r / kFwdChunk) * a.B_pad + b) * kFwdChunk + r % kFwdChunk];
-      const double wb = (slot < kSlots && b < a.B) ? a.w[b] : 0.0;
+      const int sr = gmem(a.msa_cm)[((size_t)(r / kFwdChunk) * a.B_pad + b) * kFwdChunk + r % kFwdChunk];
+      const double wb = (slot < kSlots && b < a.B) ? gmem(a.w)[b] : 0.0;
       const float P = ex / sum;
       const float Rv = act ? (float)wb * (P - (s == sr ? 1.f : 0.f)) : 0.f;
       if (act && s == sr) facc += wb * (double)(lse - e);
@@ -213,14 +213,14 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
     }
   }
   const double ftot = block_sum_f64(facc, red);
-  if (tid == 0) a.f_part[(size_t)tile * N + r] = ftot;
+  if (tid == 0) gmem_w(a.f_part)[(size_t)tile * N + r] = ftot;
   red[wid * 64 + lane] = (slot < kSlots) ? ghacc : 0.0;
   __syncthreads();
   if (tid < kSlot) {
     double t = 0.0;
     for (int w = 0; w < kFwdWaves; ++w)
       for (int c = 0; c < kSlots; ++c) t += red[w * 64 + c * kSlot + tid];
-    a.gh_part[((size_t)tile * N + r) * kSlot + tid] = t;
+    gmem_w(a.gh_part)[((size_t)tile * N + r) * kSlot + tid] = t;
   }
 }
 

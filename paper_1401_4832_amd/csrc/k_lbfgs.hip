@@ -88,40 +88,46 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
   const double ib = 1.0 / beff;
   const size_t h0 = (size_t)r * q, j0 = (size_t)r * Nqq;
   const int self0 = q + r * q * q, self1 = self0 + q * q;  // self block range in e
-  double* StY = a.small + (size_t)r * 2 * M * M;            // [M][M] s_i . y_j by slot
-  double* YtY = StY + (size_t)M * M;                         // [M][M] y_i . y_j by slot
+  // every buffer seen as global memory (the descriptor comes from memory, so
+  // the pointers would otherwise be generic and every access a flat one)
+  const auto Th = gmem_w(a.Th), TJ = gmem_w(a.TJ), Xh = gmem_w(a.Xh), XJ = gmem_w(a.XJ);
+  const auto Ghp = gmem_w(a.Gh), GJp = gmem_w(a.GJ), Dhp = gmem_w(a.Dh), DJp = gmem_w(a.DJ);
+  const auto Shp = gmem_w(a.Sh), SJp = gmem_w(a.SJ), Yhp = gmem_w(a.Yh), YJp = gmem_w(a.YJ);
+  const auto gJd = gmem(a.gJ);
+  const auto StY = gmem_w(a.small + (size_t)r * 2 * M * M);  // [M][M] s_i . y_j by slot
+  const auto YtY = StY + (size_t)M * M;                       // [M][M] y_i . y_j by slot
 
   // ---- gather the evaluation at the trial point ----
   if (tid < q) {
     double t = 0.0;
-    for (int k = 0; k < a.tiles; ++k) t += a.gh_part[((size_t)k * N + r) * kSlot + tid];
+    for (int k = 0; k < a.tiles; ++k) t += gmem(a.gh_part)[((size_t)k * N + r) * kSlot + tid];
     sh.ghd[tid] = t;
   }
   double fdata = 0.0;
   if (tid == 0)
-    for (int k = 0; k < a.tiles; ++k) fdata += a.f_part[(size_t)k * N + r];
+    for (int k = 0; k < a.tiles; ++k) fdata += gmem(a.f_part)[(size_t)k * N + r];
   __syncthreads();
 
   const double lam_h = a.lambda_h, lam_J = a.lambda_Jp;
   auto lam = [&](int e) -> double { return e < q ? lam_h : ((e >= self0 && e < self1) ? 0.0 : lam_J); };
-  auto Tv = [&](int e) -> double { return e < q ? (double)a.Th[h0 + e] : (double)a.TJ[j0 + (e - q)]; };
-  auto Xv = [&](int e) -> double { return e < q ? (double)a.Xh[h0 + e] : (double)a.XJ[j0 + (e - q)]; };
+  auto Tv = [&](int e) -> double { return e < q ? (double)Th[h0 + e] : (double)TJ[j0 + (e - q)]; };
+  auto Xv = [&](int e) -> double { return e < q ? (double)Xh[h0 + e] : (double)XJ[j0 + (e - q)]; };
   auto gtv = [&](int e) -> double {
-    const double d = e < q ? sh.ghd[e] : a.gJ[j0 + (e - q)];
+    const double d = e < q ? sh.ghd[e] : gJd[j0 + (e - q)];
     return d * ib + 2.0 * lam(e) * Tv(e);
   };
-  auto Gv = [&](int e) -> double { return e < q ? a.Gh[h0 + e] : a.GJ[j0 + (e - q)]; };
-  auto Dp = [&](int e) -> double* { return e < q ? a.Dh + h0 + e : a.DJ + j0 + (e - q); };
-  auto Gp = [&](int e) -> double* { return e < q ? a.Gh + h0 + e : a.GJ + j0 + (e - q); };
-  auto Sp = [&](int k, int e) -> double* {
-    return e < q ? a.Sh + ((size_t)k * N) * q + h0 + e : a.SJ + (size_t)k * N * Nqq + j0 + (e - q);
+  auto Gv = [&](int e) -> double { return e < q ? Ghp[h0 + e] : GJp[j0 + (e - q)]; };
+  auto Dp = [&](int e) { return e < q ? Dhp + h0 + e : DJp + j0 + (e - q); };
+  auto Gp = [&](int e) { return e < q ? Ghp + h0 + e : GJp + j0 + (e - q); };
+  auto Sp = [&](int k, int e) {
+    return e < q ? Shp + ((size_t)k * N) * q + h0 + e : SJp + (size_t)k * N * Nqq + j0 + (e - q);
   };
-  auto Yp = [&](int k, int e) -> double* {
-    return e < q ? a.Yh + ((size_t)k * N) * q + h0 + e : a.YJ + (size_t)k * N * Nqq + j0 + (e - q);
+  auto Yp = [&](int k, int e) {
+    return e < q ? Yhp + ((size_t)k * N) * q + h0 + e : YJp + (size_t)k * N * Nqq + j0 + (e - q);
   };
   auto storeT = [&](int e, double v) {
     const float f = (float)v;
-    if (e < q) a.Th[h0 + e] = f; else a.TJ[j0 + (e - q)] = (e >= self0 && e < self1) ? 0.f : f;
+    if (e < q) Th[h0 + e] = f; else TJ[j0 + (e - q)] = (e >= self0 && e < self1) ? 0.f : f;
   };
   auto writeT = [&](double alpha) {
     for (int e = tid; e < P; e += nth) storeT(e, Xv(e) + alpha * *Dp(e));
@@ -184,7 +190,7 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
           }
       }
       *Gp(e) = g;
-      if (e < q) a.Xh[h0 + e] = a.Th[h0 + e]; else a.XJ[j0 + (e - q)] = a.TJ[j0 + (e - q)];
+      if (e < q) Xh[h0 + e] = Th[h0 + e]; else XJ[j0 + (e - q)] = TJ[j0 + (e - q)];
     }
     if (pair) {
       block_sum_vec(acc, sh);
@@ -333,17 +339,40 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
       }
     }
     __syncthreads();
+    // four elements per thread at a time (e, e + nth, e + 2 nth, e + 3 nth,
+    // the same order as a plain strided loop), so that the history loads of
+    // four elements are in flight together
     double dg = 0.0;
-    for (int e = tid; e < P; e += nth) {
-      const double g = Gv(e);
-      double d = -gamma * g;
+    constexpr int U = 4;
+    for (int e0 = tid; e0 < P; e0 += U * nth) {
+      int ee[U];
+      double g[U], d[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        ee[u] = min(e0 + u * nth, P - 1);
+        g[u] = Gv(ee[u]);
+        d[u] = -gamma * g[u];
+      }
+#pragma unroll 2
       for (int i = 0; i < n; ++i) {
         const int k = sh.ord[i];
-        d += sh.cs[i] * *Sp(k, e) + sh.cy[i] * *Yp(k, e);
+        const double ci = sh.cs[i], yi = sh.cy[i];
+        double sv[U], yv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          sv[u] = *Sp(k, ee[u]);
+          yv[u] = *Yp(k, ee[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) d[u] += ci * sv[u] + yi * yv[u];
       }
-      *Dp(e) = d;
-      storeT(e, Xv(e) + d);  // trial point at alpha = 1
-      dg += d * g;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (e0 + u * nth < P) {
+          *Dp(ee[u]) = d[u];
+          storeT(ee[u], Xv(ee[u]) + d[u]);  // trial point at alpha = 1
+          dg += d[u] * g[u];
+        }
     }
     dg = block_sum_f64(dg, red);
     if (dg < 0.0) {

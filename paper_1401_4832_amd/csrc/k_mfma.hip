@@ -20,6 +20,8 @@
 // lane l holds row l % 32, inner indices 8 (l / 32) + 0..7; B lane l holds
 // column l % 32, the same inner indices; D lane l register j holds row
 // 8 (j / 4) + 4 (l / 32) + j % 4, column l % 32.
+#include <type_traits>
+
 #include "plm_internal.h"
 
 namespace plm {
@@ -519,7 +521,12 @@ constexpr int kGRB = 2;                          // 32-row blocks per wave
 constexpr int kGT = 2;                           // 32-column tiles (63 residual columns)
 constexpr int kGRows = kGWaves * kGRB * 32;      // 512
 constexpr int kGPosMax = 32;                     // alignment columns per block at most
-constexpr int kGSiteWords = kRfChunkBytes / 2;   // one site's chunk in 16-bit words
+// LDS stride between the sites' chunks: 21504 + 80 bytes, so that the 16-byte
+// slot (address / 16 mod 8) of column c is c mod 8 within every site's run
+// and the B-fragment reads of any 8 consecutive lanes hit distinct banks
+constexpr int kGSiteStride = kRfChunkBytes + 80;
+static_assert((kGSiteStride / 16 - kSlot) % 8 == 0 && kGSiteStride % 16 == 0, "bank-disjoint site runs");
+constexpr int kGBufWords = (2 * kGSiteStride + kRfChunkBytes) / 2;  // one chunk buffer in 16-bit words
 
 __host__ __device__ inline int32_t g3_block_positions(int32_t q) {
   return kGRows / q < kGPosMax ? kGRows / q : kGPosMax;
@@ -560,7 +567,7 @@ __device__ inline void g3_item(const BatchArgs& bt, const EvalArgs& a, const Ite
   for (int T = 0; T < kGT; ++T) {
     const int col = min(32 * T + l32, 3 * kSlot - 1);
     const int g = col / kSlot, sidx = col - g * kSlot;
-    boff[T] = (uint32_t)(g * kRfChunkBytes + half * (kSlot * 16) + sidx * 16);
+    boff[T] = (uint32_t)(g * kGSiteStride + half * (kSlot * 16) + sidx * 16);
   }
 
   const int nchunks = (a.B3 + kMChunk - 1) / kMChunk;
@@ -576,7 +583,7 @@ __device__ inline void g3_item(const BatchArgs& bt, const EvalArgs& a, const Ite
                         ((size_t)rg * nch_site + c) * kRfChunkBytes + part * 1024 + lane * 16;
       __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
                                        (void __attribute__((address_space(3)))*)(
-                                           reinterpret_cast<char*>(dst) + g * kRfChunkBytes + part * 1024),
+                                           reinterpret_cast<char*>(dst) + g * kGSiteStride + part * 1024),
                                        16, 0, 0);
     }
   };
@@ -614,8 +621,8 @@ __device__ inline void g3_item(const BatchArgs& bt, const EvalArgs& a, const Ite
     if (wave_live) {
       const char* rb = reinterpret_cast<const char*>(cur);
       const uint8_t* sgb = scur + half * 8;
-#pragma unroll 2
-      for (int t = 0; t < kMSteps; ++t) {
+      // one MFMA step; the first of a chunk starts its accumulators at zero
+      auto step = [&](int t, auto first) {
         uint4 av[kGRB];
 #pragma unroll
         for (int m = 0; m < kGRB; ++m)
@@ -626,20 +633,25 @@ __device__ inline void g3_item(const BatchArgs& bt, const EvalArgs& a, const Ite
           for (int T = 0; T < kGT; ++T) {
             const uint4 bp = *reinterpret_cast<const uint4*>(rb + boff[T] + (p * 16 + t) * (2 * kSlot * 16));
 #pragma unroll
-            for (int m = 0; m < kGRB; ++m)
+            for (int m = 0; m < kGRB; ++m) {
+              floatx16 c = acc[m][T];
+              if constexpr (decltype(first)::value) {
+                if (p == 0) c = floatx16{};
+              }
               acc[m][T] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, av[m]),
-                                                                 __builtin_bit_cast(f16x8, bp), acc[m][T], 0, 0, 0);
+                                                                 __builtin_bit_cast(f16x8, bp), c, 0, 0, 0);
+            }
           }
-      }
+      };
+      step(0, std::true_type{});
+#pragma unroll 3
+      for (int t = 1; t < kMSteps; ++t) step(t, std::false_type{});
 #pragma unroll
       for (int m = 0; m < kGRB; ++m)
 #pragma unroll
         for (int T = 0; T < kGT; ++T)
 #pragma unroll
-          for (int j = 0; j < 16; ++j) {
-            acc64[m][T][j] += (double)acc[m][T][j];
-            acc[m][T][j] = 0.f;
-          }
+          for (int j = 0; j < 16; ++j) acc64[m][T][j] += (double)acc[m][T][j];
     }
     // this wave's copies of chunk c + 1 (and the symbols of c + 2) have landed
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -678,8 +690,8 @@ __device__ inline void g3_item(const BatchArgs& bt, const EvalArgs& a, const Ite
 }
 
 __global__ __launch_bounds__(kGThreads) void bwd_g3_kernel(BatchArgs b) {
-  __shared__ __attribute__((aligned(16))) uint16_t Rf0[kG3Sites * kGSiteWords];
-  __shared__ __attribute__((aligned(16))) uint16_t Rf1[kG3Sites * kGSiteWords];
+  __shared__ __attribute__((aligned(16))) uint16_t Rf0[kGBufWords];
+  __shared__ __attribute__((aligned(16))) uint16_t Rf1[kGBufWords];
   __shared__ __attribute__((aligned(16))) uint8_t sig0[kGPosMax * kSigPitch];
   __shared__ __attribute__((aligned(16))) uint8_t sig1[kGPosMax * kSigPitch];
   __shared__ int32_t item_s;
