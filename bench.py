@@ -41,10 +41,12 @@ Q = 21
 ALU_ADD_PEAK = 256 * 64 * 2.4e9
 # dense BF16 matrix-core peak of the MI355X
 MFMA_BF16_PEAK = 2.5e15
+# dense int8 matrix-core peak (ops/s)
+MFMA_I8_PEAK = 5.0e15
 PATH_NAMES = {0: "gather_fp32", 1: "mfma_bf16x2", 2: "gather_mfma_fp32", 3: "mfma_fp32",
-              4: "gather_mfma_f16x2"}
+              4: "gather_mfma_f16x2", 5: "gather_mfma_i8x3"}
 # 16-bit pieces of the non-one-hot operand, per path: (forward, backward); 0 = LDS gather/scatter
-PATH_PIECES = {0: (0, 0), 1: (2, 2), 2: (0, 3), 3: (3, 3), 4: (0, 2)}
+PATH_PIECES = {0: (0, 0), 1: (2, 2), 2: (0, 3), 3: (3, 3), 4: (0, 2), 5: (0, 3)}
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -236,11 +238,13 @@ def main():
         if np_dom:
             # dense matrix-core flops of the one-hot product: q MACs per unit and piece
             flops = units_all * 2 * Q * np_dom
-            # path 4's gradient is the grouped three-site kernel
-            kname = "backward_g3" if (dom == "backward" and path == 4) else f"{dom}_mfma"
-            # BF16 and FP16 dense matrix-core peaks are the same on this chip
-            roofline = {"bound": "mfma", "achieved": flops / t_dom / 1e12, "peak": MFMA_BF16_PEAK / 1e12,
-                        "unit": "TFLOP/s", "frac": flops / t_dom / MFMA_BF16_PEAK,
+            # path 4's gradient is the grouped three-site kernel, path 5's its int8 form
+            kname = {4: "backward_g3", 5: "backward_i8"}.get(path, "backward_mfma") if dom == "backward" \
+                else f"{dom}_mfma"
+            # BF16 and FP16 dense matrix-core peaks are the same on this chip; int8 runs at twice the rate
+            peak = MFMA_I8_PEAK if (dom == "backward" and path == 5) else MFMA_BF16_PEAK
+            roofline = {"bound": "mfma", "achieved": flops / t_dom / 1e12, "peak": peak / 1e12,
+                        "unit": "TOP/s" if peak == MFMA_I8_PEAK else "TFLOP/s", "frac": flops / t_dom / peak,
                         "flops_per_unit": 2 * Q * np_dom}
         else:
             kname = dom

@@ -74,6 +74,11 @@ extern "C" {
                                   product with FP16 hi/lo pieces of R * 2^12 (22 significant
                                   bits: |dR| <= 2^-22 |R|; the scaling keeps the low piece out
                                   of the FP16 subnormal range) */
+#define PLM_PATH_GATHER_MFMA_I8X3 5 /* energies by LDS gather; coupling gradient as an int8 MFMA
+                                  product with R in fixed point: round(R * 2^22) as three signed
+                                  int8 digits (|dR| <= 2^-23, absolute; |R| <= w_b <= 1),
+                                  accumulated exactly in int32; at most 2^24 - 1 sequences
+                                  (PLM_E_UNSUPPORTED beyond) */
 
 typedef struct plm_ctx plm_ctx;
 

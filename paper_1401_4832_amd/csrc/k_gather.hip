@@ -195,7 +195,22 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
       const float Rv = act ? (float)wb * (P - (s == sr ? 1.f : 0.f)) : 0.f;
       if (act && s == sr) facc += wb * (double)(lse - e);
       ghacc += (double)Rv;
-      if (a.rfrag) {
+      if (a.rfrag == 2) {
+        // int8 digits of round(R * 2^22) in the int8 gradient's fragment
+        // order, for every row of the tile (zero past B)
+        if (slot < kSlots) {
+          const int v = (int)rintf(Rv * (float)(1 << kRiScaleLog2));
+          const int lo = (int)(int8_t)(v & 255);
+          const int v1 = (v - lo) >> 8;
+          const int mid = (int)(int8_t)(v1 & 255);
+          const int hi = (v1 - mid) >> 8;
+          auto Ri = gmem_w(reinterpret_cast<int8_t*>(a.R));
+          const size_t ix = rifrag_index(r, a.B_pad >> 8, b, s);
+          Ri[ix] = (int8_t)hi;
+          Ri[ix + kRiDigitBytes] = (int8_t)mid;
+          Ri[ix + 2 * kRiDigitBytes] = (int8_t)lo;
+        }
+      } else if (a.rfrag) {
         // FP16 hi/lo pieces of R * 2^12 in the grouped gradient's fragment
         // order, for every row of the tile (zero past B)
         if (slot < kSlots) {

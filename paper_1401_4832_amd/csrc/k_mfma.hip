@@ -709,22 +709,25 @@ __global__ __launch_bounds__(kGThreads) void bwd_g3_kernel(BatchArgs b) {
   }
 }
 
-__global__ void rfrag_tail_zero_kernel(uint4* R, int32_t N, int32_t nch_site, int32_t c0, int32_t c1) {
-  const int64_t per = (int64_t)(c1 - c0) * (kRfChunkBytes / 16);
+__global__ void rfrag_tail_zero_kernel(uint4* R, int32_t N, int32_t nch_site, int32_t c0, int32_t c1,
+                                       int32_t chunk16) {
+  const int64_t per = (int64_t)(c1 - c0) * chunk16;
   const int64_t total = per * N;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e / per, k = e - r * per;
-    R[(r * nch_site + c0) * (kRfChunkBytes / 16) + k] = make_uint4(0, 0, 0, 0);
+    R[(r * nch_site + c0) * chunk16 + k] = make_uint4(0, 0, 0, 0);
   }
 }
 
-hipError_t launch_rfrag_tail_zero(float* R, int32_t N, int32_t B, int32_t B3, int32_t B_pad, hipStream_t st) {
+hipError_t launch_rfrag_tail_zero(float* R, int32_t N, int32_t B, int32_t B3, int32_t B_pad, int32_t chunk_bytes,
+                                  hipStream_t st) {
   const int32_t c0 = B >> 8, c1 = (B3 + 255) >> 8;
   if (c0 >= c1) return hipSuccess;
-  const int64_t total = (int64_t)(c1 - c0) * (kRfChunkBytes / 16) * N;
+  const int32_t chunk16 = chunk_bytes / 16;
+  const int64_t total = (int64_t)(c1 - c0) * chunk16 * N;
   const int blocks = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
   hipLaunchKernelGGL(rfrag_tail_zero_kernel, dim3(blocks), dim3(256), 0, st, reinterpret_cast<uint4*>(R), N,
-                     B_pad >> 8, c0, c1);
+                     B_pad >> 8, c0, c1, chunk16);
   return hipGetLastError();
 }
 
@@ -741,6 +744,207 @@ int32_t g3_resident_blocks() {
 
 hipError_t launch_backward_g3(const BatchArgs& b, int32_t nblocks, hipStream_t st) {
   hipLaunchKernelGGL(bwd_g3_kernel, dim3(nblocks), dim3(kGThreads), 0, st, b);
+  return hipGetLastError();
+}
+
+// ------------------------------------------ grouped int8 fixed-point gradient
+// The grouped product of the three-site kernel above, with the residuals as
+// three signed int8 digits of round(R * 2^22) (written by the forward) on
+// v_mfma_i32_32x32x32_i8: the one-hot is the byte 1, every digit plane has its
+// own int32 accumulators, and integer accumulation over all sequences is exact
+// (|digit| <= 128, so the sums fit for up to 2^24 sequences), so there is no
+// per-chunk fold; the digit sums are combined in FP64 once at the end.
+// Operand layouts (verified on the device): A lane l holds row l % 32, inner
+// indices 16 (l / 32) + 0..15; B lane l column l % 32, the same inner
+// indices; D as for v_mfma_f32_32x32x16_f16.
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x16 __attribute__((ext_vector_type(16)));
+constexpr int kISteps = kMChunk / 32;                 // MFMA steps per chunk
+constexpr int kISiteStride = kRiChunkBytes + 80;      // bank-disjoint site runs, as above
+static_assert((kISiteStride / 16 - kSlot) % 8 == 0 && kISiteStride % 16 == 0, "bank-disjoint site runs");
+constexpr int kIBufBytes = 2 * kISiteStride + kRiChunkBytes;
+
+// One-hot of 16 symbols against k as sixteen int8 values (1 where sigma == k):
+// a byte of x = sigma ^ k is below 32, so x + 0x7f keeps bit 7 clear exactly
+// where x == 0 and never carries out of the byte.
+__device__ inline uint4 onehot16_i8(uint4 s16, uint32_t kk) {
+  uint32_t w[4] = {s16.x, s16.y, s16.z, s16.w};
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const uint32_t y = (w[h] ^ kk) + 0x7f7f7f7fu;
+    w[h] = (~y & 0x80808080u) >> 7;
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Item& it, int8_t* Rb0, int8_t* Rb1,
+                               uint8_t* sig0, uint8_t* sig1) {
+  const int npos_blk = g3_block_positions(a.q);
+  const int q = a.q, N = a.N, qq = q * q;
+  const int i0 = it.sub * npos_blk;
+  const int npos = min(npos_blk, N - i0);
+  const int nrows = npos * q;
+  const int tid = item_tid(), lane = tid & 63, wid = tid >> 6;
+  const int half = lane >> 5, l32 = lane & 31;
+  const int cnt = it.cnt;
+  int32_t rs[kG3Sites];
+#pragma unroll
+  for (int g = 0; g < kG3Sites; ++g)
+    rs[g] = g < cnt ? bt.active[it.first + g] - bt.site_base[it.m] : it.r;
+
+  int arow_off[kGRB];
+  uint32_t arow_kk[kGRB];
+#pragma unroll
+  for (int m = 0; m < kGRB; ++m) {
+    const int rho = (wid * kGRB + m) * 32 + l32;
+    const bool ok = rho < nrows;
+    arow_off[m] = ok ? (rho / q) * kSigPitch : 0;
+    arow_kk[m] = (ok ? (uint32_t)(rho % q) : 31u) * 0x01010101u;
+  }
+  const bool wave_live = wid * kGRB * 32 < nrows;
+  uint32_t boff[kGT];
+#pragma unroll
+  for (int T = 0; T < kGT; ++T) {
+    const int col = min(32 * T + l32, 3 * kSlot - 1);
+    const int g = col / kSlot, sidx = col - g * kSlot;
+    boff[T] = (uint32_t)(g * kISiteStride + half * (kSlot * 16) + sidx * 16);
+  }
+
+  const int nchunks = (a.B3 + kMChunk - 1) / kMChunk;
+  const int nch_site = a.B_pad >> 8;
+  const int nsig = npos_blk * (kMChunk / 16);
+  // a site's chunk is 15.75 KB: 16 wave copies of 1 KB, the last one moved
+  // back to end at the chunk end (it re-copies 256 bytes with the same values);
+  // the LDS destination of a copy is uniform over the wave
+  auto fetch_r = [&](int c, int8_t* dst) {
+    const int ninst = cnt * 16;
+    for (int k = wid; k < ninst; k += kGWaves) {
+      const int g = k >> 4, part = k & 15;
+      const int off = min(part * 1024, kRiChunkBytes - 1024);
+      const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
+      const char* src = reinterpret_cast<const char*>(a.R) + ((size_t)rg * nch_site + c) * kRiChunkBytes + off +
+                        lane * 16;
+      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
+                                       (void __attribute__((address_space(3)))*)(
+                                           reinterpret_cast<char*>(dst) + g * kISiteStride + off),
+                                       16, 0, 0);
+    }
+  };
+  uint4 sv;
+  auto load_sig = [&](int c) {
+    const int bc = c * kMChunk;
+    const int pos = tid >> 4, part = tid & 15;
+    sv = make_uint4(0, 0, 0, 0);
+    if (tid < nsig && i0 + pos < N) sv = gload_u4(a.msaT + (size_t)(i0 + pos) * a.B_pad + bc + part * 16);
+  };
+  auto store_sig = [&](uint8_t* dst) {
+    if (tid < nsig) *reinterpret_cast<uint4*>(dst + (tid >> 4) * kSigPitch + (tid & 15) * 16) = sv;
+  };
+
+  i32x16 acc[3][kGRB][kGT];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int m = 0; m < kGRB; ++m)
+#pragma unroll
+      for (int T = 0; T < kGT; ++T) acc[d][m][T] = i32x16{};
+
+  auto chunk = [&](int c, const int8_t* cur, int8_t* nxt, const uint8_t* scur, uint8_t* snxt) {
+    if (c + 1 < nchunks) {
+      fetch_r(c + 1, nxt);
+      store_sig(snxt);
+    }
+    if (c + 2 < nchunks) load_sig(c + 2);
+    if (wave_live) {
+      const char* rb = reinterpret_cast<const char*>(cur);
+      const uint8_t* sgb = scur + half * 16;
+#pragma unroll 2
+      for (int t = 0; t < kISteps; ++t) {
+        uint4 av[kGRB];
+#pragma unroll
+        for (int m = 0; m < kGRB; ++m)
+          av[m] = onehot16_i8(*reinterpret_cast<const uint4*>(sgb + arow_off[m] + t * 32), arow_kk[m]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int T = 0; T < kGT; ++T) {
+            const uint4 bp = *reinterpret_cast<const uint4*>(rb + boff[T] + (d * kISteps + t) * (2 * kSlot * 16));
+#pragma unroll
+            for (int m = 0; m < kGRB; ++m)
+              acc[d][m][T] = __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(i32x4, av[m]),
+                                                                   __builtin_bit_cast(i32x4, bp), acc[d][m][T], 0, 0,
+                                                                   0);
+          }
+      }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  };
+
+  fetch_r(0, Rb0);
+  load_sig(0);
+  store_sig(sig0);
+  if (nchunks > 1) load_sig(1);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int c = 0; c < nchunks; c += 2) {
+    chunk(c, Rb0, Rb1, sig0, sig1);
+    if (c + 1 < nchunks) chunk(c + 1, Rb1, Rb0, sig1, sig0);
+  }
+  if (!wave_live) return;
+  constexpr double kScale = 1.0 / (double)(1 << kRiScaleLog2);
+#pragma unroll
+  for (int T = 0; T < kGT; ++T) {
+    const int col = 32 * T + l32;
+    const int g = col / kSlot, sidx = col - g * kSlot;
+    if (g >= cnt || sidx >= q) continue;
+    const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
+#pragma unroll
+    for (int m = 0; m < kGRB; ++m)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int row = (wid * kGRB + m) * 32 + 8 * (j >> 2) + 4 * half + (j & 3);
+        if (row < nrows) {
+          const int i = i0 + row / q, k = row % q;
+          // exact: every digit sum is an integer below 2^31
+          const double v = (double)acc[0][m][T][j] * 65536.0 + (double)acc[1][m][T][j] * 256.0 +
+                           (double)acc[2][m][T][j];
+          gmem_w(a.gJ)[((size_t)rg * N + i) * qq + (size_t)k * q + sidx] = (i == rg) ? 0.0 : v * kScale;
+        }
+      }
+  }
+}
+
+__global__ __launch_bounds__(kGThreads) void bwd_i8_kernel(BatchArgs b) {
+  __shared__ __attribute__((aligned(16))) int8_t Rb0[kIBufBytes];
+  __shared__ __attribute__((aligned(16))) int8_t Rb1[kIBufBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t sig0[kGPosMax * kSigPitch];
+  __shared__ __attribute__((aligned(16))) uint8_t sig1[kGPosMax * kSigPitch];
+  __shared__ int32_t item_s;
+  int32_t qi = 0;
+  const int32_t total = total_items(b, KIND_BWD);
+  for (;;) {
+    if (threadIdx.x == 0) item_s = next_item(b.ctr + KIND_BWD * kQueues, total, qi);
+    __syncthreads();
+    const int32_t t = __builtin_amdgcn_readfirstlane(item_s);
+    if (t < 0) break;
+    const Item it = decode_item(b, KIND_BWD, t);
+    const EvalArgs a = load_uniform(b.ev + it.m);
+    i8_item(b, a, it, Rb0, Rb1, sig0, sig1);
+    __syncthreads();
+  }
+}
+
+int32_t i8_backward_blocks_per_site(int32_t N, int32_t q) { return g3_backward_blocks_per_site(N, q); }
+
+int32_t i8_resident_blocks() {
+  int per = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bwd_i8_kernel, kGThreads, 0);
+  return (e == hipSuccess && per > 0) ? per : 1;
+}
+
+hipError_t launch_backward_i8(const BatchArgs& b, int32_t nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(bwd_i8_kernel, dim3(nblocks), dim3(kGThreads), 0, st, b);
   return hipGetLastError();
 }
 

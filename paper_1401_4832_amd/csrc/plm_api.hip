@@ -223,18 +223,23 @@ struct PathSpec {
   int fwd_np, bwd_np;
   int bwd_f16;  // gradient pieces in FP16 (of R * 2^12) instead of BF16
   int bwd_g3;   // grouped gradient: three sites per item, R split by the forward
+  int bwd_i8;   // grouped gradient on int8 digits of R (fixed point, exact accumulation)
 };
 
 // sites per gradient work item
-int32_t bwd_group(const PathSpec& p) { return p.bwd_g3 ? kG3Sites : 1; }
+int32_t bwd_group(const PathSpec& p) { return (p.bwd_g3 || p.bwd_i8) ? kG3Sites : 1; }
+
+// the int8 gradient sums up to 2^24 sequences exactly
+bool path_fits(const PathSpec& p, int32_t B) { return !p.bwd_i8 || B < (1 << 24); }
 
 bool path_spec(int32_t path, PathSpec* p) {
   switch (path) {
-    case PLM_PATH_GATHER_FP32: *p = {0, 0, 0, 0}; return true;
-    case PLM_PATH_MFMA_BF16X2: *p = {2, 2, 0, 0}; return true;
-    case PLM_PATH_GATHER_MFMA_FP32: *p = {0, 3, 0, 0}; return true;
-    case PLM_PATH_MFMA_FP32: *p = {3, 3, 0, 0}; return true;
-    case PLM_PATH_GATHER_MFMA_F16X2: *p = {0, 2, 1, 1}; return true;
+    case PLM_PATH_GATHER_FP32: *p = {0, 0, 0, 0, 0}; return true;
+    case PLM_PATH_MFMA_BF16X2: *p = {2, 2, 0, 0, 0}; return true;
+    case PLM_PATH_GATHER_MFMA_FP32: *p = {0, 3, 0, 0, 0}; return true;
+    case PLM_PATH_MFMA_FP32: *p = {3, 3, 0, 0, 0}; return true;
+    case PLM_PATH_GATHER_MFMA_F16X2: *p = {0, 2, 1, 1, 0}; return true;
+    case PLM_PATH_GATHER_MFMA_I8X3: *p = {0, 3, 0, 0, 1}; return true;
     default: return false;
   }
 }
@@ -246,6 +251,7 @@ int32_t eval_tiles(const PathSpec& p, int32_t B, int32_t nb) {
 
 int32_t eval_bwd_blocks(const PathSpec& p, int32_t N, int32_t q) {
   if (p.bwd_g3) return g3_backward_blocks_per_site(N, q);
+  if (p.bwd_i8) return i8_backward_blocks_per_site(N, q);
   return p.bwd_np ? mfma_backward_blocks_per_site(N, q) : backward_blocks_per_site(N);
 }
 
@@ -253,8 +259,9 @@ int32_t eval_bwd_blocks(const PathSpec& p, int32_t N, int32_t q) {
 // copy (and, for the grouped gradient, the residual rows no forward tile writes).
 hipError_t eval_prepare(const PathSpec& p, const EvalArgs& a, uint8_t* msaT, uint16_t* sorted,
                         hipStream_t st) {
-  if (p.bwd_g3) {
-    const hipError_t e = launch_rfrag_tail_zero(a.R, a.N, a.B, a.B3, a.B_pad, st);
+  if (p.bwd_g3 || p.bwd_i8) {
+    const hipError_t e =
+        launch_rfrag_tail_zero(a.R, a.N, a.B, a.B3, a.B_pad, p.bwd_i8 ? kRiChunkBytes : kRfChunkBytes, st);
     if (e != hipSuccess) return e;
   }
   if (p.bwd_np) return launch_transpose_msa(a.msa_cm, a.B_pad, a.N_pad, msaT, st);
@@ -270,6 +277,7 @@ Grids eval_grids(const plm_ctx* c, const PathSpec& p, int32_t nb) {
   Grids g;
   g.fwd = c->ncu * (p.fwd_np ? mfma_resident_blocks(KIND_FWD, p.fwd_np) : forward_resident_blocks(nb));
   g.bwd = c->ncu * (p.bwd_g3   ? g3_resident_blocks()
+                    : p.bwd_i8 ? i8_resident_blocks()
                     : p.bwd_np ? mfma_resident_blocks(KIND_BWD, p.bwd_np)
                                : backward_resident_blocks());
   return g;
@@ -282,6 +290,7 @@ hipError_t eval_forward(const PathSpec& p, const BatchArgs& b, int32_t nb, const
 
 hipError_t eval_backward(const PathSpec& p, const BatchArgs& b, const Grids& g, hipStream_t st) {
   if (p.bwd_g3) return launch_backward_g3(b, g.bwd, st);
+  if (p.bwd_i8) return launch_backward_i8(b, g.bwd, st);
   return p.bwd_np ? launch_backward_mfma(b, p.bwd_np, p.bwd_f16, g.bwd, st) : launch_backward(b, g.bwd, st);
 }
 
@@ -295,7 +304,7 @@ EvalArgs eval_args(const EvalBufs& e, const uint8_t* msa_unused, int32_t B, int3
   a.w = w; a.h = h; a.J = J;
   a.R = e.R; a.f_part = e.f_part; a.gh_part = e.gh_part; a.gJ = e.gJ;
   a.tiles = tiles;
-  a.rfrag = ps.bwd_g3;
+  a.rfrag = ps.bwd_i8 ? 2 : (ps.bwd_g3 ? 1 : 0);
   a.sorted = e.sorted;
   return a;
 }
@@ -426,6 +435,7 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
   PathSpec ps;
   if (!path_spec(path, &ps))
     return set_err(c, PLM_E_UNSUPPORTED, "evaluation path %d is not available", path);
+  if (!path_fits(ps, B)) return set_err(c, PLM_E_UNSUPPORTED, "path %d sums at most 2^24 - 1 sequences exactly", path);
   if (!sites) n_sites = N;
   if (n_sites < 1 || n_sites > N) return set_err(c, PLM_E_INVALID, "n_sites out of range");
   const size_t need = plm_objgrad_workspace_bytes(B, N, q, path);
@@ -546,6 +556,7 @@ int prepare_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const p
       return set_err(c, PLM_E_INVALID, "null pointer in alignment %d", k);
     int rc = check_sizes(c, m.B, m.N, q);
     if (rc) return rc;
+    if (!path_fits(ps, m.B)) return set_err(c, PLM_E_UNSUPPORTED, "path %d sums at most 2^24 - 1 sequences exactly", o->path);
     total += m.N;
     if (m.B > Bmax) Bmax = m.B;
   }
@@ -793,12 +804,15 @@ int plm_tune(plm_ctx* c, const plm_msa_desc* descs, int32_t n_msas, int32_t q, c
     int32_t path, tile;
   };
   std::vector<Cand> cands;
-  const int32_t paths[] = {PLM_PATH_GATHER_MFMA_F16X2, PLM_PATH_GATHER_MFMA_FP32, PLM_PATH_GATHER_FP32,
-                           PLM_PATH_MFMA_FP32, PLM_PATH_MFMA_BF16X2};
+  const int32_t paths[] = {PLM_PATH_GATHER_MFMA_I8X3, PLM_PATH_GATHER_MFMA_F16X2, PLM_PATH_GATHER_MFMA_FP32,
+                           PLM_PATH_GATHER_FP32,       PLM_PATH_MFMA_FP32,         PLM_PATH_MFMA_BF16X2};
   for (int32_t p : paths) {
     if (fp32_only && p == PLM_PATH_MFMA_BF16X2) continue;
     PathSpec ps;
     path_spec(p, &ps);
+    bool fits = true;
+    for (int32_t k = 0; k < n_msas; ++k) fits = fits && path_fits(ps, descs[k].B);
+    if (!fits) continue;
     if (ps.fwd_np) {
       cands.push_back({p, 0});
     } else {
@@ -921,6 +935,7 @@ int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int3
   PathSpec ps;
   if (!path_spec(o->path, &ps))
     return set_err(c, PLM_E_UNSUPPORTED, "evaluation path %d is not available", o->path);
+  if (!path_fits(ps, B)) return set_err(c, PLM_E_UNSUPPORTED, "path %d sums at most 2^24 - 1 sequences exactly", o->path);
   HIPCHK(c, hipSetDevice(c->device));
   const int32_t nblk = 4 * c->ncu;
   {

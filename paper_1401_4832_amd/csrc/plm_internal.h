@@ -68,7 +68,7 @@ struct EvalArgs {
   double* gh_part;         // [tiles][N][21]
   double* gJ;              // [N][N][q][q] data part of d f / d J (FP64)
   int32_t tiles;
-  int32_t rfrag;           // 1: R is stored as FP16 pieces in gradient-fragment order (see below)
+  int32_t rfrag;           // R in gradient-fragment order: 1 FP16 hi/lo pieces, 2 int8 digits (see below)
   const uint16_t* sorted;  // [nchunks][N][kBwdSeqChunk]: (row << 8) | symbol, rows sorted by symbol
 };
 
@@ -84,6 +84,19 @@ constexpr int kRfChunkBytes = 2 * kRfPieceWords * 2;       // 21504
 __device__ inline size_t rfrag_index(int32_t r, int32_t nch, int32_t b, int32_t s) {
   const size_t c = (size_t)r * nch + (b >> 8);
   return ((((c * 2) * 16 + ((b >> 4) & 15)) * 2 + ((b >> 3) & 1)) * kSlot + s) * 8 + (b & 7);
+}
+
+// Residuals as fixed-point digits (rfrag = 2): v = round(R_b(s) * 2^22) (|R| <=
+// w_b <= 1, so |v| <= 2^22) written as v = hi 2^16 + mid 2^8 + lo with signed
+// int8 digits, stored per site as [chunk of 256][digit][step of 32][half of
+// 16][state 0..20][sequence 0..15] bytes: 16128 contiguous bytes per (chunk,
+// site).  Integer accumulation of the digits is exact.
+constexpr int kRiScaleLog2 = 22;
+constexpr int kRiDigitBytes = 8 * 2 * kSlot * 16;           // 5376
+constexpr int kRiChunkBytes = 3 * kRiDigitBytes;            // 16128
+__device__ inline size_t rifrag_index(int32_t r, int32_t nch, int32_t b, int32_t s) {
+  const size_t c = (size_t)r * nch + (b >> 8);
+  return ((((c * 3) * 8 + ((b >> 5) & 7)) * 2 + ((b >> 4) & 1)) * kSlot + s) * 16 + (b & 15);
 }
 
 
@@ -331,7 +344,12 @@ hipError_t launch_backward_g3(const BatchArgs& b, int32_t nblocks, hipStream_t s
 // zero the fragment-order residual rows [B rounded down to 256, B3 rounded up
 // to 256) of every site: the forward writes only the rows of its tiles, and the
 // last gradient chunk may reach past them
-hipError_t launch_rfrag_tail_zero(float* R, int32_t N, int32_t B, int32_t B3, int32_t B_pad, hipStream_t st);
+hipError_t launch_rfrag_tail_zero(float* R, int32_t N, int32_t B, int32_t B3, int32_t B_pad, int32_t chunk_bytes,
+                                  hipStream_t st);
+// grouped int8 fixed-point MFMA gradient (three sites per item, R as digits)
+int32_t i8_backward_blocks_per_site(int32_t N, int32_t q);
+int32_t i8_resident_blocks();
+hipError_t launch_backward_i8(const BatchArgs& b, int32_t nblocks, hipStream_t st);
 hipError_t launch_forward_mfma(const BatchArgs& b, int32_t npieces, int32_t nblocks, hipStream_t st);
 hipError_t launch_backward_mfma(const BatchArgs& b, int32_t npieces, int32_t f16, int32_t nblocks,
                                 hipStream_t st);
