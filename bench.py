@@ -44,9 +44,11 @@ MFMA_BF16_PEAK = 2.5e15
 # dense int8 matrix-core peak (ops/s)
 MFMA_I8_PEAK = 5.0e15
 PATH_NAMES = {0: "gather_fp32", 1: "mfma_bf16x2", 2: "gather_mfma_fp32", 3: "mfma_fp32",
-              4: "gather_mfma_f16x2", 5: "gather_mfma_i8x3"}
+              4: "gather_mfma_f16x2", 5: "gather_mfma_i8x3", 6: "mfma_i8x3"}
 # 16-bit pieces of the non-one-hot operand, per path: (forward, backward); 0 = LDS gather/scatter
-PATH_PIECES = {0: (0, 0), 1: (2, 2), 2: (0, 3), 3: (3, 3), 4: (0, 2), 5: (0, 3)}
+PATH_PIECES = {0: (0, 0), 1: (2, 2), 2: (0, 3), 3: (3, 3), 4: (0, 2), 5: (0, 3), 6: (3, 3)}
+# the int8 matrix-core kernels (path, direction)
+INT8_KERNELS = {(5, "backward"), (6, "backward"), (6, "forward")}
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -239,10 +241,10 @@ def main():
             # dense matrix-core flops of the one-hot product: q MACs per unit and piece
             flops = units_all * 2 * Q * np_dom
             # path 4's gradient is the grouped three-site kernel, path 5's its int8 form
-            kname = {4: "backward_g3", 5: "backward_i8"}.get(path, "backward_mfma") if dom == "backward" \
-                else f"{dom}_mfma"
+            kname = {4: "backward_g3", 5: "backward_i8", 6: "backward_i8"}.get(path, "backward_mfma") \
+                if dom == "backward" else ("forward_i8" if path == 6 else "forward_mfma")
             # BF16 and FP16 dense matrix-core peaks are the same on this chip; int8 runs at twice the rate
-            peak = MFMA_I8_PEAK if (dom == "backward" and path == 5) else MFMA_BF16_PEAK
+            peak = MFMA_I8_PEAK if (path, dom) in INT8_KERNELS else MFMA_BF16_PEAK
             roofline = {"bound": "mfma", "achieved": flops / t_dom / 1e12, "peak": peak / 1e12,
                         "unit": "TOP/s" if peak == MFMA_I8_PEAK else "TFLOP/s", "frac": flops / t_dom / peak,
                         "flops_per_unit": 2 * Q * np_dom}
@@ -299,7 +301,12 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {1: "bf16x2 operands, f32 accumulate", 4: "f32 forward, f16x2 gradient operands (22-bit), "
-                  "FP64 reductions and optimiser"}.get(path, "f32 (FP64 reductions and optimiser)"),
+                  "FP64 reductions and optimiser",
+                  5: "f32 forward, int8x3 fixed-point gradient (2^-23), exact int32 accumulation, "
+                  "FP64 reductions and optimiser",
+                  6: "int8x3 fixed-point energies (2^-23 max|J_r|) and gradient (2^-23), exact int32 "
+                  "accumulation, FP32 softmax, FP64 reductions and optimiser"}.get(
+                      path, "f32 (FP64 reductions and optimiser)"),
         "data": "synthetic planted-Potts alignment (seeded Gibbs sampling)",
         "config": cfg,
         "time_to_fit_s": ms_per_step / 1e3,

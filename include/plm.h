@@ -79,6 +79,11 @@ extern "C" {
                                   int8 digits (|dR| <= 2^-23, absolute; |R| <= w_b <= 1),
                                   accumulated exactly in int32; at most 2^24 - 1 sequences
                                   (PLM_E_UNSUPPORTED beyond) */
+#define PLM_PATH_MFMA_I8X3 6   /* both directions as int8 MFMA products in fixed point: the
+                                  gradient of path 5, and energies from each site's couplings
+                                  scaled by a power of two 2^k_r with max|J_r| 2^k_r < 2^22 and
+                                  rounded (|dJ| <= 2^-23 max_i,s,k |J_ri(s,k)|), three int8 digits
+                                  accumulated exactly in int32; at most 2^24 - 1 sequences */
 
 typedef struct plm_ctx plm_ctx;
 

@@ -22,6 +22,7 @@ PATH_GATHER_MFMA_FP32 = 2
 PATH_MFMA_FP32 = 3
 PATH_GATHER_MFMA_F16X2 = 4
 PATH_GATHER_MFMA_I8X3 = 5
+PATH_MFMA_I8X3 = 6
 
 SITE_STATUS = {0: "converged", 1: "maxiter", 2: "linesearch", 3: "nonfinite"}
 

@@ -1,0 +1,382 @@
+// k_fwd8.hip -- the energies of the pseudolikelihood (eq. condpfinal)
+// E_b(s) = h_r(s) + sum_{i != r} J_ri(s, sigma_i^b) as an int8 matrix-core
+// product, for three sites at once, followed by the log-softmax, objective,
+// residual and field-gradient epilogue of the gather forward (sec. 3.4 step 3).
+//
+// Couplings in fixed point: each site's J_r is scaled by 2^k_r with
+// max |J_r| 2^k_r < 2^22 and rounded (|dJ| <= 2^-(k_r + 1) <= 2^-23 max |J_r|),
+// then written as three signed int8 digits (hi 2^16 + mid 2^8 + lo), once per
+// evaluation (jquant_kernel).  The product runs on v_mfma_i32_32x32x32_i8
+// with rows = sequences, columns = the 63 (site, state) pairs of the group in
+// two 32-column tiles, and the inner index over position triples: a triple
+// (3G, 3G+1, 3G+2) x 21 states = 63 inner indices, padded to 64 = two steps
+// of 32.  The one-hot operand of a lane (one sequence, 16 consecutive inner
+// indices) is bits [32 t + 16 half, +16) of the 64-bit mask with bits
+// 21 p + sigma_{3G+p} set, each 4 bits spread to 4 bytes by one multiply.
+// Each digit plane accumulates exactly in int32 (|digit| <= 128, at most
+// 3 ceil(N/3) one-hot terms per output); the planes are combined and scaled
+// back in FP64 once at the end.  The couplings stream through LDS four
+// triples at a time (global -> LDS copies, double-buffered in two separate
+// arrays), the triples' symbols likewise.
+#include <math.h>
+
+#include "plm_internal.h"
+
+namespace plm {
+
+typedef int32_t fi32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t fi32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kFIWaves = 8;
+constexpr int kFIThreads = kFIWaves * 64;
+constexpr int kFIRB = 2;                                   // 32-sequence row blocks per wave
+constexpr int kFISeqs = kFIWaves * kFIRB * 32;             // 512 sequences per item
+constexpr int kFIStageG = 4;                               // position triples per LDS stage
+constexpr int kFISiteBytes = kFIStageG * kWqGroupBytes;    // 16128
+// bank-disjoint site runs: column c of a tile reads 16-byte slot c mod 8
+constexpr int kFISiteStride = kFISiteBytes + 80;
+static_assert((kFISiteStride / 16 - kSlot) % 8 == 0 && kFISiteStride % 16 == 0, "bank-disjoint site runs");
+constexpr int kFIBufBytes = 2 * kFISiteStride + kFISiteBytes;
+constexpr int kFISymWords = kFIStageG * kFISeqs;
+constexpr int kFIParkFloats = 32 * 64;                     // one row block of energies per wave
+static_assert(4 * kFIParkFloats * 4 <= kFIBufBytes, "four waves' energies fit one buffer");
+constexpr int kJexpBad = -100000;                          // non-finite coupling: energies NaN
+
+int32_t fwd_i8_tile_seqs() { return kFISeqs; }
+
+// ---- couplings -> digits, one block per active site ---------------------------
+__global__ __launch_bounds__(256) void jquant_kernel(BatchArgs b) {
+  __shared__ float red[4];
+  __shared__ int32_t bad_s[4];
+  __shared__ int32_t kexp_s;
+  const int idx = blockIdx.x;
+  if (idx >= *b.n_active) return;
+  const int g = b.active[idx];
+  const int m = b.msa_of[g];
+  const EvalArgs a = load_uniform(b.ev + m);
+  const int r = g - b.site_base[m];
+  const int q = a.q, N = a.N, qq = q * q;
+  const auto Jr = gmem(a.J + (size_t)r * N * qq);
+  float mx = 0.f;
+  int bad = 0;
+  for (int e = threadIdx.x; e < N * qq; e += blockDim.x) {
+    if (e / qq == r) continue;
+    const float v = Jr[e];
+    bad |= !isfinite(v);
+    mx = fmaxf(mx, fabsf(v));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    bad |= __shfl_xor(bad, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = mx;
+    bad_s[threadIdx.x >> 6] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float t = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    int ex = 0;
+    (void)frexpf(t, &ex);  // t = f 2^ex with f in [0.5, 1) (ex = 0 for t = 0)
+    const int k = (bad_s[0] | bad_s[1] | bad_s[2] | bad_s[3]) ? kJexpBad : kRiScaleLog2 - ex;
+    kexp_s = k;
+    gmem_w(a.jexp)[r] = k;
+  }
+  __syncthreads();
+  const int k = kexp_s == kJexpBad ? 0 : kexp_s;
+  const int units = a.NG * 4 * kSlot;  // (triple, step, half, state)
+  auto Wq = gmem_w(a.Wq + (size_t)r * a.NG * kWqGroupBytes);
+  for (int u = threadIdx.x; u < units; u += blockDim.x) {
+    const int G = u / (4 * kSlot), rem = u - G * (4 * kSlot);
+    const int th = rem / kSlot, sidx = rem - th * kSlot;  // th = 2 t + half
+    uint32_t w[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int K = 16 * th + j;  // inner index within the triple
+      const int p = K / kSlot, kk = K - p * kSlot;
+      const int i = 3 * G + p;
+      int v = 0;
+      if (p < 3 && i < N && i != r && kk < q && sidx < q && kexp_s != kJexpBad)
+        v = (int)rintf(ldexpf(Jr[(size_t)i * qq + kk * q + sidx], k));
+      const int lo = (int)(int8_t)(v & 255);
+      const int v1 = (v - lo) >> 8;
+      const int mid = (int)(int8_t)(v1 & 255);
+      const int hi = (v1 - mid) >> 8;
+      w[0][j >> 2] |= (uint32_t)(uint8_t)hi << (8 * (j & 3));
+      w[1][j >> 2] |= (uint32_t)(uint8_t)mid << (8 * (j & 3));
+      w[2][j >> 2] |= (uint32_t)(uint8_t)lo << (8 * (j & 3));
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      *reinterpret_cast<__attribute__((address_space(1))) u32x4_t*>(
+          Wq + (size_t)G * kWqGroupBytes + d * (kWqGroupBytes / 3) + (th * kSlot + sidx) * 16) =
+          u32x4_t{w[d][0], w[d][1], w[d][2], w[d][3]};
+  }
+}
+
+// ---- symbols of position triples ---------------------------------------------
+__global__ void sym3_kernel(const uint8_t* __restrict__ msa_cm, int32_t B_pad, int32_t N, int32_t NG,
+                            uint32_t* __restrict__ sym3) {
+  const size_t total = (size_t)NG * B_pad;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int G = (int)(e / B_pad), b = (int)(e - (size_t)G * B_pad);
+    uint32_t v = 0;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const int i = 3 * G + p;
+      if (i < N) v |= (uint32_t)msa_cm[((size_t)(i >> 4) * B_pad + b) * 16 + (i & 15)] << (8 * p);
+    }
+    sym3[e] = v;
+  }
+}
+
+hipError_t launch_sym3(const uint8_t* msa_cm, int32_t B_pad, int32_t N, int32_t NG, uint32_t* sym3, hipStream_t st) {
+  const size_t total = (size_t)NG * B_pad;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(sym3_kernel, dim3(blocks), dim3(256), 0, st, msa_cm, B_pad, N, NG, sym3);
+  return hipGetLastError();
+}
+
+// 16 one-hot bytes (1 where the inner index matches) from 16 mask bits
+__device__ inline uint4 spread16(uint32_t bits) {
+  uint32_t w[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) w[d] = (((bits >> (4 * d)) & 15u) * 0x00204081u) & 0x01010101u;
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const Item& it, int8_t* W0, int8_t* W1,
+                                   uint32_t* S0, uint32_t* S1, double* red) {
+  const int q = a.q, N = a.N, NG = a.NG;
+  const int tid = item_tid(), lane = tid & 63, wid = tid >> 6;
+  const int half = lane >> 5, l32 = lane & 31;
+  const int cnt = it.cnt;
+  const int tile = it.sub;
+  const int b0 = tile * kFISeqs;
+  int32_t rs[kG3Sites], ks[kG3Sites];
+#pragma unroll
+  for (int g = 0; g < kG3Sites; ++g) {
+    rs[g] = g < cnt ? bt.active[it.first + g] - bt.site_base[it.m] : it.r;
+    ks[g] = gmem(a.jexp)[rs[g]];
+  }
+  uint32_t boff[2];
+#pragma unroll
+  for (int T = 0; T < 2; ++T) {
+    const int col = min(32 * T + l32, 3 * kSlot - 1);
+    const int g = col / kSlot, sidx = col - g * kSlot;
+    boff[T] = (uint32_t)(g * kFISiteStride + half * (kSlot * 16) + sidx * 16);
+  }
+  const int nst = (NG + kFIStageG - 1) / kFIStageG;
+
+  // global -> LDS copies of stage c: the group's digits of triples 4c .. 4c+3
+  // (a site's run is contiguous; the last 1 KB copy of a run is moved back to
+  // end at the run's end) and the triples' symbols of the item's sequences
+  auto fetch = [&](int c, int8_t* Wd, uint32_t* Sd) {
+    const int ng = min(kFIStageG, NG - c * kFIStageG);
+    const int bytes = ng * kWqGroupBytes;
+    const int per = (bytes + 1023) / 1024;
+    const int ninst = cnt * per + 2 * ng;
+    for (int k = wid; k < ninst; k += kFIWaves) {
+      if (k < cnt * per) {
+        const int g = k / per, part = k - g * per;
+        const int off = min(part * 1024, bytes - 1024);
+        const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
+        const char* src = reinterpret_cast<const char*>(a.Wq) +
+                          ((size_t)rg * NG + (size_t)c * kFIStageG) * kWqGroupBytes + off + lane * 16;
+        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
+                                         (void __attribute__((address_space(3)))*)(Wd + g * kFISiteStride + off),
+                                         16, 0, 0);
+      } else {
+        const int k2 = k - cnt * per, kg = k2 >> 1, part = k2 & 1;
+        const uint32_t* src = a.sym3 + (size_t)(c * kFIStageG + kg) * a.B_pad + b0 + part * 256 + lane * 4;
+        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
+                                         (void __attribute__((address_space(3)))*)(Sd + kg * kFISeqs + part * 256),
+                                         16, 0, 0);
+      }
+    }
+  };
+
+  fi32x16 acc[3][kFIRB][2];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int m = 0; m < kFIRB; ++m)
+#pragma unroll
+      for (int T = 0; T < 2; ++T) acc[d][m][T] = fi32x16{};
+
+  auto stage = [&](int c, const int8_t* Wc, const uint32_t* Sc, int8_t* Wn, uint32_t* Sn) {
+    if (c + 1 < nst) fetch(c + 1, Wn, Sn);
+    const int ng = min(kFIStageG, NG - c * kFIStageG);
+    const char* wb = reinterpret_cast<const char*>(Wc);
+    for (int kg = 0; kg < ng; ++kg) {
+      // the one-hot mask of each row block's sequence for this triple
+      uint32_t mlo[kFIRB], mhi[kFIRB];
+#pragma unroll
+      for (int m = 0; m < kFIRB; ++m) {
+        const uint32_t s3 = Sc[kg * kFISeqs + (wid * kFIRB + m) * 32 + l32];
+        uint64_t mask = 0;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) mask |= 1ull << (kSlot * p + ((s3 >> (8 * p)) & 255u));
+        mlo[m] = (uint32_t)mask;
+        mhi[m] = (uint32_t)(mask >> 32);
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        uint4 av[kFIRB];
+#pragma unroll
+        for (int m = 0; m < kFIRB; ++m) av[m] = spread16(((t ? mhi[m] : mlo[m]) >> (16 * half)) & 0xffffu);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int T = 0; T < 2; ++T) {
+            const uint4 bp = *reinterpret_cast<const uint4*>(wb + boff[T] + kg * kWqGroupBytes +
+                                                            (d * 2 + t) * (2 * kSlot * 16));
+#pragma unroll
+            for (int m = 0; m < kFIRB; ++m)
+              acc[d][m][T] = __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(fi32x4, av[m]),
+                                                                   __builtin_bit_cast(fi32x4, bp), acc[d][m][T], 0, 0,
+                                                                   0);
+          }
+      }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  };
+
+  fetch(0, W0, S0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int c = 0; c < nst; c += 2) {
+    stage(c, W0, S0, W1, S1);
+    if (c + 1 < nst) stage(c + 1, W1, S1, W0, S0);
+  }
+
+  // ---- epilogue: energies -> log-softmax, objective, residual digits, dh ----
+  const int slot = lane / kSlot, s = lane - slot * kSlot;
+  const int slotA = slot < kG3Sites ? slot : kG3Sites - 1;
+  const bool act = slot < kG3Sites && slot < cnt && s < q;
+  const int rA = slotA == 0 ? rs[0] : (slotA == 1 ? rs[1] : rs[2]);
+  const int sbase = slotA * kSlot;
+  const int nch = a.B_pad >> 8;
+  float* park = wid < 4 ? reinterpret_cast<float*>(W0) + wid * kFIParkFloats
+                        : reinterpret_cast<float*>(W1) + (wid - 4) * kFIParkFloats;
+  double facc = 0.0, ghacc = 0.0;
+  const float hv = act ? gmem(a.h)[rA * q + s] : 0.f;
+#pragma unroll
+  for (int m = 0; m < kFIRB; ++m) {
+    // this row block's energies, [sequence][column], column = 21 site + state
+#pragma unroll
+    for (int T = 0; T < 2; ++T) {
+      const int col = 32 * T + l32;
+      const int g = col / kSlot;
+      const int kg_ = g == 0 ? ks[0] : (g == 1 ? ks[1] : ks[2]);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int row = 8 * (j >> 2) + 4 * half + (j & 3);
+        const double v = (double)acc[0][m][T][j] * 65536.0 + (double)acc[1][m][T][j] * 256.0 +
+                         (double)acc[2][m][T][j];
+        if (col < 3 * kSlot) park[row * 64 + col] = kg_ == kJexpBad ? NAN : (float)ldexp(v, -kg_);
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int row = 0; row < 32; ++row) {
+      const int b = b0 + (wid * kFIRB + m) * 32 + row;
+      const float e = act ? park[row * 64 + sbase + s] + hv : -INFINITY;
+      float mxv = e;
+#pragma unroll
+      for (int dd = 1; dd < 32; dd <<= 1) {
+        const float o = __shfl_down(mxv, dd, 64);
+        if (s + dd < kSlot) mxv = fmaxf(mxv, o);
+      }
+      mxv = __shfl(mxv, sbase, 64);
+      const float ex = act ? expf(e - mxv) : 0.f;
+      float sum = ex;
+#pragma unroll
+      for (int dd = 1; dd < 32; dd <<= 1) {
+        const float o = __shfl_down(sum, dd, 64);
+        if (s + dd < kSlot) sum += o;
+      }
+      sum = __shfl(sum, sbase, 64);
+      const float lse = mxv + logf(sum);
+      const int sr = gmem(a.msa_cm)[((size_t)(rA / kFwdChunk) * a.B_pad + b) * kFwdChunk + rA % kFwdChunk];
+      const double wb = (slot < kG3Sites && b < a.B) ? gmem(a.w)[b] : 0.0;
+      const float P = ex / sum;
+      const float Rv = act ? (float)wb * (P - (s == sr ? 1.f : 0.f)) : 0.f;
+      if (act && s == sr) facc += wb * (double)(lse - e);
+      ghacc += (double)Rv;
+      if (slot < kG3Sites && slot < cnt) {
+        const int v = (int)rintf(Rv * (float)(1 << kRiScaleLog2));
+        const int lo = (int)(int8_t)(v & 255);
+        const int v1 = (v - lo) >> 8;
+        const int mid = (int)(int8_t)(v1 & 255);
+        const int hi = (v1 - mid) >> 8;
+        auto Ri = gmem_w(reinterpret_cast<int8_t*>(a.R));
+        const size_t ix = rifrag_index(rA, nch, b, s);
+        Ri[ix] = (int8_t)hi;
+        Ri[ix + kRiDigitBytes] = (int8_t)mid;
+        Ri[ix + 2 * kRiDigitBytes] = (int8_t)lo;
+      }
+    }
+    __syncthreads();
+  }
+  // objective and field-gradient partials of this tile, per site of the group
+  red[wid * 64 + lane] = facc;
+  __syncthreads();
+  if (tid < cnt) {
+    double t = 0.0;
+    for (int w = 0; w < kFIWaves; ++w)
+      for (int ss = 0; ss < kSlot; ++ss) t += red[w * 64 + tid * kSlot + ss];
+    const int rg = tid == 0 ? rs[0] : (tid == 1 ? rs[1] : rs[2]);
+    gmem_w(a.f_part)[(size_t)tile * N + rg] = t;
+  }
+  __syncthreads();
+  red[wid * 64 + lane] = ghacc;
+  __syncthreads();
+  if (tid < cnt * kSlot) {
+    const int g = tid / kSlot, ss = tid - g * kSlot;
+    double t = 0.0;
+    for (int w = 0; w < kFIWaves; ++w) t += red[w * 64 + tid];
+    const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
+    gmem_w(a.gh_part)[((size_t)tile * N + rg) * kSlot + ss] = t;
+  }
+}
+
+__global__ __launch_bounds__(kFIThreads) void fwd_i8_kernel(BatchArgs b) {
+  __shared__ __attribute__((aligned(16))) int8_t W0[kFIBufBytes];
+  __shared__ __attribute__((aligned(16))) int8_t W1[kFIBufBytes];
+  __shared__ __attribute__((aligned(16))) uint32_t S0[kFISymWords];
+  __shared__ __attribute__((aligned(16))) uint32_t S1[kFISymWords];
+  __shared__ double red[kFIWaves * 64];
+  __shared__ int32_t item_s;
+  int32_t qi = 0;
+  const int32_t total = total_items(b, KIND_FWD);
+  for (;;) {
+    if (threadIdx.x == 0) item_s = next_item(b.ctr + KIND_FWD * kQueues, total, qi);
+    __syncthreads();
+    const int32_t t = __builtin_amdgcn_readfirstlane(item_s);
+    if (t < 0) break;
+    const Item it = decode_item(b, KIND_FWD, t);
+    const EvalArgs a = load_uniform(b.ev + it.m);
+    fwd_i8_item(b, a, it, W0, W1, S0, S1, red);
+    __syncthreads();
+  }
+}
+
+int32_t fwd_i8_resident_blocks() {
+  int per = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_i8_kernel, kFIThreads, 0);
+  return (e == hipSuccess && per > 0) ? per : 1;
+}
+
+// Couplings of every active site to digits, then the energies and the rest of
+// the forward.  total_sites bounds the active list (the grid of the first kernel).
+hipError_t launch_forward_i8(const BatchArgs& b, int32_t total_sites, int32_t nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(jquant_kernel, dim3(total_sites), dim3(256), 0, st, b);
+  hipLaunchKernelGGL(fwd_i8_kernel, dim3(nblocks), dim3(kFIThreads), 0, st, b);
+  return hipGetLastError();
+}
+
+}  // namespace plm

@@ -66,6 +66,10 @@ struct EvalBufs {
   double* gJ;
   uint16_t* sorted;
   int32_t B_pad, N_pad, B3, tiles_max, nchunks;
+  int8_t* Wq;
+  int32_t* jexp;
+  uint32_t* sym3;
+  int32_t NG;
 };
 
 void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
@@ -82,6 +86,10 @@ void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
   e.gJ = bp.take<double>((size_t)N * N * q * q);
   e.nchunks = (e.B3 + kBwdSeqChunk - 1) / kBwdSeqChunk;
   e.sorted = bp.take<uint16_t>((size_t)e.nchunks * N * kBwdSeqChunk);
+  e.NG = (N + 2) / 3;
+  e.Wq = bp.take<int8_t>((size_t)N * e.NG * kWqGroupBytes);
+  e.jexp = bp.take<int32_t>((size_t)N);
+  e.sym3 = bp.take<uint32_t>((size_t)e.NG * e.B_pad);
 }
 
 // per-alignment optimiser buffers
@@ -132,7 +140,7 @@ void layout_tables(Bump& bp, int32_t n_msas, int32_t total, bool fit, Tables& t)
   t.site_evals = bp.take<unsigned long long>(1);
 }
 
-BatchArgs batch_args(const Tables& t, int32_t n_msas, int32_t total, int32_t group) {
+BatchArgs batch_args(const Tables& t, int32_t n_msas, int32_t total, int32_t group, int32_t fgroup) {
   BatchArgs b;
   b.ev = t.ev;
   b.lb = t.lb;
@@ -147,6 +155,7 @@ BatchArgs batch_args(const Tables& t, int32_t n_msas, int32_t total, int32_t gro
   b.nsub = t.nsub;
   b.ctr = t.ctr;
   b.bwd_group = group;
+  b.fwd_group = fgroup;
   return b;
 }
 
@@ -224,28 +233,31 @@ struct PathSpec {
   int bwd_f16;  // gradient pieces in FP16 (of R * 2^12) instead of BF16
   int bwd_g3;   // grouped gradient: three sites per item, R split by the forward
   int bwd_i8;   // grouped gradient on int8 digits of R (fixed point, exact accumulation)
+  int fwd_i8;   // grouped forward on int8 digits of J (fixed point, exact accumulation)
 };
 
-// sites per gradient work item
+// sites per work item
 int32_t bwd_group(const PathSpec& p) { return (p.bwd_g3 || p.bwd_i8) ? kG3Sites : 1; }
+int32_t fwd_group(const PathSpec& p) { return p.fwd_i8 ? kG3Sites : 1; }
 
 // the int8 gradient sums up to 2^24 sequences exactly
 bool path_fits(const PathSpec& p, int32_t B) { return !p.bwd_i8 || B < (1 << 24); }
 
 bool path_spec(int32_t path, PathSpec* p) {
   switch (path) {
-    case PLM_PATH_GATHER_FP32: *p = {0, 0, 0, 0, 0}; return true;
-    case PLM_PATH_MFMA_BF16X2: *p = {2, 2, 0, 0, 0}; return true;
-    case PLM_PATH_GATHER_MFMA_FP32: *p = {0, 3, 0, 0, 0}; return true;
-    case PLM_PATH_MFMA_FP32: *p = {3, 3, 0, 0, 0}; return true;
-    case PLM_PATH_GATHER_MFMA_F16X2: *p = {0, 2, 1, 1, 0}; return true;
-    case PLM_PATH_GATHER_MFMA_I8X3: *p = {0, 3, 0, 0, 1}; return true;
+    case PLM_PATH_GATHER_FP32: *p = {0, 0, 0, 0, 0, 0}; return true;
+    case PLM_PATH_MFMA_BF16X2: *p = {2, 2, 0, 0, 0, 0}; return true;
+    case PLM_PATH_GATHER_MFMA_FP32: *p = {0, 3, 0, 0, 0, 0}; return true;
+    case PLM_PATH_MFMA_FP32: *p = {3, 3, 0, 0, 0, 0}; return true;
+    case PLM_PATH_GATHER_MFMA_F16X2: *p = {0, 2, 1, 1, 0, 0}; return true;
+    case PLM_PATH_GATHER_MFMA_I8X3: *p = {0, 3, 0, 0, 1, 0}; return true;
+    case PLM_PATH_MFMA_I8X3: *p = {0, 3, 0, 0, 1, 1}; return true;
     default: return false;
   }
 }
 
 int32_t eval_tiles(const PathSpec& p, int32_t B, int32_t nb) {
-  const int32_t t = p.fwd_np ? mfma_forward_tile_seqs() : forward_tile_seqs(nb);
+  const int32_t t = p.fwd_i8 ? fwd_i8_tile_seqs() : p.fwd_np ? mfma_forward_tile_seqs() : forward_tile_seqs(nb);
   return (B + t - 1) / t;
 }
 
@@ -264,6 +276,10 @@ hipError_t eval_prepare(const PathSpec& p, const EvalArgs& a, uint8_t* msaT, uin
         launch_rfrag_tail_zero(a.R, a.N, a.B, a.B3, a.B_pad, p.bwd_i8 ? kRiChunkBytes : kRfChunkBytes, st);
     if (e != hipSuccess) return e;
   }
+  if (p.fwd_i8) {
+    const hipError_t e = launch_sym3(a.msa_cm, a.B_pad, a.N, a.NG, const_cast<uint32_t*>(a.sym3), st);
+    if (e != hipSuccess) return e;
+  }
   if (p.bwd_np) return launch_transpose_msa(a.msa_cm, a.B_pad, a.N_pad, msaT, st);
   return launch_chunk_sort(a.msa_cm, a.B3, a.B_pad, a.N, a.q, sorted, st);
 }
@@ -275,7 +291,9 @@ struct Grids {
 
 Grids eval_grids(const plm_ctx* c, const PathSpec& p, int32_t nb) {
   Grids g;
-  g.fwd = c->ncu * (p.fwd_np ? mfma_resident_blocks(KIND_FWD, p.fwd_np) : forward_resident_blocks(nb));
+  g.fwd = c->ncu * (p.fwd_i8   ? fwd_i8_resident_blocks()
+                    : p.fwd_np ? mfma_resident_blocks(KIND_FWD, p.fwd_np)
+                               : forward_resident_blocks(nb));
   g.bwd = c->ncu * (p.bwd_g3   ? g3_resident_blocks()
                     : p.bwd_i8 ? i8_resident_blocks()
                     : p.bwd_np ? mfma_resident_blocks(KIND_BWD, p.bwd_np)
@@ -285,6 +303,7 @@ Grids eval_grids(const plm_ctx* c, const PathSpec& p, int32_t nb) {
 
 hipError_t eval_forward(const PathSpec& p, const BatchArgs& b, int32_t nb, const Grids& g,
                         hipStream_t st) {
+  if (p.fwd_i8) return launch_forward_i8(b, b.total_sites, g.fwd, st);
   return p.fwd_np ? launch_forward_mfma(b, p.fwd_np, g.fwd, st) : launch_forward(b, nb, g.fwd, st);
 }
 
@@ -305,6 +324,11 @@ EvalArgs eval_args(const EvalBufs& e, const uint8_t* msa_unused, int32_t B, int3
   a.R = e.R; a.f_part = e.f_part; a.gh_part = e.gh_part; a.gJ = e.gJ;
   a.tiles = tiles;
   a.rfrag = ps.bwd_i8 ? 2 : (ps.bwd_g3 ? 1 : 0);
+  a.Wq = e.Wq;
+  a.jexp = e.jexp;
+  a.sym3 = e.sym3;
+  a.NG = e.NG;
+  a.pad_ = 0;
   a.sorted = e.sorted;
   return a;
 }
@@ -447,7 +471,7 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
   layout_eval(bp, B, N, q, e);
   Tables t;
   layout_tables(bp, 1, N, false, t);
-  const BatchArgs b = batch_args(t, 1, N, bwd_group(ps));
+  const BatchArgs b = batch_args(t, 1, N, bwd_group(ps), fwd_group(ps));
   HIPCHK(c, launch_check_f64(w, (size_t)B, c->pin_dev, c->stream));
   HIPCHK(c, launch_check_f32(h, (size_t)N * q, c->pin_dev, c->stream));
   HIPCHK(c, launch_check_f32(J, (size_t)N * N * q * q, c->pin_dev, c->stream));
@@ -571,7 +595,7 @@ int prepare_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const p
   Tables t;
   fit_layout(d, n, q, o, (char*)ws, &fb, &t);
   const std::vector<int32_t> ord = batch_order(d, n);
-  const BatchArgs b = batch_args(t, n, total, bwd_group(ps));
+  const BatchArgs b = batch_args(t, n, total, bwd_group(ps), fwd_group(ps));
   // the fit runs on the context's private stream once the caller's stream has
   // delivered its inputs, and returns after the private stream has finished
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -804,8 +828,9 @@ int plm_tune(plm_ctx* c, const plm_msa_desc* descs, int32_t n_msas, int32_t q, c
     int32_t path, tile;
   };
   std::vector<Cand> cands;
-  const int32_t paths[] = {PLM_PATH_GATHER_MFMA_I8X3, PLM_PATH_GATHER_MFMA_F16X2, PLM_PATH_GATHER_MFMA_FP32,
-                           PLM_PATH_GATHER_FP32,       PLM_PATH_MFMA_FP32,         PLM_PATH_MFMA_BF16X2};
+  const int32_t paths[] = {PLM_PATH_MFMA_I8X3,   PLM_PATH_GATHER_MFMA_I8X3, PLM_PATH_GATHER_MFMA_F16X2,
+                           PLM_PATH_GATHER_MFMA_FP32, PLM_PATH_GATHER_FP32,    PLM_PATH_MFMA_FP32,
+                           PLM_PATH_MFMA_BF16X2};
   for (int32_t p : paths) {
     if (fp32_only && p == PLM_PATH_MFMA_BF16X2) continue;
     PathSpec ps;
@@ -813,7 +838,7 @@ int plm_tune(plm_ctx* c, const plm_msa_desc* descs, int32_t n_msas, int32_t q, c
     bool fits = true;
     for (int32_t k = 0; k < n_msas; ++k) fits = fits && path_fits(ps, descs[k].B);
     if (!fits) continue;
-    if (ps.fwd_np) {
+    if (ps.fwd_np || ps.fwd_i8) {
       cands.push_back({p, 0});
     } else {
       for (int32_t tl : {16, 32, 64}) cands.push_back({p, tl});
@@ -961,7 +986,7 @@ int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int3
   HIPCHK(c, hipMemcpyAsync(f.pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice, st));
 
   const int32_t nb = pick_nb(B, o->tile_seqs);
-  const BatchArgs b = batch_args(f.t, 1, N, bwd_group(ps));
+  const BatchArgs b = batch_args(f.t, 1, N, bwd_group(ps), fwd_group(ps));
   HIPCHK(c, launch_check_f64(w, (size_t)B, c->pin_dev, st));
   HIPCHK(c, launch_check_f32(h_io, (size_t)N * q, c->pin_dev, st));
   HIPCHK(c, launch_check_f32(J_io, (size_t)N * N * q * q, c->pin_dev, st));

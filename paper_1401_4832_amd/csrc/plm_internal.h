@@ -70,6 +70,12 @@ struct EvalArgs {
   int32_t tiles;
   int32_t rfrag;           // R in gradient-fragment order: 1 FP16 hi/lo pieces, 2 int8 digits (see below)
   const uint16_t* sorted;  // [nchunks][N][kBwdSeqChunk]: (row << 8) | symbol, rows sorted by symbol
+  // int8 forward (path 6): couplings as fixed-point digits, symbols by position triple
+  int8_t* Wq;              // [N][NG][3 digits][2 steps][2 halves][21 states][16] bytes
+  int32_t* jexp;           // [N] scale exponent: digits of round(J * 2^jexp)
+  const uint32_t* sym3;    // [NG][B_pad] symbols of positions 3G, 3G+1, 3G+2 (bytes 0..2)
+  int32_t NG;              // position triples, ceil(N / 3)
+  int32_t pad_;
 };
 
 // Residuals in gradient-fragment order (rfrag = 1): R_b(s) * kRfScale split
@@ -163,11 +169,12 @@ struct BatchArgs {
   const int32_t* nsub;       // [2][n_msas] work items per site (forward tiles, backward blocks)
   uint32_t* ctr;             // [2][kQueues] queue counters, cleared when the tables are built
   int32_t bwd_group;         // sites per gradient work item (consecutive in the active list)
+  int32_t fwd_group;         // sites per forward work item
 };
 
 // sites per work item of a kind
 __host__ __device__ inline int32_t kind_group(const BatchArgs& b, int kind) {
-  return kind == KIND_BWD ? b.bwd_group : 1;
+  return kind == KIND_BWD ? b.bwd_group : b.fwd_group;
 }
 
 // g, r: the first site of the item; first: its position in the active list;
@@ -346,6 +353,12 @@ hipError_t launch_backward_g3(const BatchArgs& b, int32_t nblocks, hipStream_t s
 // last gradient chunk may reach past them
 hipError_t launch_rfrag_tail_zero(float* R, int32_t N, int32_t B, int32_t B3, int32_t B_pad, int32_t chunk_bytes,
                                   hipStream_t st);
+// int8 fixed-point MFMA forward (three sites per item; path 6)
+constexpr int kWqGroupBytes = 3 * 2 * 2 * kSlot * 16;      // 4032 per (site, position triple)
+int32_t fwd_i8_tile_seqs();
+int32_t fwd_i8_resident_blocks();
+hipError_t launch_sym3(const uint8_t* msa_cm, int32_t B_pad, int32_t N, int32_t NG, uint32_t* sym3, hipStream_t st);
+hipError_t launch_forward_i8(const BatchArgs& b, int32_t total_sites, int32_t nblocks, hipStream_t st);
 // grouped int8 fixed-point MFMA gradient (three sites per item, R as digits)
 int32_t i8_backward_blocks_per_site(int32_t N, int32_t q);
 int32_t i8_resident_blocks();

@@ -36,7 +36,7 @@ def _prep(plm, s):
     return msa, w, beff
 
 
-@pytest.mark.parametrize("path", [0, 2, 3, 4, 5])
+@pytest.mark.parametrize("path", [0, 2, 3, 4, 5, 6])
 def test_batch_equals_single_alignment_fits(plm, ragged, path):
     print(f"[case] batch vs single fits path={path} sizes={[s.msa.shape for s in ragged]}", flush=True)
     items = [_prep(plm, s) for s in ragged]
@@ -89,11 +89,11 @@ def test_tuner_times_every_candidate_and_autotuned_fit_converges(plm, ragged, tm
     monkeypatch.setenv("PLM_TUNE_CACHE", str(tmp_path / "tune.json"))
     items = [_prep(plm, s) for s in ragged]
     res = plm.tune(items, plm.FitOptions(), fp32_only=True)
-    # paths 5, 4, 2 and 0 with three forward tiles each, path 3 with the MFMA forward
-    assert len(res) == 13
+    # paths 5, 4, 2 and 0 with three forward tiles each, paths 6 and 3 with their MFMA forwards
+    assert len(res) == 14
     assert sorted((r["path"], r["tile_seqs"]) for r in res) == sorted(
         [(5, 16), (5, 32), (5, 64), (4, 16), (4, 32), (4, 64), (2, 16), (2, 32), (2, 64), (0, 16), (0, 32),
-         (0, 64), (3, 0)])
+         (0, 64), (3, 0), (6, 0)])
     assert all(r["eval_ms"] > 0 for r in res)
     assert [r["eval_ms"] for r in res] == sorted(r["eval_ms"] for r in res)
     out = plm.fit_batch(items, plm.FitOptions(tol=1e-6, autotune=True))

@@ -57,7 +57,7 @@ def test_fit_small_all_sites(plm):
     np.testing.assert_allclose(cfn.cpu().numpy(), cfn_o, rtol=1e-9, atol=1e-12)
 
 
-@pytest.mark.parametrize("path", [0, 2, 3, 4, 5])
+@pytest.mark.parametrize("path", [0, 2, 3, 4, 5, 6])
 def test_fit_gapped_sampled_sites(plm, path):
     print(f"[case] fit potts_n120_b5000_gaps sampled sites path={path}", flush=True)
     s = synth.workload("potts_n120_b5000_gaps")

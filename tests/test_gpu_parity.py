@@ -87,7 +87,7 @@ def test_reweight_uniform(plm):
 # paths held to the FP32 tolerance: gather/scatter; gather + three-piece BF16 MFMA gradient;
 # three-piece MFMA both ways; gather + FP16 hi/lo MFMA gradient (22 significant bits of R, error
 # <= 2^-22 |R| per residual, i.e. <= 2.4e-7 on the normalised gradient, inside the FP32 bound)
-PATHS = [0, 2, 3, 4, 5]
+PATHS = [0, 2, 3, 4, 5, 6]
 
 
 def _objgrad_case(plm, msa, w_o, beff_o, h, J, lh=0.01, lJ=0.01, sites=None, path=0, fabs=False):

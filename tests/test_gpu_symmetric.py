@@ -58,7 +58,7 @@ def _certificate(s, h, J, lh, lJ):
     return F, float(np.sqrt(np.sum(gh ** 2) + np.sum(gJ ** 2)))
 
 
-@pytest.mark.parametrize("path", [0, 2, 3, 4, 5])
+@pytest.mark.parametrize("path", [0, 2, 3, 4, 5, 6])
 def test_symmetric_fit_matches_oracle(plm, small, path):
     s, h_o, J_o = small
     print(f"[case] symmetric fit N=10 B=700 path={path}", flush=True)
