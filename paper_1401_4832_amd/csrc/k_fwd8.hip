@@ -31,6 +31,7 @@ constexpr int kFIWaves = 8;
 constexpr int kFIThreads = kFIWaves * 64;
 constexpr int kFIRB = 2;                                   // 32-sequence row blocks per wave
 constexpr int kFISeqs = kFIWaves * kFIRB * 32;             // 512 sequences per item
+static_assert(kFISeqs % 256 == 0, "symbol copies of 1 KB");
 constexpr int kFIStageG = 4;                               // position triples per LDS stage
 constexpr int kFISiteBytes = kFIStageG * kWqGroupBytes;    // 16128
 // bank-disjoint site runs: column c of a tile reads 16-byte slot c mod 8
@@ -148,7 +149,7 @@ __device__ inline uint4 spread16(uint32_t bits) {
 }
 
 __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const Item& it, int8_t* W0, int8_t* W1,
-                                   uint32_t* S0, uint32_t* S1, double* red) {
+                                   uint32_t* S0, uint32_t* S1, double* red, double* wrow, uint8_t* srow) {
   const int q = a.q, N = a.N, NG = a.NG;
   const int tid = item_tid(), lane = tid & 63, wid = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
@@ -177,7 +178,8 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
     const int ng = min(kFIStageG, NG - c * kFIStageG);
     const int bytes = ng * kWqGroupBytes;
     const int per = (bytes + 1023) / 1024;
-    const int ninst = cnt * per + 2 * ng;
+    constexpr int kSymParts = kFISeqs / 256;  // 1 KB copies of a triple's symbols
+    const int ninst = cnt * per + kSymParts * ng;
     for (int k = wid; k < ninst; k += kFIWaves) {
       if (k < cnt * per) {
         const int g = k / per, part = k - g * per;
@@ -189,7 +191,7 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
                                          (void __attribute__((address_space(3)))*)(Wd + g * kFISiteStride + off),
                                          16, 0, 0);
       } else {
-        const int k2 = k - cnt * per, kg = k2 >> 1, part = k2 & 1;
+        const int k2 = k - cnt * per, kg = k2 / kSymParts, part = k2 - kg * kSymParts;
         const uint32_t* src = a.sym3 + (size_t)(c * kFIStageG + kg) * a.B_pad + b0 + part * 256 + lane * 4;
         __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
                                          (void __attribute__((address_space(3)))*)(Sd + kg * kFISeqs + part * 256),
@@ -264,9 +266,23 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
                         : reinterpret_cast<float*>(W1) + (wid - 4) * kFIParkFloats;
   double facc = 0.0, ghacc = 0.0;
   const float hv = act ? gmem(a.h)[rA * q + s] : 0.f;
+  double* wv = wrow + wid * 32;    // this wave's row block: weights and
+  uint8_t* sv = srow + wid * 96;   // the group's own symbols, [site][row]
 #pragma unroll
   for (int m = 0; m < kFIRB; ++m) {
-    // this row block's energies, [sequence][column], column = 21 site + state
+    const int brow = b0 + (wid * kFIRB + m) * 32;
+    // the row block's weights and own symbols, staged once instead of loaded per row
+    if (lane < 32) wv[lane] = brow + lane < a.B ? gmem(a.w)[brow + lane] : 0.0;
+#pragma unroll
+    for (int k2 = 0; k2 < 2; ++k2) {
+      const int e2 = lane + 64 * k2;
+      if (e2 < 96) {
+        const int g2 = e2 >> 5, row2 = e2 & 31;
+        const int r2 = g2 == 0 ? rs[0] : (g2 == 1 ? rs[1] : rs[2]);
+        sv[e2] = gmem(a.msa_cm)[((size_t)(r2 / kFwdChunk) * a.B_pad + brow + row2) * kFwdChunk + r2 % kFwdChunk];
+      }
+    }
+    // this row block's energies without h, [sequence][column], column = 21 site + state
 #pragma unroll
     for (int T = 0; T < 2; ++T) {
       const int col = 32 * T + l32;
@@ -274,50 +290,67 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
       const int kg_ = g == 0 ? ks[0] : (g == 1 ? ks[1] : ks[2]);
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const int row = 8 * (j >> 2) + 4 * half + (j & 3);
         const double v = (double)acc[0][m][T][j] * 65536.0 + (double)acc[1][m][T][j] * 256.0 +
                          (double)acc[2][m][T][j];
-        if (col < 3 * kSlot) park[row * 64 + col] = kg_ == kJexpBad ? NAN : (float)ldexp(v, -kg_);
+        if (col < 3 * kSlot)
+          park[(8 * (j >> 2) + 4 * half + (j & 3)) * 64 + col] = kg_ == kJexpBad ? NAN : (float)ldexp(v, -kg_);
       }
     }
     __syncthreads();
+    // four rows at a time, so that their chains of cross-lane reductions overlap
+    constexpr int U = 4;
 #pragma unroll 1
-    for (int row = 0; row < 32; ++row) {
-      const int b = b0 + (wid * kFIRB + m) * 32 + row;
-      const float e = act ? park[row * 64 + sbase + s] + hv : -INFINITY;
-      float mxv = e;
+    for (int row0 = 0; row0 < 32; row0 += U) {
+      float e[U], mx[U], ex[U], sm[U];
 #pragma unroll
-      for (int dd = 1; dd < 32; dd <<= 1) {
-        const float o = __shfl_down(mxv, dd, 64);
-        if (s + dd < kSlot) mxv = fmaxf(mxv, o);
+      for (int u = 0; u < U; ++u) {
+        e[u] = act ? park[(row0 + u) * 64 + sbase + s] + hv : -INFINITY;
+        mx[u] = e[u];
       }
-      mxv = __shfl(mxv, sbase, 64);
-      const float ex = act ? expf(e - mxv) : 0.f;
-      float sum = ex;
 #pragma unroll
-      for (int dd = 1; dd < 32; dd <<= 1) {
-        const float o = __shfl_down(sum, dd, 64);
-        if (s + dd < kSlot) sum += o;
+      for (int dd = 1; dd < 32; dd <<= 1)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const float o = __shfl_down(mx[u], dd, 64);
+          if (s + dd < kSlot) mx[u] = fmaxf(mx[u], o);
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        mx[u] = __shfl(mx[u], sbase, 64);
+        ex[u] = act ? expf(e[u] - mx[u]) : 0.f;
+        sm[u] = ex[u];
       }
-      sum = __shfl(sum, sbase, 64);
-      const float lse = mxv + logf(sum);
-      const int sr = gmem(a.msa_cm)[((size_t)(rA / kFwdChunk) * a.B_pad + b) * kFwdChunk + rA % kFwdChunk];
-      const double wb = (slot < kG3Sites && b < a.B) ? gmem(a.w)[b] : 0.0;
-      const float P = ex / sum;
-      const float Rv = act ? (float)wb * (P - (s == sr ? 1.f : 0.f)) : 0.f;
-      if (act && s == sr) facc += wb * (double)(lse - e);
-      ghacc += (double)Rv;
-      if (slot < kG3Sites && slot < cnt) {
-        const int v = (int)rintf(Rv * (float)(1 << kRiScaleLog2));
-        const int lo = (int)(int8_t)(v & 255);
-        const int v1 = (v - lo) >> 8;
-        const int mid = (int)(int8_t)(v1 & 255);
-        const int hi = (v1 - mid) >> 8;
-        auto Ri = gmem_w(reinterpret_cast<int8_t*>(a.R));
-        const size_t ix = rifrag_index(rA, nch, b, s);
-        Ri[ix] = (int8_t)hi;
-        Ri[ix + kRiDigitBytes] = (int8_t)mid;
-        Ri[ix + 2 * kRiDigitBytes] = (int8_t)lo;
+#pragma unroll
+      for (int dd = 1; dd < 32; dd <<= 1)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const float o = __shfl_down(sm[u], dd, 64);
+          if (s + dd < kSlot) sm[u] += o;
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int row = row0 + u;
+        const int b = brow + row;
+        const float sum = __shfl(sm[u], sbase, 64);
+        const float lse = mx[u] + logf(sum);
+        const int sr = sv[slotA * 32 + row];
+        const double wb = slot < kG3Sites ? wv[row] : 0.0;
+        const float P = ex[u] / sum;
+        const float Rv = act ? (float)wb * (P - (s == sr ? 1.f : 0.f)) : 0.f;
+        if (act && s == sr) facc += wb * (double)(lse - e[u]);
+        ghacc += (double)Rv;
+        if (slot < kG3Sites && slot < cnt) {
+          const int v = (int)rintf(Rv * (float)(1 << kRiScaleLog2));
+          const int lo = (int)(int8_t)(v & 255);
+          const int v1 = (v - lo) >> 8;
+          const int mid = (int)(int8_t)(v1 & 255);
+          const int hi = (v1 - mid) >> 8;
+          auto Ri = gmem_w(reinterpret_cast<int8_t*>(a.R));
+          const size_t ix = rifrag_index(rA, nch, b, s);
+          Ri[ix] = (int8_t)hi;
+          Ri[ix + kRiDigitBytes] = (int8_t)mid;
+          Ri[ix + 2 * kRiDigitBytes] = (int8_t)lo;
+        }
       }
     }
     __syncthreads();
@@ -350,6 +383,8 @@ __global__ __launch_bounds__(kFIThreads) void fwd_i8_kernel(BatchArgs b) {
   __shared__ __attribute__((aligned(16))) uint32_t S0[kFISymWords];
   __shared__ __attribute__((aligned(16))) uint32_t S1[kFISymWords];
   __shared__ double red[kFIWaves * 64];
+  __shared__ double wrow[kFIWaves * 32];
+  __shared__ uint8_t srow[kFIWaves * 96];
   __shared__ int32_t item_s;
   int32_t qi = 0;
   const int32_t total = total_items(b, KIND_FWD);
@@ -360,7 +395,7 @@ __global__ __launch_bounds__(kFIThreads) void fwd_i8_kernel(BatchArgs b) {
     if (t < 0) break;
     const Item it = decode_item(b, KIND_FWD, t);
     const EvalArgs a = load_uniform(b.ev + it.m);
-    fwd_i8_item(b, a, it, W0, W1, S0, S1, red);
+    fwd_i8_item(b, a, it, W0, W1, S0, S1, red, wrow, srow);
     __syncthreads();
   }
 }

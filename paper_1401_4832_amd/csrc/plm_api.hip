@@ -76,7 +76,9 @@ void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
   e.B_pad = (int32_t)rup(B, kBPadUnit);
   e.N_pad = (int32_t)rup(N, kFwdChunk);
   e.B3 = (int32_t)rup(B, 3);
-  e.tiles_max = (B + forward_tile_seqs(16) - 1) / forward_tile_seqs(16);
+  // the smallest forward tile gives the most tiles
+  const int32_t tmin = std::min(forward_tile_seqs(16), fwd_i8_tile_seqs());
+  e.tiles_max = (B + tmin - 1) / tmin;
   e.msa_cm = bp.take<uint8_t>((size_t)e.B_pad * e.N_pad);
   e.msaT = bp.take<uint8_t>((size_t)e.B_pad * e.N_pad);
   // FP32 rows [B3][21], or the fragment-order FP16 pieces over B_pad rows
