@@ -81,9 +81,10 @@ extern "C" {
                                   (PLM_E_UNSUPPORTED beyond) */
 #define PLM_PATH_MFMA_I8X3 6   /* both directions as int8 MFMA products in fixed point: the
                                   gradient of path 5, and energies from each site's couplings
-                                  scaled by a power of two 2^k_r with max|J_r| 2^k_r < 2^22 and
-                                  rounded (|dJ| <= 2^-23 max_i,s,k |J_ri(s,k)|), three int8 digits
-                                  accumulated exactly in int32; at most 2^24 - 1 sequences */
+                                  scaled by a power of two 2^k_r with max|J_r| 2^k_r in
+                                  [2^21, 2^22) and rounded (|dJ| <= 2^-22 max_i,s,k |J_ri(s,k)|),
+                                  three int8 digits accumulated exactly in int32; at most
+                                  2^24 - 1 sequences */
 
 typedef struct plm_ctx plm_ctx;
 
@@ -186,6 +187,8 @@ typedef struct {
   double total_ms;      /* wall time of the fit on the device stream */
   int64_t iterations;   /* graph replays (or eager iterations) executed */
   int64_t site_evals;   /* site objective+gradient evaluations performed */
+  double quant_ms;      /* the part of forward_ms spent writing the couplings' int8 digits
+                           (evaluation path 6; 0 on the others) */
 } plm_fit_timing;
 
 int plm_fit_last_timing(const plm_ctx *ctx, plm_fit_timing *out);

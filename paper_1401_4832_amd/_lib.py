@@ -54,6 +54,7 @@ class FitTiming(ctypes.Structure):
         ("total_ms", ctypes.c_double),
         ("iterations", ctypes.c_int64),
         ("site_evals", ctypes.c_int64),
+        ("quant_ms", ctypes.c_double),
     ]
 
 

@@ -325,7 +325,8 @@ def last_fit_timing(device=None) -> dict:
     t = L.FitTiming()
     _check(L.lib().plm_fit_last_timing(ctx, ctypes.byref(t)), ctx)
     return dict(forward_ms=t.forward_ms, backward_ms=t.backward_ms, lbfgs_ms=t.lbfgs_ms,
-                total_ms=t.total_ms, iterations=int(t.iterations), site_evals=int(t.site_evals))
+                total_ms=t.total_ms, iterations=int(t.iterations), site_evals=int(t.site_evals),
+                quant_ms=t.quant_ms)
 
 
 def score(J: torch.Tensor, combine: str = "avg", norm: str = "frob", p: float = 2.0,

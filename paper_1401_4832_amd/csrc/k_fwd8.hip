@@ -4,9 +4,9 @@
 // residual and field-gradient epilogue of the gather forward (sec. 3.4 step 3).
 //
 // Couplings in fixed point: each site's J_r is scaled by 2^k_r with
-// max |J_r| 2^k_r < 2^22 and rounded (|dJ| <= 2^-(k_r + 1) <= 2^-23 max |J_r|),
+// max |J_r| 2^k_r in [2^21, 2^22) and rounded (|dJ| <= 2^-(k_r + 1) <= 2^-22 max |J_r|),
 // then written as three signed int8 digits (hi 2^16 + mid 2^8 + lo), once per
-// evaluation (jquant_kernel).  The product runs on v_mfma_i32_32x32x32_i8
+// evaluation (jmax_kernel, jquant_kernel).  The product runs on v_mfma_i32_32x32x32_i8
 // with rows = sequences, columns = the 63 (site, state) pairs of the group in
 // two 32-column tiles, and the inner index over position triples: a triple
 // (3G, 3G+1, 3G+2) x 21 states = 63 inner indices, padded to 64 = two steps
@@ -45,12 +45,50 @@ constexpr int kJexpBad = -100000;                          // non-finite couplin
 
 int32_t fwd_i8_tile_seqs() { return kFISeqs; }
 
-// ---- couplings -> digits, one block per active site ---------------------------
+// ---- couplings -> digits, kJParts blocks per active site -------------------------
+// jmax_kernel: block (site, part) takes the positions [part N / P, (part + 1) N / P)
+// of the site's slice (the i = r block left out) and stores the largest |J| as
+// float bits, or -1 when a value is not finite.
+__global__ __launch_bounds__(256) void jmax_kernel(BatchArgs b) {
+  __shared__ int32_t red[4];
+  const int idx = blockIdx.x / kJParts, part = blockIdx.x - idx * kJParts;
+  if (idx >= *b.n_active) return;
+  const int g = b.active[idx];
+  const int m = b.msa_of[g];
+  const EvalArgs a = load_uniform(b.ev + m);
+  const int r = g - b.site_base[m];
+  const int N = a.N, qq = a.q * a.q;
+  const auto Jr = gmem(a.J + (size_t)r * N * qq);
+  const int e0 = (int)((int64_t)part * N / kJParts) * qq, e1 = (int)((int64_t)(part + 1) * N / kJParts) * qq;
+  const int s0 = r * qq, s1 = s0 + qq;
+  float mx = 0.f;
+  int bad = 0;
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += 256) {
+    if (e >= s0 && e < s1) continue;
+    const float v = Jr[e];
+    bad |= !isfinite(v);
+    mx = fmaxf(mx, fabsf(v));
+  }
+  int32_t t = bad ? -1 : __float_as_int(mx);  // non-negative floats order as their bits
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int32_t u = __shfl_xor(t, o, 64);
+    t = (t < 0 || u < 0) ? -1 : max(t, u);
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t v = red[0];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) v = (v < 0 || red[w] < 0) ? -1 : max(v, red[w]);
+    gmem_w(a.jexp + a.N)[r * kJParts + part] = v;
+  }
+}
+
+// jquant_kernel: block (site, part) combines the site's partial maxima into the
+// exponent k_r (part 0 stores it) and writes its share of the digit units.
 __global__ __launch_bounds__(256) void jquant_kernel(BatchArgs b) {
-  __shared__ float red[4];
-  __shared__ int32_t bad_s[4];
-  __shared__ int32_t kexp_s;
-  const int idx = blockIdx.x;
+  const int idx = blockIdx.x / kJParts, part = blockIdx.x - idx * kJParts;
   if (idx >= *b.n_active) return;
   const int g = b.active[idx];
   const int m = b.msa_of[g];
@@ -58,37 +96,23 @@ __global__ __launch_bounds__(256) void jquant_kernel(BatchArgs b) {
   const int r = g - b.site_base[m];
   const int q = a.q, N = a.N, qq = q * q;
   const auto Jr = gmem(a.J + (size_t)r * N * qq);
-  float mx = 0.f;
-  int bad = 0;
-  for (int e = threadIdx.x; e < N * qq; e += blockDim.x) {
-    if (e / qq == r) continue;
-    const float v = Jr[e];
-    bad |= !isfinite(v);
-    mx = fmaxf(mx, fabsf(v));
-  }
+  const auto parts = gmem(a.jexp + N + (size_t)r * kJParts);
+  int32_t t = 0;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-    bad |= __shfl_xor(bad, o, 64);
+  for (int p = 0; p < kJParts; ++p) {
+    const int32_t u = parts[p];
+    t = (t < 0 || u < 0) ? -1 : max(t, u);
   }
-  if ((threadIdx.x & 63) == 0) {
-    red[threadIdx.x >> 6] = mx;
-    bad_s[threadIdx.x >> 6] = bad;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const float t = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    int ex = 0;
-    (void)frexpf(t, &ex);  // t = f 2^ex with f in [0.5, 1) (ex = 0 for t = 0)
-    const int k = (bad_s[0] | bad_s[1] | bad_s[2] | bad_s[3]) ? kJexpBad : kRiScaleLog2 - ex;
-    kexp_s = k;
-    gmem_w(a.jexp)[r] = k;
-  }
-  __syncthreads();
-  const int k = kexp_s == kJexpBad ? 0 : kexp_s;
+  const bool badsite = t < 0;
+  int ex = 0;
+  if (!badsite) (void)frexpf(__int_as_float(t), &ex);  // max = f 2^ex, f in [0.5, 1) (ex = 0 for 0)
+  const int kexp = badsite ? kJexpBad : kRiScaleLog2 - ex;
+  if (part == 0 && threadIdx.x == 0) gmem_w(a.jexp)[r] = kexp;
+  const int k = badsite ? 0 : kexp;
   const int units = a.NG * 4 * kSlot;  // (triple, step, half, state)
+  const int u0 = (int)((int64_t)part * units / kJParts), u1 = (int)((int64_t)(part + 1) * units / kJParts);
   auto Wq = gmem_w(a.Wq + (size_t)r * a.NG * kWqGroupBytes);
-  for (int u = threadIdx.x; u < units; u += blockDim.x) {
+  for (int u = u0 + (int)threadIdx.x; u < u1; u += 256) {
     const int G = u / (4 * kSlot), rem = u - G * (4 * kSlot);
     const int th = rem / kSlot, sidx = rem - th * kSlot;  // th = 2 t + half
     uint32_t w[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
@@ -98,7 +122,7 @@ __global__ __launch_bounds__(256) void jquant_kernel(BatchArgs b) {
       const int p = K / kSlot, kk = K - p * kSlot;
       const int i = 3 * G + p;
       int v = 0;
-      if (p < 3 && i < N && i != r && kk < q && sidx < q && kexp_s != kJexpBad)
+      if (p < 3 && i < N && i != r && kk < q && sidx < q && !badsite)
         v = (int)rintf(ldexpf(Jr[(size_t)i * qq + kk * q + sidx], k));
       const int lo = (int)(int8_t)(v & 255);
       const int v1 = (v - lo) >> 8;
@@ -408,8 +432,13 @@ int32_t fwd_i8_resident_blocks() {
 
 // Couplings of every active site to digits, then the energies and the rest of
 // the forward.  total_sites bounds the active list (the grid of the first kernel).
-hipError_t launch_forward_i8(const BatchArgs& b, int32_t total_sites, int32_t nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(jquant_kernel, dim3(total_sites), dim3(256), 0, st, b);
+hipError_t launch_jquant(const BatchArgs& b, int32_t total_sites, hipStream_t st) {
+  hipLaunchKernelGGL(jmax_kernel, dim3(total_sites * kJParts), dim3(256), 0, st, b);
+  hipLaunchKernelGGL(jquant_kernel, dim3(total_sites * kJParts), dim3(256), 0, st, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_i8(const BatchArgs& b, int32_t nblocks, hipStream_t st) {
   hipLaunchKernelGGL(fwd_i8_kernel, dim3(nblocks), dim3(kFIThreads), 0, st, b);
   return hipGetLastError();
 }

@@ -8,8 +8,12 @@
 // search decision (sufficient decrease with backtracking by safeguarded
 // quadratic interpolation), and on acceptance stores the curvature pair and
 // writes the next trial point.  All dot products, the history and the small
-// matrices are FP64; the iterate is kept at FP32-representable values so that
-// the evaluated point and the stored point are the same.
+// matrices are FP64, the stored curvature pairs FP32 (the gradients they are
+// differences of carry the rounding noise of the FP32 evaluation, far above
+// the 2^-24 relative rounding of the stored values; halving the history's
+// bytes halves most of this streaming kernel's traffic); the iterate is kept
+// at FP32-representable values so that the evaluated point and the stored
+// point are the same.
 //
 // The search direction d = -H g uses the compact representation of the
 // limited-memory inverse Hessian (Byrd, Nocedal and Schnabel, 1994), which
@@ -171,9 +175,12 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
     for (int e = tid; e < P; e += nth) {
       const double g = gtv(e);
       if (pair) {
-        const double sv = Tv(e) - Xv(e), yv = g - Gv(e);
-        *Sp(head, e) = sv;
-        *Yp(head, e) = yv;
+        // the pair is stored in FP32 and used as stored, so that its dot
+        // products describe exactly the vectors the direction is formed from
+        const float svf = (float)(Tv(e) - Xv(e)), yvf = (float)(g - Gv(e));
+        *Sp(head, e) = svf;
+        *Yp(head, e) = yvf;
+        const double sv = svf, yv = yvf;
         acc[0] += sv * yv;
         acc[1] += yv * yv;
         acc[2] += sv * g;

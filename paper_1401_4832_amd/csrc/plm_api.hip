@@ -90,7 +90,7 @@ void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
   e.sorted = bp.take<uint16_t>((size_t)e.nchunks * N * kBwdSeqChunk);
   e.NG = (N + 2) / 3;
   e.Wq = bp.take<int8_t>((size_t)N * e.NG * kWqGroupBytes);
-  e.jexp = bp.take<int32_t>((size_t)N);
+  e.jexp = bp.take<int32_t>((size_t)N * (1 + kJParts));
   e.sym3 = bp.take<uint32_t>((size_t)e.NG * e.B_pad);
 }
 
@@ -98,7 +98,8 @@ void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
 struct FitBufs {
   EvalBufs ev;
   float *Th, *TJ;
-  double *Gh, *GJ, *Dh, *DJ, *Sh, *SJ, *Yh, *YJ, *small;
+  double *Gh, *GJ, *Dh, *DJ, *small;
+  float *Sh, *SJ, *Yh, *YJ;
 };
 
 void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, FitBufs& f) {
@@ -110,10 +111,10 @@ void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, FitBufs& f
   f.GJ = bp.take<double>(NNqq);
   f.Dh = bp.take<double>(Nq);
   f.DJ = bp.take<double>(NNqq);
-  f.Sh = bp.take<double>(Nq * (m + 1));
-  f.SJ = bp.take<double>(NNqq * (m + 1));
-  f.Yh = bp.take<double>(Nq * (m + 1));
-  f.YJ = bp.take<double>(NNqq * (m + 1));
+  f.Sh = bp.take<float>(Nq * (m + 1));
+  f.SJ = bp.take<float>(NNqq * (m + 1));
+  f.Yh = bp.take<float>(Nq * (m + 1));
+  f.YJ = bp.take<float>(NNqq * (m + 1));
   f.small = bp.take<double>((size_t)N * 2 * (m + 1) * (m + 1));
 }
 
@@ -303,10 +304,21 @@ Grids eval_grids(const plm_ctx* c, const PathSpec& p, int32_t nb) {
   return g;
 }
 
+// the forward's per-evaluation preparation of the couplings (int8 digits; nothing on other paths)
+hipError_t eval_quant(const PathSpec& p, const BatchArgs& b, hipStream_t st) {
+  return p.fwd_i8 ? launch_jquant(b, b.total_sites, st) : hipSuccess;
+}
+
+hipError_t eval_forward_main(const PathSpec& p, const BatchArgs& b, int32_t nb, const Grids& g,
+                             hipStream_t st) {
+  if (p.fwd_i8) return launch_fwd_i8(b, g.fwd, st);
+  return p.fwd_np ? launch_forward_mfma(b, p.fwd_np, g.fwd, st) : launch_forward(b, nb, g.fwd, st);
+}
+
 hipError_t eval_forward(const PathSpec& p, const BatchArgs& b, int32_t nb, const Grids& g,
                         hipStream_t st) {
-  if (p.fwd_i8) return launch_forward_i8(b, b.total_sites, g.fwd, st);
-  return p.fwd_np ? launch_forward_mfma(b, p.fwd_np, g.fwd, st) : launch_forward(b, nb, g.fwd, st);
+  hipError_t e = eval_quant(p, b, st);
+  return e == hipSuccess ? eval_forward_main(p, b, nb, g, st) : e;
 }
 
 hipError_t eval_backward(const PathSpec& p, const BatchArgs& b, const Grids& g, hipStream_t st) {
@@ -685,7 +697,9 @@ int run_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_f
     auto mark = [&](int k) -> hipError_t { return timed ? hipEventRecord(c->ev[k], st) : hipSuccess; };
     auto enqueue = [&]() -> hipError_t {
       hipError_t e = mark(0);
-      if (e == hipSuccess) e = eval_forward(ps, b, nb, g, st);
+      if (e == hipSuccess) e = eval_quant(ps, b, st);
+      if (e == hipSuccess) e = mark(4);
+      if (e == hipSuccess) e = eval_forward_main(ps, b, nb, g, st);
       if (e == hipSuccess) e = mark(1);
       if (e == hipSuccess) e = eval_backward(ps, b, g, st);
       if (e == hipSuccess) e = mark(2);
@@ -724,11 +738,13 @@ int run_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_f
         break;
       }
       if (timed) {
-        float t01 = 0.f, t12 = 0.f, t23 = 0.f;
+        float t01 = 0.f, t12 = 0.f, t23 = 0.f, t04 = 0.f;
         if (hipEventElapsedTime(&t01, c->ev[0], c->ev[1]) == hipSuccess &&
             hipEventElapsedTime(&t12, c->ev[1], c->ev[2]) == hipSuccess &&
-            hipEventElapsedTime(&t23, c->ev[2], c->ev[3]) == hipSuccess) {
+            hipEventElapsedTime(&t23, c->ev[2], c->ev[3]) == hipSuccess &&
+            hipEventElapsedTime(&t04, c->ev[0], c->ev[4]) == hipSuccess) {
           tm.forward_ms += t01;
+          tm.quant_ms += t04;
           tm.backward_ms += t12;
           tm.lbfgs_ms += t23;
         } else {
@@ -1019,7 +1035,9 @@ int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int3
   auto mark = [&](int k) -> hipError_t { return timed ? hipEventRecord(c->ev[k], st) : hipSuccess; };
   auto enqueue = [&]() -> hipError_t {
     hipError_t e = mark(0);
-    if (e == hipSuccess) e = eval_forward(ps, b, nb, g, st);
+    if (e == hipSuccess) e = eval_quant(ps, b, st);
+    if (e == hipSuccess) e = mark(4);
+    if (e == hipSuccess) e = eval_forward_main(ps, b, nb, g, st);
     if (e == hipSuccess) e = mark(1);
     if (e == hipSuccess) e = eval_backward(ps, b, g, st);
     if (e == hipSuccess) e = mark(2);
@@ -1059,11 +1077,13 @@ int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int3
       break;
     }
     if (timed) {
-      float t01 = 0.f, t12 = 0.f, t23 = 0.f;
+      float t01 = 0.f, t12 = 0.f, t23 = 0.f, t04 = 0.f;
       if (hipEventElapsedTime(&t01, c->ev[0], c->ev[1]) == hipSuccess &&
           hipEventElapsedTime(&t12, c->ev[1], c->ev[2]) == hipSuccess &&
-          hipEventElapsedTime(&t23, c->ev[2], c->ev[3]) == hipSuccess) {
+          hipEventElapsedTime(&t23, c->ev[2], c->ev[3]) == hipSuccess &&
+          hipEventElapsedTime(&t04, c->ev[0], c->ev[4]) == hipSuccess) {
         tm.forward_ms += t01;
+        tm.quant_ms += t04;
         tm.backward_ms += t12;
         tm.lbfgs_ms += t23;
       } else {

@@ -72,7 +72,7 @@ struct EvalArgs {
   const uint16_t* sorted;  // [nchunks][N][kBwdSeqChunk]: (row << 8) | symbol, rows sorted by symbol
   // int8 forward (path 6): couplings as fixed-point digits, symbols by position triple
   int8_t* Wq;              // [N][NG][3 digits][2 steps][2 halves][21 states][16] bytes
-  int32_t* jexp;           // [N] scale exponent: digits of round(J * 2^jexp)
+  int32_t* jexp;           // [N] scale exponent: digits of round(J * 2^jexp); then [N][kJParts] partial maxima
   const uint32_t* sym3;    // [NG][B_pad] symbols of positions 3G, 3G+1, 3G+2 (bytes 0..2)
   int32_t NG;              // position triples, ceil(N / 3)
   int32_t pad_;
@@ -119,10 +119,10 @@ struct LbfgsArgs {
   double* GJ;
   double* Dh;
   double* DJ;
-  double* Sh;  // [m+1][N][q] history slots (one spare for the candidate pair)
-  double* SJ;  // [m+1][N][N q q]
-  double* Yh;
-  double* YJ;
+  float* Sh;   // [m+1][N][q] history slots (one spare for the candidate pair), FP32
+  float* SJ;   // [m+1][N][N q q]
+  float* Yh;
+  float* YJ;
   double* small;  // [N][2][m+1][m+1] S^T Y and Y^T Y by slot
   const double* f_part;   // [tiles][N]
   const double* gh_part;  // [tiles][N][21]
@@ -355,10 +355,13 @@ hipError_t launch_rfrag_tail_zero(float* R, int32_t N, int32_t B, int32_t B3, in
                                   hipStream_t st);
 // int8 fixed-point MFMA forward (three sites per item; path 6)
 constexpr int kWqGroupBytes = 3 * 2 * 2 * kSlot * 16;      // 4032 per (site, position triple)
+constexpr int kJParts = 16;                                 // blocks per site of the coupling quantisation
 int32_t fwd_i8_tile_seqs();
 int32_t fwd_i8_resident_blocks();
 hipError_t launch_sym3(const uint8_t* msa_cm, int32_t B_pad, int32_t N, int32_t NG, uint32_t* sym3, hipStream_t st);
-hipError_t launch_forward_i8(const BatchArgs& b, int32_t total_sites, int32_t nblocks, hipStream_t st);
+// couplings of every active site to digits (jmax_kernel, jquant_kernel), then the int8 forward
+hipError_t launch_jquant(const BatchArgs& b, int32_t total_sites, hipStream_t st);
+hipError_t launch_fwd_i8(const BatchArgs& b, int32_t nblocks, hipStream_t st);
 // grouped int8 fixed-point MFMA gradient (three sites per item, R as digits)
 int32_t i8_backward_blocks_per_site(int32_t N, int32_t q);
 int32_t i8_resident_blocks();

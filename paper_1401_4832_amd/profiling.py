@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 1 << 30
 KERNELS = {"forward": "fwd_kernel", "backward": "bwd_kernel", "forward_mfma": "fwd_mfma_kernel",
            "backward_mfma": "bwd_mfma_kernel", "backward_g3": "bwd_g3_kernel", "backward_i8": "bwd_i8_kernel", "forward_i8": "fwd_i8_kernel",
-           "lbfgs": "lbfgs_kernel",
+           "jmax": "jmax_kernel", "jquant": "jquant_kernel", "lbfgs": "lbfgs_kernel",
            "reweight": "identity_kernel"}
 
 
@@ -33,7 +33,8 @@ KERNELS = {"forward": "fwd_kernel", "backward": "bwd_kernel", "forward_mfma": "f
 KERNEL_SOURCES = {"forward": ("k_gather.hip", "plm_internal.h"), "backward": ("k_gather.hip", "plm_internal.h"),
                   "forward_mfma": ("k_mfma.hip", "plm_internal.h"), "backward_mfma": ("k_mfma.hip", "plm_internal.h"),
                   "backward_g3": ("k_mfma.hip", "plm_internal.h"), "backward_i8": ("k_mfma.hip", "plm_internal.h"),
-                  "forward_i8": ("k_fwd8.hip", "plm_internal.h"),
+                  "forward_i8": ("k_fwd8.hip", "plm_internal.h"), "jmax": ("k_fwd8.hip", "plm_internal.h"),
+                  "jquant": ("k_fwd8.hip", "plm_internal.h"),
                   "lbfgs": ("k_lbfgs.hip", "plm_internal.h"), "reweight": ("k_reweight.hip", "plm_internal.h")}
 
 

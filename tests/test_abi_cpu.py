@@ -59,8 +59,8 @@ def test_workspace_sizes_are_host_computable(lib):
     lib.plm_fit_opts_default(ctypes.byref(o))
     assert o.lbfgs_m == 10 and o.tol == 1e-6 and o.lambda_h == 0.01 and o.lambda_J == 0.01
     fit_ws = lib.plm_fit_workspace_bytes(50000, 500, 21, ctypes.byref(o))
-    # the L-BFGS history dominates: 2 m N^2 q^2 doubles
-    assert fit_ws > 2 * 10 * 500 * 500 * 441 * 8
+    # the L-BFGS history dominates: 2 (m + 1) N^2 q^2 FP32 values
+    assert fit_ws > 2 * 11 * 500 * 500 * 441 * 4
     o.lbfgs_m = 0
     assert lib.plm_fit_workspace_bytes(500, 40, 21, ctypes.byref(o)) == 0
 

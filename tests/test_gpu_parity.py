@@ -153,6 +153,43 @@ def test_objgrad_hilo_path_within_derived_bound(plm, B, N, q):
         assert np.all(gJ[r, r] == 0)
 
 
+def _fixed_point_bounds(msa, w, beff, J, sites):
+    """Error bounds of the int8 fixed-point path (6), from its arithmetic.
+
+    Each site's couplings are scaled by 2^k_r with max|J_r| 2^k_r in
+    [2^21, 2^22) and rounded, so |dJ| <= 2^-22 max_{i != r} |J_r|; an energy
+    moves by at most eps_E = (N - 1) 2^-22 max|J_r|, log Z by at most eps_E and
+    each probability by a factor exp(+-2 eps_E): |df| <= 2 eps_E per weighted
+    sequence.  The residuals are rounded to 2^-23 absolute (|R| <= w_b <= 1) and
+    accumulated exactly, so a normalised gradient entry moves by at most
+    2 eps_E + 2^-23 B / B_eff.  FP32 rounding of the softmax comes on top."""
+    N = msa.shape[1]
+    eps = 0.0
+    for r in sites:
+        Jr = np.abs(J[r].astype(np.float32).astype(np.float64))
+        Jr[r] = 0
+        eps = max(eps, (N - 1) * 2.0 ** -22 * float(Jr.max()))
+    return 2 * eps, 2 * eps + 2.0 ** -23 * msa.shape[0] / beff
+
+
+@pytest.mark.parametrize("B,N,q,sd", [(700, 97, 21, 1.0), (3001, 33, 21, 2.0), (1537, 49, 11, 0.5), (400, 200, 21, 0.8)])
+def test_objgrad_fixed_point_path_within_derived_bound(plm, B, N, q, sd):
+    _note(f"objgrad int8 fixed point B={B} N={N} q={q} sd={sd}")
+    rng = np.random.default_rng(B * 3 + N)
+    msa = rng.integers(0, q, size=(B, N), dtype=np.uint8)
+    w_o = rng.uniform(0.2, 1.0, size=B)
+    beff_o = float(np.sum(w_o))
+    h, J = random_params(B + 2 * q, N, q, 0.3, sd)
+    fb, gb = _fixed_point_bounds(msa, w_o, beff_o, J, range(N))
+    ferr, gerr, gJ = _objgrad_case(plm, msa, w_o, beff_o, h, J, path=6, fabs=True)
+    print(f"  int8 errors: f {ferr:.2e} (bound {fb:.2e}), grad {gerr:.2e} (bound {gb:.2e})")
+    # the FP32 parts (softmax, residuals before rounding) add at most the FP32 tolerance
+    assert ferr <= fb + 1e-5 * np.log(q) * 10, (ferr, fb)
+    assert gerr <= gb + 2e-6, (gerr, gb)
+    for r in range(N):
+        assert np.all(gJ[r, r] == 0)
+
+
 @pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("B,N,q", [(500, 40, 21), (1, 2, 21), (7, 17, 21), (3001, 33, 21), (800, 25, 3),
                                    (1537, 49, 11), (4000, 70, 21), (700, 97, 21)])
