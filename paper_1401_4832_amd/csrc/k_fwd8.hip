@@ -172,10 +172,21 @@ __device__ inline uint4 spread16(uint32_t bits) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// A wave-uniform address held in scalar registers (so that a copy takes the
+// scalar base + 32-bit lane offset form)
+template <typename T>
+__device__ inline const T* uniform_ptr(const T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
+}
+
 __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const Item& it, int8_t* W0, int8_t* W1,
                                    uint32_t* S0, uint32_t* S1, double* red, double* wrow, uint8_t* srow) {
   const int q = a.q, N = a.N, NG = a.NG;
-  const int tid = item_tid(), lane = tid & 63, wid = tid >> 6;
+  const int tid = item_tid(), lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: copy bookkeeping in scalars
   const int half = lane >> 5, l32 = lane & 31;
   const int cnt = it.cnt;
   const int tile = it.sub;
@@ -183,7 +194,7 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
   int32_t rs[kG3Sites], ks[kG3Sites];
 #pragma unroll
   for (int g = 0; g < kG3Sites; ++g) {
-    rs[g] = g < cnt ? bt.active[it.first + g] - bt.site_base[it.m] : it.r;
+    rs[g] = __builtin_amdgcn_readfirstlane(g < cnt ? bt.active[it.first + g] - bt.site_base[it.m] : it.r);
     ks[g] = gmem(a.jexp)[rs[g]];
   }
   uint32_t boff[2];
@@ -197,12 +208,44 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
 
   // global -> LDS copies of stage c: the group's digits of triples 4c .. 4c+3
   // (a site's run is contiguous; the last 1 KB copy of a run is moved back to
-  // end at the run's end) and the triples' symbols of the item's sequences
+  // end at the run's end) and the triples' symbols of the item's sequences,
+  // 1 KB per copy, copy k issued by wave k mod 8.  A full stage of a full
+  // group has the same copies every stage, shifted by the stage's offsets:
+  // each wave's six coupling copies and one symbol copy are set up once.
+  constexpr int kSymParts = kFISeqs / 256;  // 1 KB copies of a triple's symbols
+  constexpr int kFullPer = (kFISiteBytes + 1023) / 1024;
+  static_assert(kG3Sites * kFullPer == 6 * kFIWaves && kSymParts * kFIStageG == kFIWaves,
+                "six coupling copies and one symbol copy per wave in a full stage");
+  const char* wsrc[6];
+  uint32_t wdst[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int k = wid + kFIWaves * j;
+    const int g = k / kFullPer, part = k - g * kFullPer;
+    const int off = min(part * 1024, kFISiteBytes - 1024);
+    const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
+    wsrc[j] = reinterpret_cast<const char*>(a.Wq) + (size_t)rg * NG * kWqGroupBytes + off;
+    wdst[j] = (uint32_t)(g * kFISiteStride + off);
+  }
+  const uint32_t* ssrc = a.sym3 + (size_t)(wid / kSymParts) * a.B_pad + b0 + (wid % kSymParts) * 256;
+  const uint32_t sdst = (uint32_t)((wid / kSymParts) * kFISeqs + (wid % kSymParts) * 256);
   auto fetch = [&](int c, int8_t* Wd, uint32_t* Sd) {
     const int ng = min(kFIStageG, NG - c * kFIStageG);
+    if (ng == kFIStageG && cnt == kG3Sites) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j)
+        __builtin_amdgcn_global_load_lds(
+            (const void __attribute__((address_space(1)))*)(uniform_ptr(wsrc[j] + (size_t)c * kFISiteBytes) +
+                                                            lane * 16),
+            (void __attribute__((address_space(3)))*)(Wd + wdst[j]), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(
+          (const void __attribute__((address_space(1)))*)(uniform_ptr(ssrc + (size_t)c * kFIStageG * a.B_pad) +
+                                                          lane * 4),
+          (void __attribute__((address_space(3)))*)(Sd + sdst), 16, 0, 0);
+      return;
+    }
     const int bytes = ng * kWqGroupBytes;
     const int per = (bytes + 1023) / 1024;
-    constexpr int kSymParts = kFISeqs / 256;  // 1 KB copies of a triple's symbols
     const int ninst = cnt * per + kSymParts * ng;
     for (int k = wid; k < ninst; k += kFIWaves) {
       if (k < cnt * per) {
