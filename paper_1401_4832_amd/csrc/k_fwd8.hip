@@ -39,8 +39,9 @@ constexpr int kFISiteStride = kFISiteBytes + 80;
 static_assert((kFISiteStride / 16 - kSlot) % 8 == 0 && kFISiteStride % 16 == 0, "bank-disjoint site runs");
 constexpr int kFIBufBytes = 2 * kFISiteStride + kFISiteBytes;
 constexpr int kFISymWords = kFIStageG * kFISeqs;
-constexpr int kFIParkFloats = 32 * 64;                     // one row block of energies per wave
+constexpr int kFIParkFloats = 3 * 32 * 24;                 // one row block of energies per wave, [site][row][24]
 static_assert(4 * kFIParkFloats * 4 <= kFIBufBytes, "four waves' energies fit one buffer");
+static_assert(3 * 672 <= 32 * 24 * 4, "a site's staged digits fit its park rows");
 constexpr int kJexpBad = -100000;                          // non-finite coupling: energies NaN
 
 int32_t fwd_i8_tile_seqs() { return kFISeqs; }
@@ -172,16 +173,6 @@ __device__ inline uint4 spread16(uint32_t bits) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// A wave-uniform address held in scalar registers (so that a copy takes the
-// scalar base + 32-bit lane offset form)
-template <typename T>
-__device__ inline const T* uniform_ptr(const T* p) {
-  const uint64_t v = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
-}
-
 __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const Item& it, int8_t* W0, int8_t* W1,
                                    uint32_t* S0, uint32_t* S1, double* red, double* wrow, uint8_t* srow) {
   const int q = a.q, N = a.N, NG = a.NG;
@@ -296,18 +287,23 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
         uint4 av[kFIRB];
 #pragma unroll
         for (int m = 0; m < kFIRB; ++m) av[m] = spread16(((t ? mhi[m] : mlo[m]) >> (16 * half)) & 0xffffu);
+        // the six B fragments (digit, tile) of this step, each read two ahead of its use
+        const char* fb = wb + kg * kWqGroupBytes + t * (2 * kSlot * 16);
+        auto ldb = [&](int f) {
+          return *reinterpret_cast<const uint4*>(fb + boff[f & 1] + (f >> 1) * 2 * (2 * kSlot * 16));
+        };
+        uint4 bq0 = ldb(0), bq1 = ldb(1);
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
+        for (int f = 0; f < 6; ++f) {
+          uint4 bq2 = bq1;
+          if (f + 2 < 6) bq2 = ldb(f + 2);
 #pragma unroll
-          for (int T = 0; T < 2; ++T) {
-            const uint4 bp = *reinterpret_cast<const uint4*>(wb + boff[T] + kg * kWqGroupBytes +
-                                                            (d * 2 + t) * (2 * kSlot * 16));
-#pragma unroll
-            for (int m = 0; m < kFIRB; ++m)
-              acc[d][m][T] = __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(fi32x4, av[m]),
-                                                                   __builtin_bit_cast(fi32x4, bp), acc[d][m][T], 0, 0,
-                                                                   0);
-          }
+          for (int m = 0; m < kFIRB; ++m)
+            acc[f >> 1][m][f & 1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                __builtin_bit_cast(fi32x4, av[m]), __builtin_bit_cast(fi32x4, bq0), acc[f >> 1][m][f & 1], 0, 0, 0);
+          bq0 = bq1;
+          bq1 = bq2;
+        }
       }
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -323,22 +319,35 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
   }
 
   // ---- epilogue: energies -> log-softmax, objective, residual digits, dh ----
-  const int slot = lane / kSlot, s = lane - slot * kSlot;
-  const int slotA = slot < kG3Sites ? slot : kG3Sites - 1;
-  const bool act = slot < kG3Sites && slot < cnt && s < q;
-  const int rA = slotA == 0 ? rs[0] : (slotA == 1 ? rs[1] : rs[2]);
-  const int sbase = slotA * kSlot;
+  // A lane takes one (sequence, site) pair and runs over the states serially,
+  // so that the log-sum-exp needs no cross-lane reductions: pass 0 takes the
+  // pairs (row lane % 32, site lane / 32), pass 1 (row lane, site 2) on lanes
+  // 0..31.  Energies are parked per wave as [site][row][24]; the residual
+  // digits of a site are staged over its consumed park rows in the layout of
+  // the gradient's fragments ([digit][16-row half][state][16 rows], 672 bytes
+  // per digit and row block) and copied out 16 bytes per lane.  The field
+  // gradient sums the staged digits (exact integers).  Park, weights, symbols
+  // and staging are this wave's own, so the epilogue needs no block barrier.
   const int nch = a.B_pad >> 8;
   float* park = wid < 4 ? reinterpret_cast<float*>(W0) + wid * kFIParkFloats
                         : reinterpret_cast<float*>(W1) + (wid - 4) * kFIParkFloats;
-  double facc = 0.0, ghacc = 0.0;
-  const float hv = act ? gmem(a.h)[rA * q + s] : 0.f;
+  uint8_t* stg = reinterpret_cast<uint8_t*>(park);
+  float* hsh = reinterpret_cast<float*>(S0);  // fields of the group's sites, [site][24]
+  if (tid < 3 * 24) {
+    const int g = tid / 24, ss = tid - g * 24;
+    const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
+    hsh[tid] = (g < cnt && ss < q) ? gmem(a.h)[rg * q + ss] : 0.f;
+  }
+  __syncthreads();
   double* wv = wrow + wid * 32;    // this wave's row block: weights and
   uint8_t* sv = srow + wid * 96;   // the group's own symbols, [site][row]
+  const int row = lane & 31;
+  double fpass[2] = {0.0, 0.0};    // objective terms of pass 0 (site lane / 32) and pass 1 (site 2)
+  int32_t ghi = 0;                 // lane (site, state) < 63: digit sum of the residuals, scaled 2^22
+  const int gl = lane / kSlot, sl = lane - gl * kSlot;
 #pragma unroll
   for (int m = 0; m < kFIRB; ++m) {
     const int brow = b0 + (wid * kFIRB + m) * 32;
-    // the row block's weights and own symbols, staged once instead of loaded per row
     if (lane < 32) wv[lane] = brow + lane < a.B ? gmem(a.w)[brow + lane] : 0.0;
 #pragma unroll
     for (int k2 = 0; k2 < 2; ++k2) {
@@ -349,98 +358,133 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
         sv[e2] = gmem(a.msa_cm)[((size_t)(r2 / kFwdChunk) * a.B_pad + brow + row2) * kFwdChunk + r2 % kFwdChunk];
       }
     }
-    // this row block's energies without h, [sequence][column], column = 21 site + state
+    // this row block's energies without h
 #pragma unroll
     for (int T = 0; T < 2; ++T) {
       const int col = 32 * T + l32;
-      const int g = col / kSlot;
+      const int g = col / kSlot, sc = col - g * kSlot;
       const int kg_ = g == 0 ? ks[0] : (g == 1 ? ks[1] : ks[2]);
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const double v = (double)acc[0][m][T][j] * 65536.0 + (double)acc[1][m][T][j] * 256.0 +
                          (double)acc[2][m][T][j];
         if (col < 3 * kSlot)
-          park[(8 * (j >> 2) + 4 * half + (j & 3)) * 64 + col] = kg_ == kJexpBad ? NAN : (float)ldexp(v, -kg_);
+          park[(g * 32 + 8 * (j >> 2) + 4 * half + (j & 3)) * 24 + sc] =
+              kg_ == kJexpBad ? NAN : (float)ldexp(v, -kg_);
       }
     }
-    __syncthreads();
-    // four rows at a time, so that their chains of cross-lane reductions overlap
-    constexpr int U = 4;
-#pragma unroll 1
-    for (int row0 = 0; row0 < 32; row0 += U) {
-      float e[U], mx[U], ex[U], sm[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        e[u] = act ? park[(row0 + u) * 64 + sbase + s] + hv : -INFINITY;
-        mx[u] = e[u];
+    for (int pass = 0; pass < 2; ++pass) {
+      const int g = pass == 0 ? (lane >> 5) : 2;
+      if (pass == 1 && lane >= 32) continue;
+      float e[24];
+      const float4* pr = reinterpret_cast<const float4*>(park + (g * 32 + row) * 24);
+      const float4* hr = reinterpret_cast<const float4*>(hsh + g * 24);
+#pragma unroll
+      for (int v4 = 0; v4 < 6; ++v4) {
+        const float4 x = pr[v4], hh = hr[v4];
+        e[4 * v4] = x.x + hh.x;
+        e[4 * v4 + 1] = x.y + hh.y;
+        e[4 * v4 + 2] = x.z + hh.z;
+        e[4 * v4 + 3] = x.w + hh.w;
       }
+      const int sr = sv[g * 32 + row];
+      const double wb = wv[row];
+      float mx = -INFINITY, esr = 0.f;
 #pragma unroll
-      for (int dd = 1; dd < 32; dd <<= 1)
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const float o = __shfl_down(mx[u], dd, 64);
-          if (s + dd < kSlot) mx[u] = fmaxf(mx[u], o);
-        }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        mx[u] = __shfl(mx[u], sbase, 64);
-        ex[u] = act ? expf(e[u] - mx[u]) : 0.f;
-        sm[u] = ex[u];
+      for (int st = 0; st < kSlot; ++st) {
+        if (st >= q) e[st] = -INFINITY;
+        mx = fmaxf(mx, e[st]);
+        esr = st == sr ? e[st] : esr;
       }
+      float sum = 0.f;
 #pragma unroll
-      for (int dd = 1; dd < 32; dd <<= 1)
+      for (int st = 0; st < kSlot; ++st) {
+        e[st] = expf(e[st] - mx);
+        sum += e[st];
+      }
+      const float lse = mx + logf(sum);
+      fpass[pass] += wb * (double)(lse - esr);
+      const float wf = (float)wb;
+      // digits of round(R 2^22), R = w (P - [s = sigma_r]), into the staging of site g
+      uint8_t* sg = stg + g * (32 * 24 * 4) + (row >> 4) * (kSlot * 16) + (row & 15);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const float o = __shfl_down(sm[u], dd, 64);
-          if (s + dd < kSlot) sm[u] += o;
-        }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int row = row0 + u;
-        const int b = brow + row;
-        const float sum = __shfl(sm[u], sbase, 64);
-        const float lse = mx[u] + logf(sum);
-        const int sr = sv[slotA * 32 + row];
-        const double wb = slot < kG3Sites ? wv[row] : 0.0;
-        const float P = ex[u] / sum;
-        const float Rv = act ? (float)wb * (P - (s == sr ? 1.f : 0.f)) : 0.f;
-        if (act && s == sr) facc += wb * (double)(lse - e[u]);
-        ghacc += (double)Rv;
-        if (slot < kG3Sites && slot < cnt) {
-          const int v = (int)rintf(Rv * (float)(1 << kRiScaleLog2));
-          const int lo = (int)(int8_t)(v & 255);
-          const int v1 = (v - lo) >> 8;
-          const int mid = (int)(int8_t)(v1 & 255);
-          const int hi = (v1 - mid) >> 8;
-          auto Ri = gmem_w(reinterpret_cast<int8_t*>(a.R));
-          const size_t ix = rifrag_index(rA, nch, b, s);
-          Ri[ix] = (int8_t)hi;
-          Ri[ix + kRiDigitBytes] = (int8_t)mid;
-          Ri[ix + 2 * kRiDigitBytes] = (int8_t)lo;
-        }
+      for (int st = 0; st < kSlot; ++st) {
+        const float P = e[st] / sum;
+        const float Rv = st < q ? wf * (P - (st == sr ? 1.f : 0.f)) : 0.f;
+        const int v = (int)rintf(Rv * (float)(1 << kRiScaleLog2));
+        const int lo = (int)(int8_t)(v & 255);
+        const int v1 = (v - lo) >> 8;
+        const int mid = (int)(int8_t)(v1 & 255);
+        const int hi = (v1 - mid) >> 8;
+        sg[st * 16] = (uint8_t)hi;
+        sg[672 + st * 16] = (uint8_t)mid;
+        sg[2 * 672 + st * 16] = (uint8_t)lo;
       }
     }
-    __syncthreads();
+    // staged digits -> the fragment layout, 16 bytes per lane (sites of the group only)
+    auto Ri = gmem_w(reinterpret_cast<int8_t*>(a.R));
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const int k = lane + 64 * i;  // (site, digit) segment k / 42, 16-byte part k % 42
+      const int seg = k / 42, part = k - seg * 42;
+      const int g = seg / 3, d = seg - g * 3;
+      if (k < 9 * 42 && g < cnt) {
+        const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
+        const uint4 x = *reinterpret_cast<const uint4*>(stg + g * (32 * 24 * 4) + d * 672 + part * 16);
+        *reinterpret_cast<__attribute__((address_space(1))) u32x4_t*>(
+            Ri + rifrag_index(rg, nch, brow, 0) + (size_t)d * kRiDigitBytes + part * 16) =
+            u32x4_t{x.x, x.y, x.z, x.w};
+      }
+    }
+    // field gradient: lane (site, state) sums its 32 rows of each digit plane
+    if (lane < 3 * kSlot) {
+      int32_t dsum[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        int32_t t = 0;
+#pragma unroll
+        for (int h16 = 0; h16 < 2; ++h16) {
+          const uint4 x = *reinterpret_cast<const uint4*>(stg + gl * (32 * 24 * 4) + d * 672 + h16 * (kSlot * 16) +
+                                                          sl * 16);
+          t = __builtin_amdgcn_sdot4((int)x.x, 0x01010101, t, false);
+          t = __builtin_amdgcn_sdot4((int)x.y, 0x01010101, t, false);
+          t = __builtin_amdgcn_sdot4((int)x.z, 0x01010101, t, false);
+          t = __builtin_amdgcn_sdot4((int)x.w, 0x01010101, t, false);
+        }
+        dsum[d] = t;
+      }
+      ghi += dsum[0] * 65536 + dsum[1] * 256 + dsum[2];
+    }
   }
-  // objective and field-gradient partials of this tile, per site of the group
-  red[wid * 64 + lane] = facc;
+  // objective partials: per site, a fixed-order tree over the wave's lanes, then the waves in order
+  double f0 = fpass[0], f1 = fpass[1];
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) {
+    f0 += __shfl_xor(f0, o, 64);
+    f1 += __shfl_xor(f1, o, 64);
+  }
+  if (lane == 0) {
+    red[wid * 64] = f0;       // site 0
+    red[wid * 64 + 2] = f1;   // site 2
+  }
+  if (lane == 32) red[wid * 64 + 1] = f0;  // site 1
   __syncthreads();
   if (tid < cnt) {
     double t = 0.0;
-    for (int w = 0; w < kFIWaves; ++w)
-      for (int ss = 0; ss < kSlot; ++ss) t += red[w * 64 + tid * kSlot + ss];
+    for (int w = 0; w < kFIWaves; ++w) t += red[w * 64 + tid];
     const int rg = tid == 0 ? rs[0] : (tid == 1 ? rs[1] : rs[2]);
     gmem_w(a.f_part)[(size_t)tile * N + rg] = t;
   }
   __syncthreads();
-  red[wid * 64 + lane] = ghacc;
+  red[wid * 64 + lane] = (double)ghi;
   __syncthreads();
   if (tid < cnt * kSlot) {
     const int g = tid / kSlot, ss = tid - g * kSlot;
     double t = 0.0;
     for (int w = 0; w < kFIWaves; ++w) t += red[w * 64 + tid];
     const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
-    gmem_w(a.gh_part)[((size_t)tile * N + rg) * kSlot + ss] = t;
+    gmem_w(a.gh_part)[((size_t)tile * N + rg) * kSlot + ss] = ss < q ? t * (1.0 / (double)(1 << kRiScaleLog2)) : 0.0;
   }
 }
 

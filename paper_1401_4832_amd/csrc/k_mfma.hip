@@ -784,13 +784,14 @@ __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Ite
   const int i0 = it.sub * npos_blk;
   const int npos = min(npos_blk, N - i0);
   const int nrows = npos * q;
-  const int tid = item_tid(), lane = tid & 63, wid = tid >> 6;
+  const int tid = item_tid(), lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: copy bookkeeping in scalars
   const int half = lane >> 5, l32 = lane & 31;
   const int cnt = it.cnt;
   int32_t rs[kG3Sites];
 #pragma unroll
   for (int g = 0; g < kG3Sites; ++g)
-    rs[g] = g < cnt ? bt.active[it.first + g] - bt.site_base[it.m] : it.r;
+    rs[g] = __builtin_amdgcn_readfirstlane(g < cnt ? bt.active[it.first + g] - bt.site_base[it.m] : it.r);
 
   int arow_off[kGRB];
   uint32_t arow_kk[kGRB];
@@ -816,7 +817,29 @@ __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Ite
   // a site's chunk is 15.75 KB: 16 wave copies of 1 KB, the last one moved
   // back to end at the chunk end (it re-copies 256 bytes with the same values);
   // the LDS destination of a copy is uniform over the wave
+  // with three sites, each wave's six copies are set up once per item
+  static_assert(kG3Sites * 16 == 6 * kGWaves, "six copies per wave for a full group");
+  const char* rsrc[6];
+  uint32_t rdst[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int k = wid + kGWaves * j;
+    const int g = k >> 4, part = k & 15;
+    const int off = min(part * 1024, kRiChunkBytes - 1024);
+    const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
+    rsrc[j] = reinterpret_cast<const char*>(a.R) + (size_t)rg * nch_site * kRiChunkBytes + off;
+    rdst[j] = (uint32_t)(g * kISiteStride + off);
+  }
   auto fetch_r = [&](int c, int8_t* dst) {
+    if (cnt == kG3Sites) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j)
+        __builtin_amdgcn_global_load_lds(
+            (const void __attribute__((address_space(1)))*)(uniform_ptr(rsrc[j] + (size_t)c * kRiChunkBytes) +
+                                                            lane * 16),
+            (void __attribute__((address_space(3)))*)(reinterpret_cast<char*>(dst) + rdst[j]), 16, 0, 0);
+      return;
+    }
     const int ninst = cnt * 16;
     for (int k = wid; k < ninst; k += kGWaves) {
       const int g = k >> 4, part = k & 15;

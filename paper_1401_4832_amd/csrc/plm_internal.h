@@ -242,6 +242,16 @@ __device__ inline uint2 gload_u2(const void* p) {
 // kernels derive their per-lane offsets from it, so that those are recomputed
 // per item instead of being hoisted out of the item loop (where they would
 // occupy registers for the whole kernel).
+// A wave-uniform address held in scalar registers (so that a copy takes the
+// scalar base + 32-bit lane offset form)
+template <typename T>
+__device__ inline const T* uniform_ptr(const T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
+}
+
 __device__ inline int item_tid() {
   int t = (int)threadIdx.x;
   asm volatile("" : "+v"(t));
