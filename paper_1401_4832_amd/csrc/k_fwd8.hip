@@ -366,11 +366,14 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
       const int kg_ = g == 0 ? ks[0] : (g == 1 ? ks[1] : ks[2]);
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const double v = (double)acc[0][m][T][j] * 65536.0 + (double)acc[1][m][T][j] * 256.0 +
-                         (double)acc[2][m][T][j];
+        // v = 65536 a0 + 256 a1 + a2 exactly: u = 256 a1 + a2 fits int32, and
+        // with a0' = a0 + (u >> 16), r = u & 0xffff both FP32 operands are
+        // exact, so the fma rounds v to FP32 once
+        const int32_t u = acc[1][m][T][j] * 256 + acc[2][m][T][j];
+        const float v = fmaf((float)(acc[0][m][T][j] + (u >> 16)), 65536.f, (float)(u & 0xffff));
         if (col < 3 * kSlot)
           park[(g * 32 + 8 * (j >> 2) + 4 * half + (j & 3)) * 24 + sc] =
-              kg_ == kJexpBad ? NAN : (float)ldexp(v, -kg_);
+              kg_ == kJexpBad ? NAN : ldexpf(v, -kg_);
       }
     }
 #pragma unroll
@@ -397,20 +400,24 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
         mx = fmaxf(mx, e[st]);
         esr = st == sr ? e[st] : esr;
       }
+      // exp(x) = 2^(x log2 e) on the hardware exponential; x <= 0, so no range
+      // handling is needed (|x| log2 e is rounded to 2^-24 relative, i.e. the
+      // probability e^x moves by at most 2^-24 |x| e^x < 2.2e-8 absolute)
       float sum = 0.f;
 #pragma unroll
       for (int st = 0; st < kSlot; ++st) {
-        e[st] = expf(e[st] - mx);
+        e[st] = __builtin_amdgcn_exp2f((e[st] - mx) * 1.4426950408889634f);
         sum += e[st];
       }
       const float lse = mx + logf(sum);
+      const float inv = 1.f / sum;
       fpass[pass] += wb * (double)(lse - esr);
       const float wf = (float)wb;
       // digits of round(R 2^22), R = w (P - [s = sigma_r]), into the staging of site g
       uint8_t* sg = stg + g * (32 * 24 * 4) + (row >> 4) * (kSlot * 16) + (row & 15);
 #pragma unroll
       for (int st = 0; st < kSlot; ++st) {
-        const float P = e[st] / sum;
+        const float P = e[st] * inv;
         const float Rv = st < q ? wf * (P - (st == sr ? 1.f : 0.f)) : 0.f;
         const int v = (int)rintf(Rv * (float)(1 << kRiScaleLog2));
         const int lo = (int)(int8_t)(v & 255);
