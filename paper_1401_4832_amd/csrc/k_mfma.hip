@@ -887,17 +887,23 @@ __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Ite
 #pragma unroll
         for (int m = 0; m < kGRB; ++m)
           av[m] = onehot16_i8(*reinterpret_cast<const uint4*>(sgb + arow_off[m] + t * 32), arow_kk[m]);
+        // the six B fragments (digit, tile) of this step, each read two ahead of its use
+        static_assert(kGT == 2, "two column tiles");
+        auto ldb = [&](int f) {
+          return *reinterpret_cast<const uint4*>(rb + boff[f & 1] + ((f >> 1) * kISteps + t) * (2 * kSlot * 16));
+        };
+        uint4 bq0 = ldb(0), bq1 = ldb(1);
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
+        for (int f = 0; f < 6; ++f) {
+          uint4 bq2 = bq1;
+          if (f + 2 < 6) bq2 = ldb(f + 2);
 #pragma unroll
-          for (int T = 0; T < kGT; ++T) {
-            const uint4 bp = *reinterpret_cast<const uint4*>(rb + boff[T] + (d * kISteps + t) * (2 * kSlot * 16));
-#pragma unroll
-            for (int m = 0; m < kGRB; ++m)
-              acc[d][m][T] = __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(i32x4, av[m]),
-                                                                   __builtin_bit_cast(i32x4, bp), acc[d][m][T], 0, 0,
-                                                                   0);
-          }
+          for (int m = 0; m < kGRB; ++m)
+            acc[f >> 1][m][f & 1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                __builtin_bit_cast(i32x4, av[m]), __builtin_bit_cast(i32x4, bq0), acc[f >> 1][m][f & 1], 0, 0, 0);
+          bq0 = bq1;
+          bq1 = bq2;
+        }
       }
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
