@@ -31,7 +31,7 @@
 
 namespace plm {
 
-constexpr int kLbThreads = 1024;
+constexpr int kLbThreads = 512;  // two blocks per CU: every site of the benchmark alignment in one round
 constexpr int kLbWaves = kLbThreads / 64;
 constexpr int kGroupA = 4;  // stored pairs whose dot products ride on the acceptance pass
 constexpr int kGroupB = 4;  // stored pairs per further dot-product pass
