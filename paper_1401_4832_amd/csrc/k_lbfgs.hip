@@ -24,18 +24,21 @@
 //   R^T q1 = (D + gamma Y^T Y) t - gamma Y^T g.
 // S^T Y and Y^T Y are kept per site and gain one column per accepted pair, so
 // an accepted step streams the history twice (one pass of dot products, one
-// pass forming d) instead of the 2m passes of the two-loop recursion.  The
-// history has m + 1 slots, so that a candidate pair can be written before the
-// curvature test decides whether it is kept.
+// pass forming d) instead of the 2m passes of the two-loop recursion.  S^T g
+// and Y^T g are kept per site as well and updated by the same column
+// (s_j . g_new = s_j . g_old + s_j . y), so the dot-product pass needs two
+// products per stored pair and no gradient.  The history has m + 1 slots, so
+// that a candidate pair can be written before the curvature test decides
+// whether it is kept.
 #include "plm_internal.h"
 
 namespace plm {
 
 constexpr int kLbThreads = 512;  // two blocks per CU: every site of the benchmark alignment in one round
 constexpr int kLbWaves = kLbThreads / 64;
-constexpr int kGroupA = 4;  // stored pairs whose dot products ride on the acceptance pass
-constexpr int kGroupB = 4;  // stored pairs per further dot-product pass
-constexpr int kVecMax = 4 * kGroupB;
+constexpr int kGroupA = 8;  // stored pairs whose dot products ride on the acceptance pass
+constexpr int kGroupB = 8;  // stored pairs per further dot-product pass
+constexpr int kVecMax = 4 + 2 * kGroupA > 2 * kGroupB ? 4 + 2 * kGroupA : 2 * kGroupB;  // widest block sum
 constexpr int kSlotsMax = kMMax + 1;
 
 struct LbShared {
@@ -49,7 +52,7 @@ struct LbShared {
   double tv[kMMax];
   double p1[kSlotsMax];       // s_j . g and y_j . g of the stored pairs, newest first
   double p2[kSlotsMax];
-  double colS[kSlotsMax];     // s_j . y_cand and y_j . y_cand, newest first
+  double colS[kSlotsMax];     // s_j . y_cand and y_j . y_cand, newest first (y_cand as stored)
   double colY[kSlotsMax];
   double cand[4];             // candidate pair: s.y, y.y, s.g, y.g
   int32_t ord[kMMax];         // slots of the stored pairs, oldest first
@@ -59,6 +62,7 @@ struct LbShared {
 // wave, then the waves in order); every thread gets the sums.
 template <int NV>
 __device__ inline void block_sum_vec(double (&v)[NV], LbShared& sh) {
+  static_assert(NV <= kVecMax, "block sums sized for kVecMax values");
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k)
@@ -95,11 +99,14 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
   // every buffer seen as global memory (the descriptor comes from memory, so
   // the pointers would otherwise be generic and every access a flat one)
   const auto Th = gmem_w(a.Th), TJ = gmem_w(a.TJ), Xh = gmem_w(a.Xh), XJ = gmem_w(a.XJ);
-  const auto Ghp = gmem_w(a.Gh), GJp = gmem_w(a.GJ), Dhp = gmem_w(a.Dh), DJp = gmem_w(a.DJ);
+  const auto Ghp = gmem_w(a.Gh), GJp = gmem_w(a.GJ);
+  const auto Dhp = gmem_w(a.Dh), DJp = gmem_w(a.DJ);
   const auto Shp = gmem_w(a.Sh), SJp = gmem_w(a.SJ), Yhp = gmem_w(a.Yh), YJp = gmem_w(a.YJ);
   const auto gJd = gmem(a.gJ);
-  const auto StY = gmem_w(a.small + (size_t)r * 2 * M * M);  // [M][M] s_i . y_j by slot
-  const auto YtY = StY + (size_t)M * M;                       // [M][M] y_i . y_j by slot
+  const auto StY = gmem_w(a.small + (size_t)r * 2 * M * (M + 1));  // [M][M] s_i . y_j by slot
+  const auto YtY = StY + (size_t)M * M;                             // [M][M] y_i . y_j by slot
+  const auto SG = YtY + (size_t)M * M;                              // [M] s_k . G by slot
+  const auto YG = SG + M;                                           // [M] y_k . G by slot
 
   // ---- gather the evaluation at the trial point ----
   if (tid < q) {
@@ -134,7 +141,7 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
     if (e < q) Th[h0 + e] = f; else TJ[j0 + (e - q)] = (e >= self0 && e < self1) ? 0.f : f;
   };
   auto writeT = [&](double alpha) {
-    for (int e = tid; e < P; e += nth) storeT(e, Xv(e) + alpha * *Dp(e));
+    for (int e = tid; e < P; e += nth) storeT(e, Xv(e) + alpha * (double)*Dp(e));
   };
 
   double reg = 0.0, gg = 0.0;
@@ -169,9 +176,9 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
     // the dot products of the newest stored pairs with y and g.
     const bool pair = phase != PH_INIT;
     const int nA = min(stored, kGroupA);
-    double acc[4 + 4 * kGroupA];
+    double acc[4 + 2 * kGroupA];
 #pragma unroll
-    for (int k = 0; k < 4 + 4 * kGroupA; ++k) acc[k] = 0.0;
+    for (int k = 0; k < 4 + 2 * kGroupA; ++k) acc[k] = 0.0;
     for (int e = tid; e < P; e += nth) {
       const double g = gtv(e);
       if (pair) {
@@ -190,10 +197,8 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
           if (j < nA) {
             const int k = (head - 1 - j + 2 * M) % M;
             const double s_ = *Sp(k, e), y_ = *Yp(k, e);
-            acc[4 + 4 * j] += s_ * yv;
-            acc[5 + 4 * j] += y_ * yv;
-            acc[6 + 4 * j] += s_ * g;
-            acc[7 + 4 * j] += y_ * g;
+            acc[4 + 2 * j] += s_ * yv;
+            acc[5 + 2 * j] += y_ * yv;
           }
       }
       *Gp(e) = g;
@@ -207,30 +212,26 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
 #pragma unroll
         for (int j = 0; j < kGroupA; ++j)
           if (j < nA) {
-            sh.colS[j] = acc[4 + 4 * j];
-            sh.colY[j] = acc[5 + 4 * j];
-            sh.p1[j] = acc[6 + 4 * j];
-            sh.p2[j] = acc[7 + 4 * j];
+            sh.colS[j] = acc[4 + 2 * j];
+            sh.colY[j] = acc[5 + 2 * j];
           }
       }
-      // the older stored pairs, kGroupB at a time (g and y from the buffers
-      // this thread has just written)
+      // the older stored pairs, kGroupB at a time (y from the slot this thread
+      // has just written)
       for (int jg = kGroupA; jg < stored; jg += kGroupB) {
-        double bcc[4 * kGroupB];
+        double bcc[2 * kGroupB];
 #pragma unroll
-        for (int k = 0; k < 4 * kGroupB; ++k) bcc[k] = 0.0;
+        for (int k = 0; k < 2 * kGroupB; ++k) bcc[k] = 0.0;
         const int nB = min(kGroupB, stored - jg);
         for (int e = tid; e < P; e += nth) {
-          const double g = Gv(e), yv = *Yp(head, e);
+          const double yv = *Yp(head, e);
 #pragma unroll
           for (int j = 0; j < kGroupB; ++j)
             if (j < nB) {
               const int k = (head - 1 - (jg + j) + 2 * M) % M;
               const double s_ = *Sp(k, e), y_ = *Yp(k, e);
-              bcc[4 * j] += s_ * yv;
-              bcc[4 * j + 1] += y_ * yv;
-              bcc[4 * j + 2] += s_ * g;
-              bcc[4 * j + 3] += y_ * g;
+              bcc[2 * j] += s_ * yv;
+              bcc[2 * j + 1] += y_ * yv;
             }
         }
         block_sum_vec(bcc, sh);
@@ -238,12 +239,22 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
 #pragma unroll
           for (int j = 0; j < kGroupB; ++j)
             if (j < nB) {
-              sh.colS[jg + j] = bcc[4 * j];
-              sh.colY[jg + j] = bcc[4 * j + 1];
-              sh.p1[jg + j] = bcc[4 * j + 2];
-              sh.p2[jg + j] = bcc[4 * j + 3];
+              sh.colS[jg + j] = bcc[2 * j];
+              sh.colY[jg + j] = bcc[2 * j + 1];
             }
       }
+      __syncthreads();
+      // S^T g and Y^T g at the new point: the stored products moved by the
+      // candidate's y (G changes by y whether or not the pair is kept)
+      if (tid == 0)
+        for (int j = 0; j < stored; ++j) {
+          const int k = (head - 1 - j + 2 * M) % M;
+          const double pg1 = SG[k] + sh.colS[j], pg2 = YG[k] + sh.colY[j];
+          SG[k] = pg1;
+          YG[k] = pg2;
+          sh.p1[j] = pg1;
+          sh.p2[j] = pg2;
+        }
       __syncthreads();
       const double sy = sh.cand[0], yy = sh.cand[1];
       if (sy > 0.0 && yy > 0.0) {
@@ -265,6 +276,8 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
           }
           sh.p1[0] = sh.cand[2];
           sh.p2[0] = sh.cand[3];
+          SG[c] = sh.cand[2];
+          YG[c] = sh.cand[3];
         }
         gamma = sy / yy;
         head = (head + 1) % M;
@@ -376,7 +389,7 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (e0 + u * nth < P) {
-          *Dp(ee[u]) = d[u];
+          *Dp(ee[u]) = (float)d[u];
           storeT(ee[u], Xv(ee[u]) + d[u]);  // trial point at alpha = 1
           dg += d[u] * g[u];
         }
@@ -392,7 +405,7 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
   }
   if (dir == STEEPEST) {
     __syncthreads();
-    for (int e = tid; e < P; e += nth) *Dp(e) = -Gv(e);
+    for (int e = tid; e < P; e += nth) *Dp(e) = (float)-Gv(e);
     gtd = -gnorm * gnorm;
     alpha = fmin(1.0, 1.0 / gnorm);
     stored = 0;

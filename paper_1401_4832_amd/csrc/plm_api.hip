@@ -98,8 +98,8 @@ void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
 struct FitBufs {
   EvalBufs ev;
   float *Th, *TJ;
-  double *Gh, *GJ, *Dh, *DJ, *small;
-  float *Sh, *SJ, *Yh, *YJ;
+  double *Gh, *GJ, *small;
+  float *Dh, *DJ, *Sh, *SJ, *Yh, *YJ;
 };
 
 void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, FitBufs& f) {
@@ -109,13 +109,13 @@ void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, FitBufs& f
   f.TJ = bp.take<float>(NNqq);
   f.Gh = bp.take<double>(Nq);
   f.GJ = bp.take<double>(NNqq);
-  f.Dh = bp.take<double>(Nq);
-  f.DJ = bp.take<double>(NNqq);
+  f.Dh = bp.take<float>(Nq);
+  f.DJ = bp.take<float>(NNqq);
   f.Sh = bp.take<float>(Nq * (m + 1));
   f.SJ = bp.take<float>(NNqq * (m + 1));
   f.Yh = bp.take<float>(Nq * (m + 1));
   f.YJ = bp.take<float>(NNqq * (m + 1));
-  f.small = bp.take<double>((size_t)N * 2 * (m + 1) * (m + 1));
+  f.small = bp.take<double>((size_t)N * 2 * (m + 1) * (m + 2));
 }
 
 // device tables of a batch (BatchArgs points into them)

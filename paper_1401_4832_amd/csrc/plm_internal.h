@@ -117,13 +117,13 @@ struct LbfgsArgs {
   float* TJ;
   double* Gh;
   double* GJ;
-  double* Dh;
-  double* DJ;
+  float* Dh;   // search direction, FP32 (the step along it is rounded to FP32 anyway)
+  float* DJ;
   float* Sh;   // [m+1][N][q] history slots (one spare for the candidate pair), FP32
   float* SJ;   // [m+1][N][N q q]
   float* Yh;
   float* YJ;
-  double* small;  // [N][2][m+1][m+1] S^T Y and Y^T Y by slot
+  double* small;  // per site: [m+1][m+1] S^T Y, [m+1][m+1] Y^T Y, [m+1] S^T G, [m+1] Y^T G by slot
   const double* f_part;   // [tiles][N]
   const double* gh_part;  // [tiles][N][21]
   const double* gJ;       // [N][N][q][q] data part
