@@ -158,7 +158,9 @@ def main():
     if args.path == "auto":
         items = [(m, w, beff) for m, (_, w, beff) in zip(msas, weights())]
         t = time.perf_counter()
-        tuned = plm.autotune.choose(items, plm.FitOptions(tol=args.tol), Q)
+        # the symmetric fit's tolerance is on the norm over all parameters, below
+        # what the fixed-point paths' rounding allows there
+        tuned = plm.autotune.choose(items, plm.FitOptions(tol=args.tol), Q, fixed_point=not symmetric)
         print(f"[bench] schedule path={tuned['path']} tile_seqs={tuned['tile_seqs']} "
               f"({time.perf_counter() - t:.1f} s to choose)", file=sys.stderr, flush=True)
         path, tile = int(tuned["path"]), int(tuned["tile_seqs"])

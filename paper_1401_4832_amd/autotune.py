@@ -32,10 +32,29 @@ def _arch(dev) -> str:
     return getattr(torch.cuda.get_device_properties(dev), "gcnArchName", "gpu").split(":")[0]
 
 
-def key(items, q: int, fp32_only: bool) -> str:
+# the fixed-point evaluation paths: residuals (and on path 6 couplings) rounded
+# on a fixed grid, with exact integer sums
+FIXED_POINT_PATHS = (5, 6)
+
+
+def fixed_point_floor(item, q: int) -> float:
+    """Expected size of the per-site gradient norm (B_eff-normalised) that the
+    rounding of the residuals to 2^-23 leaves on the fixed-point paths: each of
+    the N q^2 coupling entries sums B rounding errors of standard deviation
+    2^-23 / sqrt(3)."""
+    if len(item) < 3:
+        return 0.0
+    msa, _, beff = item
+    B, N = int(msa.shape[0]), int(msa.shape[1])
+    be = float(beff.item()) if hasattr(beff, "item") else float(beff)
+    return 2.0 ** -23 * math.sqrt(N * q * q * B / 3.0) / max(be, 1e-300)
+
+
+def key(items, q: int, fp32_only: bool, fixed_point: bool = True) -> str:
     arch = _arch(items[0][0].device)
     bs = sorted(bucket(int(it[0].shape[1]), int(it[0].shape[0])) for it in items)
-    return f"{arch}|q{q}|{'fp32' if fp32_only else 'any'}|" + ",".join(f"{n}x{b}" for n, b in bs)
+    cls = ("fp32" if fp32_only else "any") + ("" if fixed_point else "-nofixed")
+    return f"{arch}|q{q}|{cls}|" + ",".join(f"{n}x{b}" for n, b in bs)
 
 
 def load(path: str | None = None) -> dict:
@@ -58,15 +77,21 @@ def store(d: dict, path: str | None = None) -> None:
 
 
 def choose(items, opts=None, q: int = 21, fp32_only: bool = True, path: str | None = None,
-           retune: bool = False) -> dict:
+           retune: bool = False, fixed_point: bool = True) -> dict:
     """The cached schedule for this batch's bucket, timing the candidates on
-    the batch itself on a miss (or when retune is set)."""
+    the batch itself on a miss (or when retune is set).  fixed_point=False
+    leaves out the fixed-point paths (for objectives whose gradient norm is
+    taken over so many parameters that their rounding noise would exceed the
+    tolerance, as in the symmetric fit)."""
     opts = opts or api.FitOptions()
-    k = key(items, q, fp32_only)
+    fixed_point = fixed_point and all(fixed_point_floor(it, q) * 2.0 < opts.tol for it in items)
+    k = key(items, q, fp32_only, fixed_point)
     d = load(path)
     if not retune and k in d:
         return d[k]
     res = api.tune(items, opts, q, fp32_only)
+    if not fixed_point:
+        res = [r for r in res if r["path"] not in FIXED_POINT_PATHS]
     entry = dict(path=res[0]["path"], tile_seqs=res[0]["tile_seqs"], eval_ms=res[0]["eval_ms"],
                  candidates=res)
     d = load(path)  # re-read: another process may have written meanwhile
@@ -75,7 +100,7 @@ def choose(items, opts=None, q: int = 21, fp32_only: bool = True, path: str | No
     return entry
 
 
-def tuned_options(items, opts, q: int = 21):
+def tuned_options(items, opts, q: int = 21, fixed_point: bool = True):
     """opts with path and tile_seqs taken from the tuner (autotune cleared)."""
-    ch = choose(items, opts, q)
+    ch = choose(items, opts, q, fixed_point=fixed_point)
     return dataclasses.replace(opts, path=int(ch["path"]), tile_seqs=int(ch["tile_seqs"]), autotune=False)

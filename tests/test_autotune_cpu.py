@@ -44,6 +44,24 @@ def test_store_load_roundtrip_and_cached_choice(monkeypatch, tmp_path):
     assert dataclasses.replace(o, path=0).path == 0
 
 
+def test_fixed_point_paths_left_out_where_their_rounding_floor_reaches_tol(monkeypatch, tmp_path):
+    path = str(tmp_path / "tune.json")
+    monkeypatch.setattr(autotune, "_arch", lambda dev: "gfx950")
+    cands = [dict(path=6, tile_seqs=0, eval_ms=1.0), dict(path=5, tile_seqs=32, eval_ms=1.5),
+             dict(path=4, tile_seqs=32, eval_ms=2.0), dict(path=0, tile_seqs=16, eval_ms=3.0)]
+    monkeypatch.setattr(api, "tune", lambda *a, **k: [dict(c) for c in cands])
+    # 2^-23 sqrt(N q^2 B / 3) / B_eff: 1.4e-7 at N = 500, B = B_eff = 50000 (allowed at tol 1e-6),
+    # 1.4e-6 at N = B = B_eff = 100 (left out)
+    big = (torch.zeros(50000, 500, dtype=torch.uint8), None, torch.tensor([50000.0], dtype=torch.float64))
+    small = (torch.zeros(100, 100, dtype=torch.uint8), None, torch.tensor([100.0], dtype=torch.float64))
+    assert autotune.fixed_point_floor(big, 21) == pytest.approx(2.0 ** -23 * (500 * 441 * 50000 / 3) ** 0.5 / 50000)
+    assert autotune.choose([big], api.FitOptions(), 21, path=path)["path"] == 6
+    assert autotune.choose([small], api.FitOptions(), 21, path=path)["path"] == 4
+    assert autotune.choose([big], api.FitOptions(), 21, path=path, fixed_point=False)["path"] == 4
+    # a looser tolerance admits them again
+    assert autotune.choose([small], api.FitOptions(tol=1e-5), 21, path=path)["path"] == 6
+
+
 def test_load_tolerates_missing_and_corrupt_files(tmp_path):
     assert autotune.load(str(tmp_path / "none.json")) == {}
     bad = tmp_path / "bad.json"
