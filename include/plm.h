@@ -157,7 +157,15 @@ typedef struct {
   int32_t timing;       /* 1: launch the iteration eagerly (no graph) with HIP events
                            between the kernels on the fit's stream, synchronise every
                            iteration, and keep the kernel times: plm_fit_last_timing */
-  int32_t reserved[4];
+  int32_t refine;       /* a second fit from the first one's point, to the same tolerance,
+                           on another evaluation path: 0 = automatic (after
+                           PLM_PATH_MFMA_I8X3, whose rounded couplings move the gradient
+                           by up to about 1e-6 in norm at N = 500, refine on
+                           PLM_PATH_GATHER_MFMA_I8X3, whose gradient is within the FP32
+                           tolerance; nothing after other paths), -1 = never, 1 + p =
+                           always, on path p.  Site statistics and timing add both fits.
+                           plm_fit and plm_fit_batch; the symmetric fit ignores it. */
+  int32_t reserved[3];
 } plm_fit_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -189,6 +197,9 @@ typedef struct {
   int64_t site_evals;   /* site objective+gradient evaluations performed */
   double quant_ms;      /* the part of forward_ms spent writing the couplings' int8 digits
                            (evaluation path 6; 0 on the others) */
+  /* the part of the above spent in the refinement fit (plm_fit_opts.refine) */
+  double refine_forward_ms, refine_backward_ms, refine_lbfgs_ms;
+  int64_t refine_iterations, refine_site_evals;
 } plm_fit_timing;
 
 int plm_fit_last_timing(const plm_ctx *ctx, plm_fit_timing *out);

@@ -42,7 +42,8 @@ class FitOpts(ctypes.Structure):
         ("tile_seqs", ctypes.c_int32),
         ("site_limit", ctypes.c_int32),
         ("timing", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("refine", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -55,6 +56,11 @@ class FitTiming(ctypes.Structure):
         ("iterations", ctypes.c_int64),
         ("site_evals", ctypes.c_int64),
         ("quant_ms", ctypes.c_double),
+        ("refine_forward_ms", ctypes.c_double),
+        ("refine_backward_ms", ctypes.c_double),
+        ("refine_lbfgs_ms", ctypes.c_double),
+        ("refine_iterations", ctypes.c_int64),
+        ("refine_site_evals", ctypes.c_int64),
     ]
 
 

@@ -135,6 +135,9 @@ class FitOptions:
     tile_seqs: int = 0
     site_limit: int = 0
     timing: bool = False
+    # a second fit from the first one's point on another path: 0 automatic
+    # (path 6 is refined on path 5), -1 never, 1 + p always on path p
+    refine: int = 0
     # pick path and tile_seqs with the autotuner (cached per size bucket)
     autotune: bool = False
 
@@ -143,7 +146,8 @@ class FitOptions:
         L.lib().plm_fit_opts_default(ctypes.byref(o))
         for k in ("lambda_h", "lambda_J", "tol"):
             setattr(o, k, float(getattr(self, k)))
-        for k in ("max_iter", "lbfgs_m", "max_linesearch", "path", "sync_every", "tile_seqs", "site_limit"):
+        for k in ("max_iter", "lbfgs_m", "max_linesearch", "path", "sync_every", "tile_seqs", "site_limit",
+                  "refine"):
             setattr(o, k, int(getattr(self, k)))
         o.use_graph = int(bool(self.use_graph))
         o.single_site = int(bool(self.single_site))
@@ -332,7 +336,9 @@ def last_fit_timing(device=None) -> dict:
     _check(L.lib().plm_fit_last_timing(ctx, ctypes.byref(t)), ctx)
     return dict(forward_ms=t.forward_ms, backward_ms=t.backward_ms, lbfgs_ms=t.lbfgs_ms,
                 total_ms=t.total_ms, iterations=int(t.iterations), site_evals=int(t.site_evals),
-                quant_ms=t.quant_ms)
+                quant_ms=t.quant_ms, refine_forward_ms=t.refine_forward_ms,
+                refine_backward_ms=t.refine_backward_ms, refine_lbfgs_ms=t.refine_lbfgs_ms,
+                refine_iterations=int(t.refine_iterations), refine_site_evals=int(t.refine_site_evals))
 
 
 def score(J: torch.Tensor, combine: str = "avg", norm: str = "frob", p: float = 2.0,

@@ -525,6 +525,7 @@ void plm_fit_opts_default(plm_fit_opts* o) {
   o->tile_seqs = 0;
   o->site_limit = 0;
   o->timing = 0;
+  o->refine = 0;
 }
 
 }  // extern "C"
@@ -661,8 +662,8 @@ int prepare_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const p
 }
 
 // The fit of a batch of alignments (plm_fit is a batch of one).
-int run_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_fit_opts* o,
-            void* ws, size_t ws_bytes) {
+int run_fit_once(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_fit_opts* o,
+                 void* ws, size_t ws_bytes) {
   Prep P;
   int rc = prepare_fit(c, d, n, q, o, ws, ws_bytes, &P);
   if (rc) return rc;
@@ -788,6 +789,57 @@ int run_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_f
     }
   }
   return any_max ? PLM_W_MAXITER : PLM_OK;
+}
+
+// the refinement path of plm_fit_opts.refine, or -1
+int32_t refine_path(const plm_fit_opts* o) {
+  if (o->refine == 0) return o->path == PLM_PATH_MFMA_I8X3 ? PLM_PATH_GATHER_MFMA_I8X3 : -1;
+  if (o->refine < 0) return -1;
+  const int32_t p = o->refine - 1;
+  return p == o->path ? -1 : p;
+}
+
+// The fit, then (plm_fit_opts.refine) a second fit from its point on another
+// path; the site statistics and the kernel times add both.
+int run_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_fit_opts* o,
+            void* ws, size_t ws_bytes) {
+  const int32_t rp = refine_path(o);
+  if (rp >= 0 && (rp < PLM_PATH_GATHER_FP32 || rp > PLM_PATH_MFMA_I8X3))
+    return set_err(c, PLM_E_INVALID, "refine: unknown path %d", rp);
+  int rc = run_fit_once(c, d, n, q, o, ws, ws_bytes);
+  if (rp < 0 || (rc != PLM_OK && rc != PLM_W_MAXITER)) return rc;
+  std::vector<std::vector<plm_site_stats>> first(n);
+  for (int32_t k = 0; k < n; ++k)
+    if (d[k].stats_out) first[k].assign(d[k].stats_out, d[k].stats_out + d[k].N);
+  const plm_fit_timing t1 = c->timing;
+  plm_fit_opts o2 = *o;
+  o2.path = rp;
+  o2.refine = -1;
+  o2.tile_seqs = 0;
+  const int rc2 = run_fit_once(c, d, n, q, &o2, ws, ws_bytes);
+  if (rc2 != PLM_OK && rc2 != PLM_W_MAXITER) return rc2;
+  for (int32_t k = 0; k < n; ++k)
+    if (d[k].stats_out)
+      for (int32_t r = 0; r < d[k].N; ++r) {
+        d[k].stats_out[r].iterations += first[k][r].iterations;
+        d[k].stats_out[r].evaluations += first[k][r].evaluations;
+      }
+  if (o->timing) {
+    plm_fit_timing& t = c->timing;
+    t.refine_forward_ms = t.forward_ms;
+    t.refine_backward_ms = t.backward_ms;
+    t.refine_lbfgs_ms = t.lbfgs_ms;
+    t.refine_iterations = t.iterations;
+    t.refine_site_evals = t.site_evals;
+    t.forward_ms += t1.forward_ms;
+    t.backward_ms += t1.backward_ms;
+    t.lbfgs_ms += t1.lbfgs_ms;
+    t.quant_ms += t1.quant_ms;
+    t.total_ms += t1.total_ms;
+    t.iterations += t1.iterations;
+    t.site_evals += t1.site_evals;
+  }
+  return rc2;
 }
 
 plm_msa_desc single_desc(const uint8_t* msa, int32_t B, int32_t N, const double* w, const double* beff,
