@@ -97,3 +97,43 @@ def test_maxiter_status(plm):
     res = plm.fit(msa, w, beff, plm.FitOptions(tol=1e-12, max_iter=3))
     assert res.status == 1
     assert all(st["status"] == "maxiter" and st["iterations"] == 3 for st in res.stats)
+
+
+def test_refinement_fit_continues_the_first_one(plm):
+    """refine = 0 (automatic) after path 6 runs a second fit on path 5 from the
+    first fit's point: the first fit is the refine = -1 fit bit for bit, the
+    statistics and the timing add both, and the result meets the tolerance on
+    the refinement path's evaluation and within 1e-4 of the oracle's minimiser."""
+    print("[case] refinement fit after path 6", flush=True)
+    s = synth.workload("potts_n120_b5000_gaps")
+    msa = torch.from_numpy(s.msa).to(DEV)
+    m, w, beff = plm.reweight(msa, theta=0.8)
+    base = plm.fit(msa, w, beff, plm.FitOptions(tol=1e-6, path=6, refine=-1, timing=True))
+    tb = plm.last_fit_timing(DEV)
+    assert tb["refine_site_evals"] == 0 and tb["refine_iterations"] == 0
+    ref = plm.fit(msa, w, beff, plm.FitOptions(tol=1e-6, path=6, timing=True))
+    tr = plm.last_fit_timing(DEV)
+    ev_b = sum(x["evaluations"] for x in base.stats)
+    ev_r = sum(x["evaluations"] for x in ref.stats)
+    assert tr["refine_site_evals"] == ev_r - ev_b > 0
+    assert tr["site_evals"] == tb["site_evals"] + tr["refine_site_evals"]
+    assert tr["iterations"] == tb["iterations"] + tr["refine_iterations"]
+    assert all(a["iterations"] <= b["iterations"] for a, b in zip(base.stats, ref.stats))
+    assert all(st["status"] == "converged" for st in ref.stats)
+    # the refined point, evaluated on the refinement path, meets the tolerance
+    _, gh, gJ = plm.objgrad(msa, w, beff, ref.h, ref.J, 0.01, 0.01, path=5)
+    beff_h = float(beff.item())
+    gn = torch.sqrt(gh.double().pow(2).sum(1) + gJ.double().pow(2).sum((1, 2, 3))) / beff_h
+    assert float(gn.max()) <= 1.05e-6, float(gn.max())
+    # and against the oracle's minimiser
+    sites = [0, 60, 119]
+    m_o, w_o, beff_o = oracle.reweight(s.msa, theta=0.8)
+    h_o, J_o, _ = oracle.fit(s.msa, w_o, beff_o, 0.01, 0.01, sites=sites, tol=1e-8)
+    J = ref.J.cpu().numpy().astype(np.float64)
+    for t, r in enumerate(sites):
+        assert np.max(np.abs(J[r] - J_o[t])) <= 1e-4
+    # an explicit refinement path, and an unknown one rejected
+    exp = plm.fit(msa, w, beff, plm.FitOptions(tol=1e-6, path=6, refine=1 + 2))
+    assert all(st["status"] == "converged" for st in exp.stats)
+    with pytest.raises(plm.PlmError):
+        plm.fit(msa, w, beff, plm.FitOptions(tol=1e-6, path=6, refine=1 + 9))
