@@ -21,8 +21,10 @@ FP64 CPU oracle on a bounded sample of the same evaluations.
 
 The evaluation schedule (path, forward tile) is the autotuner's choice for
 the workload, timed on the device before the warm-up (--path to force one).
+A fit on the int8 fixed-point path (6) ends with the library's refinement fit
+on path 5 (inside the timed step; its evaluations are counted and reported).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload W] [--path auto|0..4]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload W] [--path auto|0..6]
                        [--method asymmetric|symmetric] [--init zero|mf]
 """
 from __future__ import annotations
@@ -106,7 +108,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="potts_n500_b50000")
-    ap.add_argument("--path", default="auto", help="auto (autotuner) or an evaluation path 0..4")
+    ap.add_argument("--path", default="auto", help="auto (autotuner) or an evaluation path 0..6")
     ap.add_argument("--tile-seqs", type=int, default=0)
     ap.add_argument("--method", default="asymmetric", choices=("asymmetric", "symmetric"))
     ap.add_argument("--init", default="zero", choices=("zero", "mf"))
@@ -120,7 +122,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the per-site "
-              "problems shard by site across GPUs, which this build does not run).", file=sys.stderr)
+              "problems would shard by site across GPUs; only the one-GPU path is implemented).",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
