@@ -321,13 +321,13 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {1: "bf16x2 operands, f32 accumulate", 4: "f32 forward, f16x2 gradient operands (22-bit), "
-                  "FP64 reductions and optimiser",
+                  "FP64 reductions, FP32 L-BFGS history",
                   5: "f32 forward, int8x3 fixed-point gradient (2^-23), exact int32 accumulation, "
-                  "FP64 reductions and optimiser",
+                  "FP64 reductions, FP32 L-BFGS history",
                   6: "int8x3 fixed-point energies (2^-22 max|J_r|) and gradient (2^-23), exact int32 "
-                  "accumulation, FP32 softmax, FP64 reductions and optimiser; refined to the tolerance "
+                  "accumulation, FP32 softmax, FP64 reductions, FP32 L-BFGS history; refined to the tolerance "
                   "on f32 energies with the int8x3 gradient"}.get(
-                      path, "f32 (FP64 reductions and optimiser)"),
+                      path, "f32 (FP64 reductions, FP32 L-BFGS history)"),
         "data": "synthetic planted-Potts alignment (seeded Gibbs sampling)",
         "config": cfg,
         "time_to_fit_s": ms_per_step / 1e3,

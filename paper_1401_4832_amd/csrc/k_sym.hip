@@ -194,10 +194,12 @@ __global__ __launch_bounds__(kSymThreads) void sym_accept_kernel(SymArgs a) {
     if (pair) {
       const double t = is_h ? (double)a.Th[j] : (double)a.TJ[j];
       const double x = is_h ? (double)a.Xh[j] : (double)a.XJ[j];
-      const double sv = t - x, yv = g - *Gp;
+      // the pair is stored in FP32 and its products taken from the stored values
+      const float svf = (float)(t - x), yvf = (float)(g - *Gp);
       const size_t hs = (size_t)a.N * a.q, js = (size_t)a.N * a.N * a.q * a.q;
-      (is_h ? a.Sh + (size_t)head * hs : a.SJ + (size_t)head * js)[j] = sv;
-      (is_h ? a.Yh + (size_t)head * hs : a.YJ + (size_t)head * js)[j] = yv;
+      (is_h ? a.Sh + (size_t)head * hs : a.SJ + (size_t)head * js)[j] = svf;
+      (is_h ? a.Yh + (size_t)head * hs : a.YJ + (size_t)head * js)[j] = yvf;
+      const double sv = svf, yv = yvf;
       v[0] += sv * yv;
       v[1] += yv * yv;
       v[2] += sv * g;

@@ -166,7 +166,8 @@ BatchArgs batch_args(const Tables& t, int32_t n_msas, int32_t total, int32_t gro
 struct SymBufs {
   EvalBufs ev;
   float *Th, *TJ;
-  double *Gh, *GJ, *Dh, *DJ, *Sh, *SJ, *Yh, *YJ, *part, *small;
+  double *Gh, *GJ, *Dh, *DJ, *part, *small;
+  float *Sh, *SJ, *Yh, *YJ;
   SymCoef* coef;
   SymState* st;
   int2* pairs;
@@ -182,10 +183,10 @@ void layout_sym(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, int32_t nb
   f.GJ = bp.take<double>(NNqq);
   f.Dh = bp.take<double>(Nq);
   f.DJ = bp.take<double>(NNqq);
-  f.Sh = bp.take<double>(Nq * (m + 1));
-  f.SJ = bp.take<double>(NNqq * (m + 1));
-  f.Yh = bp.take<double>(Nq * (m + 1));
-  f.YJ = bp.take<double>(NNqq * (m + 1));
+  f.Sh = bp.take<float>(Nq * (m + 1));
+  f.SJ = bp.take<float>(NNqq * (m + 1));
+  f.Yh = bp.take<float>(Nq * (m + 1));
+  f.YJ = bp.take<float>(NNqq * (m + 1));
   f.part = bp.take<double>((size_t)(1 + sym_groups(m)) * nblk * sym_part_stride());
   f.small = bp.take<double>((size_t)2 * (m + 1) * (m + 1));
   f.coef = bp.take<SymCoef>(1);

@@ -303,7 +303,8 @@ struct SymArgs {
   double tol, lambda_h, lambda_J, c1, noise;
   const double* beff;
   float *Xh, *XJ, *Th, *TJ;  // iterate (caller's h, J) and trial point, couplings mirrored
-  double *Gh, *GJ, *Dh, *DJ, *Sh, *SJ, *Yh, *YJ;  // full-layout vectors, blocks r < i used
+  double *Gh, *GJ, *Dh, *DJ;  // full-layout vectors, blocks r < i used
+  float *Sh, *SJ, *Yh, *YJ;    // curvature pairs, FP32 (used as stored)
   const double *f_part, *gh_part, *gJ;            // evaluation of the trial point
   double* part;   // block partial sums
   double* small;  // [2][m+1][m+1] S^T Y, Y^T Y by slot
