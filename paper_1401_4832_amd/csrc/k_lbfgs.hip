@@ -30,14 +30,16 @@
 // products per stored pair and no gradient.  The history has m + 1 slots, so
 // that a candidate pair can be written before the curvature test decides
 // whether it is kept.
+#include <type_traits>
+
 #include "plm_internal.h"
 
 namespace plm {
 
 constexpr int kLbThreads = 512;  // two blocks per CU: every site of the benchmark alignment in one round
 constexpr int kLbWaves = kLbThreads / 64;
-constexpr int kGroupA = 8;  // stored pairs whose dot products ride on the acceptance pass
-constexpr int kGroupB = 8;  // stored pairs per further dot-product pass
+constexpr int kGroupA = 4;  // stored pairs whose dot products ride on the acceptance pass
+constexpr int kGroupB = 6;  // stored pairs per further dot-product pass (m = 10: one such pass)
 constexpr int kVecMax = 4 + 2 * kGroupA > 2 * kGroupB ? 4 + 2 * kGroupA : 2 * kGroupB;  // widest block sum
 constexpr int kSlotsMax = kMMax + 1;
 
@@ -82,6 +84,17 @@ __device__ inline void block_sum_vec(double (&v)[NV], LbShared& sh) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = sh.vec[k];
   __syncthreads();
+}
+
+// f(std::integral_constant<int, n>) for a runtime n in [K, Max] (n > Max runs Max)
+template <int K, int Max, class F>
+__device__ inline void with_count(int n, F&& f) {
+  if constexpr (K >= Max) {
+    f(std::integral_constant<int, Max>{});
+  } else {
+    if (n == K) f(std::integral_constant<int, K>{});
+    else with_count<K + 1, Max>(n, f);
+  }
 }
 
 __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, double* red) {
@@ -144,10 +157,31 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
     for (int e = tid; e < P; e += nth) storeT(e, Xv(e) + alpha * (double)*Dp(e));
   };
 
+  // The element loops below visit, per thread, its field element (e = tid < q;
+  // nth >= q, so there is at most one and it comes first) and then the coupling
+  // elements e = q + o of the site's row in increasing order, o = e - q, the
+  // order of a plain strided loop over e.  The coupling part addresses each
+  // vector from a uniform (scalar) base.
+  const int o_first = (tid < q ? tid + nth : tid) - q;  // first coupling offset of this thread
+  const int nJ = (int)Nqq;
+  const int sb0 = r * q * q, sb1 = sb0 + q * q;  // self block in o (no penalty, kept at zero)
+  const auto TJr = TJ + j0, XJr = XJ + j0;
+  const auto GJr = GJp + j0;
+  const auto gJr = gJd + j0;
+  const size_t slot = (size_t)N * Nqq;  // coupling entries per history slot
+  auto lamJ = [&](int o) -> double { return (o >= sb0 && o < sb1) ? 0.0 : lam_J; };
+
   double reg = 0.0, gg = 0.0;
-  for (int e = tid; e < P; e += nth) {
-    const double t = Tv(e), g = gtv(e);
-    reg += lam(e) * t * t;
+  if (tid < q) {
+    const double t = Tv(tid), g = gtv(tid);
+    reg += lam(tid) * t * t;
+    gg += g * g;
+  }
+#pragma unroll 4
+  for (int o = o_first; o < nJ; o += nth) {
+    const double t = TJr[o], lo = lamJ(o);
+    const double g = gJr[o] * ib + 2.0 * lo * t;
+    reg += lo * t * t;
     gg += g * g;
   }
   reg = block_sum_f64(reg, red);
@@ -158,7 +192,8 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
   const bool finite = isfinite(ft) && isfinite(gnt);
 
   int evals = S->evals + 1;
-  int iter = S->iter, ls = S->ls_count, head = S->head, stored = S->stored, status = S->status;
+  int iter = S->iter, ls = S->ls_count, status = S->status;
+  int head = __builtin_amdgcn_readfirstlane(S->head), stored = __builtin_amdgcn_readfirstlane(S->stored);
   double f = S->f, gnorm = S->gnorm, alpha = S->alpha, gtd = S->gtd, gamma = S->gamma;
   int newphase = phase;
   // what to do with the search direction once the decision is taken
@@ -179,30 +214,90 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
     double acc[4 + 2 * kGroupA];
 #pragma unroll
     for (int k = 0; k < 4 + 2 * kGroupA; ++k) acc[k] = 0.0;
-    for (int e = tid; e < P; e += nth) {
-      const double g = gtv(e);
-      if (pair) {
-        // the pair is stored in FP32 and used as stored, so that its dot
-        // products describe exactly the vectors the direction is formed from
-        const float svf = (float)(Tv(e) - Xv(e)), yvf = (float)(g - Gv(e));
-        *Sp(head, e) = svf;
-        *Yp(head, e) = yvf;
-        const double sv = svf, yv = yvf;
-        acc[0] += sv * yv;
-        acc[1] += yv * yv;
-        acc[2] += sv * g;
-        acc[3] += yv * g;
-#pragma unroll
-        for (int j = 0; j < kGroupA; ++j)
-          if (j < nA) {
-            const int k = (head - 1 - j + 2 * M) % M;
-            const double s_ = *Sp(k, e), y_ = *Yp(k, e);
-            acc[4 + 2 * j] += s_ * yv;
-            acc[5 + 2 * j] += y_ * yv;
-          }
+    if (!pair) {
+      // the start point: gradient and iterate only
+      if (tid < q) {
+        *Gp(tid) = gtv(tid);
+        Xh[h0 + tid] = Th[h0 + tid];
       }
-      *Gp(e) = g;
-      if (e < q) Xh[h0 + e] = Th[h0 + e]; else XJ[j0 + (e - q)] = TJ[j0 + (e - q)];
+      for (int o = o_first; o < nJ; o += nth) {
+        const float tf = TJr[o];
+        GJr[o] = gJr[o] * ib + 2.0 * lamJ(o) * (double)tf;
+        XJr[o] = tf;
+      }
+    } else {
+      // NA, the number of stored pairs in this pass, is a compile-time constant,
+      // so that all of an element's history loads are issued together
+      auto accept_pass = [&](auto na_c) {
+        constexpr int NA = decltype(na_c)::value;
+        int kk[NA > 0 ? NA : 1];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) kk[j] = (head - 1 - j + 2 * M) % M;
+        if (tid < q) {
+          const int e = tid;
+          const double g = gtv(e);
+          // the pair is stored in FP32 and used as stored, so that its dot
+          // products describe exactly the vectors the direction is formed from
+          const float svf = (float)(Tv(e) - Xv(e)), yvf = (float)(g - Gv(e));
+          *Sp(head, e) = svf;
+          *Yp(head, e) = yvf;
+          const double sv = svf, yv = yvf;
+          acc[0] += sv * yv;
+          acc[1] += yv * yv;
+          acc[2] += sv * g;
+          acc[3] += yv * g;
+#pragma unroll
+          for (int j = 0; j < NA; ++j) {
+            acc[4 + 2 * j] += (double)*Sp(kk[j], e) * yv;
+            acc[5 + 2 * j] += (double)*Yp(kk[j], e) * yv;
+          }
+          *Gp(e) = g;
+          Xh[h0 + e] = Th[h0 + e];
+        }
+        const auto sH = SJp + (size_t)head * slot + j0, yH = YJp + (size_t)head * slot + j0;
+        std::remove_const_t<decltype(SJp)> sJ[NA > 0 ? NA : 1];
+        std::remove_const_t<decltype(YJp)> yJ[NA > 0 ? NA : 1];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+          sJ[j] = SJp + (size_t)kk[j] * slot + j0;
+          yJ[j] = YJp + (size_t)kk[j] * slot + j0;
+        }
+        // one coupling element from its loaded values
+        auto elem = [&](int o, float tf, float xf, double gold, double gd, const float (&sl)[NA > 0 ? NA : 1],
+                        const float (&yl)[NA > 0 ? NA : 1]) {
+          const double t = tf;
+          const double g = gd * ib + 2.0 * lamJ(o) * t;
+          const float svf = (float)(t - (double)xf), yvf = (float)(g - gold);
+          sH[o] = svf;
+          yH[o] = yvf;
+          const double sv = svf, yv = yvf;
+          acc[0] += sv * yv;
+          acc[1] += yv * yv;
+          acc[2] += sv * g;
+          acc[3] += yv * g;
+#pragma unroll
+          for (int j = 0; j < NA; ++j) {
+            acc[4 + 2 * j] += (double)sl[j] * yv;
+            acc[5 + 2 * j] += (double)yl[j] * yv;
+          }
+          GJr[o] = g;
+          XJr[o] = tf;
+        };
+        for (int o = o_first; o < nJ; o += nth) {
+          const float tf = TJr[o], xf = XJr[o];
+          const double go = GJr[o], gd = gJr[o];
+          float s0[NA > 0 ? NA : 1], y0[NA > 0 ? NA : 1];
+#pragma unroll
+          for (int j = 0; j < NA; ++j) {
+            s0[j] = sJ[j][o];
+            y0[j] = yJ[j][o];
+          }
+          // all of the element's loads are issued before the first use
+          __builtin_amdgcn_sched_barrier(0);
+          elem(o, tf, xf, go, gd, s0, y0);
+        }
+      };
+      with_count<0, kGroupA>(nA, accept_pass);
     }
     if (pair) {
       block_sum_vec(acc, sh);
@@ -223,17 +318,46 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
 #pragma unroll
         for (int k = 0; k < 2 * kGroupB; ++k) bcc[k] = 0.0;
         const int nB = min(kGroupB, stored - jg);
-        for (int e = tid; e < P; e += nth) {
-          const double yv = *Yp(head, e);
+        auto pair_pass = [&](auto nb_c) {
+          constexpr int NB = decltype(nb_c)::value;
+          int kk[NB];
 #pragma unroll
-          for (int j = 0; j < kGroupB; ++j)
-            if (j < nB) {
-              const int k = (head - 1 - (jg + j) + 2 * M) % M;
-              const double s_ = *Sp(k, e), y_ = *Yp(k, e);
-              bcc[2 * j] += s_ * yv;
-              bcc[2 * j + 1] += y_ * yv;
+          for (int j = 0; j < NB; ++j) kk[j] = (head - 1 - (jg + j) + 2 * M) % M;
+          if (tid < q) {
+            const double yv = *Yp(head, tid);
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              bcc[2 * j] += (double)*Sp(kk[j], tid) * yv;
+              bcc[2 * j + 1] += (double)*Yp(kk[j], tid) * yv;
             }
-        }
+          }
+          const auto yH = YJp + (size_t)head * slot + j0;
+          std::remove_const_t<decltype(SJp)> sJ[NB];
+          std::remove_const_t<decltype(YJp)> yJ[NB];
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            sJ[j] = SJp + (size_t)kk[j] * slot + j0;
+            yJ[j] = YJp + (size_t)kk[j] * slot + j0;
+          }
+          for (int o = o_first; o < nJ; o += nth) {
+            const float yf = yH[o];
+            float sf[NB], tf[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              sf[j] = sJ[j][o];
+              tf[j] = yJ[j][o];
+            }
+            // all of the element's loads are issued before the first use
+            __builtin_amdgcn_sched_barrier(0);
+            const double yv = yf;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              bcc[2 * j] += (double)sf[j] * yv;
+              bcc[2 * j + 1] += (double)tf[j] * yv;
+            }
+          }
+        };
+        with_count<1, kGroupB>(nB, pair_pass);
         block_sum_vec(bcc, sh);
         if (tid == 0)
 #pragma unroll
@@ -433,15 +557,17 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
 }
 
 // One block per active site of the batch.
-__global__ __launch_bounds__(kLbThreads) void lbfgs_kernel(BatchArgs b) {
+// at most 128 VGPRs: two 512-thread blocks per CU
+__global__ __launch_bounds__(kLbThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void lbfgs_kernel(BatchArgs b) {
   __shared__ LbShared sh;
   __shared__ double red[16];
   const int idx = blockIdx.x;
   if (idx >= *b.n_active) return;
-  const int g = b.active[idx];
-  const int m = b.msa_of[g];
+  // site, alignment and their descriptor are block-uniform: scalar registers
+  const int g = __builtin_amdgcn_readfirstlane(b.active[idx]);
+  const int m = __builtin_amdgcn_readfirstlane(b.msa_of[g]);
   const LbfgsArgs a = load_uniform(b.lb + m);
-  lbfgs_site(a, g - b.site_base[m], sh, red);
+  lbfgs_site(a, __builtin_amdgcn_readfirstlane(g - b.site_base[m]), sh, red);
 }
 
 hipError_t launch_lbfgs(const BatchArgs& b, int32_t nblocks, hipStream_t st) {
