@@ -30,8 +30,6 @@
 // products per stored pair and no gradient.  The history has m + 1 slots, so
 // that a candidate pair can be written before the curvature test decides
 // whether it is kept.
-#include <type_traits>
-
 #include "plm_internal.h"
 
 namespace plm {
@@ -84,17 +82,6 @@ __device__ inline void block_sum_vec(double (&v)[NV], LbShared& sh) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = sh.vec[k];
   __syncthreads();
-}
-
-// f(std::integral_constant<int, n>) for a runtime n in [K, Max] (n > Max runs Max)
-template <int K, int Max, class F>
-__device__ inline void with_count(int n, F&& f) {
-  if constexpr (K >= Max) {
-    f(std::integral_constant<int, Max>{});
-  } else {
-    if (n == K) f(std::integral_constant<int, K>{});
-    else with_count<K + 1, Max>(n, f);
-  }
 }
 
 __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, double* red) {

@@ -183,47 +183,64 @@ __global__ __launch_bounds__(kSymThreads) void sym_accept_kernel(SymArgs a) {
   const SymState* S = a.st;
   if (!S->accept) return;
   const bool pair = S->pair;
-  const int M = a.m + 1, head = S->head, nA = min(S->stored, kSymGroup);
+  const int M = a.m + 1, head = __builtin_amdgcn_readfirstlane(S->head);
+  const int nA = __builtin_amdgcn_readfirstlane(min(S->stored, kSymGroup));
   const double ib = 1.0 / *a.beff;
+  const size_t hs = (size_t)a.N * a.q, js = (size_t)a.N * a.N * a.q * a.q;
   double v[kSymPart];
 #pragma unroll
   for (int k = 0; k < kSymPart; ++k) v[k] = 0.0;
-  for_each_param(a, [&](bool is_h, size_t j, size_t jm) {
-    const double g = sym_grad(a, is_h, j, jm, ib);
-    double* Gp = is_h ? a.Gh + j : a.GJ + j;
-    if (pair) {
+  // NA stored pairs, a compile-time count: all of a parameter's history loads
+  // are issued together
+  auto pass = [&](auto na_c) {
+    constexpr int NA = decltype(na_c)::value;
+    int kk[NA > 0 ? NA : 1];
+#pragma unroll
+    for (int p = 0; p < NA; ++p) kk[p] = (head - 1 - p + 2 * M) % M;
+    for_each_param(a, [&](bool is_h, size_t j, size_t jm) {
+      float sl[NA > 0 ? NA : 1], yl[NA > 0 ? NA : 1];
+      if (pair) {
+#pragma unroll
+        for (int p = 0; p < NA; ++p) {
+          sl[p] = (is_h ? a.Sh + (size_t)kk[p] * hs : a.SJ + (size_t)kk[p] * js)[j];
+          yl[p] = (is_h ? a.Yh + (size_t)kk[p] * hs : a.YJ + (size_t)kk[p] * js)[j];
+        }
+      }
+      double* Gp = is_h ? a.Gh + j : a.GJ + j;
       const double t = is_h ? (double)a.Th[j] : (double)a.TJ[j];
       const double x = is_h ? (double)a.Xh[j] : (double)a.XJ[j];
-      // the pair is stored in FP32 and its products taken from the stored values
-      const float svf = (float)(t - x), yvf = (float)(g - *Gp);
-      const size_t hs = (size_t)a.N * a.q, js = (size_t)a.N * a.N * a.q * a.q;
-      (is_h ? a.Sh + (size_t)head * hs : a.SJ + (size_t)head * js)[j] = svf;
-      (is_h ? a.Yh + (size_t)head * hs : a.YJ + (size_t)head * js)[j] = yvf;
-      const double sv = svf, yv = yvf;
-      v[0] += sv * yv;
-      v[1] += yv * yv;
-      v[2] += sv * g;
-      v[3] += yv * g;
+      const double gold = *Gp;
+      const double g = sym_grad(a, is_h, j, jm, ib);
+      if (pair) {
+        // the pair is stored in FP32 and its products taken from the stored values
+        const float svf = (float)(t - x), yvf = (float)(g - gold);
+        (is_h ? a.Sh + (size_t)head * hs : a.SJ + (size_t)head * js)[j] = svf;
+        (is_h ? a.Yh + (size_t)head * hs : a.YJ + (size_t)head * js)[j] = yvf;
+        const double sv = svf, yv = yvf;
+        v[0] += sv * yv;
+        v[1] += yv * yv;
+        v[2] += sv * g;
+        v[3] += yv * g;
 #pragma unroll
-      for (int p = 0; p < kSymGroup; ++p)
-        if (p < nA) {
-          const int k = (head - 1 - p + 2 * M) % M;
-          const double s_ = (is_h ? a.Sh + (size_t)k * hs : a.SJ + (size_t)k * js)[j];
-          const double y_ = (is_h ? a.Yh + (size_t)k * hs : a.YJ + (size_t)k * js)[j];
+        for (int p = 0; p < NA; ++p) {
+          const double s_ = sl[p], y_ = yl[p];
           v[4 + 4 * p] += s_ * yv;
           v[5 + 4 * p] += y_ * yv;
           v[6 + 4 * p] += s_ * g;
           v[7 + 4 * p] += y_ * g;
         }
-    }
-    *Gp = g;
-    if (is_h) {
-      a.Xh[j] = a.Th[j];
-    } else {
-      a.XJ[j] = a.TJ[j];
-      a.XJ[jm] = a.TJ[jm];
-    }
-  });
+      }
+      *Gp = g;
+      if (is_h) {
+        a.Xh[j] = a.Th[j];
+      } else {
+        a.XJ[j] = a.TJ[j];
+        a.XJ[jm] = a.TJ[jm];
+      }
+    });
+  };
+  if (pair) with_count<0, kSymGroup>(nA, pass);
+  else pass(std::integral_constant<int, 0>{});
   block_partials(v, red, a.part + (size_t)blockIdx.x * kSymPart);
 }
 
@@ -233,25 +250,35 @@ __global__ __launch_bounds__(kSymThreads) void sym_group_kernel(SymArgs a, int32
   const SymState* S = a.st;
   const int j0 = kSymGroup * (group + 1);  // the first kSymGroup pairs ride on the accept pass
   if (!S->accept || !S->pair || j0 >= S->stored) return;
-  const int M = a.m + 1, head = S->head, nB = min(kSymGroup, S->stored - j0);
+  const int M = a.m + 1, head = __builtin_amdgcn_readfirstlane(S->head);
+  const int nB = __builtin_amdgcn_readfirstlane(min(kSymGroup, S->stored - j0));
   const size_t hs = (size_t)a.N * a.q, js = (size_t)a.N * a.N * a.q * a.q;
   double v[4 * kSymGroup];
 #pragma unroll
   for (int k = 0; k < 4 * kSymGroup; ++k) v[k] = 0.0;
-  for_each_param(a, [&](bool is_h, size_t j, size_t) {
-    const double g = (is_h ? a.Gh : a.GJ)[j];
-    const double yv = (is_h ? a.Yh + (size_t)head * hs : a.YJ + (size_t)head * js)[j];
+  with_count<1, kSymGroup>(nB, [&](auto nb_c) {
+    constexpr int NB = decltype(nb_c)::value;
+    int kk[NB];
 #pragma unroll
-    for (int p = 0; p < kSymGroup; ++p)
-      if (p < nB) {
-        const int k = (head - 1 - (j0 + p) + 2 * M) % M;
-        const double s_ = (is_h ? a.Sh + (size_t)k * hs : a.SJ + (size_t)k * js)[j];
-        const double y_ = (is_h ? a.Yh + (size_t)k * hs : a.YJ + (size_t)k * js)[j];
+    for (int p = 0; p < NB; ++p) kk[p] = (head - 1 - (j0 + p) + 2 * M) % M;
+    for_each_param(a, [&](bool is_h, size_t j, size_t) {
+      const double g = (is_h ? a.Gh : a.GJ)[j];
+      const double yv = (is_h ? a.Yh + (size_t)head * hs : a.YJ + (size_t)head * js)[j];
+      float sl[NB], yl[NB];
+#pragma unroll
+      for (int p = 0; p < NB; ++p) {
+        sl[p] = (is_h ? a.Sh + (size_t)kk[p] * hs : a.SJ + (size_t)kk[p] * js)[j];
+        yl[p] = (is_h ? a.Yh + (size_t)kk[p] * hs : a.YJ + (size_t)kk[p] * js)[j];
+      }
+#pragma unroll
+      for (int p = 0; p < NB; ++p) {
+        const double s_ = sl[p], y_ = yl[p];
         v[4 * p] += s_ * yv;
         v[4 * p + 1] += y_ * yv;
         v[4 * p + 2] += s_ * g;
         v[4 * p + 3] += y_ * g;
       }
+    });
   });
   block_partials(v, red, a.part + ((size_t)(1 + group) * a.nblk + blockIdx.x) * kSymPart);
 }
@@ -369,7 +396,20 @@ __global__ __launch_bounds__(kSymThreads) void sym_direct_kernel(SymArgs a) {
   for_each_param(a, [&](bool is_h, size_t j, size_t jm) {
     const double g = (is_h ? a.Gh : a.GJ)[j];
     double d = -gamma * g;
-    for (int i = 0; i < n; ++i) {
+    // four pairs per step, their loads issued together; the sum runs in pair order
+    int i = 0;
+    for (; i + 4 <= n; i += 4) {
+      float sl[4], yl[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = ord[i + u];
+        sl[u] = (is_h ? a.Sh + (size_t)k * hs : a.SJ + (size_t)k * js)[j];
+        yl[u] = (is_h ? a.Yh + (size_t)k * hs : a.YJ + (size_t)k * js)[j];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) d += cs[i + u] * (double)sl[u] + cy[i + u] * (double)yl[u];
+    }
+    for (; i < n; ++i) {
       const int k = ord[i];
       d += cs[i] * (is_h ? a.Sh + (size_t)k * hs : a.SJ + (size_t)k * js)[j] +
            cy[i] * (is_h ? a.Yh + (size_t)k * hs : a.YJ + (size_t)k * js)[j];

@@ -4,6 +4,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "plm.h"
 
 namespace plm {
@@ -225,6 +227,18 @@ __device__ inline const __attribute__((address_space(1))) T* gmem(const T* p) {
 template <class T>
 __device__ inline __attribute__((address_space(1))) T* gmem_w(T* p) {
   return (__attribute__((address_space(1))) T*)p;
+}
+
+// f(std::integral_constant<int, n>) for a runtime n in [K, Max] (n > Max runs
+// Max): loops over a uniform count become straight-line code
+template <int K, int Max, class F>
+__device__ inline void with_count(int n, F&& f) {
+  if constexpr (K >= Max) {
+    f(std::integral_constant<int, Max>{});
+  } else {
+    if (n == K) f(std::integral_constant<int, K>{});
+    else with_count<K + 1, Max>(n, f);
+  }
 }
 
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
