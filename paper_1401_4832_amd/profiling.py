@@ -106,7 +106,7 @@ def _per_kernel(rows, counter):
     return out
 
 
-def traffic(fetch_csv: str, write_csv: str, workload: str, out_prefix: str):
+def traffic(fetch_csv: str, write_csv: str, workload: str, out_prefix: str, path: str = "6"):
     fr, wr = _rows(fetch_csv), _rows(write_csv)
     fk, wk = _per_kernel(fr, "FETCH_SIZE"), _per_kernel(wr, "WRITE_SIZE")
 
@@ -128,11 +128,21 @@ def traffic(fetch_csv: str, write_csv: str, workload: str, out_prefix: str):
         d = {"kernel": kname, "workload": workload, "source_hash": h,
              "fetch_kib_per_launch": sum(f) / len(f), "write_kib_per_launch": sum(w) / len(w),
              "copy_fetch_kib": cf, "copy_write_kib": cw,
-             "bytes_per_launch": sum(f) / len(f) * sf + sum(w) / len(w) * sw}
-        path = f"{out_prefix}_{kname}_{workload}.txt"
-        with open(path, "w") as fh:
+             "bytes_per_launch": sum(f) / len(f) * sf + sum(w) / len(w) * sw,
+             "commands": [
+                 f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {os.path.dirname(fetch_csv)} -o run -- "
+                 f"python3 -u -m paper_1401_4832_amd.profiling drive {workload} {path}",
+                 f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {os.path.dirname(write_csv)} -o run -- "
+                 f"python3 -u -m paper_1401_4832_amd.profiling drive {workload} {path}",
+                 f"python -m paper_1401_4832_amd.profiling traffic {fetch_csv} {write_csv} {workload} {out_prefix}"
+                 + ("" if path == "6" else f" {path}")],
+             "note": f"one all-sites evaluation on evaluation path {path}; FETCH_SIZE scaled by {sf / 1024:.1f} "
+                     f"and WRITE_SIZE by {sw / 1024:.1f} (the {COPY_BYTES >> 30} GiB copy calibration of the "
+                     "same run)"}
+        out = f"{out_prefix}_{kname}_{workload}.txt"
+        with open(out, "w") as fh:
             json.dump(d, fh, indent=1)
-        print(path, json.dumps(d))
+        print(out, json.dumps(d))
 
 
 if __name__ == "__main__":
@@ -142,6 +152,6 @@ if __name__ == "__main__":
     elif cmd == "stats":
         stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
     elif cmd == "traffic":
-        traffic(*sys.argv[2:6])
+        traffic(*sys.argv[2:7])
     else:
         raise SystemExit(__doc__)
