@@ -149,6 +149,7 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
   // elements e = q + o of the site's row in increasing order, o = e - q, the
   // order of a plain strided loop over e.  The coupling part addresses each
   // vector from a uniform (scalar) base.
+  static_assert(kQMax <= kLbThreads, "at most one field element per thread");
   const int o_first = (tid < q ? tid + nth : tid) - q;  // first coupling offset of this thread
   const int nJ = (int)Nqq;
   const int sb0 = r * q * q, sb1 = sb0 + q * q;  // self block in o (no penalty, kept at zero)
