@@ -7,13 +7,14 @@
 // part from the backward kernel), adds the l2 terms in FP64, takes the line
 // search decision (sufficient decrease with backtracking by safeguarded
 // quadratic interpolation), and on acceptance stores the curvature pair and
-// writes the next trial point.  All dot products, the history and the small
-// matrices are FP64, the stored curvature pairs FP32 (the gradients they are
-// differences of carry the rounding noise of the FP32 evaluation, far above
-// the 2^-24 relative rounding of the stored values; halving the history's
-// bytes halves most of this streaming kernel's traffic); the iterate is kept
-// at FP32-representable values so that the evaluated point and the stored
-// point are the same.
+// writes the next trial point.  All dot products and the small matrices are
+// FP64; the stored curvature pairs, the gradient kept at the iterate and the
+// direction are FP32 (the gradients carry the rounding noise of the FP32
+// evaluation, far above the 2^-24 relative rounding of the stored values;
+// halving the stored vectors' bytes halves most of this streaming kernel's
+// traffic); the gradient at the trial point and the objective are formed in
+// FP64; the iterate is kept at FP32-representable values so that the
+// evaluated point and the stored point are the same.
 //
 // The search direction d = -H g uses the compact representation of the
 // limited-memory inverse Hessian (Byrd, Nocedal and Schnabel, 1994), which
@@ -205,12 +206,12 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
     if (!pair) {
       // the start point: gradient and iterate only
       if (tid < q) {
-        *Gp(tid) = gtv(tid);
+        *Gp(tid) = (float)gtv(tid);
         Xh[h0 + tid] = Th[h0 + tid];
       }
       for (int o = o_first; o < nJ; o += nth) {
         const float tf = TJr[o];
-        GJr[o] = gJr[o] * ib + 2.0 * lamJ(o) * (double)tf;
+        GJr[o] = (float)(gJr[o] * ib + 2.0 * lamJ(o) * (double)tf);
         XJr[o] = tf;
       }
     } else {
@@ -239,7 +240,7 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
             acc[4 + 2 * j] += (double)*Sp(kk[j], e) * yv;
             acc[5 + 2 * j] += (double)*Yp(kk[j], e) * yv;
           }
-          *Gp(e) = g;
+          *Gp(e) = (float)g;
           Xh[h0 + e] = Th[h0 + e];
         }
         const auto sH = SJp + (size_t)head * slot + j0, yH = YJp + (size_t)head * slot + j0;
@@ -268,7 +269,7 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
             acc[4 + 2 * j] += (double)sl[j] * yv;
             acc[5 + 2 * j] += (double)yl[j] * yv;
           }
-          GJr[o] = g;
+          GJr[o] = (float)g;
           XJr[o] = tf;
         };
         for (int o = o_first; o < nJ; o += nth) {

@@ -98,8 +98,8 @@ void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
 struct FitBufs {
   EvalBufs ev;
   float *Th, *TJ;
-  double *Gh, *GJ, *small;
-  float *Dh, *DJ, *Sh, *SJ, *Yh, *YJ;
+  double* small;
+  float *Gh, *GJ, *Dh, *DJ, *Sh, *SJ, *Yh, *YJ;
 };
 
 void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, FitBufs& f) {
@@ -107,8 +107,8 @@ void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, FitBufs& f
   const size_t Nq = (size_t)N * q, NNqq = (size_t)N * N * q * q;
   f.Th = bp.take<float>(Nq);
   f.TJ = bp.take<float>(NNqq);
-  f.Gh = bp.take<double>(Nq);
-  f.GJ = bp.take<double>(NNqq);
+  f.Gh = bp.take<float>(Nq);
+  f.GJ = bp.take<float>(NNqq);
   f.Dh = bp.take<float>(Nq);
   f.DJ = bp.take<float>(NNqq);
   f.Sh = bp.take<float>(Nq * (m + 1));

@@ -117,8 +117,8 @@ struct LbfgsArgs {
   float* XJ;
   float* Th;
   float* TJ;
-  double* Gh;
-  double* GJ;
+  float* Gh;   // gradient at the iterate, FP32 (y = g - G; rounding far below the evaluation's noise)
+  float* GJ;
   float* Dh;   // search direction, FP32 (the step along it is rounded to FP32 anyway)
   float* DJ;
   float* Sh;   // [m+1][N][q] history slots (one spare for the candidate pair), FP32
