@@ -137,3 +137,31 @@ def test_refinement_fit_continues_the_first_one(plm):
     assert all(st["status"] == "converged" for st in exp.stats)
     with pytest.raises(plm.PlmError):
         plm.fit(msa, w, beff, plm.FitOptions(tol=1e-6, path=6, refine=1 + 9))
+
+
+@pytest.fixture(scope="module")
+def small_oracle():
+    s = synth.workload("potts_n40_b500")
+    sites = [0, 13, 39]
+    m_o, w_o, beff_o = oracle.reweight(s.msa, theta=0.8, uniform=True)
+    h_o, J_o, _ = oracle.fit(s.msa, w_o, beff_o, 0.01, 0.01, sites=sites, tol=1e-8)
+    return s, sites, h_o, J_o
+
+
+@pytest.mark.parametrize("lbfgs_m", [1, 3, 4, 5, 11, 20, 32])
+def test_fit_history_sizes(plm, small_oracle, lbfgs_m):
+    """Every history size reaches the same minimiser: the dot-product passes
+    read 1..4 pairs on the acceptance pass and up to six per further pass, so
+    m = 1 .. 32 covers every pair count of both (and m = 32, the largest,
+    five further passes)."""
+    print(f"[case] fit potts_n40_b500 lbfgs_m={lbfgs_m}", flush=True)
+    s, sites, h_o, J_o = small_oracle
+    msa = torch.from_numpy(s.msa).to(DEV)
+    m, w, beff = plm.reweight(msa, theta=0.8, uniform=True)
+    res = plm.fit(msa, w, beff, plm.FitOptions(tol=1e-6, lbfgs_m=lbfgs_m))
+    assert all(st["status"] == "converged" for st in res.stats), res.stats[:3]
+    J = res.J.cpu().numpy().astype(np.float64)
+    h = res.h.cpu().numpy().astype(np.float64)
+    for t, r in enumerate(sites):
+        assert np.max(np.abs(J[r] - J_o[t])) <= 1e-4
+        assert np.max(np.abs(h[r] - h_o[t])) <= 1e-4
