@@ -165,3 +165,28 @@ def test_fit_history_sizes(plm, small_oracle, lbfgs_m):
     for t, r in enumerate(sites):
         assert np.max(np.abs(J[r] - J_o[t])) <= 1e-4
         assert np.max(np.abs(h[r] - h_o[t])) <= 1e-4
+
+
+@pytest.mark.parametrize("q,path", [(5, 2), (5, 6), (11, 4)])
+def test_fit_small_alphabet(plm, q, path):
+    """Alphabets below 21 states (the alphabet size is taken from the start
+    point): every site converges to the oracle's minimiser."""
+    print(f"[case] fit q={q} path={path}", flush=True)
+    N, B = 15, 800
+    s = synth.make_msa(f"fq{q}", N=N, B=B, npairs=6, seed=70 + q, min_sep=1, q=q, cache=False,
+                       burnin=100, thin=2)
+    msa = torch.from_numpy(s.msa).to(DEV)
+    m, w, beff = plm.reweight(msa, theta=0.8, q=q)
+    h0 = torch.zeros(N, q, dtype=torch.float32, device=DEV)
+    J0 = torch.zeros(N, N, q, q, dtype=torch.float32, device=DEV)
+    res = plm.fit(msa, w, beff, plm.FitOptions(tol=1e-6, path=path), h0=h0, J0=J0)
+    assert all(st["status"] == "converged" for st in res.stats), res.stats[:3]
+    sites = [0, 7, 14]
+    m_o, w_o, beff_o = oracle.reweight(s.msa, theta=0.8)
+    h_o, J_o, _ = oracle.fit(s.msa, w_o, beff_o, 0.01, 0.01, sites=sites, q=q, tol=1e-8)
+    J = res.J.cpu().numpy().astype(np.float64)
+    h = res.h.cpu().numpy().astype(np.float64)
+    for t, r in enumerate(sites):
+        assert np.max(np.abs(J[r] - J_o[t])) <= 1e-4, (r, np.max(np.abs(J[r] - J_o[t])))
+        assert np.max(np.abs(h[r] - h_o[t])) <= 1e-4
+        assert np.all(J[r, r] == 0)
