@@ -161,9 +161,9 @@ def main():
     if args.path == "auto":
         items = [(m, w, beff) for m, (_, w, beff) in zip(msas, weights())]
         t = time.perf_counter()
-        # the symmetric fit's tolerance is on the norm over all parameters, below
-        # what the fixed-point paths' rounding allows there
-        tuned = plm.autotune.choose(items, plm.FitOptions(tol=args.tol), Q, fixed_point=not symmetric)
+        # the symmetric fit's tolerance is on the norm over all parameters: the
+        # tuner weighs the fixed-point rounding against it over that many entries
+        tuned = plm.autotune.choose(items, plm.FitOptions(tol=args.tol), Q, symmetric=symmetric)
         print(f"[bench] schedule path={tuned['path']} tile_seqs={tuned['tile_seqs']} "
               f"({time.perf_counter() - t:.1f} s to choose)", file=sys.stderr, flush=True)
         path, tile = int(tuned["path"]), int(tuned["tile_seqs"])
@@ -306,7 +306,8 @@ def main():
     cfg.update({"q": Q, "theta": 0.8, "lambda_h": 0.01, "lambda_J": 0.01, "tol": args.tol,
                 "path": PATH_NAMES[path], "tile_seqs": tile, "schedule": "autotuned" if tuned else "fixed",
                 "method": args.method, "init": args.init,
-                "refine": PATH_NAMES[5] if (path == 6 and not symmetric) else None})
+                "refine": (PATH_NAMES[4] if symmetric else PATH_NAMES[5])
+                if (path == 6 or (symmetric and path == 5)) else None})
     if mf_start:
         cfg["pseudocount"] = args.pseudocount
     line = {
@@ -325,9 +326,11 @@ def main():
                   5: "f32 forward, int8x3 fixed-point gradient (2^-23), exact int32 accumulation, "
                   "FP64 reductions, FP32 L-BFGS history",
                   6: "int8x3 fixed-point energies (2^-22 max|J_r|) and gradient (2^-23), exact int32 "
-                  "accumulation, FP32 softmax, FP64 reductions, FP32 L-BFGS history; refined to the tolerance "
-                  "on f32 energies with the int8x3 gradient"}.get(
-                      path, "f32 (FP64 reductions, FP32 L-BFGS history)"),
+                  "accumulation, FP32 softmax, FP64 reductions, FP32 L-BFGS history"}.get(
+                      path, "f32 (FP64 reductions, FP32 L-BFGS history)")
+        + ({PATH_NAMES[5]: "; refined to the tolerance on f32 energies with the int8x3 gradient",
+            PATH_NAMES[4]: "; refined to the tolerance on f32 energies with the f16x2 gradient"}
+           .get(cfg["refine"], "")),
         "data": "synthetic planted-Potts alignment (seeded Gibbs sampling)",
         "config": cfg,
         "time_to_fit_s": ms_per_step / 1e3,

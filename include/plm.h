@@ -164,7 +164,9 @@ typedef struct {
                            PLM_PATH_GATHER_MFMA_I8X3, whose gradient is within the FP32
                            tolerance; nothing after other paths), -1 = never, 1 + p =
                            always, on path p.  Site statistics and timing add both fits.
-                           plm_fit and plm_fit_batch; the symmetric fit ignores it. */
+                           plm_fit_symmetric: automatic refines after either fixed-point
+                           path on PLM_PATH_GATHER_MFMA_F16X2 (their rounding, summed
+                           over all parameters, is of the order of the tolerance). */
   int32_t reserved[3];
 } plm_fit_opts;
 
@@ -282,8 +284,11 @@ int plm_score(plm_ctx *ctx, const float *J, int32_t N, int32_t q, double *fn_out
  * stats_out (HOST, one record, may be NULL) describes the whole problem.
  * The evaluation of each trial point is the all-sites evaluation of plm_fit
  * (opts->path); every decision is taken on the device and one iteration is
- * one replay of a captured graph.  Returns PLM_W_MAXITER on the iteration
- * cap.  plm_fit_last_timing reports its kernel times when opts->timing. */
+ * one replay of a captured graph; opts->refine adds a second minimisation
+ * from the first one's point on another path (automatic after the fixed-point
+ * paths), counted in stats_out and the timing.  Returns PLM_W_MAXITER on the
+ * iteration cap.  plm_fit_last_timing reports its kernel times when
+ * opts->timing. */
 size_t plm_fit_symmetric_workspace_bytes(int32_t B, int32_t N, int32_t q, const plm_fit_opts *opts);
 int plm_fit_symmetric(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, int32_t q,
                       const double *w, const double *beff, const plm_fit_opts *opts,

@@ -207,10 +207,11 @@ def fit_symmetric(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None
     q = 21 if h0 is None else h0.shape[1]
     if opts.autotune:
         # the tolerance bounds the gradient norm over all N(N-1)/2 q^2 + N q
-        # parameters: the fixed-point paths' rounding noise summed over that
-        # many entries sits above it, so they are left out
+        # parameters: the int8 gradient is a candidate only where its rounding
+        # noise summed over that many entries stays below half the tolerance
+        # (its fit is then refined on an FP32-class path by the library)
         from . import autotune
-        opts = autotune.tuned_options([(msa, w, beff)], opts, q, fixed_point=False)
+        opts = autotune.tuned_options([(msa, w, beff)], opts, q, symmetric=True)
     h = torch.zeros(N, q, dtype=torch.float32, device=dev) if h0 is None else h0.clone().contiguous()
     J = torch.zeros(N, N, q, q, dtype=torch.float32, device=dev) if J0 is None else J0.clone().contiguous()
     _dev_tensor(w, torch.float64, dev, "w")

@@ -50,10 +50,23 @@ def fixed_point_floor(item, q: int) -> float:
     return 2.0 ** -23 * math.sqrt(N * q * q * B / 3.0) / max(be, 1e-300)
 
 
-def key(items, q: int, fp32_only: bool, fixed_point: bool = True) -> str:
+def symmetric_floor(item, q: int) -> float:
+    """The same estimate for the symmetric fit, whose gradient norm runs over
+    all N q + N (N - 1) / 2 q^2 parameters (each coupling block's gradient is
+    the sum of two sites' sums)."""
+    if len(item) < 3:
+        return 0.0
+    msa, _, beff = item
+    B, N = int(msa.shape[0]), int(msa.shape[1])
+    be = float(beff.item()) if hasattr(beff, "item") else float(beff)
+    P = N * q + N * (N - 1) // 2 * q * q
+    return 2.0 ** -23 * math.sqrt(P * B / 3.0) / max(be, 1e-300)
+
+
+def key(items, q: int, fp32_only: bool, fixed_point: bool = True, symmetric: bool = False) -> str:
     arch = _arch(items[0][0].device)
     bs = sorted(bucket(int(it[0].shape[1]), int(it[0].shape[0])) for it in items)
-    cls = ("fp32" if fp32_only else "any") + ("" if fixed_point else "-nofixed")
+    cls = ("fp32" if fp32_only else "any") + ("-sym" if symmetric else "") + ("" if fixed_point else "-nofixed")
     return f"{arch}|q{q}|{cls}|" + ",".join(f"{n}x{b}" for n, b in bs)
 
 
@@ -77,21 +90,27 @@ def store(d: dict, path: str | None = None) -> None:
 
 
 def choose(items, opts=None, q: int = 21, fp32_only: bool = True, path: str | None = None,
-           retune: bool = False, fixed_point: bool = True) -> dict:
+           retune: bool = False, fixed_point: bool = True, symmetric: bool = False) -> dict:
     """The cached schedule for this batch's bucket, timing the candidates on
-    the batch itself on a miss (or when retune is set).  fixed_point=False
-    leaves out the fixed-point paths (for objectives whose gradient norm is
-    taken over so many parameters that their rounding noise would exceed the
-    tolerance, as in the symmetric fit)."""
+    the batch itself on a miss (or when retune is set).  The fixed-point paths
+    are candidates only where the expected gradient norm their residual
+    rounding leaves is below half the tolerance (fixed_point=False leaves
+    them out).  For the symmetric fit (symmetric=True) that norm runs over all
+    parameters, and only the path with FP32 energies (5) is a candidate: its
+    fit is refined on an FP32-class path; the rounded couplings of path 6
+    move the symmetric gradient by more than such tolerances."""
     opts = opts or api.FitOptions()
-    fixed_point = fixed_point and all(fixed_point_floor(it, q) * 2.0 < opts.tol for it in items)
-    k = key(items, q, fp32_only, fixed_point)
+    floor = symmetric_floor if symmetric else fixed_point_floor
+    fixed_point = fixed_point and all(floor(it, q) * 2.0 < opts.tol for it in items)
+    k = key(items, q, fp32_only, fixed_point, symmetric)
     d = load(path)
     if not retune and k in d:
         return d[k]
     res = api.tune(items, opts, q, fp32_only)
     if not fixed_point:
         res = [r for r in res if r["path"] not in FIXED_POINT_PATHS]
+    elif symmetric:
+        res = [r for r in res if r["path"] != 6]
     entry = dict(path=res[0]["path"], tile_seqs=res[0]["tile_seqs"], eval_ms=res[0]["eval_ms"],
                  candidates=res)
     d = load(path)  # re-read: another process may have written meanwhile
@@ -100,7 +119,7 @@ def choose(items, opts=None, q: int = 21, fp32_only: bool = True, path: str | No
     return entry
 
 
-def tuned_options(items, opts, q: int = 21, fixed_point: bool = True):
+def tuned_options(items, opts, q: int = 21, fixed_point: bool = True, symmetric: bool = False):
     """opts with path and tile_seqs taken from the tuner (autotune cleared)."""
-    ch = choose(items, opts, q, fixed_point=fixed_point)
+    ch = choose(items, opts, q, fixed_point=fixed_point, symmetric=symmetric)
     return dataclasses.replace(opts, path=int(ch["path"]), tile_seqs=int(ch["tile_seqs"]), autotune=False)

@@ -1020,9 +1020,13 @@ size_t plm_fit_symmetric_workspace_bytes(int32_t B, int32_t N, int32_t q, const 
   return rup(bp.off, 256);
 }
 
-int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
-                      const double* beff, const plm_fit_opts* o, void* ws, size_t ws_bytes, float* h_io,
-                      float* J_io, plm_site_stats* stats_out) {
+}  // extern "C"
+
+namespace {
+
+int run_sym_once(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
+                 const double* beff, const plm_fit_opts* o, void* ws, size_t ws_bytes, float* h_io,
+                 float* J_io, plm_site_stats* stats_out) {
   if (!c) return PLM_E_INVALID;
   if (!msa || !w || !beff || !o || !h_io || !J_io) return set_err(c, PLM_E_INVALID, "null pointer");
   int rc = check_sizes(c, B, N, q);
@@ -1169,6 +1173,69 @@ int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int3
     stats_out->gnorm = hs.gnorm;
   }
   return status == PLM_SITE_MAXITER ? PLM_W_MAXITER : PLM_OK;
+}
+
+// Refinement path of the symmetric fit: automatic after either fixed-point
+// path (their rounding noise, summed over all parameters, is of the order of
+// the tolerance), on the FP32-class gather path with the 22-bit gradient.
+int32_t refine_path_sym(const plm_fit_opts* o) {
+  if (o->refine == 0)
+    return (o->path == PLM_PATH_GATHER_MFMA_I8X3 || o->path == PLM_PATH_MFMA_I8X3) ? PLM_PATH_GATHER_MFMA_F16X2
+                                                                                   : -1;
+  if (o->refine < 0) return -1;
+  const int32_t p = o->refine - 1;
+  return p == o->path ? -1 : p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
+                      const double* beff, const plm_fit_opts* o, void* ws, size_t ws_bytes, float* h_io,
+                      float* J_io, plm_site_stats* stats_out) {
+  if (!c) return PLM_E_INVALID;
+  if (!o) return set_err(c, PLM_E_INVALID, "null pointer");
+  const int32_t rp = refine_path_sym(o);
+  if (rp >= 0 && (rp < PLM_PATH_GATHER_FP32 || rp > PLM_PATH_MFMA_I8X3))
+    return set_err(c, PLM_E_INVALID, "refine: unknown path %d", rp);
+  plm_site_stats first;
+  memset(&first, 0, sizeof(first));
+  int rc = run_sym_once(c, msa, B, N, q, w, beff, o, ws, ws_bytes, h_io, J_io, &first);
+  if (rp < 0 || (rc != PLM_OK && rc != PLM_W_MAXITER)) {
+    if (stats_out && (rc == PLM_OK || rc == PLM_W_MAXITER)) *stats_out = first;
+    return rc;
+  }
+  // a second fit from the first one's point on the refinement path: the
+  // statistics and the kernel times add both
+  const plm_fit_timing t1 = c->timing;
+  plm_fit_opts o2 = *o;
+  o2.path = rp;
+  o2.refine = -1;
+  o2.tile_seqs = 0;
+  plm_site_stats second;
+  memset(&second, 0, sizeof(second));
+  const int rc2 = run_sym_once(c, msa, B, N, q, w, beff, &o2, ws, ws_bytes, h_io, J_io, &second);
+  if (rc2 != PLM_OK && rc2 != PLM_W_MAXITER) return rc2;
+  second.iterations += first.iterations;
+  second.evaluations += first.evaluations;
+  if (stats_out) *stats_out = second;
+  if (o->timing) {
+    plm_fit_timing& t = c->timing;
+    t.refine_forward_ms = t.forward_ms;
+    t.refine_backward_ms = t.backward_ms;
+    t.refine_lbfgs_ms = t.lbfgs_ms;
+    t.refine_iterations = t.iterations;
+    t.refine_site_evals = t.site_evals;
+    t.forward_ms += t1.forward_ms;
+    t.backward_ms += t1.backward_ms;
+    t.lbfgs_ms += t1.lbfgs_ms;
+    t.quant_ms += t1.quant_ms;
+    t.total_ms += t1.total_ms;
+    t.iterations += t1.iterations;
+    t.site_evals += t1.site_evals;
+  }
+  return rc2;
 }
 
 void plm_score_opts_default(plm_score_opts* o) {

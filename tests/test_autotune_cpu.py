@@ -62,6 +62,28 @@ def test_fixed_point_paths_left_out_where_their_rounding_floor_reaches_tol(monke
     assert autotune.choose([small], api.FitOptions(tol=1e-5), 21, path=path)["path"] == 6
 
 
+def test_symmetric_fit_takes_only_the_fp32_energy_fixed_point_path(monkeypatch, tmp_path):
+    path = str(tmp_path / "tune.json")
+    monkeypatch.setattr(autotune, "_arch", lambda dev: "gfx950")
+    cands = [dict(path=6, tile_seqs=0, eval_ms=1.0), dict(path=5, tile_seqs=32, eval_ms=1.5),
+             dict(path=4, tile_seqs=32, eval_ms=2.0), dict(path=0, tile_seqs=16, eval_ms=3.0)]
+    monkeypatch.setattr(api, "tune", lambda *a, **k: [dict(c) for c in cands])
+    big = (torch.zeros(50000, 500, dtype=torch.uint8), None, torch.tensor([50000.0], dtype=torch.float64))
+    # over all N q + N (N - 1) / 2 q^2 parameters: 2.28e-6 at N = 500, B = B_eff = 50000
+    P = 500 * 21 + 500 * 499 // 2 * 441
+    fl = autotune.symmetric_floor(big, 21)
+    assert fl == pytest.approx(2.0 ** -23 * (P * 50000 / 3) ** 0.5 / 50000)
+    assert 2.2e-6 < fl < 2.4e-6
+    # twice the floor below the tolerance: path 5 (never 6); else the FP32-class paths
+    assert autotune.choose([big], api.FitOptions(tol=5e-6), 21, path=path, symmetric=True)["path"] == 5
+    assert autotune.choose([big], api.FitOptions(tol=1e-6), 21, path=path, symmetric=True)["path"] == 4
+    assert autotune.choose([big], api.FitOptions(tol=5e-6), 21, path=path, symmetric=True,
+                           fixed_point=False)["path"] == 4
+    # separate cache entries from the per-site fit's
+    assert autotune.choose([big], api.FitOptions(tol=5e-6), 21, path=path)["path"] == 6
+    assert autotune.key([big], 21, True, True, True) != autotune.key([big], 21, True, True, False)
+
+
 def test_load_tolerates_missing_and_corrupt_files(tmp_path):
     assert autotune.load(str(tmp_path / "none.json")) == {}
     bad = tmp_path / "bad.json"

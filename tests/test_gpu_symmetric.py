@@ -89,6 +89,46 @@ def test_symmetric_fit_matches_oracle(plm, small, path):
                 assert res_ri <= (0.01 * np.sqrt(21) + 0.01) * dist + 1e-8, (r, i, res_ri)
 
 
+def test_symmetric_refinement_continues_the_first_fit(plm, small):
+    """After a fixed-point path the symmetric fit is refined (automatically, on
+    path 4) from the first fit's point: the first fit is the refine = -1 fit
+    bit for bit, the statistics and timing add both, the final gradient norm
+    is that of the refinement path's evaluation, and the result stays within
+    1e-4 of the oracle's minimiser."""
+    s, h_o, J_o = small
+    print("[case] symmetric refinement after path 5", flush=True)
+    msa, w, beff = _gpu_problem(plm, s)
+    N = 10
+    base = plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=1e-6, path=5, refine=-1, timing=True))
+    tb = plm.last_fit_timing(DEV)
+    assert tb["refine_site_evals"] == 0 and tb["refine_iterations"] == 0
+    ref = plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=1e-6, path=5, timing=True))
+    tr = plm.last_fit_timing(DEV)
+    (sb,), (sr,) = base.stats, ref.stats
+    assert sr["status"] == "converged" and sr["gnorm"] <= 1e-6
+    assert tr["refine_iterations"] >= 1
+    assert tr["refine_site_evals"] == (sr["evaluations"] - sb["evaluations"]) * N > 0
+    assert tr["site_evals"] == tb["site_evals"] + tr["refine_site_evals"]
+    assert tr["iterations"] == tb["iterations"] + tr["refine_iterations"]
+    assert sr["iterations"] >= sb["iterations"]
+    h = ref.h.cpu().numpy().astype(np.float64)
+    J = ref.J.cpu().numpy().astype(np.float64)
+    _check_consistent(J)
+    assert max(np.max(np.abs(J - J_o)), np.max(np.abs(h - h_o))) <= 1e-4
+    # the refinement's own evaluation at the returned point: a further fit on
+    # path 4 from it stops at once
+    again = plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=1e-6, path=4),
+                              h0=ref.h, J0=ref.J)
+    assert again.stats[0]["iterations"] == 0
+    # an explicit refinement path, none after an FP32-class path, an unknown one rejected
+    exp = plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=1e-6, path=5, refine=1 + 2))
+    assert exp.stats[0]["status"] == "converged"
+    plain = plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=1e-6, path=4, timing=True))
+    assert plm.last_fit_timing(DEV)["refine_iterations"] == 0 and plain.stats[0]["status"] == "converged"
+    with pytest.raises(plm.PlmError):
+        plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=1e-6, path=5, refine=1 + 9))
+
+
 def test_symmetric_start_point_is_made_consistent(plm, small):
     # an inconsistent start (random blocks everywhere, self blocks included)
     # reaches the same unique minimiser; only the blocks r < i are read
