@@ -23,7 +23,7 @@ __global__ void init_fit_kernel(int32_t N, int32_t q, float* Xh, float* XJ, floa
     SiteState s;
     s.phase = PH_INIT;
     s.status = PLM_SITE_MAXITER;
-    s.iter = s.evals = s.ls_count = s.head = s.stored = s.pad = 0;
+    s.iter = s.evals = s.ls_count = s.head = s.stored = s.dpend = 0;
     s.f = s.gnorm = s.alpha = s.gtd = 0.0;
     s.gamma = 1.0;
     st[r] = s;

@@ -188,6 +188,7 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
   // what to do with the search direction once the decision is taken
   enum { KEEP = 0, STEEPEST = 1, QUASI_NEWTON = 2 } dir = KEEP;
   bool move = false;  // write a new trial point
+  int dpend = 0;      // a quasi-Newton direction left to the direction kernels
 
   if (phase == PH_INIT && !finite) {
     newphase = PH_DONE;
@@ -472,49 +473,20 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
       }
     }
     __syncthreads();
-    // four elements per thread at a time (e, e + nth, e + 2 nth, e + 3 nth,
-    // the same order as a plain strided loop), so that the history loads of
-    // four elements are in flight together
-    double dg = 0.0;
-    constexpr int U = 4;
-    for (int e0 = tid; e0 < P; e0 += U * nth) {
-      int ee[U];
-      double g[U], d[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        ee[u] = min(e0 + u * nth, P - 1);
-        g[u] = Gv(ee[u]);
-        d[u] = -gamma * g[u];
-      }
-#pragma unroll 2
-      for (int i = 0; i < n; ++i) {
-        const int k = sh.ord[i];
-        const double ci = sh.cs[i], yi = sh.cy[i];
-        double sv[U], yv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          sv[u] = *Sp(k, ee[u]);
-          yv[u] = *Yp(k, ee[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) d[u] += ci * sv[u] + yi * yv[u];
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (e0 + u * nth < P) {
-          *Dp(ee[u]) = (float)d[u];
-          storeT(ee[u], Xv(ee[u]) + d[u]);  // trial point at alpha = 1
-          dg += d[u] * g[u];
-        }
+    // the direction itself is formed by lbfgs_dir_kernel, several blocks per
+    // site, and its descent test taken by lbfgs_dir_finish_kernel
+    DirCoef* C = a.dc + r;
+    if (tid < n) {
+      C->cs[tid] = sh.cs[tid];
+      C->cy[tid] = sh.cy[tid];
+      C->ord[tid] = sh.ord[tid];
     }
-    dg = block_sum_f64(dg, red);
-    if (dg < 0.0) {
-      gtd = dg;
-      alpha = 1.0;
-      move = false;  // already written
-    } else {
-      dir = STEEPEST;  // not a descent direction
+    if (tid == 0) {
+      C->n = n;
+      C->gamma = gamma;
     }
+    dpend = 1;
+    move = false;
   }
   if (dir == STEEPEST) {
     __syncthreads();
@@ -536,6 +508,7 @@ __device__ inline void lbfgs_site(const LbfgsArgs& a, int r, LbShared& sh, doubl
     S->ls_count = ls;
     S->head = head;
     S->stored = stored;
+    S->dpend = dpend;
     S->f = f;
     S->gnorm = gnorm;
     S->alpha = alpha;
@@ -559,8 +532,160 @@ __global__ __launch_bounds__(kLbThreads) __attribute__((amdgpu_waves_per_eu(4, 4
   lbfgs_site(a, __builtin_amdgcn_readfirstlane(g - b.site_base[m]), sh, red);
 }
 
+// Per-site vectors of the direction kernels, addressed by the element index
+// e of the site's parameter vector (fields e < q, then the couplings).
+struct SiteVecs {
+  int q, self0, self1;
+  size_t h0, j0, hs, js;  // field and coupling offsets of the site, slot strides
+  const __attribute__((address_space(1))) float *Gh, *GJ, *Xh, *XJ, *Sh, *SJ, *Yh, *YJ;
+  __attribute__((address_space(1))) float *Dh, *DJ, *Th, *TJ;
+  __device__ SiteVecs(const LbfgsArgs& a, int r) {
+    q = a.q;
+    const size_t Nqq = (size_t)a.N * a.q * a.q;
+    h0 = (size_t)r * q;
+    j0 = (size_t)r * Nqq;
+    hs = (size_t)a.N * q;
+    js = (size_t)a.N * Nqq;
+    self0 = q + r * q * q;
+    self1 = self0 + q * q;
+    Gh = gmem(a.Gh); GJ = gmem(a.GJ); Xh = gmem(a.Xh); XJ = gmem(a.XJ);
+    Sh = gmem(a.Sh); SJ = gmem(a.SJ); Yh = gmem(a.Yh); YJ = gmem(a.YJ);
+    Dh = gmem_w(a.Dh); DJ = gmem_w(a.DJ); Th = gmem_w(a.Th); TJ = gmem_w(a.TJ);
+  }
+  __device__ double G(int e) const { return e < q ? Gh[h0 + e] : GJ[j0 + (e - q)]; }
+  __device__ double X(int e) const { return e < q ? Xh[h0 + e] : XJ[j0 + (e - q)]; }
+  __device__ double S(int k, int e) const { return e < q ? Sh[k * hs + h0 + e] : SJ[k * js + j0 + (e - q)]; }
+  __device__ double Y(int k, int e) const { return e < q ? Yh[k * hs + h0 + e] : YJ[k * js + j0 + (e - q)]; }
+  __device__ void setD(int e, float d) const {
+    if (e < q) Dh[h0 + e] = d; else DJ[j0 + (e - q)] = d;
+  }
+  // the trial point, FP32; the self block stays zero
+  __device__ void setT(int e, double v) const {
+    const float f = (float)v;
+    if (e < q) Th[h0 + e] = f; else TJ[j0 + (e - q)] = (e >= self0 && e < self1) ? 0.f : f;
+  }
+};
+
+constexpr int kDirThreads = 256;
+
+// The pending quasi-Newton direction of every active site, kDirChunks blocks
+// per site, each over a contiguous range of the site's elements: d, the
+// trial point X + d (step 1) and the block's partial sum of d . g.  The
+// partition depends on the site's size only, so the sums do not depend on
+// the batch.
+__global__ __launch_bounds__(kDirThreads) void lbfgs_dir_kernel(BatchArgs b) {
+  __shared__ double cs[kMMax], cy[kMMax];
+  __shared__ int32_t ord[kMMax];
+  __shared__ double red[kDirThreads / 64];
+  const int idx = blockIdx.x / kDirChunks, chunk = blockIdx.x - idx * kDirChunks;
+  if (idx >= *b.n_active) return;
+  const int g = __builtin_amdgcn_readfirstlane(b.active[idx]);
+  const int m = __builtin_amdgcn_readfirstlane(b.msa_of[g]);
+  const LbfgsArgs a = load_uniform(b.lb + m);
+  const int r = __builtin_amdgcn_readfirstlane(g - b.site_base[m]);
+  if (__builtin_amdgcn_readfirstlane(a.st[r].dpend) == 0) return;
+  const DirCoef* C = a.dc + r;
+  const int n = __builtin_amdgcn_readfirstlane(C->n);
+  const double gamma = C->gamma;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if (tid < n) {
+    cs[tid] = C->cs[tid];
+    cy[tid] = C->cy[tid];
+    ord[tid] = C->ord[tid];
+  }
+  __syncthreads();
+  const SiteVecs v(a, r);
+  const int P = a.q + a.N * a.q * a.q;
+  const int csz = (P + kDirChunks - 1) / kDirChunks;
+  const int e_beg = chunk * csz, e_end = min(P, e_beg + csz);
+  // four elements per thread at a time (e, e + nth, e + 2 nth, e + 3 nth),
+  // so that the history loads of four elements are in flight together
+  double dg = 0.0;
+  constexpr int U = 4;
+  for (int e0 = e_beg + tid; e0 < e_end; e0 += U * nth) {
+    int ee[U];
+    double gv[U], d[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ee[u] = min(e0 + u * nth, e_end - 1);
+      gv[u] = v.G(ee[u]);
+      d[u] = -gamma * gv[u];
+    }
+#pragma unroll 2
+    for (int i = 0; i < n; ++i) {
+      const int k = ord[i];
+      const double ci = cs[i], yi = cy[i];
+      double sv[U], yv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        sv[u] = v.S(k, ee[u]);
+        yv[u] = v.Y(k, ee[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) d[u] += ci * sv[u] + yi * yv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e0 + u * nth < e_end) {
+        v.setD(ee[u], (float)d[u]);
+        v.setT(ee[u], v.X(ee[u]) + d[u]);  // trial point at alpha = 1
+        dg += d[u] * gv[u];
+      }
+  }
+  dg = block_sum_f64(dg, red);
+  if (tid == 0) a.dpart[(size_t)r * kDirChunks + chunk] = dg;
+}
+
+// The descent test of every pending direction (the block sums of d . g added
+// in chunk order); where d is not a descent direction, steepest descent from
+// the iterate with the history forgotten.
+__global__ __launch_bounds__(kDirThreads) void lbfgs_dir_finish_kernel(BatchArgs b) {
+  const int idx = blockIdx.x;
+  if (idx >= *b.n_active) return;
+  const int g = __builtin_amdgcn_readfirstlane(b.active[idx]);
+  const int m = __builtin_amdgcn_readfirstlane(b.msa_of[g]);
+  const LbfgsArgs a = load_uniform(b.lb + m);
+  const int r = __builtin_amdgcn_readfirstlane(g - b.site_base[m]);
+  SiteState* S = a.st + r;
+  const int pend = __builtin_amdgcn_readfirstlane(S->dpend);
+  __syncthreads();  // every wave has read the flag before it is cleared
+  if (pend == 0) return;
+  double dg = 0.0;
+  for (int c = 0; c < kDirChunks; ++c) dg += a.dpart[(size_t)r * kDirChunks + c];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if (dg < 0.0) {
+    if (tid == 0) {
+      S->gtd = dg;
+      S->alpha = 1.0;
+      S->dpend = 0;
+    }
+    return;
+  }
+  const double gnorm = S->gnorm;
+  const double alpha = fmin(1.0, 1.0 / gnorm);
+  const SiteVecs v(a, r);
+  const int P = a.q + a.N * a.q * a.q;
+  for (int e = tid; e < P; e += nth) {
+    const float d = (float)-v.G(e);
+    v.setD(e, d);
+    v.setT(e, v.X(e) + alpha * (double)d);
+  }
+  if (tid == 0) {
+    S->gtd = -gnorm * gnorm;
+    S->alpha = alpha;
+    S->stored = 0;
+    S->dpend = 0;
+  }
+}
+
 hipError_t launch_lbfgs(const BatchArgs& b, int32_t nblocks, hipStream_t st) {
   hipLaunchKernelGGL(lbfgs_kernel, dim3(nblocks), dim3(kLbThreads), 0, st, b);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(lbfgs_dir_kernel, dim3(nblocks * kDirChunks), dim3(kDirThreads), 0, st, b);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(lbfgs_dir_finish_kernel, dim3(nblocks), dim3(kDirThreads), 0, st, b);
   return hipGetLastError();
 }
 

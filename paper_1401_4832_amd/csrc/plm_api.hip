@@ -100,6 +100,8 @@ struct FitBufs {
   float *Th, *TJ;
   double* small;
   float *Gh, *GJ, *Dh, *DJ, *Sh, *SJ, *Yh, *YJ;
+  DirCoef* dc;
+  double* dpart;
 };
 
 void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, FitBufs& f) {
@@ -116,6 +118,8 @@ void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, FitBufs& f
   f.Yh = bp.take<float>(Nq * (m + 1));
   f.YJ = bp.take<float>(NNqq * (m + 1));
   f.small = bp.take<double>((size_t)N * 2 * (m + 1) * (m + 2));
+  f.dc = bp.take<DirCoef>(N);
+  f.dpart = bp.take<double>((size_t)N * kDirChunks);
 }
 
 // device tables of a batch (BatchArgs points into them)
@@ -640,6 +644,7 @@ int prepare_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const p
     L.Xh = m.h_io; L.XJ = m.J_io; L.Th = f.Th; L.TJ = f.TJ;
     L.Gh = f.Gh; L.GJ = f.GJ; L.Dh = f.Dh; L.DJ = f.DJ;
     L.Sh = f.Sh; L.SJ = f.SJ; L.Yh = f.Yh; L.YJ = f.YJ; L.small = f.small;
+    L.dc = f.dc; L.dpart = f.dpart;
     L.f_part = f.ev.f_part; L.gh_part = f.ev.gh_part; L.gJ = f.ev.gJ;
     L.st = t.st + base[k];
     L.phase_host = phase_host_dev + base[k];

@@ -47,7 +47,7 @@ struct SiteState {
   int32_t ls_count;
   int32_t head;
   int32_t stored;
-  int32_t pad;
+  int32_t dpend;       // 1: a quasi-Newton direction is pending (DirCoef, direction kernels)
   double f;            // normalised objective at the current point
   double gnorm;
   double alpha;        // step of the pending trial point
@@ -56,6 +56,19 @@ struct SiteState {
 };
 
 enum { PH_INIT = 0, PH_LS = 1, PH_DONE = 2 };
+
+// The quasi-Newton direction d = -gamma g + sum_i (cs_i s_i + cy_i y_i) of
+// one site, over its stored pairs in chronological order (slots ord), as
+// computed by the L-BFGS step and formed by the direction kernels.
+constexpr int kDirChunks = 16;  // blocks per site that form the direction
+struct DirCoef {
+  int32_t n;
+  int32_t pad;
+  double gamma;
+  double cs[kMMax];
+  double cy[kMMax];
+  int32_t ord[kMMax];
+};
 
 // Everything the evaluation kernels need about one alignment.
 struct EvalArgs {
@@ -126,6 +139,8 @@ struct LbfgsArgs {
   float* Yh;
   float* YJ;
   double* small;  // per site: [m+1][m+1] S^T Y, [m+1][m+1] Y^T Y, [m+1] S^T G, [m+1] Y^T G by slot
+  DirCoef* dc;    // per site: the pending direction's coefficients
+  double* dpart;  // per site: [kDirChunks] partial sums of d . g
   const double* f_part;   // [tiles][N]
   const double* gh_part;  // [tiles][N][21]
   const double* gJ;       // [N][N][q][q] data part

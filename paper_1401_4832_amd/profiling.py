@@ -35,7 +35,8 @@ KERNEL_SOURCES = {"forward": ("k_gather.hip", "plm_internal.h"), "backward": ("k
                   "backward_g3": ("k_mfma.hip", "plm_internal.h"), "backward_i8": ("k_mfma.hip", "plm_internal.h"),
                   "forward_i8": ("k_fwd8.hip", "plm_internal.h"), "jmax": ("k_fwd8.hip", "plm_internal.h"),
                   "jquant": ("k_fwd8.hip", "plm_internal.h"),
-                  "lbfgs": ("k_lbfgs.hip", "plm_internal.h"), "reweight": ("k_reweight.hip", "plm_internal.h")}
+                  "lbfgs": ("k_lbfgs.hip", "plm_internal.h"), "lbfgs_dir": ("k_lbfgs.hip", "plm_internal.h"),
+                  "reweight": ("k_reweight.hip", "plm_internal.h")}
 
 
 def source_hash(kernel: str | None = None) -> str:
