@@ -573,7 +573,7 @@ constexpr int kDirThreads = 256;
 // trial point X + d (step 1) and the block's partial sum of d . g.  The
 // partition depends on the site's size only, so the sums do not depend on
 // the batch.
-__global__ __launch_bounds__(kDirThreads) void lbfgs_dir_kernel(BatchArgs b) {
+__global__ __launch_bounds__(kDirThreads) __attribute__((amdgpu_waves_per_eu(6))) void lbfgs_dir_kernel(BatchArgs b) {
   __shared__ double cs[kMMax], cy[kMMax];
   __shared__ int32_t ord[kMMax];
   __shared__ double red[kDirThreads / 64];

@@ -60,7 +60,7 @@ enum { PH_INIT = 0, PH_LS = 1, PH_DONE = 2 };
 // The quasi-Newton direction d = -gamma g + sum_i (cs_i s_i + cy_i y_i) of
 // one site, over its stored pairs in chronological order (slots ord), as
 // computed by the L-BFGS step and formed by the direction kernels.
-constexpr int kDirChunks = 16;  // blocks per site that form the direction
+constexpr int kDirChunks = 32;  // blocks per site that form the direction
 struct DirCoef {
   int32_t n;
   int32_t pad;
