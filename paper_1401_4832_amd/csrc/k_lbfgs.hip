@@ -2,12 +2,16 @@
 // problems of asymmetric plmDCA (sec. 3.4 step 3; the paper minimises each
 // g_r^reg by L-BFGS from the origin, secs. 5 and 6).
 //
-// One block owns one site.  Each launch consumes the evaluation of the site's
-// trial point (objective partials from the forward kernel, FP64 gradient data
-// part from the backward kernel), adds the l2 terms in FP64, takes the line
-// search decision (sufficient decrease with backtracking by safeguarded
-// quadratic interpolation), and on acceptance stores the curvature pair and
-// writes the next trial point.  All dot products and the small matrices are
+// One block owns one site in the step (lbfgs_kernel).  Each launch consumes
+// the evaluation of the site's trial point (objective partials from the
+// forward kernel, FP64 gradient data part from the backward kernel), adds the
+// l2 terms in FP64, takes the line search decision (sufficient decrease with
+// backtracking by safeguarded quadratic interpolation), and on acceptance
+// stores the curvature pair and computes the coefficients of the next
+// direction, which lbfgs_dir_kernel forms with several blocks per site
+// (writing the next trial point) and lbfgs_dir_finish_kernel tests for
+// descent; backtracking and steepest-descent trial points are written by the
+// step itself.  All dot products and the small matrices are
 // FP64; the stored curvature pairs, the gradient kept at the iterate and the
 // direction are FP32 (the gradients carry the rounding noise of the FP32
 // evaluation, far above the 2^-24 relative rounding of the stored values;
