@@ -166,3 +166,24 @@ def ragged_set(count: int = 16, seed: int = 4, n_range=(60, 300), b_range=(2000,
         cfg.update(over)
         out.append(make_msa(f"ragged{k}", **cfg))
     return out
+
+
+def sample_sites(seed: int, N: int, k: int) -> list:
+    """k distinct site indices drawn uniformly from 0..N-1 (partial
+    Fisher-Yates shuffle on the seeded stream (seed, 55)), sorted."""
+    u = uniform(seed, 55, k)
+    idx = list(range(N))
+    for t in range(k):
+        j = t + min(int(u[t] * (N - t)), N - t - 1)
+        idx[t], idx[j] = idx[j], idx[t]
+    return sorted(idx[:k])
+
+
+def msa_digest(msa: np.ndarray) -> str:
+    """SHA-256 of an alignment's bytes and shape (identifies stored fixtures)."""
+    import hashlib
+    a = np.ascontiguousarray(msa, dtype=np.uint8)
+    h = hashlib.sha256()
+    h.update(np.asarray(a.shape, dtype=np.int64).tobytes())
+    h.update(a.tobytes())
+    return h.hexdigest()
