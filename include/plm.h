@@ -22,7 +22,9 @@
  *      J    float  [N][N][q][q]  J[r][i][k][s] = J^{(r)}_{ri}(s,k): coupling of
  *                                state s at site r with state k at site i, as
  *                                seen by the site-r problem.  The self blocks
- *                                J[r][r] are ignored on input, zero on output.
+ *                                J[r][r] take no part in any result (they
+ *                                must be finite: the input check covers the
+ *                                whole array) and are zero on output.
  *  - Objective scale: f_r = B_eff * g_r^reg (eq. g_regdef2 multiplied by B_eff);
  *    gradients are of f_r.  Convergence tolerances are on the paper's
  *    normalised scale g_r^reg = f_r / B_eff.
@@ -57,7 +59,12 @@ extern "C" {
 #define PLM_E_UNSUPPORTED -6 /* device is not gfx950, or an option not built */
 
 /* Objective/gradient evaluation paths.  All reduce objectives and gradients
- * over sequences in FP64 and keep the optimiser in FP64.  The one-hot matrix
+ * over sequences in FP64.  The optimiser (plm_fit and its variants) takes its
+ * dot products, small matrices, objective and the gradient at the trial point
+ * in FP64; the iterate and trial point are FP32 (the values the evaluation
+ * kernels read), and the stored curvature pairs (s, y), the gradient kept at
+ * the iterate and the search direction are FP32 unless
+ * plm_fit_opts.history_fp64 asks for FP64 pairs and gradient copy.  The one-hot matrix
  * X[b][(i,k)] = [sigma_i^b = k] is exact in BF16; the MFMA paths split the
  * other operand (the couplings W_r[(i,k)][s] = J_ri(s,k) in the forward, the
  * residuals R_b(s) in the backward) into BF16 pieces and accumulate in FP32. */
@@ -157,21 +164,50 @@ typedef struct {
   int32_t timing;       /* 1: launch the iteration eagerly (no graph) with HIP events
                            between the kernels on the fit's stream, synchronise every
                            iteration, and keep the kernel times: plm_fit_last_timing */
-  int32_t refine;       /* a second fit from the first one's point, to the same tolerance,
-                           on another evaluation path: 0 = automatic (after
-                           PLM_PATH_MFMA_I8X3, whose rounded couplings move the gradient
-                           by up to about 1e-6 in norm at N = 500, refine on
+  int32_t refine;       /* a second fit from the first one's point, to refine_tol (0: the
+                           same tolerance), on another evaluation path: 0 = automatic
+                           (after PLM_PATH_MFMA_I8X3, whose rounded couplings move the
+                           gradient by up to about 1e-6 in norm at N = 500, refine on
                            PLM_PATH_GATHER_MFMA_I8X3, whose gradient is within the FP32
-                           tolerance; nothing after other paths), -1 = never, 1 + p =
-                           always, on path p.  Site statistics and timing add both fits.
+                           tolerance; after PLM_PATH_MFMA_BF16X2, whose 16-bit operands
+                           leave a gradient error far above 1e-6, refine on
+                           PLM_PATH_MFMA_FP32; nothing after other paths), -1 = never,
+                           1 + p = always, on path p.  Site statistics and timing add both
+                           fits.  With a noisy first path, give the first fit a tolerance
+                           above its rounding floor (tol) and the refinement the target
+                           (refine_tol).
                            plm_fit_symmetric: automatic refines after either fixed-point
                            path on PLM_PATH_GATHER_MFMA_F16X2 (their rounding, summed
                            over all parameters, is of the order of the tolerance). */
-  int32_t reserved[3];
+  int32_t n_probe;      /* plm_fit only: number of sites watched by the convergence probe
+                           (0 = none).  After the start point is set up and after every
+                           iteration (of the refinement fit too), the probe writes one
+                           entry of probe_out: [0] the device wall clock in seconds,
+                           [1] the largest max-abs difference over the watched sites
+                           between the iterate (h_r, and J_r without its self block) and
+                           the reference, [2 + k] that difference for watched site k.
+                           probe_count (caller-zeroed) receives the entries written;
+                           entries beyond probe_cap are dropped.  Meant for measuring the
+                           time until a fit is within a given distance of a known
+                           minimiser; it adds one small kernel per iteration. */
+  double refine_tol;    /* tolerance of the refinement fit; 0 = tol */
+  const int32_t *probe_sites; /* DEVICE int32[n_probe], distinct sites in [0, N) */
+  const float *probe_h;       /* DEVICE float[n_probe][q] reference fields */
+  const float *probe_J;       /* DEVICE float[n_probe][N][q][q] reference couplings */
+  double *probe_out;          /* DEVICE double[probe_cap][2 + n_probe] */
+  int32_t *probe_count;       /* DEVICE int32[1] */
+  int32_t probe_cap;
+  int32_t history_fp64; /* 1: the curvature pairs and the gradient kept at the iterate are stored
+                           in FP64 (twice the optimiser's history traffic); 0: FP32, the
+                           default (their entries are differences of gradients that carry
+                           the FP32 evaluation's rounding, far above FP32 storage rounding) */
+  int32_t reserved[2];
 } plm_fit_opts;
 
 /* Fill *opts with the defaults listed above. */
 void plm_fit_opts_default(plm_fit_opts *opts);
+/* sizeof(plm_fit_opts) as compiled into the library (a binding's layout check). */
+size_t plm_fit_opts_size(void);
 
 #define PLM_SITE_CONVERGED 0
 #define PLM_SITE_MAXITER 1

@@ -43,7 +43,16 @@ class FitOpts(ctypes.Structure):
         ("site_limit", ctypes.c_int32),
         ("timing", ctypes.c_int32),
         ("refine", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("n_probe", ctypes.c_int32),
+        ("refine_tol", ctypes.c_double),
+        ("probe_sites", ctypes.c_void_p),
+        ("probe_h", ctypes.c_void_p),
+        ("probe_J", ctypes.c_void_p),
+        ("probe_out", ctypes.c_void_p),
+        ("probe_count", ctypes.c_void_p),
+        ("probe_cap", ctypes.c_int32),
+        ("history_fp64", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -142,6 +151,7 @@ def lib():
             "plm_objgrad": (ctypes.c_int, [P, P, I32, I32, I32, P, P, P, P, D, D, P, I32, I32, P, SZ,
                                            P, P, P, P]),
             "plm_fit_opts_default": (None, [ctypes.POINTER(FitOpts)]),
+            "plm_fit_opts_size": (SZ, []),
             "plm_fit_workspace_bytes": (SZ, [I32, I32, I32, ctypes.POINTER(FitOpts)]),
             "plm_fit": (ctypes.c_int, [P, P, I32, I32, I32, P, P, ctypes.POINTER(FitOpts), P, SZ, P, P,
                                        ctypes.POINTER(SiteStats)]),
@@ -176,6 +186,7 @@ def exported_symbols():
     """Names declared in include/plm.h that the ABI tests check for."""
     return ["plm_ctx_create", "plm_ctx_destroy", "plm_last_error", "plm_status_string", "plm_sync",
             "plm_reweight", "plm_objgrad_workspace_bytes", "plm_objgrad", "plm_fit_opts_default",
+            "plm_fit_opts_size",
             "plm_fit_workspace_bytes", "plm_fit", "plm_score", "plm_fit_last_timing",
             "plm_fit_batch_workspace_bytes", "plm_fit_batch", "plm_tune", "plm_score_opts_default",
             "plm_frequencies", "plm_score_ex", "plm_contact_tpr", "plm_parse_alignment",

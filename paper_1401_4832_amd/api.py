@@ -136,15 +136,19 @@ class FitOptions:
     site_limit: int = 0
     timing: bool = False
     # a second fit from the first one's point on another path: 0 automatic
-    # (path 6 is refined on path 5), -1 never, 1 + p always on path p
+    # (path 6 is refined on path 5, path 1 on path 3), -1 never, 1 + p always on path p
     refine: int = 0
     # pick path and tile_seqs with the autotuner (cached per size bucket)
     autotune: bool = False
+    # tolerance of the refinement fit (0: tol)
+    refine_tol: float = 0.0
+    # curvature pairs and the gradient kept at the iterate in FP64 (default FP32)
+    history_fp64: bool = False
 
     def to_c(self) -> L.FitOpts:
         o = L.FitOpts()
         L.lib().plm_fit_opts_default(ctypes.byref(o))
-        for k in ("lambda_h", "lambda_J", "tol"):
+        for k in ("lambda_h", "lambda_J", "tol", "refine_tol"):
             setattr(o, k, float(getattr(self, k)))
         for k in ("max_iter", "lbfgs_m", "max_linesearch", "path", "sync_every", "tile_seqs", "site_limit",
                   "refine"):
@@ -152,7 +156,20 @@ class FitOptions:
         o.use_graph = int(bool(self.use_graph))
         o.single_site = int(bool(self.single_site))
         o.timing = int(bool(self.timing))
+        o.history_fp64 = int(bool(self.history_fp64))
         return o
+
+
+@dataclass
+class Probe:
+    """Convergence probe of fit(): after the start point and after every
+    iteration, the device records its wall clock (seconds) and the max-abs
+    difference between the iterate and reference values (h_ref [n, q],
+    J_ref [n, N, q, q], float32 on the device) for the watched sites."""
+    sites: torch.Tensor
+    h_ref: torch.Tensor
+    J_ref: torch.Tensor
+    cap: int = 20000
 
 
 @dataclass
@@ -161,13 +178,15 @@ class FitResult:
     J: torch.Tensor
     stats: list = field(default_factory=list)
     status: int = 0
+    # probe entries (numpy [count, 2 + n]: time s, max over sites, per site), if probed
+    probe: object = None
 
     @property
     def evaluations(self) -> int:
         return int(sum(s["evaluations"] for s in self.stats))
 
 
-def fit(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None) -> FitResult:
+def fit(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None, probe: Probe | None = None) -> FitResult:
     """Minimise every site's g_r^reg (sec. 3.4 step 3) from (h0, J0) (zeros by default)."""
     opts = opts or FitOptions()
     if opts.autotune and not opts.single_site:
@@ -182,6 +201,19 @@ def fit(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None) -> FitRe
     _dev_tensor(w, torch.float64, dev, "w")
     _dev_tensor(beff, torch.float64, dev, "beff")
     co = opts.to_c()
+    pout = pcount = None
+    if probe is not None:
+        sites = _dev_tensor(probe.sites, torch.int32, dev, "probe.sites")
+        n = int(sites.numel())
+        _dev_tensor(probe.h_ref, torch.float32, dev, "probe.h_ref")
+        _dev_tensor(probe.J_ref, torch.float32, dev, "probe.J_ref")
+        if tuple(probe.h_ref.shape) != (n, q) or tuple(probe.J_ref.shape) != (n, N, q, q):
+            raise ValueError("probe reference shapes must be [n, q] and [n, N, q, q]")
+        pout = torch.full((int(probe.cap), 2 + n), float("nan"), dtype=torch.float64, device=dev)
+        pcount = torch.zeros(1, dtype=torch.int32, device=dev)
+        co.n_probe = n
+        co.probe_sites, co.probe_h, co.probe_J = sites.data_ptr(), probe.h_ref.data_ptr(), probe.J_ref.data_ptr()
+        co.probe_out, co.probe_count, co.probe_cap = pout.data_ptr(), pcount.data_ptr(), int(probe.cap)
     nbytes = L.lib().plm_fit_workspace_bytes(B, N, q, ctypes.byref(co))
     if nbytes == 0:
         raise L.PlmError(L.PLM_E_INVALID, "invalid sizes or options")
@@ -191,7 +223,11 @@ def fit(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None) -> FitRe
     rc = _check(L.lib().plm_fit(ctx, _ptr(msa), B, N, q, _ptr(w), _ptr(beff), ctypes.byref(co), _ptr(ws),
                                 ws.numel(), _ptr(h), _ptr(J), stats), ctx)
     del ws
-    return FitResult(h, J, _stats_list(stats), rc)
+    entries = None
+    if probe is not None:
+        cnt = int(pcount.item())
+        entries = pout[:cnt].cpu().numpy()
+    return FitResult(h, J, _stats_list(stats), rc, entries)
 
 
 def fit_symmetric(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None) -> FitResult:

@@ -23,7 +23,7 @@ __global__ void init_fit_kernel(int32_t N, int32_t q, float* Xh, float* XJ, floa
     SiteState s;
     s.phase = PH_INIT;
     s.status = PLM_SITE_MAXITER;
-    s.iter = s.evals = s.ls_count = s.head = s.stored = s.dpend = 0;
+    s.iter = s.evals = s.ls_count = s.head = s.stored = s.dpend = s.action = s.pad2 = 0;
     s.f = s.gnorm = s.alpha = s.gtd = 0.0;
     s.gamma = 1.0;
     st[r] = s;
@@ -230,5 +230,68 @@ hipError_t launch_list_tables(const BatchArgs& b, const int32_t* list, int32_t f
   return hipGetLastError();
 }
 
+
+// Convergence probe: one block per watched site computes the largest
+// |iterate - reference| over the site's fields and couplings (its self block
+// left out) into entry *count of out; then probe_finish_kernel writes the
+// entry's time (device wall clock) and the largest of those maxima and
+// advances the count.  Entries past cap are dropped.
+constexpr int kProbeThreads = 256;
+
+__global__ __launch_bounds__(kProbeThreads) void probe_site_kernel(ProbeArgs p) {
+  __shared__ float red[kProbeThreads / 64];
+  const int k = blockIdx.x;
+  const int32_t idx = *p.count;
+  if (idx >= p.cap) return;
+  const int r = p.sites[k];
+  if (r < 0 || r >= p.N) {  // not a site of the alignment
+    if (threadIdx.x == 0) p.out[(size_t)idx * (2 + p.n) + 2 + k] = __builtin_nan("");
+    return;
+  }
+  const int q = p.q;
+  const size_t qq = (size_t)q * q, Nqq = (size_t)p.N * qq;
+  const size_t self0 = (size_t)r * qq, self1 = self0 + qq;
+  float mx = 0.f;
+  for (int e = threadIdx.x; e < q; e += blockDim.x)
+    mx = fmaxf(mx, fabsf(p.Xh[(size_t)r * q + e] - p.ref_h[(size_t)k * q + e]));
+  const float* X = p.XJ + (size_t)r * Nqq;
+  const float* R = p.ref_J + (size_t)k * Nqq;
+  for (size_t e = threadIdx.x; e < Nqq; e += blockDim.x)
+    if (e < self0 || e >= self1) mx = fmaxf(mx, fabsf(X[e] - R[e]));
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = red[0];
+    for (int w = 1; w < kProbeThreads / 64; ++w) t = fmaxf(t, red[w]);
+    p.out[(size_t)idx * (2 + p.n) + 2 + k] = (double)t;
+  }
+}
+
+__global__ void probe_finish_kernel(ProbeArgs p) {
+  if (threadIdx.x != 0) return;
+  const int32_t idx = *p.count;
+  if (idx >= p.cap) return;
+  double* e = p.out + (size_t)idx * (2 + p.n);
+  double mx = 0.0;
+  bool bad = false;
+  for (int k = 0; k < p.n; ++k) {
+    bad = bad || !(e[2 + k] == e[2 + k]);
+    mx = fmax(mx, e[2 + k]);
+  }
+  if (bad) mx = __builtin_nan("");
+  e[0] = (double)wall_clock64() * p.sec_per_tick;
+  e[1] = mx;
+  *p.count = idx + 1;
+}
+
+hipError_t launch_probe(const ProbeArgs& p, hipStream_t st) {
+  if (p.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(probe_site_kernel, dim3(p.n), dim3(kProbeThreads), 0, st, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(probe_finish_kernel, dim3(1), dim3(64), 0, st, p);
+  return hipGetLastError();
+}
 
 }  // namespace plm

@@ -99,27 +99,30 @@ struct FitBufs {
   EvalBufs ev;
   float *Th, *TJ;
   double* small;
-  float *Gh, *GJ, *Dh, *DJ, *Sh, *SJ, *Yh, *YJ;
+  float *Dh, *DJ;
+  void *Gh, *GJ, *Sh, *SJ, *Yh, *YJ;  // history type: FP32, or FP64 with history_fp64
   DirCoef* dc;
-  double* dpart;
+  double *dpart, *part;
 };
 
-void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, FitBufs& f) {
+void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, int32_t hist64, FitBufs& f) {
   layout_eval(bp, B, N, q, f.ev);
   const size_t Nq = (size_t)N * q, NNqq = (size_t)N * N * q * q;
+  const size_t hb = hist64 ? 2 : 1;  // history values in floats
   f.Th = bp.take<float>(Nq);
   f.TJ = bp.take<float>(NNqq);
-  f.Gh = bp.take<float>(Nq);
-  f.GJ = bp.take<float>(NNqq);
+  f.Gh = bp.take<float>(Nq * hb);
+  f.GJ = bp.take<float>(NNqq * hb);
   f.Dh = bp.take<float>(Nq);
   f.DJ = bp.take<float>(NNqq);
-  f.Sh = bp.take<float>(Nq * (m + 1));
-  f.SJ = bp.take<float>(NNqq * (m + 1));
-  f.Yh = bp.take<float>(Nq * (m + 1));
-  f.YJ = bp.take<float>(NNqq * (m + 1));
+  f.Sh = bp.take<float>(Nq * (m + 1) * hb);
+  f.SJ = bp.take<float>(NNqq * (m + 1) * hb);
+  f.Yh = bp.take<float>(Nq * (m + 1) * hb);
+  f.YJ = bp.take<float>(NNqq * (m + 1) * hb);
   f.small = bp.take<double>((size_t)N * 2 * (m + 1) * (m + 2));
   f.dc = bp.take<DirCoef>(N);
-  f.dpart = bp.take<double>((size_t)N * kDirChunks);
+  f.dpart = bp.take<double>((size_t)N * kLbChunks);
+  f.part = bp.take<double>((size_t)N * kLbChunks * kLbPartW);
 }
 
 // device tables of a batch (BatchArgs points into them)
@@ -275,10 +278,14 @@ int32_t eval_bwd_blocks(const PathSpec& p, int32_t N, int32_t q) {
   return p.bwd_np ? mfma_backward_blocks_per_site(N, q) : backward_blocks_per_site(N);
 }
 
-// Once per alignment, before the first forward: the gradient path's symbol
-// copy (and, for the grouped gradient, the residual rows no forward tile writes).
+// Once per alignment, before the first forward: the int8 forward's packed
+// symbols, and (backward = true) the gradient path's symbol copy and, for the
+// grouped gradient, the residual rows no forward tile writes.
 hipError_t eval_prepare(const PathSpec& p, const EvalArgs& a, uint8_t* msaT, uint16_t* sorted,
-                        hipStream_t st) {
+                        hipStream_t st, bool backward = true) {
+  if (!backward)
+    return p.fwd_i8 ? launch_sym3(a.msa_cm, a.B_pad, a.N, a.NG, const_cast<uint32_t*>(a.sym3), st)
+                    : hipSuccess;
   if (p.bwd_g3 || p.bwd_i8) {
     const hipError_t e =
         launch_rfrag_tail_zero(a.R, a.N, a.B, a.B3, a.B_pad, p.bwd_i8 ? kRiChunkBytes : kRfChunkBytes, st);
@@ -465,12 +472,16 @@ size_t plm_objgrad_workspace_bytes(int32_t B, int32_t N, int32_t q, int32_t path
   return rup(bp.off, 256);
 }
 
-int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
-                const double* beff, const float* h, const float* J, double lambda_h,
-                double lambda_J, const int32_t* sites, int32_t n_sites, int32_t path, void* ws,
-                size_t ws_bytes, const double* grad_scale, double* f_out, float* gh_out,
-                float* gJ_out) {
-  if (!c) return PLM_E_INVALID;
+}  // extern "C"
+
+namespace {
+
+// plm_objgrad on the given scratch (the caller's workspace)
+int objgrad_impl(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
+                 const double* beff, const float* h, const float* J, double lambda_h,
+                 double lambda_J, const int32_t* sites, int32_t n_sites, int32_t path, void* ws,
+                 size_t ws_bytes, const double* grad_scale, double* f_out, float* gh_out,
+                 float* gJ_out) {
   if (!msa || !w || !beff || !h || !J || !f_out) return set_err(c, PLM_E_INVALID, "null pointer");
   int rc = check_sizes(c, B, N, q);
   if (rc) return rc;
@@ -502,7 +513,7 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
                              c->stream));
   HIPCHK(c, launch_list_tables(b, sites, 0, n_sites, c->pin_dev, c->stream));
   const Grids g = eval_grids(c, ps, nb);
-  if (gJ_out) HIPCHK(c, eval_prepare(ps, a, e.msaT, e.sorted, c->stream));
+  HIPCHK(c, eval_prepare(ps, a, e.msaT, e.sorted, c->stream, gJ_out != nullptr));
   HIPCHK(c, eval_forward(ps, b, nb, g, c->stream));
   if (gJ_out) HIPCHK(c, eval_backward(ps, b, g, c->stream));
   FinalArgs fa;
@@ -512,6 +523,20 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
   fa.f_out = f_out; fa.gh_out = gh_out; fa.gJ_out = gJ_out;
   HIPCHK(c, launch_objgrad_final(fa, n_sites, c->stream));
   return PLM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
+                const double* beff, const float* h, const float* J, double lambda_h,
+                double lambda_J, const int32_t* sites, int32_t n_sites, int32_t path, void* ws,
+                size_t ws_bytes, const double* grad_scale, double* f_out, float* gh_out,
+                float* gJ_out) {
+  if (!c) return PLM_E_INVALID;
+  return objgrad_impl(c, msa, B, N, q, w, beff, h, J, lambda_h, lambda_J, sites, n_sites, path, ws,
+                      ws_bytes, grad_scale, f_out, gh_out, gJ_out);
 }
 
 void plm_fit_opts_default(plm_fit_opts* o) {
@@ -531,15 +556,31 @@ void plm_fit_opts_default(plm_fit_opts* o) {
   o->site_limit = 0;
   o->timing = 0;
   o->refine = 0;
+  o->n_probe = 0;
+  o->refine_tol = 0.0;
+  o->probe_sites = nullptr;
+  o->probe_h = nullptr;
+  o->probe_J = nullptr;
+  o->probe_out = nullptr;
+  o->probe_count = nullptr;
+  o->probe_cap = 0;
+  o->history_fp64 = 0;
 }
+
+size_t plm_fit_opts_size(void) { return sizeof(plm_fit_opts); }
 
 }  // extern "C"
 
 namespace {
 
 bool fit_opts_ok(const plm_fit_opts* o) {
-  return o->lambda_h >= 0.0 && o->lambda_J >= 0.0 && o->tol >= 0.0 && o->max_iter >= 1 &&
-         o->lbfgs_m >= 1 && o->lbfgs_m <= kMMax && o->max_linesearch >= 1;
+  if (o->n_probe < 0 ||
+      (o->n_probe > 0 && (!o->probe_sites || !o->probe_h || !o->probe_J || !o->probe_out ||
+                          !o->probe_count || o->probe_cap < 1)))
+    return false;
+  return o->lambda_h >= 0.0 && o->lambda_J >= 0.0 && o->tol >= 0.0 && o->refine_tol >= 0.0 &&
+         o->max_iter >= 1 && o->lbfgs_m >= 1 && o->lbfgs_m <= kMMax && o->max_linesearch >= 1 &&
+         (o->history_fp64 == 0 || o->history_fp64 == 1);
 }
 
 // Alignments in batch order: decreasing evaluation cost B * N^2, ties by index.
@@ -561,7 +602,7 @@ size_t fit_layout(const plm_msa_desc* d, int32_t n, int32_t q, const plm_fit_opt
   for (int32_t k = 0; k < n; ++k) {
     const plm_msa_desc& m = d[ord[k]];
     FitBufs f;
-    layout_fit(bp, m.B, m.N, q, o->lbfgs_m, f);
+    layout_fit(bp, m.B, m.N, q, o->lbfgs_m, o->history_fp64, f);
     if (bufs) (*bufs)[k] = f;
     total += m.N;
   }
@@ -644,7 +685,7 @@ int prepare_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const p
     L.Xh = m.h_io; L.XJ = m.J_io; L.Th = f.Th; L.TJ = f.TJ;
     L.Gh = f.Gh; L.GJ = f.GJ; L.Dh = f.Dh; L.DJ = f.DJ;
     L.Sh = f.Sh; L.SJ = f.SJ; L.Yh = f.Yh; L.YJ = f.YJ; L.small = f.small;
-    L.dc = f.dc; L.dpart = f.dpart;
+    L.dc = f.dc; L.dpart = f.dpart; L.part = f.part;
     L.f_part = f.ev.f_part; L.gh_part = f.ev.gh_part; L.gJ = f.ev.gJ;
     L.st = t.st + base[k];
     L.phase_host = phase_host_dev + base[k];
@@ -669,7 +710,7 @@ int prepare_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const p
 
 // The fit of a batch of alignments (plm_fit is a batch of one).
 int run_fit_once(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_fit_opts* o,
-                 void* ws, size_t ws_bytes) {
+                 void* ws, size_t ws_bytes, const ProbeArgs* probe) {
   Prep P;
   int rc = prepare_fit(c, d, n, q, o, ws, ws_bytes, &P);
   if (rc) return rc;
@@ -692,7 +733,7 @@ int run_fit_once(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const 
         HIPCHK(c, launch_list_tables(b, nullptr, r, 1, nullptr, st));
         HIPCHK(c, eval_forward(ps, b, nb, g, st));
         HIPCHK(c, eval_backward(ps, b, g, st));
-        HIPCHK(c, launch_lbfgs(b, 1, st));
+        HIPCHK(c, launch_lbfgs(b, 1, o->history_fp64, st));
         HIPCHK(c, hipStreamSynchronize(st));
         if (phase_host[r] == PH_DONE) break;
       }
@@ -710,9 +751,10 @@ int run_fit_once(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const 
       if (e == hipSuccess) e = mark(1);
       if (e == hipSuccess) e = eval_backward(ps, b, g, st);
       if (e == hipSuccess) e = mark(2);
-      if (e == hipSuccess) e = launch_lbfgs(b, total, st);
+      if (e == hipSuccess) e = launch_lbfgs(b, total, o->history_fp64, st);
       if (e == hipSuccess) e = mark(3);
       if (e == hipSuccess) e = launch_compact(b, t.st, c->pin_dev + 1, t.site_evals, st);
+      if (e == hipSuccess && probe) e = launch_probe(*probe, st);
       return e;
     };
     plm_fit_timing tm;
@@ -799,7 +841,11 @@ int run_fit_once(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const 
 
 // the refinement path of plm_fit_opts.refine, or -1
 int32_t refine_path(const plm_fit_opts* o) {
-  if (o->refine == 0) return o->path == PLM_PATH_MFMA_I8X3 ? PLM_PATH_GATHER_MFMA_I8X3 : -1;
+  if (o->refine == 0) {
+    if (o->path == PLM_PATH_MFMA_I8X3) return PLM_PATH_GATHER_MFMA_I8X3;
+    if (o->path == PLM_PATH_MFMA_BF16X2) return PLM_PATH_MFMA_FP32;
+    return -1;
+  }
   if (o->refine < 0) return -1;
   const int32_t p = o->refine - 1;
   return p == o->path ? -1 : p;
@@ -812,7 +858,27 @@ int run_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_f
   const int32_t rp = refine_path(o);
   if (rp >= 0 && (rp < PLM_PATH_GATHER_FP32 || rp > PLM_PATH_MFMA_I8X3))
     return set_err(c, PLM_E_INVALID, "refine: unknown path %d", rp);
-  int rc = run_fit_once(c, d, n, q, o, ws, ws_bytes);
+  if (!fit_opts_ok(o)) return set_err(c, PLM_E_INVALID, "invalid fit options");
+  ProbeArgs pa;
+  const ProbeArgs* probe = nullptr;
+  if (o->n_probe > 0) {
+    if (n != 1 || o->single_site)
+      return set_err(c, PLM_E_INVALID, "the convergence probe watches a single alignment's batched fit");
+    int khz = 0;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device));
+    if (khz <= 0) return set_err(c, PLM_E_UNSUPPORTED, "device wall clock rate unknown");
+    pa.N = d[0].N; pa.q = q; pa.n = o->n_probe; pa.cap = o->probe_cap;
+    pa.Xh = d[0].h_io; pa.XJ = d[0].J_io;
+    pa.sites = o->probe_sites; pa.ref_h = o->probe_h; pa.ref_J = o->probe_J;
+    pa.out = o->probe_out; pa.count = o->probe_count;
+    pa.sec_per_tick = 1.0 / (1e3 * (double)khz);
+    probe = &pa;
+    // the first entry: the start point, once the caller's stream has delivered it
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, launch_probe(pa, c->fit_stream));
+  }
+  int rc = run_fit_once(c, d, n, q, o, ws, ws_bytes, probe);
   if (rp < 0 || (rc != PLM_OK && rc != PLM_W_MAXITER)) return rc;
   std::vector<std::vector<plm_site_stats>> first(n);
   for (int32_t k = 0; k < n; ++k)
@@ -822,7 +888,8 @@ int run_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_f
   o2.path = rp;
   o2.refine = -1;
   o2.tile_seqs = 0;
-  const int rc2 = run_fit_once(c, d, n, q, &o2, ws, ws_bytes);
+  if (o->refine_tol > 0.0) o2.tol = o->refine_tol;
+  const int rc2 = run_fit_once(c, d, n, q, &o2, ws, ws_bytes, probe);
   if (rc2 != PLM_OK && rc2 != PLM_W_MAXITER) return rc2;
   for (int32_t k = 0; k < n; ++k)
     if (d[k].stats_out)

@@ -47,7 +47,9 @@ struct SiteState {
   int32_t ls_count;
   int32_t head;
   int32_t stored;
-  int32_t dpend;       // 1: a quasi-Newton direction is pending (DirCoef, direction kernels)
+  int32_t dpend;       // direction pending for the direction kernels: 1 quasi-Newton (DirCoef), 2 steepest
+  int32_t action;      // what the update pass does with the decision just taken
+  int32_t pad2;
   double f;            // normalised objective at the current point
   double gnorm;
   double alpha;        // step of the pending trial point
@@ -60,7 +62,8 @@ enum { PH_INIT = 0, PH_LS = 1, PH_DONE = 2 };
 // The quasi-Newton direction d = -gamma g + sum_i (cs_i s_i + cy_i y_i) of
 // one site, over its stored pairs in chronological order (slots ord), as
 // computed by the L-BFGS step and formed by the direction kernels.
-constexpr int kDirChunks = 32;  // blocks per site that form the direction
+constexpr int kLbChunks = 32;   // blocks per site of the optimiser's passes over a site's parameters
+constexpr int kLbPartW = 4 + 2 * kMMax;  // FP64 partial sums per (site, block)
 struct DirCoef {
   int32_t n;
   int32_t pad;
@@ -130,17 +133,18 @@ struct LbfgsArgs {
   float* XJ;
   float* Th;
   float* TJ;
-  float* Gh;   // gradient at the iterate, FP32 (y = g - G; rounding far below the evaluation's noise)
-  float* GJ;
+  void* Gh;    // gradient at the iterate, FP32 or FP64 (the history type)
+  void* GJ;
   float* Dh;   // search direction, FP32 (the step along it is rounded to FP32 anyway)
   float* DJ;
-  float* Sh;   // [m+1][N][q] history slots (one spare for the candidate pair), FP32
-  float* SJ;   // [m+1][N][N q q]
-  float* Yh;
-  float* YJ;
+  void* Sh;    // [m+1][N][q] history slots (one spare for the candidate pair), FP32 or FP64
+  void* SJ;    // [m+1][N][N q q]
+  void* Yh;
+  void* YJ;
   double* small;  // per site: [m+1][m+1] S^T Y, [m+1][m+1] Y^T Y, [m+1] S^T G, [m+1] Y^T G by slot
   DirCoef* dc;    // per site: the pending direction's coefficients
-  double* dpart;  // per site: [kDirChunks] partial sums of d . g
+  double* dpart;  // per site: [kLbChunks] partial sums of d . g
+  double* part;   // per site: [kLbChunks][kLbPartW] partial sums of the passes
   const double* f_part;   // [tiles][N]
   const double* gh_part;  // [tiles][N][21]
   const double* gJ;       // [N][N][q][q] data part
@@ -343,6 +347,20 @@ struct SymArgs {
   int32_t* done_host;
 };
 
+// Convergence probe of plm_fit (plm_fit_opts.n_probe): the iterate of the
+// watched sites against reference values, one entry per call.
+struct ProbeArgs {
+  int32_t N, q, n, cap;
+  const float* Xh;      // iterate [N][q], [N][N][q][q]
+  const float* XJ;
+  const int32_t* sites;  // [n]
+  const float* ref_h;   // [n][q]
+  const float* ref_J;   // [n][N][q][q]
+  double* out;          // [cap][2 + n]: time (s), max over sites, per site
+  int32_t* count;
+  double sec_per_tick;  // of wall_clock64()
+};
+
 // Options of the pair scores (PLM_COMBINE_*, PLM_NORM_*, PLM_CORR_*).
 struct ScoreOpts {
   int32_t combine, norm;
@@ -409,7 +427,7 @@ hipError_t launch_backward_i8(const BatchArgs& b, int32_t nblocks, hipStream_t s
 hipError_t launch_forward_mfma(const BatchArgs& b, int32_t npieces, int32_t nblocks, hipStream_t st);
 hipError_t launch_backward_mfma(const BatchArgs& b, int32_t npieces, int32_t f16, int32_t nblocks,
                                 hipStream_t st);
-hipError_t launch_lbfgs(const BatchArgs& b, int32_t nblocks, hipStream_t st);
+hipError_t launch_lbfgs(const BatchArgs& b, int32_t nblocks, int32_t history_fp64, hipStream_t st);
 hipError_t launch_compact(const BatchArgs& b, const SiteState* st_, int32_t* host_count,
                           unsigned long long* site_evals, hipStream_t st);
 hipError_t launch_list_tables(const BatchArgs& b, const int32_t* list, int32_t first, int32_t n,
@@ -445,6 +463,7 @@ hipError_t launch_frequencies(const uint8_t* msa, int32_t B, int32_t N, int32_t 
                               const double* beff, double* f, hipStream_t st);
 hipError_t launch_objgrad_final(const FinalArgs& a, int32_t nsites, hipStream_t st);
 hipError_t launch_check_f32(const float* p, size_t n, int32_t* flag, hipStream_t st);
+hipError_t launch_probe(const ProbeArgs& p, hipStream_t st);
 hipError_t launch_check_f64(const double* p, size_t n, int32_t* flag, hipStream_t st);
 
 }  // namespace plm

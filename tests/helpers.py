@@ -1,6 +1,6 @@
-"""Shared test helpers: seeded input construction and fixture loading.
-
-Nothing here computes any part of the method; inputs only."""
+"""Shared test helpers: seeded input construction, fixture loading, and the
+error bounds the reduced-precision paths are held to (derived from their
+arithmetic).  Nothing here computes any part of the method itself."""
 from __future__ import annotations
 
 import numpy as np
@@ -69,3 +69,44 @@ def weighted_frequencies(msa, w, q):
     fi = np.einsum("b,bik->ik", w, oh) / beff
     fij = np.einsum("b,bik,bjl->ijkl", w, oh, oh) / beff
     return fi, fij
+
+
+def hilo_bounds(msa, h, J, sites):
+    """Error bounds of the two-piece (hi/lo BF16) path, from its arithmetic.
+
+    hi + lo represents each coupling and residual to 16 significant bits, so
+    |dJ| <= 2^-16 |J| and |dR| <= 2^-16 |R| <= 2^-16 w_b.  An energy then moves
+    by at most eps_E = 2^-16 max_b sum_i max_s |J_ri(s, sigma_i^b)|; the
+    log-partition function by at most eps_E, each probability by a factor
+    exp(+-2 eps_E).  Hence, on the B_eff-normalised scale,
+    |dg| <= 2 eps_E + 2^-16 per gradient entry and |df| <= 2 eps_E.  The FP32
+    accumulation bounds of the other paths are added on top."""
+    u = 2.0 ** -16
+    Jf = np.abs(J.astype(np.float32).astype(np.float64))
+    epsE = 0.0
+    for r in sites:
+        # max over s of |J_ri(s, k)|, indexed by (i, k): layout [i][k][s]
+        mx = Jf[r].max(axis=2)
+        mx[r] = 0
+        per_b = mx[np.arange(msa.shape[1])[None, :], msa.astype(np.int64)].sum(axis=1)
+        epsE = max(epsE, u * float(per_b.max()))
+    return 2 * epsE, 2 * epsE + u
+
+
+def fixed_point_bounds(msa, w, beff, J, sites):
+    """Error bounds of the int8 fixed-point path (6), from its arithmetic.
+
+    Each site's couplings are scaled by 2^k_r with max|J_r| 2^k_r in
+    [2^21, 2^22) and rounded, so |dJ| <= 2^-22 max_{i != r} |J_r|; an energy
+    moves by at most eps_E = (N - 1) 2^-22 max|J_r|, log Z by at most eps_E and
+    each probability by a factor exp(+-2 eps_E): |df| <= 2 eps_E per weighted
+    sequence.  The residuals are rounded to 2^-23 absolute (|R| <= w_b <= 1) and
+    accumulated exactly, so a normalised gradient entry moves by at most
+    2 eps_E + 2^-23 B / B_eff.  FP32 rounding of the softmax comes on top."""
+    N = msa.shape[1]
+    eps = 0.0
+    for r in sites:
+        Jr = np.abs(J[r].astype(np.float32).astype(np.float64))
+        Jr[r] = 0
+        eps = max(eps, (N - 1) * 2.0 ** -22 * float(Jr.max()))
+    return 2 * eps, 2 * eps + 2.0 ** -23 * msa.shape[0] / beff

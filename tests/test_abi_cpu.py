@@ -68,3 +68,11 @@ def test_workspace_sizes_are_host_computable(lib):
 def test_null_context_is_rejected(lib):
     assert lib.plm_sync(None) == -1
     assert lib.plm_score(None, None, 10, 21, None, None) == -1
+
+
+def test_fit_options_layout_matches_the_library(lib):
+    from paper_1401_4832_amd import _lib
+    assert lib.plm_fit_opts_size() == ctypes.sizeof(_lib.FitOpts)
+    o = _lib.FitOpts()
+    lib.plm_fit_opts_default(ctypes.byref(o))
+    assert o.refine_tol == 0.0 and o.n_probe == 0 and o.history_fp64 == 0 and not o.probe_out

@@ -6,6 +6,8 @@ alone (same kernels and per-item arithmetic; the forward tile size is fixed
 so that both use the same tiles), and sampled sites must meet the fit bar of
 the single-alignment tests against the FP64 oracle (couplings within 1e-4,
 strong-convexity certificate)."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -53,7 +55,7 @@ def test_batch_equals_single_alignment_fits(plm, ragged, path):
 def test_batch_sampled_sites_match_oracle(plm, ragged):
     print("[case] batch vs oracle on sampled sites", flush=True)
     items = [_prep(plm, s) for s in ragged]
-    opts = plm.FitOptions(tol=1e-6, path=2)
+    opts = plm.FitOptions(tol=0.9e-6, path=2)
     res = plm.fit_batch(items, opts)
     mu = 2 * min(opts.lambda_h, 0.5 * opts.lambda_J)
     for k in (0, 3):
@@ -69,7 +71,7 @@ def test_batch_sampled_sites_match_oracle(plm, ragged):
             assert err <= 1e-4, (k, r, err)
             f, gh, gJ = oracle.site_objgrad(s.msa, r, w_o, beff_o, h[r], J[r], opts.lambda_h, opts.lambda_J)
             gn = np.sqrt(np.sum(gh ** 2) + np.sum(gJ ** 2)) / beff_o
-            assert gn / mu <= 1e-3, (k, r, gn)
+            assert gn / mu <= 1e-4, (k, r, gn)
 
 
 def test_batch_of_one_and_errors(plm, ragged):
@@ -100,3 +102,61 @@ def test_tuner_times_every_candidate_and_autotuned_fit_converges(plm, ragged, tm
     assert all(x["status"] == "converged" for r in out for x in r.stats)
     ch = plm.autotune.choose(items)  # now cached
     assert (ch["path"], ch["tile_seqs"]) in [(r["path"], r["tile_seqs"]) for r in res]
+
+
+@pytest.mark.timeout(420)
+def test_ragged16_configured_sizes(plm):
+    """The 16-alignment ragged batch at its configured sizes (N in [60, 300],
+    B in [2000, 30000], seeds 400 + k) on the autotuned schedule, as the
+    benchmark runs it: every alignment's weights bit for bit against the
+    oracle's stored ones; every site converges; on two sampled sites per
+    alignment the oracle's FP64 gradient at the returned point is at most
+    1e-6 (so, by strong convexity, within 1e-4 of the minimiser); and the
+    main fit of the batch equals each alignment's own fit, bit for bit, for
+    the smallest, the middle and the largest alignment."""
+    print("[case] ragged16 at configured sizes", flush=True)
+    sets = synth.ragged_set(16)
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ragged16_reweight.npz"),
+                allow_pickle=False)
+    assert [str(x) for x in g["digest"]] == [synth.msa_digest(a.msa) for a in sets]
+    items, gold = [], []
+    off = 0
+    for k, a in enumerate(sets):
+        msa = torch.from_numpy(a.msa).to(DEV)
+        m, w, beff = plm.reweight(msa, theta=0.8)
+        plm.sync(DEV)
+        m_o, w_o = g["m"][off:off + a.B], g["w"][off:off + a.B]
+        off += a.B
+        assert np.array_equal(m.cpu().numpy(), m_o), k
+        assert np.array_equal(w.cpu().numpy(), w_o), k
+        assert float(beff.item()) == float(g["beff"][k]), k
+        items.append((msa, w, beff))
+        gold.append((w_o, float(g["beff"][k])))
+    ch = plm.autotune.choose(items, plm.FitOptions())
+    print(f"  schedule: path {ch['path']} tile {ch['tile_seqs']}", flush=True)
+    opts = plm.FitOptions(tol=1e-6, refine_tol=0.9e-6, path=int(ch["path"]), tile_seqs=int(ch["tile_seqs"]))
+    res = plm.fit_batch(items, opts)
+    mu = 2 * min(opts.lambda_h, 0.5 * opts.lambda_J)
+    worst = 0.0
+    for k, (a, r) in enumerate(zip(sets, res)):
+        assert all(x["status"] == "converged" for x in r.stats), k
+        sites = synth.sample_sites(400 + k, a.N, 2)
+        h = r.h.cpu().numpy().astype(np.float64)
+        J = r.J.cpu().numpy().astype(np.float64)
+        w_o, beff_o = gold[k]
+        _, gh, gJ = oracle.objgrad_slices(a.msa, w_o, beff_o, h[sites], J[sites], sites)
+        for t, site in enumerate(sites):
+            gn = np.sqrt(np.sum(gh[t] ** 2) + np.sum(gJ[t] ** 2)) / beff_o
+            worst = max(worst, gn)
+            assert gn <= 1e-6 and gn / mu <= 1e-4, (k, site, gn)
+    print(f"  largest FP64 gradient norm on the sampled sites {worst:.2e}", flush=True)
+    # batch = single alignment, main fit (its forward tile does not depend on the batch)
+    o1 = plm.FitOptions(tol=1e-6, path=int(ch["path"]), tile_seqs=int(ch["tile_seqs"]), refine=-1)
+    one_batch = plm.fit_batch(items, o1)
+    cost = [a.B * a.N * a.N for a in sets]
+    order = np.argsort(cost)
+    for k in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        msa, w, beff = items[k]
+        one = plm.fit(msa, w, beff, o1)
+        assert torch.equal(one.h, one_batch[k].h) and torch.equal(one.J, one_batch[k].J), k
+        assert [x["evaluations"] for x in one.stats] == [x["evaluations"] for x in one_batch[k].stats], k

@@ -15,7 +15,7 @@ import torch
 
 import oracle
 import synth
-from tests.helpers import clustered_msa, load_reweight_golden, random_params
+from tests.helpers import clustered_msa, fixed_point_bounds, hilo_bounds, load_reweight_golden, random_params
 
 pytestmark = pytest.mark.gpu
 
@@ -114,28 +114,6 @@ def _objgrad_case(plm, msa, w_o, beff_o, h, J, lh=0.01, lJ=0.01, sites=None, pat
     return frel, gerr, gJ
 
 
-def _hilo_bounds(msa, h, J, sites):
-    """Error bounds of the two-piece (hi/lo BF16) path, from its arithmetic.
-
-    hi + lo represents each coupling and residual to 16 significant bits, so
-    |dJ| <= 2^-16 |J| and |dR| <= 2^-16 |R| <= 2^-16 w_b.  An energy then moves
-    by at most eps_E = 2^-16 max_b sum_i max_s |J_ri(s, sigma_i^b)|; the
-    log-partition function by at most eps_E, each probability by a factor
-    exp(+-2 eps_E).  Hence, on the B_eff-normalised scale,
-    |dg| <= 2 eps_E + 2^-16 per gradient entry and |df| <= 2 eps_E.  The FP32
-    accumulation bounds of the other paths are added on top."""
-    u = 2.0 ** -16
-    Jf = np.abs(J.astype(np.float32).astype(np.float64))
-    epsE = 0.0
-    for r in sites:
-        # max over s of |J_ri(s, k)|, indexed by (i, k): layout [i][k][s]
-        mx = Jf[r].max(axis=2)
-        mx[r] = 0
-        per_b = mx[np.arange(msa.shape[1])[None, :], msa.astype(np.int64)].sum(axis=1)
-        epsE = max(epsE, u * float(per_b.max()))
-    return 2 * epsE, 2 * epsE + u
-
-
 @pytest.mark.parametrize("B,N,q", [(500, 40, 21), (7, 17, 21), (3001, 33, 21), (1537, 49, 11), (700, 97, 21)])
 def test_objgrad_hilo_path_within_derived_bound(plm, B, N, q):
     _note(f"objgrad hi/lo B={B} N={N} q={q}")
@@ -144,32 +122,13 @@ def test_objgrad_hilo_path_within_derived_bound(plm, B, N, q):
     w_o = rng.uniform(0.2, 1.0, size=B)
     beff_o = float(np.sum(w_o))
     h, J = random_params(B + q, N, q, 0.3, 0.2)
-    fb, gb = _hilo_bounds(msa, h, J, range(N))
+    fb, gb = hilo_bounds(msa, h, J, range(N))
     ferr, gerr, gJ = _objgrad_case(plm, msa, w_o, beff_o, h, J, path=1, fabs=True)
     print(f"  hi/lo errors: f {ferr:.2e} (bound {fb:.2e}), grad {gerr:.2e} (bound {gb:.2e})")
     assert gerr <= gb + 2e-6, (gerr, gb)
     assert ferr <= fb + 1e-5 * np.log(q) * 10, (ferr, fb)
     for r in range(N):
         assert np.all(gJ[r, r] == 0)
-
-
-def _fixed_point_bounds(msa, w, beff, J, sites):
-    """Error bounds of the int8 fixed-point path (6), from its arithmetic.
-
-    Each site's couplings are scaled by 2^k_r with max|J_r| 2^k_r in
-    [2^21, 2^22) and rounded, so |dJ| <= 2^-22 max_{i != r} |J_r|; an energy
-    moves by at most eps_E = (N - 1) 2^-22 max|J_r|, log Z by at most eps_E and
-    each probability by a factor exp(+-2 eps_E): |df| <= 2 eps_E per weighted
-    sequence.  The residuals are rounded to 2^-23 absolute (|R| <= w_b <= 1) and
-    accumulated exactly, so a normalised gradient entry moves by at most
-    2 eps_E + 2^-23 B / B_eff.  FP32 rounding of the softmax comes on top."""
-    N = msa.shape[1]
-    eps = 0.0
-    for r in sites:
-        Jr = np.abs(J[r].astype(np.float32).astype(np.float64))
-        Jr[r] = 0
-        eps = max(eps, (N - 1) * 2.0 ** -22 * float(Jr.max()))
-    return 2 * eps, 2 * eps + 2.0 ** -23 * msa.shape[0] / beff
 
 
 @pytest.mark.parametrize("B,N,q,sd", [(700, 97, 21, 1.0), (3001, 33, 21, 2.0), (1537, 49, 11, 0.5), (400, 200, 21, 0.8)])
@@ -180,7 +139,7 @@ def test_objgrad_fixed_point_path_within_derived_bound(plm, B, N, q, sd):
     w_o = rng.uniform(0.2, 1.0, size=B)
     beff_o = float(np.sum(w_o))
     h, J = random_params(B + 2 * q, N, q, 0.3, sd)
-    fb, gb = _fixed_point_bounds(msa, w_o, beff_o, J, range(N))
+    fb, gb = fixed_point_bounds(msa, w_o, beff_o, J, range(N))
     ferr, gerr, gJ = _objgrad_case(plm, msa, w_o, beff_o, h, J, path=6, fabs=True)
     print(f"  int8 errors: f {ferr:.2e} (bound {fb:.2e}), grad {gerr:.2e} (bound {gb:.2e})")
     # the FP32 parts (softmax, residuals before rounding) add at most the FP32 tolerance
@@ -215,6 +174,70 @@ def test_objgrad_workload_gapped(plm, path):
     h, J = random_params(3, s.N, 21, 0.1, 0.1)
     frel, gerr, _ = _objgrad_case(plm, s.msa, w_o, beff_o, h, J, sites=[0, 5, 60, 119], path=path)
     assert frel <= 1e-5 and gerr <= 2e-6, (frel, gerr)
+
+
+@pytest.mark.parametrize("path", PATHS + [1])
+def test_objgrad_ignores_self_blocks(plm, path):
+    """The self blocks J[r][r] take no part in any result (eq. condpfinal sums
+    over i != r): large finite values there give exactly the results of zero
+    self blocks, and the gradient's self blocks are zero."""
+    _note(f"objgrad with garbage self blocks path={path}")
+    B, N, q = 1300, 27, 21
+    rng = np.random.default_rng(77)
+    msa = rng.integers(0, q, size=(B, N), dtype=np.uint8)
+    w = _to(rng.uniform(0.2, 1.0, size=B))
+    beff = _to(np.array([float(w.sum().item())]))
+    h, J = random_params(78, N, q, 0.3, 0.2)
+    Jg = J.astype(np.float32).copy()
+    for r in range(N):
+        Jg[r, r] = (1e4 * rng.standard_normal((q, q))).astype(np.float32)
+    ht = _to(h.astype(np.float32))
+    a = plm.objgrad(_to(msa), w, beff, ht, _to(J.astype(np.float32)), path=path)
+    b = plm.objgrad(_to(msa), w, beff, ht, _to(Jg), path=path)
+    plm.sync(DEV)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2])
+    for r in range(N):
+        assert torch.all(b[2][r, r] == 0)
+
+
+def test_fit_ignores_start_point_self_blocks(plm):
+    """A start point with garbage self blocks gives the fit of zero self
+    blocks, bit for bit, with zero self blocks returned."""
+    _note("fit with garbage self blocks in the start point")
+    s = synth.make_msa("sb", N=14, B=700, npairs=8, seed=34, cache=False, burnin=100, thin=2)
+    msa = _to(s.msa)
+    m, w, beff = plm.reweight(msa, theta=0.8)
+    N, q = 14, 21
+    J0 = torch.zeros(N, N, q, q, dtype=torch.float32, device=DEV)
+    Jg = J0.clone()
+    for r in range(N):
+        Jg[r, r] = 1e4 * torch.randn(q, q, device=DEV, generator=None)
+    h0 = torch.zeros(N, q, dtype=torch.float32, device=DEV)
+    a = plm.fit(msa, w, beff, plm.FitOptions(tol=1e-6), h0=h0, J0=J0)
+    b = plm.fit(msa, w, beff, plm.FitOptions(tol=1e-6), h0=h0, J0=Jg)
+    assert torch.equal(a.J, b.J) and torch.equal(a.h, b.h)
+    for r in range(N):
+        assert torch.all(b.J[r, r] == 0)
+
+
+@pytest.mark.parametrize("path", PATHS + [1])
+def test_objgrad_without_gradient_gives_the_same_objective(plm, path):
+    """With the gradient outputs absent only the forward runs; its objective is
+    the one of the full evaluation, bit for bit (the forward's own set-up, such
+    as the int8 path's packed symbols, runs either way)."""
+    _note(f"objgrad without gradient path={path}")
+    B, N, q = 2100, 31, 21
+    rng = np.random.default_rng(91)
+    msa = rng.integers(0, q, size=(B, N), dtype=np.uint8)
+    w = _to(rng.uniform(0.2, 1.0, size=B))
+    beff = _to(np.array([float(w.sum().item())]))
+    h, J = random_params(92, N, q, 0.3, 0.2)
+    ht, Jt = _to(h.astype(np.float32)), _to(J.astype(np.float32))
+    full = plm.objgrad(_to(msa), w, beff, ht, Jt, path=path)
+    fonly, gh, gJ = plm.objgrad(_to(msa), w, beff, ht, Jt, path=path, grad=False)
+    plm.sync(DEV)
+    assert gh is None and gJ is None
+    assert torch.equal(full[0], fonly)
 
 
 def test_objgrad_at_origin_is_beff_log_q(plm):
