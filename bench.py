@@ -2,8 +2,11 @@
 
 One step = reweighting (0.8 identity) + the all-sites batched L-BFGS fit to
 ||grad g_r^reg||_2 <= 1e-6 (every per-site objective+gradient evaluation on the
-GPU) + Ising-gauge/FN/APC scoring, on a seeded synthetic planted-Potts
-alignment of N = 500 columns and B = 50000 rows (q = 21), resident in HBM.
+GPU; a fit on a reduced-precision path is refined on an FP32-class path to
+0.9e-6, so that the FP64 gradient at the returned point is within 1e-6) +
+Ising-gauge/FN/APC scoring, on a seeded synthetic planted-Potts alignment of
+N = 500 columns and B = 50000 rows (q = 21), resident in HBM.  The timed
+steps run the fit as shipped: one captured graph replayed per iteration.
 `--workload ragged16` runs the ragged batch instead: 16 alignments with N in
 [60, 300] and B in [2000, 30000], fitted together by plm_fit_batch.
 `--method symmetric` fits the symmetric pseudolikelihood instead (one
@@ -14,15 +17,21 @@ the timed step) instead of the origin.
 metric: objective+gradient updates per second, one update being one
 (site r, sequence b, column i, state s) term of the energy sums -- B*N*q per
 site evaluation, B*N^2*q per evaluation of every site; converged sites are
-not counted.  Also reported: time to fit, the same fit on the plain
-single-site GPU path (one site per launch, eager, host sync every iteration;
-sampled and extrapolated), per-kernel roofline of the dominant kernel, and the
-FP64 CPU oracle on a bounded sample of the same evaluations.
+not counted.  Also reported:
+  * time to fit: the step's wall time, and (N = 500 workload) the time from
+    the fit's start until every one of eight sampled sites is within 1e-4
+    (max-abs over its fields and couplings) of the FP64 oracle's minimiser,
+    read from the library's on-device convergence probe (device wall clock
+    after every iteration) against the oracle minimisers stored under
+    tests/golden;
+  * the same fit on the plain single-site GPU path (one site per launch,
+    eager, host sync every iteration; sampled and extrapolated);
+  * the roofline of the dominant kernel, from a separate fit with HIP events
+    between the kernels on the fit's stream (the per-kernel breakdown);
+  * the FP64 CPU oracle on a bounded sample of the same work.
 
 The evaluation schedule (path, forward tile) is the autotuner's choice for
 the workload, timed on the device before the warm-up (--path to force one).
-A fit on the int8 fixed-point path (6) ends with the library's refinement fit
-on path 5 (inside the timed step; its evaluations are counted and reported).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload W] [--path auto|0..6]
                        [--method asymmetric|symmetric] [--init zero|mf]
@@ -32,6 +41,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -39,7 +49,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 Q = 21
-# one FP32 add per lane per clock: 256 CUs x 64 lanes x 2.4 GHz
+# one non-packed FP32 add per lane per clock: 256 CUs x 64 lanes x 2.4 GHz =
+# 39.3 T adds/s (the published 157.3 TFLOP/s FP32 peak counts packed FMAs:
+# 2 operations x 2 packed lanes on top of this)
 ALU_ADD_PEAK = 256 * 64 * 2.4e9
 # dense BF16 matrix-core peak of the MI355X
 MFMA_BF16_PEAK = 2.5e15
@@ -47,10 +59,18 @@ MFMA_BF16_PEAK = 2.5e15
 MFMA_I8_PEAK = 5.0e15
 PATH_NAMES = {0: "gather_fp32", 1: "mfma_bf16x2", 2: "gather_mfma_fp32", 3: "mfma_fp32",
               4: "gather_mfma_f16x2", 5: "gather_mfma_i8x3", 6: "mfma_i8x3"}
-# 16-bit pieces of the non-one-hot operand, per path: (forward, backward); 0 = LDS gather/scatter
+# 16-bit pieces (or int8 digits) of the non-one-hot operand, per path: (forward, backward); 0 = LDS gather/scatter
 PATH_PIECES = {0: (0, 0), 1: (2, 2), 2: (0, 3), 3: (3, 3), 4: (0, 2), 5: (0, 3), 6: (3, 3)}
 # the int8 matrix-core kernels (path, direction)
 INT8_KERNELS = {(5, "backward"), (6, "backward"), (6, "forward")}
+# reduced-precision first paths and the FP32-class path the library refines them on
+REFINED = {6: 5, 1: 3}
+FIT_TOL_FINAL = 0.9e-6
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -70,29 +90,88 @@ def measured_traffic(kernel: str, workload: str):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(s, w_np, beff, budget_s=12.0):
-    """The FP64 oracle (as it stands) on a bounded sample of the same site
-    evaluations: rounds of one site per host thread, at the origin, until
-    about budget_s seconds of CPU work have run."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(s, w_np, beff):
+    """The FP64 oracle as it stands, on the host, on bounded samples:
+    * site objective+gradient evaluations of the benchmark alignment at a seeded
+      point, one site on 1 thread and one site per thread on all threads, each
+      the median of 3 runs, with the full evaluation and the full fit
+      extrapolated from them (labelled);
+    * time to fit (oracle L-BFGS to 1e-6) of the small (N = 40, all sites),
+      N = 120 and N = 150 alignments: reweighting measured, and a round of
+      sampled sites fitted one per thread, extrapolated to all sites."""
     import numpy as np
 
     import oracle
+    import synth
     threads = oracle._threads()
-    hr = np.zeros((threads, Q))
-    Jr = np.zeros((threads, s.N, Q, Q))
-    done = 0
-    t = time.perf_counter()
-    while True:
-        sites = (np.arange(threads, dtype=np.int32) + done) % s.N
-        oracle.objgrad_slices(s.msa, w_np, beff, hr, Jr, sites, nthreads=threads)
-        done += threads
-        dt = time.perf_counter() - t
-        if dt >= budget_s:
-            break
-    units = done * s.B * s.N * Q
-    return {"value": units / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} site objective+gradient evaluations ({threads} threads, one site per "
-                      f"thread per round) of the N={s.N}, B={s.B} alignment at h=J=0, FP64, {dt:.1f} s"}
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except Exception:  # pragma: no cover
+        affinity = os.cpu_count() or 1
+    rng = np.random.default_rng(77)
+    N, B = s.N, s.B
+    nmax = threads
+    hr = 0.1 * rng.standard_normal((nmax, Q))
+    Jr = 0.1 * rng.standard_normal((nmax, N, Q, Q))
+    sites = np.array(synth.sample_sites(9, N, nmax), dtype=np.int32)
+    for t, r in enumerate(sites):
+        Jr[t, r] = 0.0
+
+    def timed(k, nth):
+        t = time.perf_counter()
+        oracle.objgrad_slices(s.msa, w_np, beff, hr[:k], Jr[:k], sites[:k], nthreads=nth)
+        return time.perf_counter() - t
+
+    one = statistics.median(timed(1, 1) for _ in range(3))
+    allt = statistics.median(timed(threads, threads) for _ in range(3))
+    units_site = B * N * Q
+    out = {"value": threads * units_site / allt, "unit": "updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"site objective+gradient evaluations of the N={N}, B={B} alignment at a seeded point "
+                     f"(FP64): {threads} sites, one per thread, median of 3 runs ({allt:.2f} s each); "
+                     f"1 thread: one site, median of 3 ({one:.2f} s)",
+           "value_1_thread": units_site / one,
+           "nproc": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": cpu_model(),
+           "full_evaluation_s_extrapolated": one * N / threads}
+    gold = os.path.join(GOLDEN, f"{s.name}_sites.npz")
+    if os.path.exists(gold):
+        g = np.load(gold, allow_pickle=False)
+        ev = float(np.mean(g["evaluations"]))
+        out["time_to_fit_s_extrapolated"] = ev * one * N / threads
+        out["time_to_fit_note"] = (f"extrapolated: {ev:.0f} oracle evaluations per site fit to 1e-8 (the stored "
+                                   f"oracle fits of 8 sampled sites) x {one:.2f} s per site evaluation x "
+                                   f"{N} sites / {threads} threads")
+    fits = {}
+    for name in ("potts_n40_b500", "potts_n120_b5000_gaps", "potts_n150_b8000"):
+        a = synth.workload(name)
+        t = time.perf_counter()
+        m, w, bf = oracle.reweight(a.msa, theta=0.8, uniform=a.uniform_weights, nthreads=threads)
+        t_rw = time.perf_counter() - t
+        if a.N <= 64:
+            samp = list(range(a.N))
+        else:
+            samp = synth.sample_sites(11, a.N, min(4, threads))
+        t = time.perf_counter()
+        _, _, st = oracle.fit(a.msa, w, bf, sites=samp, tol=1e-6, nthreads=threads)
+        t_fit = time.perf_counter() - t
+        rounds = -(-a.N // threads) if len(samp) < a.N else 1
+        fits[name] = {"reweight_s": t_rw, "sites_fitted": len(samp), "fit_s_measured": t_fit,
+                      "evaluations_per_site": float(np.mean([x["evaluations"] for x in st])),
+                      "time_to_fit_s": t_rw + t_fit * rounds,
+                      "extrapolated": len(samp) < a.N}
+    out["time_to_fit_small"] = fits
+    return out
 
 
 def load_sets(name: str):
@@ -114,9 +193,12 @@ def main():
     ap.add_argument("--init", default="zero", choices=("zero", "mf"))
     ap.add_argument("--pseudocount", type=float, default=0.5)
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--refine-tol", type=float, default=FIT_TOL_FINAL)
+    ap.add_argument("--history-fp64", action="store_true")
     ap.add_argument("--plain-sites", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -130,6 +212,7 @@ def main():
     import torch
 
     import paper_1401_4832_amd as plm
+    import synth
 
     dev = torch.device("cuda:0")
     sets = load_sets(args.workload)
@@ -142,8 +225,7 @@ def main():
     if symmetric and ragged:
         print("--method symmetric takes a single alignment", file=sys.stderr)
         sys.exit(2)
-    print(f"[bench] workload {args.workload}: " + ", ".join(f"N={s.N} B={s.B}" for s in sets),
-          file=sys.stderr, flush=True)
+    log(f"workload {args.workload}: " + ", ".join(f"N={s.N} B={s.B}" for s in sets))
     msas = [torch.from_numpy(s.msa).to(dev) for s in sets]
     torch.cuda.synchronize()
     if args.copy_calibration:
@@ -164,12 +246,25 @@ def main():
         # the symmetric fit's tolerance is on the norm over all parameters: the
         # tuner weighs the fixed-point rounding against it over that many entries
         tuned = plm.autotune.choose(items, plm.FitOptions(tol=args.tol), Q, symmetric=symmetric)
-        print(f"[bench] schedule path={tuned['path']} tile_seqs={tuned['tile_seqs']} "
-              f"({time.perf_counter() - t:.1f} s to choose)", file=sys.stderr, flush=True)
+        log(f"schedule path={tuned['path']} tile_seqs={tuned['tile_seqs']} ({time.perf_counter() - t:.1f} s to choose)")
         path, tile = int(tuned["path"]), int(tuned["tile_seqs"])
     else:
         path, tile = int(args.path), args.tile_seqs
-    opts = plm.FitOptions(tol=args.tol, path=path, tile_seqs=tile, timing=True)
+    refined = (not symmetric and path in REFINED) or (symmetric and path in (5, 6))
+    opts = plm.FitOptions(tol=args.tol, refine_tol=args.refine_tol if refined else 0.0, path=path,
+                          tile_seqs=tile, history_fp64=args.history_fp64)
+
+    # the convergence probe: eight sampled sites against the oracle's stored minimisers
+    probe = None
+    probe_gold = os.path.join(GOLDEN, f"{args.workload}_sites.npz")
+    if not ragged and not symmetric and os.path.exists(probe_gold):
+        g = np.load(probe_gold, allow_pickle=False)
+        if str(g["digest"]) == synth.msa_digest(sets[0].msa):
+            probe = plm.Probe(torch.from_numpy(g["sites"]).to(dev),
+                              torch.from_numpy(g["h"].astype(np.float32)).to(dev),
+                              torch.from_numpy(g["J"]).to(dev), cap=20000)
+        else:
+            log("stored oracle minimisers do not match the generated alignment: no probe")
 
     mf_ms = []
 
@@ -183,51 +278,51 @@ def main():
         mf_ms.append((time.perf_counter() - t0) * 1e3)
         return h0, J0
 
-    def step():
+    def step(o, with_probe=False):
         ws = weights()
         if ragged:
-            res = plm.fit_batch([(m, w, beff) for m, (_, w, beff) in zip(msas, ws)], opts)
+            res = plm.fit_batch([(m, w, beff) for m, (_, w, beff) in zip(msas, ws)], o)
         elif symmetric:
             _, w, beff = ws[0]
             h0, J0 = start_point(w, beff)
-            res = [plm.fit_symmetric(msas[0], w, beff, opts, h0=h0, J0=J0)]
+            res = [plm.fit_symmetric(msas[0], w, beff, o, h0=h0, J0=J0)]
         else:
             _, w, beff = ws[0]
             h0, J0 = start_point(w, beff)
-            res = [plm.fit(msas[0], w, beff, opts, h0=h0, J0=J0)]
+            res = [plm.fit(msas[0], w, beff, o, h0=h0, J0=J0, probe=probe if with_probe else None)]
         cfn = [plm.score(r.J)[1] for r in res]
         torch.cuda.synchronize()
         return ws, res, cfn
 
     for k in range(args.warmup):
         t = time.perf_counter()
-        step()
-        print(f"[bench] warmup {k} {time.perf_counter() - t:.2f} s", file=sys.stderr, flush=True)
+        step(opts)
+        log(f"warmup {k} {time.perf_counter() - t:.2f} s")
 
+    # one symmetric evaluation covers every site of the alignment
+    per_eval = (lambda s: s.B * s.N * s.N * Q) if symmetric else (lambda s: s.B * s.N * Q)
     torch.cuda.synchronize()
     tot_time = 0.0
     tot_units = 0
-    kt = dict(forward_ms=0.0, quant_ms=0.0, backward_ms=0.0, lbfgs_ms=0.0, iterations=0, site_evals=0,
-              refine_forward_ms=0.0, refine_backward_ms=0.0, refine_lbfgs_ms=0.0, refine_iterations=0,
-              refine_site_evals=0)
+    ttf = []
     last = None
     for k in range(args.steps):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        last = step()
+        last = step(opts, with_probe=True)
         dt = time.perf_counter() - t
-        tm = plm.last_fit_timing(dev)
-        for key in kt:
-            kt[key] += tm[key]
         ws, res, _ = last
-        # one symmetric evaluation covers every site of the alignment
-        per_eval = (lambda s: s.B * s.N * s.N * Q) if symmetric else (lambda s: s.B * s.N * Q)
         units = sum(sum(st["evaluations"] for st in r.stats) * per_eval(s) for r, s in zip(res, sets))
         tot_time += dt
         tot_units += units
-        print(f"[bench] step {k} {dt:.2f} s, site evals {tm['site_evals']}, "
-              f"fwd {tm['forward_ms']:.0f} ms (quant {tm['quant_ms']:.0f}) bwd {tm['backward_ms']:.0f} ms lbfgs {tm['lbfgs_ms']:.0f} ms",
-              file=sys.stderr, flush=True)
+        msg = f"step {k} {dt:.2f} s, site evals {sum(r.evaluations for r in res)}"
+        if probe is not None and res[0].probe is not None and len(res[0].probe):
+            e = res[0].probe
+            hit = np.nonzero(e[:, 1] <= 1e-4)[0]
+            if len(hit):
+                ttf.append(float(e[hit[0], 0] - e[0, 0]))
+                msg += f", within 1e-4 of the oracle after {ttf[-1]:.2f} s (device clock, {hit[0]} iterations)"
+        log(msg)
     ws, res, cfn = last
     statuses = {}
     for r in res:
@@ -235,52 +330,83 @@ def main():
             statuses[st["status"]] = statuses.get(st["status"], 0) + 1
     gmax = max(st["gnorm"] for r in res for st in r.stats)
     mu = 2 * min(0.01, 0.01 if symmetric else 0.005)
+    probe_final = None
+    if probe is not None and res[0].probe is not None and len(res[0].probe):
+        probe_final = float(res[0].probe[-1, 1])
 
-    # dominant kernel: the one with the largest share of device time, in the main
-    # fit (the refinement fit, a few evaluations on another path, is left out)
-    shares = {"backward": kt["backward_ms"] - kt["refine_backward_ms"],
-              "forward": kt["forward_ms"] - kt["refine_forward_ms"],
-              "lbfgs": kt["lbfgs_ms"] - kt["refine_lbfgs_ms"]}
-    dom = max(shares, key=shares.get)
-    main_evals = kt["site_evals"] - kt["refine_site_evals"]
-    units_all = tot_units * (main_evals / kt["site_evals"] if kt["site_evals"] else 1.0)
-    main_launches = kt["iterations"] - kt["refine_iterations"]
+    # per-kernel breakdown: the same fit with HIP events between the kernels on
+    # the fit's stream (eager launches; not the timed steps)
+    kt = None
     roofline = None
-    if dom in ("backward", "forward"):
-        np_dom = PATH_PIECES[path][0 if dom == "forward" else 1]
-        # the forward's time includes the coupling quantisation of path 6 (kernels of their own)
-        t_kern = shares[dom] - (kt["quant_ms"] if dom == "forward" else 0.0)
-        t_dom = t_kern * 1e-3
-        if np_dom:
-            # dense matrix-core flops of the one-hot product: q MACs per unit and piece
-            flops = units_all * 2 * Q * np_dom
-            # path 4's gradient is the grouped three-site kernel, path 5's its int8 form
-            kname = {4: "backward_g3", 5: "backward_i8", 6: "backward_i8"}.get(path, "backward_mfma") \
-                if dom == "backward" else ("forward_i8" if path == 6 else "forward_mfma")
-            # BF16 and FP16 dense matrix-core peaks are the same on this chip; int8 runs at twice the rate
-            peak = MFMA_I8_PEAK if (path, dom) in INT8_KERNELS else MFMA_BF16_PEAK
-            roofline = {"bound": "mfma", "achieved": flops / t_dom / 1e12, "peak": peak / 1e12,
-                        "unit": "TOP/s" if peak == MFMA_I8_PEAK else "TFLOP/s", "frac": flops / t_dom / peak,
-                        "flops_per_unit": 2 * Q * np_dom}
+    if not args.no_breakdown:
+        ob = plm.FitOptions(**{**opts.__dict__, "timing": True})
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, res_b, _ = step(ob)
+        kt = plm.last_fit_timing(dev)
+        log(f"breakdown fit {time.perf_counter() - t:.2f} s: fwd {kt['forward_ms']:.0f} ms (quant {kt['quant_ms']:.0f}) "
+            f"bwd {kt['backward_ms']:.0f} ms lbfgs {kt['lbfgs_ms']:.0f} ms, {kt['iterations']} iterations")
+        # dominant kernel: the one with the largest share of device time, in the main
+        # fit (the refinement fit, a few evaluations on another path, is left out)
+        shares = {"backward": kt["backward_ms"] - kt["refine_backward_ms"],
+                  "forward": kt["forward_ms"] - kt["refine_forward_ms"] - kt["quant_ms"],
+                  "lbfgs": kt["lbfgs_ms"] - kt["refine_lbfgs_ms"]}
+        dom = max(shares, key=shares.get)
+        main_launches = kt["iterations"] - kt["refine_iterations"]
+        s0 = sets[0]
+        units_b = sum(sum(st["evaluations"] for st in r.stats) * per_eval(a) for r, a in zip(res_b, sets))
+        if symmetric:
+            units_main = main_launches * s0.B * s0.N * s0.N * Q
         else:
-            kname = dom
-            adds = units_all  # one FP32 add per update in the gather or the scatter
-            roofline = {"bound": "alu", "achieved": adds / t_dom / 1e12, "peak": ALU_ADD_PEAK / 1e12,
-                        "unit": "TFLOP/s", "frac": adds / t_dom / ALU_ADD_PEAK, "flops_per_unit": 1}
-        # (bytes were counted on one all-sites evaluation of the asymmetric fit; a fit's
-        # launch covers only its active sites, so they are scaled by the units per launch)
-        traffic_all = None if symmetric or ragged else measured_traffic(kname, args.workload)
-        traffic = None
-        if traffic_all is not None:
-            s0 = sets[0]
-            traffic = traffic_all * (units_all / max(1, main_launches)) / (s0.B * s0.N * s0.N * Q)
-        roofline.update({"traffic": traffic, "traffic_all_sites_launch": traffic_all, "kernel": kname,
-                         "launches": main_launches, "avg_launch_ms": t_kern / max(1, main_launches)})
+            # the main fit's share of the breakdown fit's units (by site evaluations)
+            main_evals = kt["site_evals"] - kt["refine_site_evals"]
+            units_main = units_b * main_evals / max(1, kt["site_evals"])
+        if dom in ("backward", "forward") and units_main:
+            npc = PATH_PIECES[path][0 if dom == "forward" else 1]
+            t_kern = shares[dom]
+            t_dom = t_kern * 1e-3
+            units_launch = units_main / max(1, main_launches)
+            # algorithmic HBM bytes of one launch: the forward reads the active sites'
+            # couplings (FP32) and the alignment; the gradient writes the active sites'
+            # coupling gradients (FP32) and reads the alignment (residuals stay on chip)
+            active = units_launch / (s0.B * s0.N * Q)
+            alg_bytes = None if (ragged or symmetric) else active * s0.N * Q * Q * 4 + s0.B * s0.N
+            if npc:
+                kname = {4: "backward_g3", 5: "backward_i8", 6: "backward_i8"}.get(path, "backward_mfma") \
+                    if dom == "backward" else ("forward_i8" if path == 6 else "forward_mfma")
+                int8 = (path, dom) in INT8_KERNELS
+                peak = MFMA_I8_PEAK if int8 else MFMA_BF16_PEAK
+                dense_per_unit = 2 * Q * npc
+                # the method's own work: one add per unit in this direction
+                roofline = {"bound": "mfma", "achieved": units_main / t_dom / 1e12, "peak": peak / 1e12,
+                            "unit": "TOP/s" if int8 else "TFLOP/s", "frac": units_main / t_dom / peak,
+                            "ops_per_unit": 1,
+                            "dense_ops_per_unit": dense_per_unit,
+                            "dense_achieved": units_main * dense_per_unit / t_dom / 1e12,
+                            "dense_frac": units_main * dense_per_unit / t_dom / peak,
+                            "alu_add_equivalent_frac": units_main / t_dom / ALU_ADD_PEAK}
+            else:
+                kname = dom
+                roofline = {"bound": "alu", "achieved": units_main / t_dom / 1e12, "peak": ALU_ADD_PEAK / 1e12,
+                            "unit": "T adds/s", "frac": units_main / t_dom / ALU_ADD_PEAK, "ops_per_unit": 1}
+            # (bytes were counted on one all-sites evaluation; a fit's launch covers only
+            # its active sites, so they are scaled by the units per launch)
+            traffic_all = None if symmetric or ragged else measured_traffic(kname, args.workload)
+            traffic = None
+            if traffic_all is not None:
+                traffic = traffic_all * units_launch / (s0.B * s0.N * s0.N * Q)
+            roofline.update({"traffic": traffic, "traffic_all_sites_launch": traffic_all,
+                             "algorithmic_bytes": alg_bytes,
+                             "traffic_over_algorithmic": (traffic / alg_bytes) if (traffic and alg_bytes) else None,
+                             "kernel": kname, "launches": main_launches, "avg_launch_ms": t_kern / max(1, main_launches),
+                             "units_per_launch": units_launch, "timing": "HIP events on the fit's stream, "
+                             "separate eager fit of the same workload and schedule"})
 
     plain = None
     if not args.no_plain and not ragged and not symmetric and not mf_start:
         _, w, beff = ws[0]
-        po = plm.FitOptions(tol=args.tol, path=path, tile_seqs=tile, single_site=True, site_limit=args.plain_sites)
+        po = plm.FitOptions(tol=args.tol, path=path, tile_seqs=tile, single_site=True, site_limit=args.plain_sites,
+                            refine=-1)
         torch.cuda.synchronize()
         t = time.perf_counter()
         plm.fit(msas[0], w, beff, po)
@@ -295,7 +421,9 @@ def main():
     if not args.no_cpu:
         k = max(range(len(sets)), key=lambda j: sets[j].B * sets[j].N ** 2)
         _, w, beff = ws[k]
+        t = time.perf_counter()
         cpu = cpu_baseline(sets[k], w.cpu().numpy(), float(beff.item()))
+        log(f"cpu baseline {time.perf_counter() - t:.1f} s")
 
     ms_per_step = tot_time / args.steps * 1e3
     if ragged:
@@ -304,12 +432,14 @@ def main():
     else:
         cfg = {"workload": args.workload, "N": sets[0].N, "B": sets[0].B}
     cfg.update({"q": Q, "theta": 0.8, "lambda_h": 0.01, "lambda_J": 0.01, "tol": args.tol,
+                "refine_tol": args.refine_tol if refined else None,
                 "path": PATH_NAMES[path], "tile_seqs": tile, "schedule": "autotuned" if tuned else "fixed",
-                "method": args.method, "init": args.init,
-                "refine": (PATH_NAMES[4] if symmetric else PATH_NAMES[5])
-                if (path == 6 or (symmetric and path == 5)) else None})
+                "method": args.method, "init": args.init, "history_fp64": args.history_fp64,
+                "refine": (PATH_NAMES[4] if symmetric else PATH_NAMES[REFINED[path]]) if refined else None,
+                "fit_launch": "captured graph, one replay per iteration"})
     if mf_start:
         cfg["pseudocount"] = args.pseudocount
+    hist = "FP64" if args.history_fp64 else "FP32"
     line = {
         "metric": "plm objective+gradient updates/s (B*N^2*q, active sites) and time-to-fit at <=1e-4 vs plain",
         "value": tot_units / tot_time,
@@ -321,24 +451,30 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {1: "bf16x2 operands, f32 accumulate", 4: "f32 forward, f16x2 gradient operands (22-bit), "
-                  "FP64 reductions, FP32 L-BFGS history",
-                  5: "f32 forward, int8x3 fixed-point gradient (2^-23), exact int32 accumulation, "
-                  "FP64 reductions, FP32 L-BFGS history",
+        "dtype": {1: "bf16x2 operands, f32 accumulate", 4: "f32 forward, f16x2 gradient operands (22-bit)",
+                  5: "f32 forward, int8x3 fixed-point gradient (2^-23), exact int32 accumulation",
                   6: "int8x3 fixed-point energies (2^-22 max|J_r|) and gradient (2^-23), exact int32 "
-                  "accumulation, FP32 softmax, FP64 reductions, FP32 L-BFGS history"}.get(
-                      path, "f32 (FP64 reductions, FP32 L-BFGS history)")
-        + ({PATH_NAMES[5]: "; refined to the tolerance on f32 energies with the int8x3 gradient",
-            PATH_NAMES[4]: "; refined to the tolerance on f32 energies with the f16x2 gradient"}
+                  "accumulation, f32 softmax"}.get(path, "f32")
+        + f", FP64 reductions, FP64 L-BFGS arithmetic with {hist} curvature pairs"
+        + ({PATH_NAMES[5]: "; refined on f32 energies with the int8x3 gradient",
+            PATH_NAMES[4]: "; refined on f32 energies with the f16x2 gradient",
+            PATH_NAMES[3]: "; refined on three-piece bf16 (f32-exact) operands"}
            .get(cfg["refine"], "")),
         "data": "synthetic planted-Potts alignment (seeded Gibbs sampling)",
         "config": cfg,
         "time_to_fit_s": ms_per_step / 1e3,
-        "fit": {"site_evals": kt["site_evals"], "iterations": kt["iterations"], "status": statuses,
-                "max_gnorm": gmax, "coupling_error_bound_l2": gmax / mu},
-        "kernel_ms": {k: kt[k] for k in ("forward_ms", "quant_ms", "backward_ms", "lbfgs_ms")},
-        "refinement": {k: kt["refine_" + k] for k in ("site_evals", "iterations", "forward_ms", "backward_ms",
-                                                       "lbfgs_ms")},
+        "time_to_1e-4_vs_oracle_s": (statistics.median(ttf) if ttf else None),
+        "fit": {"site_evals": sum(r.evaluations for r in res), "status": statuses,
+                "max_device_gnorm": gmax,
+                "device_gnorm_bound_l2": gmax / mu,
+                "device_gnorm_note": "largest ||grad g_r^reg||_2 as the device evaluated it (the final "
+                                     "evaluation is FP32-class) / mu; the FP64 certificate on sampled sites "
+                                     "is checked by the full-size tests",
+                "oracle_sites_maxabs_final": probe_final},
+        "kernel_ms": ({k: kt[k] for k in ("forward_ms", "quant_ms", "backward_ms", "lbfgs_ms")} if kt else None),
+        "breakdown": ({k: kt[k] for k in ("iterations", "site_evals", "refine_site_evals", "refine_iterations",
+                                           "refine_forward_ms", "refine_backward_ms", "refine_lbfgs_ms")}
+                      if kt else None),
         "mf_init_ms": (sum(mf_ms[-args.steps:]) / args.steps) if mf_start else None,
         "roofline": roofline,
         "plain_single_site": plain,
