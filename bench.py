@@ -3,7 +3,7 @@
 One step = reweighting (0.8 identity) + the all-sites batched L-BFGS fit to
 ||grad g_r^reg||_2 <= 1e-6 (every per-site objective+gradient evaluation on the
 GPU; a fit on a reduced-precision path is refined on an FP32-class path to
-0.9e-6, so that the FP64 gradient at the returned point is within 1e-6) +
+0.7e-6, so that the FP64 gradient at the returned point is within 1e-6) +
 Ising-gauge/FN/APC scoring, on a seeded synthetic planted-Potts alignment of
 N = 500 columns and B = 50000 rows (q = 21), resident in HBM.  The timed
 steps run the fit as shipped: one captured graph replayed per iteration.
@@ -65,7 +65,9 @@ PATH_PIECES = {0: (0, 0), 1: (2, 2), 2: (0, 3), 3: (3, 3), 4: (0, 2), 5: (0, 3),
 INT8_KERNELS = {(5, "backward"), (6, "backward"), (6, "forward")}
 # reduced-precision first paths and the FP32-class path the library refines them on
 REFINED = {6: 5, 1: 3}
-FIT_TOL_FINAL = 0.9e-6
+# the refinement's tolerance on its FP32-class evaluation: at N = 500 its gradient
+# norm near the optimum differs from the FP64 one by up to about 3e-7
+FIT_TOL_FINAL = 0.7e-6
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 

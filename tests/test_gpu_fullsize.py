@@ -42,8 +42,9 @@ CLUSTERED = dict(seed=5005, B=50000, N=500, n_anc=1250, p_mut=0.1)
 LH, LJ = 0.01, 0.01
 MU = 2 * min(LH, 0.5 * LJ)
 # every fit ends on an FP32-class evaluation at this tolerance, so that the FP64
-# gradient (the FP32 evaluation differs by a few 1e-8) is below 1e-6
-FIT_TOL = 0.9e-6
+# gradient is below 1e-6: at this size the FP32 evaluations' gradient norms
+# near the optimum differ from the FP64 ones by up to about 3e-7 (measured)
+FIT_TOL = 0.65e-6
 ROWS = []  # the error table
 
 
