@@ -141,6 +141,27 @@ int plm_objgrad(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, int32_t 
                 int32_t path, void *workspace, size_t workspace_bytes,
                 const double *grad_scale, double *f_out, float *gh_out, float *gJ_out);
 
+/* ---- Objective and gradient without a workspace ----------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation.  plm_objgrad
+ * (same arguments, results and stream semantics, same kernels) with its
+ * scratch in a fixed device array of PLM_STATIC_SCRATCH_BYTES per GPU, which
+ * the library holds from the first plm_ctx_create on that GPU until the
+ * process ends; the call allocates nothing.  Problems whose
+ * plm_objgrad_workspace_bytes exceeds the array are rejected with
+ * PLM_E_WORKSPACE (at q = 21, 64 MiB holds N = 20 with B up to 33 700,
+ * N = 40 with B up to 15 300, N = 60 with B up to 8 000).  Every call on a GPU shares that GPU's
+ * array: calls ordered on one stream are safe, calls that overlap on one GPU
+ * (other streams or contexts, other threads) race.  The array keeps the last
+ * call's contents; an evaluation writes every scratch byte before it reads it,
+ * so nothing needs clearing between calls. */
+#define PLM_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int plm_objgrad_static(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, int32_t q,
+                       const double *w, const double *beff, const float *h, const float *J,
+                       double lambda_h, double lambda_J, const int32_t *sites, int32_t n_sites,
+                       int32_t path, const double *grad_scale, double *f_out, float *gh_out,
+                       float *gJ_out);
+
 /* ---- Minimisation of every site (sec. 3.4 step 3) --------------------------
  * One limited-memory BFGS state per site, all sites advanced together on the
  * device; one replay of the captured iteration graph evaluates the trial

@@ -6,7 +6,7 @@ from . import _lib
 from .autograd import PLMObjective, plm_objective
 from . import autotune
 from .api import (FitOptions, FitResult, Probe, contact_tpr, context, fit, fit_batch, fit_symmetric, frequencies, mf_init, last_fit_timing,
-                  objgrad, parse_alignment, read_alignment, reweight, score, sync, tune, workspace)
+                  objgrad, objgrad_static, parse_alignment, read_alignment, reweight, score, sync, tune, workspace)
 from ._lib import (PATH_GATHER_FP32, PATH_GATHER_MFMA_F16X2, PATH_GATHER_MFMA_FP32, PATH_GATHER_MFMA_I8X3,
                    PATH_MFMA_BF16X2,
                    PATH_MFMA_FP32, PATH_MFMA_I8X3, PlmError)

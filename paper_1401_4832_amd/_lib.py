@@ -24,6 +24,8 @@ PATH_GATHER_MFMA_F16X2 = 4
 PATH_GATHER_MFMA_I8X3 = 5
 PATH_MFMA_I8X3 = 6
 
+STATIC_SCRATCH_BYTES = 64 << 20
+
 SITE_STATUS = {0: "converged", 1: "maxiter", 2: "linesearch", 3: "nonfinite"}
 
 
@@ -150,6 +152,7 @@ def lib():
             "plm_objgrad_workspace_bytes": (SZ, [I32, I32, I32, I32]),
             "plm_objgrad": (ctypes.c_int, [P, P, I32, I32, I32, P, P, P, P, D, D, P, I32, I32, P, SZ,
                                            P, P, P, P]),
+            "plm_objgrad_static": (ctypes.c_int, [P, P, I32, I32, I32, P, P, P, P, D, D, P, I32, I32, P, P, P, P]),
             "plm_fit_opts_default": (None, [ctypes.POINTER(FitOpts)]),
             "plm_fit_opts_size": (SZ, []),
             "plm_fit_workspace_bytes": (SZ, [I32, I32, I32, ctypes.POINTER(FitOpts)]),
@@ -186,7 +189,7 @@ def exported_symbols():
     """Names declared in include/plm.h that the ABI tests check for."""
     return ["plm_ctx_create", "plm_ctx_destroy", "plm_last_error", "plm_status_string", "plm_sync",
             "plm_reweight", "plm_objgrad_workspace_bytes", "plm_objgrad", "plm_fit_opts_default",
-            "plm_fit_opts_size",
+            "plm_fit_opts_size", "plm_objgrad_static",
             "plm_fit_workspace_bytes", "plm_fit", "plm_score", "plm_fit_last_timing",
             "plm_fit_batch_workspace_bytes", "plm_fit_batch", "plm_tune", "plm_score_opts_default",
             "plm_frequencies", "plm_score_ex", "plm_contact_tpr", "plm_parse_alignment",

@@ -120,6 +120,42 @@ def objgrad(msa, w, beff, h, J, lambda_h=0.01, lambda_J=0.01, sites=None, grad=T
     return f, gh, gJ
 
 
+def objgrad_static(msa, w, beff, h, J, lambda_h=0.01, lambda_J=0.01, sites=None, grad=True,
+                   path=L.PATH_GATHER_FP32, grad_scale=None, out=None):
+    """objgrad() through plm_objgrad_static: no workspace, the library's fixed
+    scratch array (problems up to L.STATIC_SCRATCH_BYTES of scratch).  out may
+    hold preallocated (f, gh, gJ) tensors, so that the call allocates nothing."""
+    dev = msa.device
+    _dev_tensor(msa, torch.uint8, dev, "msa")
+    B, N = msa.shape
+    q = h.shape[1]
+    _dev_tensor(w, torch.float64, dev, "w")
+    _dev_tensor(beff, torch.float64, dev, "beff")
+    _dev_tensor(h, torch.float32, dev, "h")
+    _dev_tensor(J, torch.float32, dev, "J")
+    if tuple(J.shape) != (N, N, q, q) or tuple(h.shape) != (N, q) or w.numel() != B:
+        raise ValueError("shape mismatch between msa, w, h and J")
+    if sites is not None:
+        sites = _dev_tensor(sites, torch.int32, dev, "sites") if isinstance(sites, torch.Tensor) else \
+            torch.as_tensor(sites, dtype=torch.int32).to(dev).contiguous()
+        ns = int(sites.numel())
+    else:
+        ns = N
+    if grad_scale is not None:
+        _dev_tensor(grad_scale, torch.float64, dev, "grad_scale")
+    if out is None:
+        f = torch.zeros(N, dtype=torch.float64, device=dev)
+        gh = torch.zeros(N, q, dtype=torch.float32, device=dev) if grad else None
+        gJ = torch.zeros(N, N, q, q, dtype=torch.float32, device=dev) if grad else None
+    else:
+        f, gh, gJ = out
+    ctx = context(dev)
+    _check(L.lib().plm_objgrad_static(ctx, _ptr(msa), B, N, q, _ptr(w), _ptr(beff), _ptr(h), _ptr(J),
+                                      float(lambda_h), float(lambda_J), _ptr(sites), ns, path,
+                                      _ptr(grad_scale), _ptr(f), _ptr(gh), _ptr(gJ)), ctx)
+    return f, gh, gJ
+
+
 @dataclass
 class FitOptions:
     lambda_h: float = 0.01

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "plm_internal.h"
@@ -25,6 +26,36 @@ struct plm_ctx {
 };
 
 namespace {
+
+// Scratch of plm_objgrad_static: one fixed array per GPU, held from the first
+// context on that GPU until the process ends.  Host code never uses the
+// array's name as an address (on the host it is only a stand-in): the address
+// on each device comes from hipGetSymbolAddress, taken once per device with
+// that device current, and is what the kernels receive.
+__device__ __align__(256) unsigned char scratch[PLM_STATIC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+bool g_scratch_set[kMaxDevices];
+
+// (the device must be current)
+hipError_t static_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_set[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = p;
+  g_scratch_set[device] = true;
+  return hipSuccess;
+}
+
+void* static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_set[device] ? g_scratch_ptr[device] : nullptr;
+}
 
 int set_err(plm_ctx* c, int code, const char* fmt, ...) {
   if (c) {
@@ -424,7 +455,8 @@ int plm_ctx_create(plm_ctx** out, int device, void* hip_stream) {
   if (hipSetDevice(device) == hipSuccess)
     for (int k = 0; k < 5; ++k) ev_ok = ev_ok && hipEventCreate(&c->ev[k]) == hipSuccess;
   if (!ev_ok || hipSetDevice(device) != hipSuccess || ensure_pin(c, 64) != PLM_OK ||
-      hipStreamCreateWithFlags(&c->fit_stream, hipStreamNonBlocking) != hipSuccess) {
+      hipStreamCreateWithFlags(&c->fit_stream, hipStreamNonBlocking) != hipSuccess ||
+      static_scratch_setup(device) != hipSuccess) {
     if (c->pin) (void)hipHostFree(c->pin);
     delete c;
     return PLM_E_HIP;
@@ -476,7 +508,7 @@ size_t plm_objgrad_workspace_bytes(int32_t B, int32_t N, int32_t q, int32_t path
 
 namespace {
 
-// plm_objgrad on the given scratch (the caller's workspace)
+// plm_objgrad on the given scratch (a caller's workspace or the static array)
 int objgrad_impl(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
                  const double* beff, const float* h, const float* J, double lambda_h,
                  double lambda_J, const int32_t* sites, int32_t n_sites, int32_t path, void* ws,
@@ -537,6 +569,22 @@ int plm_objgrad(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
   if (!c) return PLM_E_INVALID;
   return objgrad_impl(c, msa, B, N, q, w, beff, h, J, lambda_h, lambda_J, sites, n_sites, path, ws,
                       ws_bytes, grad_scale, f_out, gh_out, gJ_out);
+}
+
+int plm_objgrad_static(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q,
+                       const double* w, const double* beff, const float* h, const float* J,
+                       double lambda_h, double lambda_J, const int32_t* sites, int32_t n_sites,
+                       int32_t path, const double* grad_scale, double* f_out, float* gh_out,
+                       float* gJ_out) {
+  if (!c) return PLM_E_INVALID;
+  void* ptr = static_scratch(c->device);
+  if (!ptr) return set_err(c, PLM_E_HIP, "the static scratch array of device %d has no address", c->device);
+  const size_t need = plm_objgrad_workspace_bytes(B, N, q, path);
+  if (need > PLM_STATIC_SCRATCH_BYTES)
+    return set_err(c, PLM_E_WORKSPACE, "B=%d N=%d q=%d needs %zu bytes of scratch; the static array holds %zu",
+                   B, N, q, need, (size_t)PLM_STATIC_SCRATCH_BYTES);
+  return objgrad_impl(c, msa, B, N, q, w, beff, h, J, lambda_h, lambda_J, sites, n_sites, path, ptr,
+                      PLM_STATIC_SCRATCH_BYTES, grad_scale, f_out, gh_out, gJ_out);
 }
 
 void plm_fit_opts_default(plm_fit_opts* o) {
