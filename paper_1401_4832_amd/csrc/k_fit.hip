@@ -231,40 +231,61 @@ hipError_t launch_list_tables(const BatchArgs& b, const int32_t* list, int32_t f
 }
 
 
-// Convergence probe: one block per watched site computes the largest
-// |iterate - reference| over the site's fields and couplings (its self block
-// left out) into entry *count of out; then probe_finish_kernel writes the
-// entry's time (device wall clock) and the largest of those maxima and
-// advances the count.  Entries past cap are dropped.
+// Convergence probe: kProbeChunks blocks per watched site take the largest
+// |iterate - reference| over their range of the site's fields and couplings
+// (the self block left out) into entry *count of out (as float bits, an
+// atomic maximum over the non-negative values, NaN above every number); then
+// probe_finish_kernel writes the entry's time (device wall clock) and the
+// largest of the per-site maxima and advances the count.  Entries past cap
+// are dropped.
 constexpr int kProbeThreads = 256;
+constexpr int kProbeChunks = 32;
+
+__device__ inline uint32_t* probe_slot(const ProbeArgs& p, int32_t idx, int k) {
+  return reinterpret_cast<uint32_t*>(p.out + (size_t)idx * (2 + p.n) + 2 + k);
+}
+
+__global__ void probe_zero_kernel(ProbeArgs p) {
+  const int32_t idx = *p.count;
+  if (idx >= p.cap) return;
+  for (int k = threadIdx.x; k < p.n; k += blockDim.x) p.out[(size_t)idx * (2 + p.n) + 2 + k] = 0.0;
+}
 
 __global__ __launch_bounds__(kProbeThreads) void probe_site_kernel(ProbeArgs p) {
   __shared__ float red[kProbeThreads / 64];
-  const int k = blockIdx.x;
+  const int k = blockIdx.x / kProbeChunks, chunk = blockIdx.x - k * kProbeChunks;
   const int32_t idx = *p.count;
   if (idx >= p.cap) return;
   const int r = p.sites[k];
   if (r < 0 || r >= p.N) {  // not a site of the alignment
-    if (threadIdx.x == 0) p.out[(size_t)idx * (2 + p.n) + 2 + k] = __builtin_nan("");
+    if (threadIdx.x == 0 && chunk == 0) atomicMax(probe_slot(p, idx, k), 0x7fc00000u);
     return;
   }
   const int q = p.q;
-  const size_t qq = (size_t)q * q, Nqq = (size_t)p.N * qq;
-  const size_t self0 = (size_t)r * qq, self1 = self0 + qq;
-  float mx = 0.f;
-  for (int e = threadIdx.x; e < q; e += blockDim.x)
-    mx = fmaxf(mx, fabsf(p.Xh[(size_t)r * q + e] - p.ref_h[(size_t)k * q + e]));
+  const int Nqq = p.N * q * q, P = q + Nqq;
+  const int self0 = q + r * q * q, self1 = self0 + q * q;
+  const int csz = (P + kProbeChunks - 1) / kProbeChunks;
+  const int beg = min(P, chunk * csz), end = min(P, beg + csz);
   const float* X = p.XJ + (size_t)r * Nqq;
   const float* R = p.ref_J + (size_t)k * Nqq;
-  for (size_t e = threadIdx.x; e < Nqq; e += blockDim.x)
-    if (e < self0 || e >= self1) mx = fmaxf(mx, fabsf(X[e] - R[e]));
-  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  float mx = 0.f;
+  for (int e = beg + (int)threadIdx.x; e < end; e += kProbeThreads) {
+    float d;
+    if (e < q) d = fabsf(p.Xh[(size_t)r * q + e] - p.ref_h[(size_t)k * q + e]);
+    else d = (e >= self0 && e < self1) ? 0.f : fabsf(X[e - q] - R[e - q]);
+    mx = (d != d || mx != mx) ? __builtin_nanf("") : fmaxf(mx, d);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const float u = __shfl_xor(mx, o, 64);
+    mx = (u != u || mx != mx) ? __builtin_nanf("") : fmaxf(mx, u);
+  }
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
   if (threadIdx.x == 0) {
     float t = red[0];
-    for (int w = 1; w < kProbeThreads / 64; ++w) t = fmaxf(t, red[w]);
-    p.out[(size_t)idx * (2 + p.n) + 2 + k] = (double)t;
+    for (int w = 1; w < kProbeThreads / 64; ++w) t = (red[w] != red[w] || t != t) ? __builtin_nanf("") : fmaxf(t, red[w]);
+    // non-negative floats and the positive quiet NaN order as their bit patterns
+    atomicMax(probe_slot(p, idx, k), t != t ? 0x7fc00000u : __float_as_uint(t));
   }
 }
 
@@ -276,20 +297,23 @@ __global__ void probe_finish_kernel(ProbeArgs p) {
   double mx = 0.0;
   bool bad = false;
   for (int k = 0; k < p.n; ++k) {
-    bad = bad || !(e[2 + k] == e[2 + k]);
-    mx = fmax(mx, e[2 + k]);
+    const float v = __uint_as_float(*probe_slot(p, idx, k));
+    e[2 + k] = (double)v;
+    bad = bad || !(v == v);
+    mx = fmax(mx, (double)v);
   }
-  if (bad) mx = __builtin_nan("");
   e[0] = (double)wall_clock64() * p.sec_per_tick;
-  e[1] = mx;
+  e[1] = bad ? __builtin_nan("") : mx;
   *p.count = idx + 1;
 }
 
 hipError_t launch_probe(const ProbeArgs& p, hipStream_t st) {
   if (p.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(probe_site_kernel, dim3(p.n), dim3(kProbeThreads), 0, st, p);
+  hipLaunchKernelGGL(probe_zero_kernel, dim3(1), dim3(64), 0, st, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(probe_site_kernel, dim3(p.n * kProbeChunks), dim3(kProbeThreads), 0, st, p);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(probe_finish_kernel, dim3(1), dim3(64), 0, st, p);
   return hipGetLastError();
 }

@@ -170,10 +170,15 @@ struct Vecs {
     const float f = (float)v;
     if (e < q) Th[h0 + e] = f; else TJ[j0 + (e - q)] = (e >= self0 && e < self1) ? 0.f : f;
   }
-  // data part of the gradient at the trial point (fields: the forward's tile sums)
+  // data part of the gradient at the trial point (fields: the forward's tile
+  // sums, added once per evaluation by the eval pass into ghd)
   __device__ double gdata(int e, int r) const {
-    if (e >= q) return gJd[j0 + (e - q)];
+    return e >= q ? gJd[j0 + (e - q)] : gmem(ap->ghd)[(size_t)r * q + e];
+  }
+  // the forward's tile sums of field e (fixed order)
+  __device__ double field_tiles(int e, int r) const {
     double t = 0.0;
+#pragma unroll 8
     for (int k = 0; k < ap->tiles; ++k) t += gmem(ap->gh_part)[((size_t)k * N + r) * kSlot + e];
     return t;
   }
@@ -204,14 +209,49 @@ __global__ __launch_bounds__(kLbThreads) void lbfgs_eval_kernel(BatchArgs b) {
   int beg, end;
   v.chunk(chunk, beg, end);
   double acc[3] = {0.0, 0.0, 0.0};  // regulariser, squared gradient norm, objective data part
-  for (int e = beg + (int)threadIdx.x; e < end; e += kLbThreads) {
-    const float t = v.T(e);
-    const double lo = v.lam(e), g = v.g(e, r, t);
-    acc[0] += lo * (double)t * (double)t;
-    acc[1] += g * g;
+  const int tid = threadIdx.x;
+  const int q = v.q;
+  if (beg < q) {
+    // the fields (the first chunk holds them all unless the site is tiny): their
+    // data part is the sum of the forward's tile partials, kept for the update pass
+    for (int e = beg + tid; e < min(end, q); e += kLbThreads) {
+      const double gd = v.field_tiles(e, r);
+      gmem_w(a.ghd)[(size_t)r * q + e] = gd;
+      const float t = v.T(e);
+      const double g = gd * v.ib + 2.0 * v.lam_h * (double)t;
+      acc[0] += v.lam_h * (double)t * (double)t;
+      acc[1] += g * g;
+    }
+    if (tid == 0 && chunk == 0) {
+      double fd = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < a.tiles; ++k) fd += gmem(a.f_part)[(size_t)k * a.N + r];
+      acc[2] = fd;
+    }
   }
-  if (chunk == 0 && threadIdx.x == 0)
-    for (int k = 0; k < a.tiles; ++k) acc[2] += gmem(a.f_part)[(size_t)k * a.N + r];
+  // the couplings, four per thread at a time so that their loads are in flight together
+  const int cb = max(beg, q);
+  constexpr int U = 4;
+  for (int e0 = cb + tid; e0 < end; e0 += U * kLbThreads) {
+    float t[U];
+    double gd[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = min(e0 + u * kLbThreads, end - 1);
+      t[u] = v.TJ[v.j0 + (e - q)];
+      gd[u] = v.gJd[v.j0 + (e - q)];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kLbThreads;
+      if (e < end) {
+        const double lo = v.lam(e);
+        const double g = gd[u] * v.ib + 2.0 * lo * (double)t[u];
+        acc[0] += lo * (double)t[u] * (double)t[u];
+        acc[1] += g * g;
+      }
+    }
+  }
   block_sum_vec(acc, red);
   if (threadIdx.x == 0) {
     double* p = site_part(a, r, chunk);
@@ -382,32 +422,49 @@ __global__ __launch_bounds__(kLbThreads) void lbfgs_update_kernel(BatchArgs b) {
     double acc[4 + 2 * kGroupA];
 #pragma unroll
     for (int k = 0; k < 4 + 2 * kGroupA; ++k) acc[k] = 0.0;
-    for (int e = beg + tid; e < end; e += kLbThreads) {
-      const float t = v.T(e), x = v.X(e);
-      const HT gold = v.G(e);
-      HT sl[NA > 0 ? NA : 1], yl[NA > 0 ? NA : 1];
+    // two elements per thread at a time (e, e + nth), all their loads issued together
+    constexpr int U = 2;
+    constexpr int NA1 = NA > 0 ? NA : 1;
+    for (int e0 = beg + tid; e0 < end; e0 += U * kLbThreads) {
+      int ee[U];
+      float t[U], x[U];
+      HT gold[U], sl[U][NA1], yl[U][NA1];
+      double gd[U];
 #pragma unroll
-      for (int j = 0; j < NA; ++j) {
-        sl[j] = *v.Sp(kk[j], e);
-        yl[j] = *v.Yp(kk[j], e);
-      }
-      const double g = v.g(e, r, t);
-      // stored as HT and used as stored
-      const HT svs = (HT)((double)t - (double)x), yvs = (HT)(g - (double)gold);
-      *v.Sp(head, e) = svs;
-      *v.Yp(head, e) = yvs;
-      const double sv = svs, yv = yvs;
-      acc[0] += sv * yv;
-      acc[1] += yv * yv;
-      acc[2] += sv * g;
-      acc[3] += yv * g;
+      for (int u = 0; u < U; ++u) {
+        ee[u] = min(e0 + u * kLbThreads, end - 1);
+        t[u] = v.T(ee[u]);
+        x[u] = v.X(ee[u]);
+        gold[u] = v.G(ee[u]);
+        gd[u] = v.gdata(ee[u], r);
 #pragma unroll
-      for (int j = 0; j < NA; ++j) {
-        acc[4 + 2 * j] += (double)sl[j] * yv;
-        acc[5 + 2 * j] += (double)yl[j] * yv;
+        for (int j = 0; j < NA; ++j) {
+          sl[u][j] = *v.Sp(kk[j], ee[u]);
+          yl[u][j] = *v.Yp(kk[j], ee[u]);
+        }
       }
-      v.setG(e, (HT)g);
-      v.setX(e, t);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (e0 + u * kLbThreads >= end) continue;
+        const int e = ee[u];
+        const double g = gd[u] * v.ib + 2.0 * v.lam(e) * (double)t[u];
+        // stored as HT and used as stored
+        const HT svs = (HT)((double)t[u] - (double)x[u]), yvs = (HT)(g - (double)gold[u]);
+        *v.Sp(head, e) = svs;
+        *v.Yp(head, e) = yvs;
+        const double sv = svs, yv = yvs;
+        acc[0] += sv * yv;
+        acc[1] += yv * yv;
+        acc[2] += sv * g;
+        acc[3] += yv * g;
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+          acc[4 + 2 * j] += (double)sl[u][j] * yv;
+          acc[5 + 2 * j] += (double)yl[u][j] * yv;
+        }
+        v.setG(e, (HT)g);
+        v.setX(e, t[u]);
+      }
     }
     block_sum_vec(acc, red);
     if (tid == 0)
@@ -425,18 +482,29 @@ __global__ __launch_bounds__(kLbThreads) void lbfgs_update_kernel(BatchArgs b) {
       double acc[2 * kGroupB];
 #pragma unroll
       for (int k = 0; k < 2 * kGroupB; ++k) acc[k] = 0.0;
-      for (int e = beg + tid; e < end; e += kLbThreads) {
-        const double yv = (double)*v.Yp(head, e);
-        HT sl[NB], yl[NB];
+      constexpr int U = 2;
+      for (int e0 = beg + tid; e0 < end; e0 += U * kLbThreads) {
+        int ee[U];
+        HT yh[U], sl[U][NB], yl[U][NB];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          sl[j] = *v.Sp(kk[j], e);
-          yl[j] = *v.Yp(kk[j], e);
+        for (int u = 0; u < U; ++u) {
+          ee[u] = min(e0 + u * kLbThreads, end - 1);
+          yh[u] = *v.Yp(head, ee[u]);
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            sl[u][j] = *v.Sp(kk[j], ee[u]);
+            yl[u][j] = *v.Yp(kk[j], ee[u]);
+          }
         }
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          acc[2 * j] += (double)sl[j] * yv;
-          acc[2 * j + 1] += (double)yl[j] * yv;
+        for (int u = 0; u < U; ++u) {
+          if (e0 + u * kLbThreads >= end) continue;
+          const double yv = (double)yh[u];
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            acc[2 * j] += (double)sl[u][j] * yv;
+            acc[2 * j + 1] += (double)yl[u][j] * yv;
+          }
         }
       }
       block_sum_vec(acc, red);

@@ -133,7 +133,7 @@ struct FitBufs {
   float *Dh, *DJ;
   void *Gh, *GJ, *Sh, *SJ, *Yh, *YJ;  // history type: FP32, or FP64 with history_fp64
   DirCoef* dc;
-  double *dpart, *part;
+  double *dpart, *part, *ghd;
 };
 
 void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, int32_t hist64, FitBufs& f) {
@@ -154,6 +154,7 @@ void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, int32_t hi
   f.dc = bp.take<DirCoef>(N);
   f.dpart = bp.take<double>((size_t)N * kLbChunks);
   f.part = bp.take<double>((size_t)N * kLbChunks * kLbPartW);
+  f.ghd = bp.take<double>(Nq);
 }
 
 // device tables of a batch (BatchArgs points into them)
@@ -733,7 +734,7 @@ int prepare_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const p
     L.Xh = m.h_io; L.XJ = m.J_io; L.Th = f.Th; L.TJ = f.TJ;
     L.Gh = f.Gh; L.GJ = f.GJ; L.Dh = f.Dh; L.DJ = f.DJ;
     L.Sh = f.Sh; L.SJ = f.SJ; L.Yh = f.Yh; L.YJ = f.YJ; L.small = f.small;
-    L.dc = f.dc; L.dpart = f.dpart; L.part = f.part;
+    L.dc = f.dc; L.dpart = f.dpart; L.part = f.part; L.ghd = f.ghd;
     L.f_part = f.ev.f_part; L.gh_part = f.ev.gh_part; L.gJ = f.ev.gJ;
     L.st = t.st + base[k];
     L.phase_host = phase_host_dev + base[k];

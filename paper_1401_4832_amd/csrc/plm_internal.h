@@ -145,6 +145,7 @@ struct LbfgsArgs {
   DirCoef* dc;    // per site: the pending direction's coefficients
   double* dpart;  // per site: [kLbChunks] partial sums of d . g
   double* part;   // per site: [kLbChunks][kLbPartW] partial sums of the passes
+  double* ghd;    // per site: [q] data part of the field gradient at the trial point
   const double* f_part;   // [tiles][N]
   const double* gh_part;  // [tiles][N][21]
   const double* gJ;       // [N][N][q][q] data part
