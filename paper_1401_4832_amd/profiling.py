@@ -85,7 +85,7 @@ def stats(csv_path: str, out_md: str, command: str):
     rows = _rows(csv_path)
     lines = [f"# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
              "| kernel | calls | total ms | average ms | % |", "|---|---|---|---|---|"]
-    for r in rows[:12]:
+    for r in rows[:24]:
         name = r.get("Name") or r.get("KERNEL_NAME") or r.get("name")
         calls = int(float(r.get("Calls") or r.get("calls")))
         tot = float(r.get("TotalDurationNs") or r.get("total_duration")) / 1e6
