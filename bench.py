@@ -58,11 +58,11 @@ MFMA_BF16_PEAK = 2.5e15
 # dense int8 matrix-core peak (ops/s)
 MFMA_I8_PEAK = 5.0e15
 PATH_NAMES = {0: "gather_fp32", 1: "mfma_bf16x2", 2: "gather_mfma_fp32", 3: "mfma_fp32",
-              4: "gather_mfma_f16x2", 5: "gather_mfma_i8x3", 6: "mfma_i8x3"}
+              4: "gather_mfma_f16x2", 5: "gather_mfma_i8x3", 6: "mfma_i8x3", 7: "gather64_mfma_i8x6"}
 # 16-bit pieces (or int8 digits) of the non-one-hot operand, per path: (forward, backward); 0 = LDS gather/scatter
-PATH_PIECES = {0: (0, 0), 1: (2, 2), 2: (0, 3), 3: (3, 3), 4: (0, 2), 5: (0, 3), 6: (3, 3)}
+PATH_PIECES = {0: (0, 0), 1: (2, 2), 2: (0, 3), 3: (3, 3), 4: (0, 2), 5: (0, 3), 6: (3, 3), 7: (0, 6)}
 # the int8 matrix-core kernels (path, direction)
-INT8_KERNELS = {(5, "backward"), (6, "backward"), (6, "forward")}
+INT8_KERNELS = {(5, "backward"), (6, "backward"), (6, "forward"), (7, "backward")}
 # reduced-precision first paths and the FP32-class path the library refines them on
 REFINED = {6: 5, 1: 3}
 # the refinement's tolerance on its FP32-class evaluation: at N = 500 its gradient
@@ -242,18 +242,28 @@ def main():
 
     # the schedule: the autotuner's choice for this workload (outside the timed region)
     tuned = None
+    # the symmetric fit: a fixed-point first fit stops at a tolerance well above
+    # its rounding floor over all parameters (five times the residual-rounding
+    # estimate; the FP32 energies add about as much), then the library refines
+    # it on the precise path to --tol
+    main_tol = args.tol
+    if symmetric:
+        item = (msas[0],) + tuple(weights()[0][1:])
+        main_tol = max(args.tol, 5.0 * plm.autotune.symmetric_floor(item, Q))
     if args.path == "auto":
         items = [(m, w, beff) for m, (_, w, beff) in zip(msas, weights())]
         t = time.perf_counter()
         # the symmetric fit's tolerance is on the norm over all parameters: the
         # tuner weighs the fixed-point rounding against it over that many entries
-        tuned = plm.autotune.choose(items, plm.FitOptions(tol=args.tol), Q, symmetric=symmetric)
+        tuned = plm.autotune.choose(items, plm.FitOptions(tol=main_tol), Q, symmetric=symmetric)
         log(f"schedule path={tuned['path']} tile_seqs={tuned['tile_seqs']} ({time.perf_counter() - t:.1f} s to choose)")
         path, tile = int(tuned["path"]), int(tuned["tile_seqs"])
     else:
         path, tile = int(args.path), args.tile_seqs
     refined = (not symmetric and path in REFINED) or (symmetric and path in (5, 6))
-    opts = plm.FitOptions(tol=args.tol, refine_tol=args.refine_tol if refined else 0.0, path=path,
+    # (the symmetric fit is refined on the precise path, whose gradient norm is the FP64 one)
+    refine_tol = (args.tol if symmetric else args.refine_tol) if refined else 0.0
+    opts = plm.FitOptions(tol=main_tol if refined else args.tol, refine_tol=refine_tol, path=path,
                           tile_seqs=tile, history_fp64=args.history_fp64)
 
     # the convergence probe: eight sampled sites against the oracle's stored minimisers
@@ -434,10 +444,10 @@ def main():
     else:
         cfg = {"workload": args.workload, "N": sets[0].N, "B": sets[0].B}
     cfg.update({"q": Q, "theta": 0.8, "lambda_h": 0.01, "lambda_J": 0.01, "tol": args.tol,
-                "refine_tol": args.refine_tol if refined else None,
+                "refine_tol": refine_tol if refined else None, "first_fit_tol": main_tol if refined else None,
                 "path": PATH_NAMES[path], "tile_seqs": tile, "schedule": "autotuned" if tuned else "fixed",
                 "method": args.method, "init": args.init, "history_fp64": args.history_fp64,
-                "refine": (PATH_NAMES[4] if symmetric else PATH_NAMES[REFINED[path]]) if refined else None,
+                "refine": (PATH_NAMES[7] if symmetric else PATH_NAMES[REFINED[path]]) if refined else None,
                 "fit_launch": "captured graph, one replay per iteration"})
     if mf_start:
         cfg["pseudocount"] = args.pseudocount
@@ -460,7 +470,8 @@ def main():
         + f", FP64 reductions, FP64 L-BFGS arithmetic with {hist} curvature pairs"
         + ({PATH_NAMES[5]: "; refined on f32 energies with the int8x3 gradient",
             PATH_NAMES[4]: "; refined on f32 energies with the f16x2 gradient",
-            PATH_NAMES[3]: "; refined on three-piece bf16 (f32-exact) operands"}
+            PATH_NAMES[3]: "; refined on three-piece bf16 (f32-exact) operands",
+            PATH_NAMES[7]: "; refined on FP64 energies and residuals (two exact int8x3 gradient passes)"}
            .get(cfg["refine"], "")),
         "data": "synthetic planted-Potts alignment (seeded Gibbs sampling)",
         "config": cfg,

@@ -92,6 +92,12 @@ extern "C" {
                                   [2^21, 2^22) and rounded (|dJ| <= 2^-22 max_i,s,k |J_ri(s,k)|),
                                   three int8 digits accumulated exactly in int32; at most
                                   2^24 - 1 sequences */
+#define PLM_PATH_GATHER64_MFMA_I8X6 7 /* the precise path: energies accumulated in FP64 by the LDS
+                                  gather, FP64 log-softmax and residuals; coupling gradient as two
+                                  passes of the int8 MFMA product of path 5, over round(R * 2^22)
+                                  and over the remainder's round((R * 2^22 - v) * 2^22), so R is
+                                  carried to 2^-45 absolute and summed exactly (FP64-class
+                                  results; slower than path 5; at most 2^24 - 1 sequences) */
 
 typedef struct plm_ctx plm_ctx;
 
@@ -198,8 +204,9 @@ typedef struct {
                            above its rounding floor (tol) and the refinement the target
                            (refine_tol).
                            plm_fit_symmetric: automatic refines after either fixed-point
-                           path on PLM_PATH_GATHER_MFMA_F16X2 (their rounding, summed
-                           over all parameters, is of the order of the tolerance). */
+                           path on PLM_PATH_GATHER64_MFMA_I8X6 (the FP32 evaluations'
+                           rounding, summed over all parameters, is of the order of
+                           1e-6 at N = 500). */
   int32_t n_probe;      /* plm_fit only: number of sites watched by the convergence probe
                            (0 = none).  After the start point is set up and after every
                            iteration (of the refinement fit too), the probe writes one

@@ -9,7 +9,7 @@ from .api import (FitOptions, FitResult, Probe, contact_tpr, context, fit, fit_b
                   objgrad, objgrad_static, parse_alignment, read_alignment, reweight, score, sync, tune, workspace)
 from ._lib import (PATH_GATHER_FP32, PATH_GATHER_MFMA_F16X2, PATH_GATHER_MFMA_FP32, PATH_GATHER_MFMA_I8X3,
                    PATH_MFMA_BF16X2,
-                   PATH_MFMA_FP32, PATH_MFMA_I8X3, PlmError)
+                   PATH_MFMA_FP32, PATH_MFMA_I8X3, PATH_GATHER64_MFMA_I8X6, PlmError)
 
 __all__ = ["PLMObjective", "plm_objective", "FitOptions", "FitResult", "context", "fit", "fit_batch", "fit_symmetric", "mf_init",
            "last_fit_timing", "objgrad", "reweight", "score", "sync", "tune", "autotune", "workspace",

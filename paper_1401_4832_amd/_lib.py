@@ -23,6 +23,7 @@ PATH_MFMA_FP32 = 3
 PATH_GATHER_MFMA_F16X2 = 4
 PATH_GATHER_MFMA_I8X3 = 5
 PATH_MFMA_I8X3 = 6
+PATH_GATHER64_MFMA_I8X6 = 7
 
 STATIC_SCRATCH_BYTES = 64 << 20
 

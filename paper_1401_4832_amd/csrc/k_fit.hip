@@ -93,6 +93,17 @@ __global__ void compact_kernel(BatchArgs b, const SiteState* st, int32_t* host_c
   finish_tables(b);
 }
 
+// Clear the queue counters of one kind, so that a second launch of that
+// kind's persistent kernel drains the same work items again.
+__global__ void reset_queues_kernel(BatchArgs b, int32_t kind) {
+  if (threadIdx.x < kQueues) b.ctr[kind * kQueues + threadIdx.x] = 0u;
+}
+
+hipError_t launch_reset_queues(const BatchArgs& b, int32_t kind, hipStream_t st) {
+  hipLaunchKernelGGL(reset_queues_kernel, dim3(1), dim3(64), 0, st, b, kind);
+  return hipGetLastError();
+}
+
 // Tables of a one-alignment batch over an explicit site list (list[j], or
 // first + j when list is null).  Site indices outside [0, N) are replaced by
 // 0 and raise bit 4 of *flag.

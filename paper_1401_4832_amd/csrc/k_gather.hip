@@ -60,14 +60,20 @@ constexpr int kPosBytes = kQMax * kRowF * 4;  // 5376
 static_assert((kFwdPos - 1) * kPosBytes + 20 * 256 + 255 < 65536, "LDS offsets fit the immediate field");
 constexpr int kFwdJFloats = kFwdPos * kQMax * kRowF;
 constexpr int kFwdParkFloats = kFwdWaves * 16 * 64;
-constexpr int kFwdLdsFloats = kFwdJFloats > kFwdParkFloats ? kFwdJFloats : kFwdParkFloats;
+// LDS floats of the forward block: the J chunk, or the parked energies (AT values)
+template <class AT>
+constexpr int fwd_lds_floats() {
+  return kFwdJFloats > kFwdParkFloats * (int)(sizeof(AT) / 4) ? kFwdJFloats : kFwdParkFloats * (int)(sizeof(AT) / 4);
+}
 
 // One forward work item: site r x sequence tile `tile` of one alignment.
 // lds: J_r for kFwdPos columns, 3 copies per row, with a fixed pitch of kQMax
 // rows per column so that a column's offset is a compile-time constant (and
 // later the parked energies); sgl: the tile's symbols for those columns; red:
-// FP64 reduction scratch.
-template <int NB>
+// FP64 reduction scratch.  AT is the accumulation type of the energies and of
+// the log-softmax and residuals: float, or double (the precise path, whose
+// residuals go out as two sets of int8 digits, rfrag = 3).
+template <int NB, class AT>
 __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, uint2* sgl,
                                 double* red) {
   constexpr int tileSeq = kFwdWaves * kSlots * NB;
@@ -80,8 +86,8 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
   const int tw = wid * (NB * kSlots) + slotA;  // tile row of row j: tw + 3j
   const int bw = tile0 + tw;
 
-  float E[NB];
-  const float hv = act ? gmem(a.h)[r * q + s] : 0.f;
+  AT E[NB];
+  const AT hv = act ? (AT)gmem(a.h)[r * q + s] : (AT)0;
 #pragma unroll
   for (int j = 0; j < NB; ++j) E[j] = hv;
 
@@ -141,12 +147,12 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
     for (int j = 0; j < NB; ++j) {
       const uint2 sg = sgl[tw + 3 * j];
       // two accumulation chains (even and odd columns)
-      float acc0 = E[j], acc1 = 0.f;
+      AT acc0 = E[j], acc1 = (AT)0;
 #pragma unroll
       for (int p = 0; p < kFwdPos; ++p) {
         const uint32_t word = p < 4 ? sg.x : sg.y;
         const uint32_t addr = __builtin_amdgcn_perm(lane4, word, 0x0c0c0004u | ((uint32_t)(p & 3) << 8));
-        const float v = *reinterpret_cast<const float*>(L + addr + p * kPosBytes);
+        const AT v = (AT)*reinterpret_cast<const float*>(L + addr + p * kPosBytes);
         if (p == 1) acc1 = v;
         else if (p & 1) acc1 += v;
         else acc0 += v;
@@ -162,7 +168,7 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
   // the per-row work below runs as a loop rather than unrolled over all rows.
   double facc = 0.0, ghacc = 0.0;
   const int sbase = slotA * kSlot;
-  float* park = lds + wid * (16 * 64);  // 16 rows x 64 lanes per wave (64 KB in all)
+  AT* park = reinterpret_cast<AT*>(lds) + wid * (16 * 64);  // 16 rows x 64 lanes per wave
 #pragma unroll
   for (int g = 0; g < NB / 16; ++g) {
     __syncthreads();
@@ -172,34 +178,58 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
 #pragma unroll 1
     for (int jj = 0; jj < 16; ++jj) {
       const int b = bw + 3 * (g * 16 + jj);
-      const float e = act ? park[jj * 64 + lane] : -INFINITY;
-      float m = e;
+      const AT e = act ? park[jj * 64 + lane] : (AT)-INFINITY;
+      AT m = e;
 #pragma unroll
       for (int d = 1; d < 32; d <<= 1) {
-        const float o = __shfl_down(m, d, 64);
-        if (s + d < kSlot) m = fmaxf(m, o);
+        const AT o = __shfl_down(m, d, 64);
+        if (s + d < kSlot) m = fmax(m, o);
       }
       m = __shfl(m, sbase, 64);
-      const float ex = act ? expf(e - m) : 0.f;
-      float sum = ex;
+      const AT ex = act ? (AT)exp(e - m) : (AT)0;
+      AT sum = ex;
 #pragma unroll
       for (int d = 1; d < 32; d <<= 1) {
-        const float o = __shfl_down(sum, d, 64);
+        const AT o = __shfl_down(sum, d, 64);
         if (s + d < kSlot) sum += o;
       }
       sum = __shfl(sum, sbase, 64);
-      const float lse = m + logf(sum);
+      const AT lse = m + (AT)log(sum);
       const int sr = gmem(a.msa_cm)[((size_t)(r / kFwdChunk) * a.B_pad + b) * kFwdChunk + r % kFwdChunk];
       const double wb = (slot < kSlots && b < a.B) ? gmem(a.w)[b] : 0.0;
-      const float P = ex / sum;
-      const float Rv = act ? (float)wb * (P - (s == sr ? 1.f : 0.f)) : 0.f;
+      const AT P = ex / sum;
+      const AT Rv = act ? (AT)wb * (P - (s == sr ? (AT)1 : (AT)0)) : (AT)0;
       if (act && s == sr) facc += wb * (double)(lse - e);
       ghacc += (double)Rv;
-      if (a.rfrag == 2) {
+      if (a.rfrag == 3) {
+        // two sets of int8 digits, in the int8 gradient's fragment order for
+        // every row of the tile (zero past B): v = round(R * 2^22) and, in the
+        // second set, the remainder's round((R * 2^22 - v) * 2^22) -- R to
+        // 2^-45 absolute; each set's integer sums are exact
+        if (slot < kSlots) {
+          const double x = (double)Rv * (double)(1 << kRiScaleLog2);
+          const double vh = rint(x);
+          const int vv[2] = {(int)vh, (int)rint((x - vh) * (double)(1 << kRiScaleLog2))};
+          auto Ri = gmem_w(reinterpret_cast<int8_t*>(a.R));
+          const size_t ix = rifrag_index(r, a.B_pad >> 8, b, s);
+          const size_t lo_off = (size_t)a.N * (a.B_pad >> 8) * kRiChunkBytes;
+#pragma unroll
+          for (int z = 0; z < 2; ++z) {
+            const int v = vv[z];
+            const int lo = (int)(int8_t)(v & 255);
+            const int v1 = (v - lo) >> 8;
+            const int mid = (int)(int8_t)(v1 & 255);
+            const int hi = (v1 - mid) >> 8;
+            Ri[z * lo_off + ix] = (int8_t)hi;
+            Ri[z * lo_off + ix + kRiDigitBytes] = (int8_t)mid;
+            Ri[z * lo_off + ix + 2 * kRiDigitBytes] = (int8_t)lo;
+          }
+        }
+      } else if (a.rfrag == 2) {
         // int8 digits of round(R * 2^22) in the int8 gradient's fragment
         // order, for every row of the tile (zero past B)
         if (slot < kSlots) {
-          const int v = (int)rintf(Rv * (float)(1 << kRiScaleLog2));
+          const int v = (int)rintf((float)Rv * (float)(1 << kRiScaleLog2));
           const int lo = (int)(int8_t)(v & 255);
           const int v1 = (v - lo) >> 8;
           const int mid = (int)(int8_t)(v1 & 255);
@@ -214,7 +244,7 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
         // FP16 hi/lo pieces of R * 2^12 in the grouped gradient's fragment
         // order, for every row of the tile (zero past B)
         if (slot < kSlots) {
-          const float v = Rv * kRfScale;
+          const float v = (float)Rv * kRfScale;
           const _Float16 hi = (_Float16)v;
           const _Float16 lo = (_Float16)(v - (float)hi);
           auto Rf = gmem_w(reinterpret_cast<uint16_t*>(a.R));
@@ -223,7 +253,7 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
           Rf[ix + kRfPieceWords] = __builtin_bit_cast(uint16_t, lo);
         }
       } else if (slot < kSlots && b < a.B3) {
-        gmem_w(a.R)[((size_t)r * a.B3 + b) * kSlot + s] = Rv;
+        gmem_w(a.R)[((size_t)r * a.B3 + b) * kSlot + s] = (float)Rv;
       }
     }
   }
@@ -240,9 +270,9 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
 }
 
 // Persistent forward kernel: drains the forward work items of the batch.
-template <int NB>
+template <int NB, class AT>
 __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(BatchArgs b) {
-  __shared__ float lds[kFwdLdsFloats];
+  __shared__ __attribute__((aligned(16))) float lds[fwd_lds_floats<AT>()];
   __shared__ uint2 sgl[kFwdWaves * kSlots * NB];
   __shared__ double red[kFwdWaves * 64];
   __shared__ int32_t item_s;
@@ -255,28 +285,40 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(BatchArgs b) {
     if (t < 0) break;
     const Item it = decode_item(b, KIND_FWD, t);
     const EvalArgs a = load_uniform(b.ev + it.m);
-    fwd_item<NB>(a, it.r, it.sub, lds, sgl, red);
+    fwd_item<NB, AT>(a, it.r, it.sub, lds, sgl, red);
     __syncthreads();
   }
 }
 
-hipError_t launch_forward(const BatchArgs& b, int32_t nb, int32_t nblocks, hipStream_t st) {
+// The precise path accumulates in FP64 with tiles of kFwdF64Rows rows per wave.
+constexpr int kFwdF64Rows = 32;
+int32_t forward_f64_tile_seqs() { return kFwdWaves * kSlots * kFwdF64Rows; }
+
+hipError_t launch_forward(const BatchArgs& b, int32_t nb, int32_t nblocks, int32_t f64, hipStream_t st) {
+  if (f64) {
+    hipLaunchKernelGGL((fwd_kernel<kFwdF64Rows, double>), dim3(nblocks), dim3(kFwdThreads), 0, st, b);
+    return hipGetLastError();
+  }
   switch (nb) {
-    case 16: hipLaunchKernelGGL(fwd_kernel<16>, dim3(nblocks), dim3(kFwdThreads), 0, st, b); break;
-    case 32: hipLaunchKernelGGL(fwd_kernel<32>, dim3(nblocks), dim3(kFwdThreads), 0, st, b); break;
-    case 64: hipLaunchKernelGGL(fwd_kernel<64>, dim3(nblocks), dim3(kFwdThreads), 0, st, b); break;
+    case 16: hipLaunchKernelGGL((fwd_kernel<16, float>), dim3(nblocks), dim3(kFwdThreads), 0, st, b); break;
+    case 32: hipLaunchKernelGGL((fwd_kernel<32, float>), dim3(nblocks), dim3(kFwdThreads), 0, st, b); break;
+    case 64: hipLaunchKernelGGL((fwd_kernel<64, float>), dim3(nblocks), dim3(kFwdThreads), 0, st, b); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-int32_t forward_resident_blocks(int32_t nb) {
+int32_t forward_resident_blocks(int32_t nb, int32_t f64) {
   int per = 0;
   hipError_t e = hipErrorInvalidValue;
+  if (f64) {
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<kFwdF64Rows, double>, kFwdThreads, 0);
+    return (e == hipSuccess && per > 0) ? per : 1;
+  }
   switch (nb) {
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<16>, kFwdThreads, 0); break;
-    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<32>, kFwdThreads, 0); break;
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<64>, kFwdThreads, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<16, float>, kFwdThreads, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<32, float>, kFwdThreads, 0); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<64, float>, kFwdThreads, 0); break;
     default: break;
   }
   return (e == hipSuccess && per > 0) ? per : 1;

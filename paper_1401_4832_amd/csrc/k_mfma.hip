@@ -777,6 +777,10 @@ __device__ inline uint4 onehot16_i8(uint4 s16, uint32_t kk) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// LO = false: the residual digits of round(R * 2^22), written to the gradient
+// data part; LO = true (second pass of the precise path): the digits of the
+// remainder, round((R * 2^22 - v) * 2^22), added to it scaled by 2^-44.
+template <bool LO>
 __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Item& it, int8_t* Rb0, int8_t* Rb1,
                                uint8_t* sig0, uint8_t* sig1) {
   const int npos_blk = g3_block_positions(a.q);
@@ -827,7 +831,8 @@ __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Ite
     const int g = k >> 4, part = k & 15;
     const int off = min(part * 1024, kRiChunkBytes - 1024);
     const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
-    rsrc[j] = reinterpret_cast<const char*>(a.R) + (size_t)rg * nch_site * kRiChunkBytes + off;
+    rsrc[j] = reinterpret_cast<const char*>(a.R) + (LO ? (size_t)N * nch_site * kRiChunkBytes : 0) +
+              (size_t)rg * nch_site * kRiChunkBytes + off;
     rdst[j] = (uint32_t)(g * kISiteStride + off);
   }
   auto fetch_r = [&](int c, int8_t* dst) {
@@ -845,8 +850,8 @@ __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Ite
       const int g = k >> 4, part = k & 15;
       const int off = min(part * 1024, kRiChunkBytes - 1024);
       const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
-      const char* src = reinterpret_cast<const char*>(a.R) + ((size_t)rg * nch_site + c) * kRiChunkBytes + off +
-                        lane * 16;
+      const char* src = reinterpret_cast<const char*>(a.R) + (LO ? (size_t)N * nch_site * kRiChunkBytes : 0) +
+                        ((size_t)rg * nch_site + c) * kRiChunkBytes + off + lane * 16;
       __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
                                        (void __attribute__((address_space(3)))*)(
                                            reinterpret_cast<char*>(dst) + g * kISiteStride + off),
@@ -921,7 +926,8 @@ __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Ite
     if (c + 1 < nchunks) chunk(c + 1, Rb1, Rb0, sig1, sig0);
   }
   if (!wave_live) return;
-  constexpr double kScale = 1.0 / (double)(1 << kRiScaleLog2);
+  constexpr double kScale = LO ? 1.0 / ((double)(1 << kRiScaleLog2) * (double)(1 << kRiScaleLog2))
+                               : 1.0 / (double)(1 << kRiScaleLog2);
 #pragma unroll
   for (int T = 0; T < kGT; ++T) {
     const int col = 32 * T + l32;
@@ -938,12 +944,18 @@ __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Ite
           // exact: every digit sum is an integer below 2^31
           const double v = (double)acc[0][m][T][j] * 65536.0 + (double)acc[1][m][T][j] * 256.0 +
                            (double)acc[2][m][T][j];
-          gmem_w(a.gJ)[((size_t)rg * N + i) * qq + (size_t)k * q + sidx] = (i == rg) ? 0.0 : v * kScale;
+          auto out = gmem_w(a.gJ) + ((size_t)rg * N + i) * qq + (size_t)k * q + sidx;
+          if (LO) {
+            if (i != rg) *out += v * kScale;
+          } else {
+            *out = (i == rg) ? 0.0 : v * kScale;
+          }
         }
       }
   }
 }
 
+template <bool LO>
 __global__ __launch_bounds__(kGThreads) void bwd_i8_kernel(BatchArgs b) {
   __shared__ __attribute__((aligned(16))) int8_t Rb0[kIBufBytes];
   __shared__ __attribute__((aligned(16))) int8_t Rb1[kIBufBytes];
@@ -959,7 +971,7 @@ __global__ __launch_bounds__(kGThreads) void bwd_i8_kernel(BatchArgs b) {
     if (t < 0) break;
     const Item it = decode_item(b, KIND_BWD, t);
     const EvalArgs a = load_uniform(b.ev + it.m);
-    i8_item(b, a, it, Rb0, Rb1, sig0, sig1);
+    i8_item<LO>(b, a, it, Rb0, Rb1, sig0, sig1);
     __syncthreads();
   }
 }
@@ -968,12 +980,13 @@ int32_t i8_backward_blocks_per_site(int32_t N, int32_t q) { return g3_backward_b
 
 int32_t i8_resident_blocks() {
   int per = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bwd_i8_kernel, kGThreads, 0);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bwd_i8_kernel<false>, kGThreads, 0);
   return (e == hipSuccess && per > 0) ? per : 1;
 }
 
-hipError_t launch_backward_i8(const BatchArgs& b, int32_t nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(bwd_i8_kernel, dim3(nblocks), dim3(kGThreads), 0, st, b);
+hipError_t launch_backward_i8(const BatchArgs& b, int32_t nblocks, int32_t lo, hipStream_t st) {
+  if (lo) hipLaunchKernelGGL(bwd_i8_kernel<true>, dim3(nblocks), dim3(kGThreads), 0, st, b);
+  else hipLaunchKernelGGL(bwd_i8_kernel<false>, dim3(nblocks), dim3(kGThreads), 0, st, b);
   return hipGetLastError();
 }
 

@@ -103,7 +103,9 @@ struct EvalBufs {
   int32_t NG;
 };
 
-void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
+// wide: room for the precise path's two residual digit sets (126 bytes per
+// site and row instead of 21 floats)
+void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e, bool wide = false) {
   e.B_pad = (int32_t)rup(B, kBPadUnit);
   e.N_pad = (int32_t)rup(N, kFwdChunk);
   e.B3 = (int32_t)rup(B, 3);
@@ -113,7 +115,7 @@ void layout_eval(Bump& bp, int32_t B, int32_t N, int32_t q, EvalBufs& e) {
   e.msa_cm = bp.take<uint8_t>((size_t)e.B_pad * e.N_pad);
   e.msaT = bp.take<uint8_t>((size_t)e.B_pad * e.N_pad);
   // FP32 rows [B3][21], or the fragment-order FP16 pieces over B_pad rows
-  e.R = bp.take<float>((size_t)N * e.B_pad * kSlot);
+  e.R = bp.take<float>((size_t)N * e.B_pad * (wide ? 32 : kSlot));
   e.f_part = bp.take<double>((size_t)e.tiles_max * N);
   e.gh_part = bp.take<double>((size_t)e.tiles_max * N * kSlot);
   e.gJ = bp.take<double>((size_t)N * N * q * q);
@@ -136,8 +138,8 @@ struct FitBufs {
   double *dpart, *part, *ghd;
 };
 
-void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, int32_t hist64, FitBufs& f) {
-  layout_eval(bp, B, N, q, f.ev);
+void layout_fit(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, int32_t hist64, bool wide, FitBufs& f) {
+  layout_eval(bp, B, N, q, f.ev, wide);
   const size_t Nq = (size_t)N * q, NNqq = (size_t)N * N * q * q;
   const size_t hb = hist64 ? 2 : 1;  // history values in floats
   f.Th = bp.take<float>(Nq);
@@ -213,8 +215,8 @@ struct SymBufs {
   Tables t;
 };
 
-void layout_sym(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, int32_t nblk, SymBufs& f) {
-  layout_eval(bp, B, N, q, f.ev);
+void layout_sym(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, int32_t nblk, bool wide, SymBufs& f) {
+  layout_eval(bp, B, N, q, f.ev, wide);
   const size_t Nq = (size_t)N * q, NNqq = (size_t)N * N * q * q;
   f.Th = bp.take<float>(Nq);
   f.TJ = bp.take<float>(NNqq);
@@ -277,6 +279,7 @@ struct PathSpec {
   int bwd_g3;   // grouped gradient: three sites per item, R split by the forward
   int bwd_i8;   // grouped gradient on int8 digits of R (fixed point, exact accumulation)
   int fwd_i8;   // grouped forward on int8 digits of J (fixed point, exact accumulation)
+  int f64;      // precise path: FP64 gather forward, residuals as two int8 digit sets, two gradient passes
 };
 
 // sites per work item
@@ -288,19 +291,23 @@ bool path_fits(const PathSpec& p, int32_t B) { return !p.bwd_i8 || B < (1 << 24)
 
 bool path_spec(int32_t path, PathSpec* p) {
   switch (path) {
-    case PLM_PATH_GATHER_FP32: *p = {0, 0, 0, 0, 0, 0}; return true;
-    case PLM_PATH_MFMA_BF16X2: *p = {2, 2, 0, 0, 0, 0}; return true;
-    case PLM_PATH_GATHER_MFMA_FP32: *p = {0, 3, 0, 0, 0, 0}; return true;
-    case PLM_PATH_MFMA_FP32: *p = {3, 3, 0, 0, 0, 0}; return true;
-    case PLM_PATH_GATHER_MFMA_F16X2: *p = {0, 2, 1, 1, 0, 0}; return true;
-    case PLM_PATH_GATHER_MFMA_I8X3: *p = {0, 3, 0, 0, 1, 0}; return true;
-    case PLM_PATH_MFMA_I8X3: *p = {0, 3, 0, 0, 1, 1}; return true;
+    case PLM_PATH_GATHER_FP32: *p = {0, 0, 0, 0, 0, 0, 0}; return true;
+    case PLM_PATH_MFMA_BF16X2: *p = {2, 2, 0, 0, 0, 0, 0}; return true;
+    case PLM_PATH_GATHER_MFMA_FP32: *p = {0, 3, 0, 0, 0, 0, 0}; return true;
+    case PLM_PATH_MFMA_FP32: *p = {3, 3, 0, 0, 0, 0, 0}; return true;
+    case PLM_PATH_GATHER_MFMA_F16X2: *p = {0, 2, 1, 1, 0, 0, 0}; return true;
+    case PLM_PATH_GATHER_MFMA_I8X3: *p = {0, 3, 0, 0, 1, 0, 0}; return true;
+    case PLM_PATH_MFMA_I8X3: *p = {0, 3, 0, 0, 1, 1, 0}; return true;
+    case PLM_PATH_GATHER64_MFMA_I8X6: *p = {0, 3, 0, 0, 1, 0, 1}; return true;
     default: return false;
   }
 }
 
 int32_t eval_tiles(const PathSpec& p, int32_t B, int32_t nb) {
-  const int32_t t = p.fwd_i8 ? fwd_i8_tile_seqs() : p.fwd_np ? mfma_forward_tile_seqs() : forward_tile_seqs(nb);
+  const int32_t t = p.fwd_i8   ? fwd_i8_tile_seqs()
+                    : p.fwd_np ? mfma_forward_tile_seqs()
+                    : p.f64    ? forward_f64_tile_seqs()
+                               : forward_tile_seqs(nb);
   return (B + t - 1) / t;
 }
 
@@ -319,8 +326,12 @@ hipError_t eval_prepare(const PathSpec& p, const EvalArgs& a, uint8_t* msaT, uin
     return p.fwd_i8 ? launch_sym3(a.msa_cm, a.B_pad, a.N, a.NG, const_cast<uint32_t*>(a.sym3), st)
                     : hipSuccess;
   if (p.bwd_g3 || p.bwd_i8) {
-    const hipError_t e =
+    hipError_t e =
         launch_rfrag_tail_zero(a.R, a.N, a.B, a.B3, a.B_pad, p.bwd_i8 ? kRiChunkBytes : kRfChunkBytes, st);
+    if (e == hipSuccess && p.f64)  // the remainder digits
+      e = launch_rfrag_tail_zero(reinterpret_cast<float*>(reinterpret_cast<char*>(a.R) +
+                                                          (size_t)a.N * (a.B_pad >> 8) * kRiChunkBytes),
+                                 a.N, a.B, a.B3, a.B_pad, kRiChunkBytes, st);
     if (e != hipSuccess) return e;
   }
   if (p.fwd_i8) {
@@ -340,7 +351,7 @@ Grids eval_grids(const plm_ctx* c, const PathSpec& p, int32_t nb) {
   Grids g;
   g.fwd = c->ncu * (p.fwd_i8   ? fwd_i8_resident_blocks()
                     : p.fwd_np ? mfma_resident_blocks(KIND_FWD, p.fwd_np)
-                               : forward_resident_blocks(nb));
+                               : forward_resident_blocks(nb, p.f64));
   g.bwd = c->ncu * (p.bwd_g3   ? g3_resident_blocks()
                     : p.bwd_i8 ? i8_resident_blocks()
                     : p.bwd_np ? mfma_resident_blocks(KIND_BWD, p.bwd_np)
@@ -356,7 +367,7 @@ hipError_t eval_quant(const PathSpec& p, const BatchArgs& b, hipStream_t st) {
 hipError_t eval_forward_main(const PathSpec& p, const BatchArgs& b, int32_t nb, const Grids& g,
                              hipStream_t st) {
   if (p.fwd_i8) return launch_fwd_i8(b, g.fwd, st);
-  return p.fwd_np ? launch_forward_mfma(b, p.fwd_np, g.fwd, st) : launch_forward(b, nb, g.fwd, st);
+  return p.fwd_np ? launch_forward_mfma(b, p.fwd_np, g.fwd, st) : launch_forward(b, nb, g.fwd, p.f64, st);
 }
 
 hipError_t eval_forward(const PathSpec& p, const BatchArgs& b, int32_t nb, const Grids& g,
@@ -367,7 +378,13 @@ hipError_t eval_forward(const PathSpec& p, const BatchArgs& b, int32_t nb, const
 
 hipError_t eval_backward(const PathSpec& p, const BatchArgs& b, const Grids& g, hipStream_t st) {
   if (p.bwd_g3) return launch_backward_g3(b, g.bwd, st);
-  if (p.bwd_i8) return launch_backward_i8(b, g.bwd, st);
+  if (p.bwd_i8) {
+    hipError_t e = launch_backward_i8(b, g.bwd, 0, st);
+    if (e != hipSuccess || !p.f64) return e;
+    // the remainder pass drains the same work items: its queues start again
+    e = launch_reset_queues(b, KIND_BWD, st);
+    return e == hipSuccess ? launch_backward_i8(b, g.bwd, 1, st) : e;
+  }
   return p.bwd_np ? launch_backward_mfma(b, p.bwd_np, p.bwd_f16, g.bwd, st) : launch_backward(b, g.bwd, st);
 }
 
@@ -381,7 +398,7 @@ EvalArgs eval_args(const EvalBufs& e, const uint8_t* msa_unused, int32_t B, int3
   a.w = w; a.h = h; a.J = J;
   a.R = e.R; a.f_part = e.f_part; a.gh_part = e.gh_part; a.gJ = e.gJ;
   a.tiles = tiles;
-  a.rfrag = ps.bwd_i8 ? 2 : (ps.bwd_g3 ? 1 : 0);
+  a.rfrag = ps.f64 ? 3 : ps.bwd_i8 ? 2 : (ps.bwd_g3 ? 1 : 0);
   a.Wq = e.Wq;
   a.jexp = e.jexp;
   a.sym3 = e.sym3;
@@ -495,11 +512,10 @@ int plm_reweight(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q
 }
 
 size_t plm_objgrad_workspace_bytes(int32_t B, int32_t N, int32_t q, int32_t path) {
-  (void)path;
   if (B < 1 || N < 2 || q < 2 || q > kQMax) return 0;
   Bump bp{nullptr, 0};
   EvalBufs e;
-  layout_eval(bp, B, N, q, e);
+  layout_eval(bp, B, N, q, e, path == PLM_PATH_GATHER64_MFMA_I8X6);
   Tables t;
   layout_tables(bp, 1, N, false, t);
   return rup(bp.off, 256);
@@ -531,7 +547,7 @@ int objgrad_impl(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q
   HIPCHK(c, hipSetDevice(c->device));
   Bump bp{(char*)ws, 0};
   EvalBufs e;
-  layout_eval(bp, B, N, q, e);
+  layout_eval(bp, B, N, q, e, path == PLM_PATH_GATHER64_MFMA_I8X6);
   Tables t;
   layout_tables(bp, 1, N, false, t);
   const BatchArgs b = batch_args(t, 1, N, bwd_group(ps), fwd_group(ps));
@@ -632,6 +648,16 @@ bool fit_opts_ok(const plm_fit_opts* o) {
          (o->history_fp64 == 0 || o->history_fp64 == 1);
 }
 
+int32_t refine_path(const plm_fit_opts* o);
+int32_t refine_path_sym(const plm_fit_opts* o);
+// the workspace needs the precise path's wide residual buffer
+bool fit_wide(const plm_fit_opts* o) {
+  return o->path == PLM_PATH_GATHER64_MFMA_I8X6 || refine_path(o) == PLM_PATH_GATHER64_MFMA_I8X6;
+}
+bool sym_wide(const plm_fit_opts* o) {
+  return o->path == PLM_PATH_GATHER64_MFMA_I8X6 || refine_path_sym(o) == PLM_PATH_GATHER64_MFMA_I8X6;
+}
+
 // Alignments in batch order: decreasing evaluation cost B * N^2, ties by index.
 std::vector<int32_t> batch_order(const plm_msa_desc* d, int32_t n) {
   std::vector<int32_t> ord(n);
@@ -651,7 +677,7 @@ size_t fit_layout(const plm_msa_desc* d, int32_t n, int32_t q, const plm_fit_opt
   for (int32_t k = 0; k < n; ++k) {
     const plm_msa_desc& m = d[ord[k]];
     FitBufs f;
-    layout_fit(bp, m.B, m.N, q, o->lbfgs_m, o->history_fp64, f);
+    layout_fit(bp, m.B, m.N, q, o->lbfgs_m, o->history_fp64, fit_wide(o), f);
     if (bufs) (*bufs)[k] = f;
     total += m.N;
   }
@@ -729,7 +755,9 @@ int prepare_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const p
     L.N = m.N; L.q = q; L.m = o->lbfgs_m; L.max_iter = o->max_iter; L.max_ls = o->max_linesearch;
     L.tiles = a.tiles; L.tol = o->tol; L.lambda_h = o->lambda_h; L.lambda_Jp = 0.5 * o->lambda_J;
     L.c1 = 1e-4;
-    L.noise = 1e-7;  // relative rounding noise allowed in the FP32 objective
+    // relative rounding noise allowed in the objective's sufficient-decrease test:
+    // that of the FP32 evaluations, or of the precise path's FP64 one
+    L.noise = ps.f64 ? 2e-14 : 1e-7;
     L.beff = m.beff;
     L.Xh = m.h_io; L.XJ = m.J_io; L.Th = f.Th; L.TJ = f.TJ;
     L.Gh = f.Gh; L.GJ = f.GJ; L.Dh = f.Dh; L.DJ = f.DJ;
@@ -905,7 +933,7 @@ int32_t refine_path(const plm_fit_opts* o) {
 int run_fit(plm_ctx* c, const plm_msa_desc* d, int32_t n, int32_t q, const plm_fit_opts* o,
             void* ws, size_t ws_bytes) {
   const int32_t rp = refine_path(o);
-  if (rp >= 0 && (rp < PLM_PATH_GATHER_FP32 || rp > PLM_PATH_MFMA_I8X3))
+  if (rp >= 0 && (rp < PLM_PATH_GATHER_FP32 || rp > PLM_PATH_GATHER64_MFMA_I8X6))
     return set_err(c, PLM_E_INVALID, "refine: unknown path %d", rp);
   if (!fit_opts_ok(o)) return set_err(c, PLM_E_INVALID, "invalid fit options");
   ProbeArgs pa;
@@ -1137,7 +1165,7 @@ size_t plm_fit_symmetric_workspace_bytes(int32_t B, int32_t N, int32_t q, const 
   }
   Bump bp{nullptr, 0};
   SymBufs f;
-  layout_sym(bp, B, N, q, o->lbfgs_m, 4 * ncu, f);
+  layout_sym(bp, B, N, q, o->lbfgs_m, 4 * ncu, sym_wide(o), f);
   return rup(bp.off, 256);
 }
 
@@ -1162,7 +1190,7 @@ int run_sym_once(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q
   {
     Bump bq{nullptr, 0};
     SymBufs fq;
-    layout_sym(bq, B, N, q, o->lbfgs_m, nblk, fq);
+    layout_sym(bq, B, N, q, o->lbfgs_m, nblk, sym_wide(o), fq);
     rc = check_ws(c, ws, ws_bytes, rup(bq.off, 256));
     if (rc) return rc;
   }
@@ -1170,7 +1198,7 @@ int run_sym_once(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q
   if (rc) return rc;
   Bump bp{(char*)ws, 0};
   SymBufs f;
-  layout_sym(bp, B, N, q, o->lbfgs_m, nblk, f);
+  layout_sym(bp, B, N, q, o->lbfgs_m, nblk, sym_wide(o), f);
   HIPCHK(c, hipStreamSynchronize(c->stream));
   hipStream_t st = c->fit_stream;
   c->pin[2] = 0;
@@ -1195,7 +1223,7 @@ int run_sym_once(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q
   SymArgs S;
   S.N = N; S.q = q; S.m = o->lbfgs_m; S.max_iter = o->max_iter; S.max_ls = o->max_linesearch;
   S.tiles = a.tiles; S.nblk = nblk; S.npairs = (int32_t)pairs.size();
-  S.tol = o->tol; S.lambda_h = o->lambda_h; S.lambda_J = o->lambda_J; S.c1 = 1e-4; S.noise = 1e-7;
+  S.tol = o->tol; S.lambda_h = o->lambda_h; S.lambda_J = o->lambda_J; S.c1 = 1e-4; S.noise = ps.f64 ? 2e-14 : 1e-7;
   S.beff = beff;
   S.Xh = h_io; S.XJ = J_io; S.Th = f.Th; S.TJ = f.TJ;
   S.Gh = f.Gh; S.GJ = f.GJ; S.Dh = f.Dh; S.DJ = f.DJ;
@@ -1298,10 +1326,12 @@ int run_sym_once(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q
 
 // Refinement path of the symmetric fit: automatic after either fixed-point
 // path (their rounding noise, summed over all parameters, is of the order of
-// the tolerance), on the FP32-class gather path with the 22-bit gradient.
+// the tolerance), on the precise path (FP64 energies and residuals): the FP32
+// evaluations' own rounding, summed over the N(N-1)/2 q^2 couplings, is of the
+// order of 1e-6 at N = 500.
 int32_t refine_path_sym(const plm_fit_opts* o) {
   if (o->refine == 0)
-    return (o->path == PLM_PATH_GATHER_MFMA_I8X3 || o->path == PLM_PATH_MFMA_I8X3) ? PLM_PATH_GATHER_MFMA_F16X2
+    return (o->path == PLM_PATH_GATHER_MFMA_I8X3 || o->path == PLM_PATH_MFMA_I8X3) ? PLM_PATH_GATHER64_MFMA_I8X6
                                                                                    : -1;
   if (o->refine < 0) return -1;
   const int32_t p = o->refine - 1;
@@ -1318,7 +1348,7 @@ int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int3
   if (!c) return PLM_E_INVALID;
   if (!o) return set_err(c, PLM_E_INVALID, "null pointer");
   const int32_t rp = refine_path_sym(o);
-  if (rp >= 0 && (rp < PLM_PATH_GATHER_FP32 || rp > PLM_PATH_MFMA_I8X3))
+  if (rp >= 0 && (rp < PLM_PATH_GATHER_FP32 || rp > PLM_PATH_GATHER64_MFMA_I8X6))
     return set_err(c, PLM_E_INVALID, "refine: unknown path %d", rp);
   plm_site_stats first;
   memset(&first, 0, sizeof(first));
@@ -1334,6 +1364,7 @@ int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int3
   o2.path = rp;
   o2.refine = -1;
   o2.tile_seqs = 0;
+  if (o->refine_tol > 0.0) o2.tol = o->refine_tol;
   plm_site_stats second;
   memset(&second, 0, sizeof(second));
   const int rc2 = run_sym_once(c, msa, B, N, q, w, beff, &o2, ws, ws_bytes, h_io, J_io, &second);

@@ -86,7 +86,8 @@ struct EvalArgs {
   double* gh_part;         // [tiles][N][21]
   double* gJ;              // [N][N][q][q] data part of d f / d J (FP64)
   int32_t tiles;
-  int32_t rfrag;           // R in gradient-fragment order: 1 FP16 hi/lo pieces, 2 int8 digits (see below)
+  int32_t rfrag;           // R in gradient-fragment order: 1 FP16 hi/lo pieces, 2 int8 digits, 3 two int8 digit
+                           // sets (R and its remainder; the second set after N * B_pad/256 chunks; see below)
   const uint16_t* sorted;  // [nchunks][N][kBwdSeqChunk]: (row << 8) | symbol, rows sorted by symbol
   // int8 forward (path 6): couplings as fixed-point digits, symbols by position triple
   int8_t* Wq;              // [N][NG][3 digits][2 steps][2 halves][21 states][16] bytes
@@ -394,8 +395,11 @@ hipError_t launch_transpose_msa(const uint8_t* msa_cm, int32_t B_pad, int32_t N_
 hipError_t launch_chunk_sort(const uint8_t* msa_cm, int32_t B3, int32_t B_pad, int32_t N, int32_t q,
                              uint16_t* sorted, hipStream_t st);
 int32_t forward_tile_seqs(int32_t nb);
-int32_t forward_resident_blocks(int32_t nb);
-hipError_t launch_forward(const BatchArgs& b, int32_t nb, int32_t nblocks, hipStream_t st);
+int32_t forward_resident_blocks(int32_t nb, int32_t f64);
+// f64: the precise path's forward (FP64 energies, log-softmax and residuals,
+// residuals out as two int8 digit sets; its own tile of forward_f64_tile_seqs rows)
+hipError_t launch_forward(const BatchArgs& b, int32_t nb, int32_t nblocks, int32_t f64, hipStream_t st);
+int32_t forward_f64_tile_seqs();
 int32_t backward_blocks_per_site(int32_t N);
 int32_t backward_resident_blocks();
 hipError_t launch_backward(const BatchArgs& b, int32_t nblocks, hipStream_t st);
@@ -424,13 +428,15 @@ hipError_t launch_fwd_i8(const BatchArgs& b, int32_t nblocks, hipStream_t st);
 // grouped int8 fixed-point MFMA gradient (three sites per item, R as digits)
 int32_t i8_backward_blocks_per_site(int32_t N, int32_t q);
 int32_t i8_resident_blocks();
-hipError_t launch_backward_i8(const BatchArgs& b, int32_t nblocks, hipStream_t st);
+// lo: the second pass of the precise path (the remainder digits, added in)
+hipError_t launch_backward_i8(const BatchArgs& b, int32_t nblocks, int32_t lo, hipStream_t st);
 hipError_t launch_forward_mfma(const BatchArgs& b, int32_t npieces, int32_t nblocks, hipStream_t st);
 hipError_t launch_backward_mfma(const BatchArgs& b, int32_t npieces, int32_t f16, int32_t nblocks,
                                 hipStream_t st);
 hipError_t launch_lbfgs(const BatchArgs& b, int32_t nblocks, int32_t history_fp64, hipStream_t st);
 hipError_t launch_compact(const BatchArgs& b, const SiteState* st_, int32_t* host_count,
                           unsigned long long* site_evals, hipStream_t st);
+hipError_t launch_reset_queues(const BatchArgs& b, int32_t kind, hipStream_t st);
 hipError_t launch_list_tables(const BatchArgs& b, const int32_t* list, int32_t first, int32_t n,
                               int32_t* flag, hipStream_t st);
 hipError_t launch_setup_msa(const BatchArgs& b, int32_t m, const EvalArgs& e, const LbfgsArgs* l,

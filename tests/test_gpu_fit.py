@@ -152,7 +152,7 @@ def test_fit_gapped_sampled_pairs_score(plm):
     print(f"  FN differences at most {worst:.2f} of their bounds", flush=True)
 
 
-@pytest.mark.parametrize("path", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("path", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_fit_gapped_sampled_sites(plm, path):
     """Every evaluation path reaches the oracle's minimiser: each fit ends on
     an FP32-class evaluation at 0.9e-6, so the FP64 gradient at the returned
@@ -170,6 +170,15 @@ def test_fit_gapped_sampled_sites(plm, path):
     assert max(st["gnorm"] for st in res.stats) <= 0.9e-6
     assert err <= 1e-4, err
     assert cert <= 1e-4, cert
+    if path == 7:
+        # the precise path's gradient norm is the FP64 one
+        m_o, w_o, beff_o = oracle.reweight(s.msa, theta=0.8)
+        h = res.h.cpu().numpy().astype(np.float64)
+        J = res.J.cpu().numpy().astype(np.float64)
+        for r in sites:
+            _, gh, gJ = oracle.site_objgrad(s.msa, r, w_o, beff_o, h[r], J[r], opts.lambda_h, opts.lambda_J)
+            gn = np.sqrt(np.sum(gh ** 2) + np.sum(gJ ** 2)) / beff_o
+            assert abs(gn - res.stats[r]["gnorm"]) <= 1e-10, (r, gn, res.stats[r]["gnorm"])
 
 
 @pytest.mark.parametrize("lbfgs_m", [3, 10, 20])

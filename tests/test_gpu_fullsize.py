@@ -141,7 +141,7 @@ def random_point(full, sites_gold):
     return h, J, fo, gho, gJo
 
 
-@pytest.mark.parametrize("path", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("path", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_objgrad_full_size_sampled_sites(plm, full, sites_gold, random_point, path):
     s, msa, m, w, beff, g = full
     sites, _ = sites_gold
@@ -169,6 +169,11 @@ def test_objgrad_full_size_sampled_sites(plm, full, sites_gold, random_point, pa
         fb, gb = hilo_bounds(s.msa, h, J, sites)
         assert fabs <= fb + 1e-5 * math.log(q) * 10, (fabs, fb)
         assert gerr <= gb + 2e-6, (gerr, gb)
+    elif path == 7:  # the precise path: FP64-class up to the FP32 rounding of the returned gradient
+        assert frel <= 1e-11, frel
+        excess = max(float(np.max(np.abs(gJs - gJo) - 2.0 ** -24 * np.abs(gJo))),
+                     float(np.max(np.abs(gh - gho) - 2.0 ** -24 * np.abs(gho)))) / beff_o
+        assert excess <= 1e-11, excess
     else:
         assert frel <= 1e-5, frel
         assert gerr <= 2e-6, gerr

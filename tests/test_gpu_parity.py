@@ -87,7 +87,7 @@ def test_reweight_uniform(plm):
 # paths held to the FP32 tolerance: gather/scatter; gather + three-piece BF16 MFMA gradient;
 # three-piece MFMA both ways; gather + FP16 hi/lo MFMA gradient (22 significant bits of R, error
 # <= 2^-22 |R| per residual, i.e. <= 2.4e-7 on the normalised gradient, inside the FP32 bound)
-PATHS = [0, 2, 3, 4, 5, 6]
+PATHS = [0, 2, 3, 4, 5, 6, 7]
 
 
 def _objgrad_case(plm, msa, w_o, beff_o, h, J, lh=0.01, lJ=0.01, sites=None, path=0, fabs=False):
@@ -162,6 +162,38 @@ def test_objgrad_random_point(plm, B, N, q, path):
     frel, gerr, gJ = _objgrad_case(plm, msa, w_o, beff_o, h, J, path=path)
     assert frel <= 1e-5, frel
     assert gerr <= 2e-6, gerr
+    for r in range(N):
+        assert np.all(gJ[r, r] == 0)
+
+
+@pytest.mark.parametrize("B,N,q", [(500, 40, 21), (1, 2, 21), (3001, 33, 21), (800, 25, 3), (1537, 49, 11),
+                                   (4000, 70, 21)])
+def test_objgrad_precise_path_is_fp64_class(plm, B, N, q):
+    """Path 7 (FP64 energies, log-softmax and residuals; residuals carried to
+    2^-45 in two exact integer passes) agrees with the FP64 oracle to FP64
+    rounding: relative objective within 1e-11, and every gradient entry
+    within the FP32 rounding of the call's FP32 output (2^-24 relative) plus
+    1e-11 on the normalised scale."""
+    _note(f"objgrad precise path B={B} N={N} q={q}")
+    rng = np.random.default_rng(B * 13 + N)
+    msa = rng.integers(0, q, size=(B, N), dtype=np.uint8)
+    w_o = rng.uniform(0.2, 1.0, size=B)
+    beff_o = float(np.sum(w_o))
+    h, J = random_params(B + 5 * q, N, q, 0.3, 0.3)
+    f, gh, gJ = plm.objgrad(_to(msa), _to(w_o), _to(np.array([beff_o])), _to(h.astype(np.float32)),
+                            _to(J.astype(np.float32)), 0.01, 0.01, path=7)
+    plm.sync(DEV)
+    Jz = J.astype(np.float32).astype(np.float64)
+    for r in range(N):
+        Jz[r, r] = 0
+    fo, gho, gJo = oracle.objgrad(msa, w_o, beff_o, h.astype(np.float32).astype(np.float64), Jz, 0.01, 0.01)
+    f, gh, gJ = f.cpu().numpy(), gh.cpu().numpy().astype(np.float64), gJ.cpu().numpy().astype(np.float64)
+    frel = float(np.max(np.abs(f - fo) / np.abs(fo)))
+    excess = max(float(np.max(np.abs(gJ - gJo) - 2.0 ** -24 * np.abs(gJo))),
+                 float(np.max(np.abs(gh - gho) - 2.0 ** -24 * np.abs(gho)))) / beff_o
+    print(f"  precise path: f rel {frel:.2e}, gradient beyond FP32 output rounding {excess:.2e}")
+    assert frel <= 1e-11, frel
+    assert excess <= 1e-11, excess
     for r in range(N):
         assert np.all(gJ[r, r] == 0)
 

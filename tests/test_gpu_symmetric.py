@@ -91,7 +91,7 @@ def test_symmetric_fit_matches_oracle(plm, small, path):
 
 def test_symmetric_refinement_continues_the_first_fit(plm, small):
     """After a fixed-point path the symmetric fit is refined (automatically, on
-    path 4) from the first fit's point: the first fit is the refine = -1 fit
+    the precise path 7) from the first fit's point: the first fit is the refine = -1 fit
     bit for bit, the statistics and timing add both, the final gradient norm
     is that of the refinement path's evaluation, and the result stays within
     1e-4 of the oracle's minimiser."""
@@ -116,8 +116,8 @@ def test_symmetric_refinement_continues_the_first_fit(plm, small):
     _check_consistent(J)
     assert max(np.max(np.abs(J - J_o)), np.max(np.abs(h - h_o))) <= 1e-4
     # the refinement's own evaluation at the returned point: a further fit on
-    # path 4 from it stops at once
-    again = plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=1e-6, path=4),
+    # the precise path from it stops at once
+    again = plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=1e-6, path=7),
                               h0=ref.h, J0=ref.J)
     assert again.stats[0]["iterations"] == 0
     # an explicit refinement path, none after an FP32-class path, an unknown one rejected
@@ -172,6 +172,35 @@ def test_symmetric_fit_larger_gapped(plm):
     _check_consistent(J)
     err = max(np.max(np.abs(J - J_o)), np.max(np.abs(res.h.cpu().numpy() - h_o)))
     assert err <= 1e-4, err
+
+
+@pytest.mark.timeout(400)
+def test_symmetric_fit_gapped_n120_precise_refinement(plm):
+    """N = 120, B = 5000 with gaps (the paper-sized single-alignment workload):
+    the symmetric fit on the int8-gradient path to 1e-5, refined automatically
+    on the precise path to 1e-6, converges at ||grad F|| <= 1e-6 over all
+    3.1 M parameters;
+    the oracle's FP64 gradient at the returned point is within 1e-9 of the
+    device's norm and at most 1e-6, so by strong convexity (mu = 0.02) every
+    parameter is within 5e-5 of the exact minimiser."""
+    print("[case] symmetric fit potts_n120_b5000_gaps path 5 + precise refinement", flush=True)
+    s = synth.workload("potts_n120_b5000_gaps")
+    msa, w, beff = _gpu_problem(plm, s)
+    # the int8-gradient path to 1e-5 (above its rounding floor, about 2e-6 here),
+    # then the precise path to 1e-6
+    res = plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=1e-5, refine_tol=1e-6, path=5, timing=True))
+    tm = plm.last_fit_timing(DEV)
+    st = res.stats[0]
+    assert st["status"] == "converged" and st["gnorm"] <= 1e-6, st
+    assert tm["refine_iterations"] >= 1
+    h = res.h.cpu().numpy().astype(np.float64)
+    J = res.J.cpu().numpy().astype(np.float64)
+    _check_consistent(J)
+    F, gn = _certificate(s, h, J, 0.01, 0.01)
+    print(f"  device ||grad F|| {st['gnorm']:.3e}, oracle {gn:.3e}, iterations {st['iterations']} "
+          f"(refinement {tm['refine_iterations']})", flush=True)
+    assert abs(gn - st["gnorm"]) <= 1e-9, (gn, st["gnorm"])
+    assert gn <= 1e-6 and gn / 0.02 <= 5e-5
 
 
 def test_symmetric_errors(plm, small):

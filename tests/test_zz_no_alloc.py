@@ -32,7 +32,7 @@ def _problem(seed, B, N, q=21):
     return msa, w, beff, torch.from_numpy(h.astype(np.float32)).to(DEV), torch.from_numpy(J.astype(np.float32)).to(DEV)
 
 
-@pytest.mark.parametrize("path", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("path", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_static_scratch_matches_workspace_call(plm, path):
     print(f"[case] plm_objgrad_static path={path}", flush=True)
     for seed, B, N in ((5, 3100, 37), (6, 700, 19)):  # the second call is smaller
