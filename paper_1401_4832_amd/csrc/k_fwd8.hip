@@ -6,13 +6,20 @@
 // Couplings in fixed point: each site's J_r is scaled by 2^k_r with
 // max |J_r| 2^k_r in [2^21, 2^22) and rounded (|dJ| <= 2^-(k_r + 1) <= 2^-22 max |J_r|),
 // then written as three signed int8 digits (hi 2^16 + mid 2^8 + lo), once per
-// evaluation (jmax_kernel, jquant_kernel).  The product runs on v_mfma_i32_32x32x32_i8
-// with rows = sequences, columns = the 63 (site, state) pairs of the group in
-// two 32-column tiles, and the inner index over position triples: a triple
-// (3G, 3G+1, 3G+2) x 21 states = 63 inner indices, padded to 64 = two steps
-// of 32.  The one-hot operand of a lane (one sequence, 16 consecutive inner
-// indices) is bits [32 t + 16 half, +16) of the 64-bit mask with bits
-// 21 p + sigma_{3G+p} set, each 4 bits spread to 4 bytes by one multiply.
+// evaluation (jmax_kernel, jquant_kernel).  The product runs on the 4:2 sparse
+// matrix-core instruction v_smfmac_i32_32x32x64_i8 with rows = sequences,
+// columns = the 63 (site, state) pairs of the group in two 32-column tiles, and
+// the inner index over position triples: a triple (3G, 3G+1, 3G+2) x 21 states
+// = 63 inner indices, padded to 64 = one instruction.  The one-hot operand is
+// sparse by construction: position p's states take the inner indices 21p .. 21p+20,
+// so any aligned group of four holds states of at most two positions, hence at
+// most two ones, which is the instruction's 4:2 format; it takes the same time
+// as the dense 32x32x32 int8 product, i.e. half the matrix-core time per triple.
+// A lane's operand (one sequence, inner indices [32 half, +32)) is 16 value
+// bytes (a value pair per group of four) and a word of 2-bit positions; it holds
+// the one of one position that lies wholly in the half and, if it lies there,
+// the one of the middle position.  The coupling operand of a lane is two
+// 16-byte digit fragments, inner indices [16 half, +16) and [32 + 16 half, +16).
 // Each digit plane accumulates exactly in int32 (|digit| <= 128, at most
 // 3 ceil(N/3) one-hot terms per output); the planes are combined and scaled
 // back in FP64 once at the end.  The couplings stream through LDS four
@@ -25,6 +32,7 @@
 namespace plm {
 
 typedef int32_t fi32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t fi32x8 __attribute__((ext_vector_type(8)));
 typedef int32_t fi32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kFIWaves = 8;
@@ -165,7 +173,7 @@ hipError_t launch_sym3(const uint8_t* msa_cm, int32_t B_pad, int32_t N, int32_t 
   return hipGetLastError();
 }
 
-// 16 one-hot bytes (1 where the inner index matches) from 16 mask bits
+// 16 bytes, byte j = bit j of bits (one multiply per 4 bits)
 __device__ inline uint4 spread16(uint32_t bits) {
   uint32_t w[4];
 #pragma unroll
@@ -173,9 +181,31 @@ __device__ inline uint4 spread16(uint32_t bits) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-__device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const Item& it, int8_t* W0, int8_t* W1,
+// The 4:2 sparse one-hot operand of one lane for one position triple.  s3 holds
+// the triple's symbols (byte p = sigma_{3G+p}); the lane's half of the inner
+// index holds the one of position shA / 8 at offset oA + sigma (always inside),
+// and position 1's at oB + sigma when that lies in [0, 32).  Inner index k of
+// the half is group k / 4, position k % 4: the first one takes value slot 0 of
+// its group, the second slot 1 (the two may share a group, never a slot).
+__device__ inline void onehot_sparse(uint32_t s3, int shA, int oA, int oB, uint4& val, uint32_t& pos) {
+  const int kA = (int)((s3 >> shA) & 255u) + oA;
+  const int kB0 = (int)((s3 >> 8) & 255u) + oB;
+  const bool in = (uint32_t)kB0 < 32u;
+  const int kB = in ? kB0 : 0;
+  const uint32_t bytes = (1u << ((kA >> 1) & 0x1e)) | ((uint32_t)in << (((kB >> 1) & 0x1e) + 1));
+  pos = ((uint32_t)(kA & 3) << (kA & 0x1c)) | ((uint32_t)(kB & 3) << ((kB & 0x1c) + 2));
+  val = spread16(bytes);
+}
+
+// The descriptor's fields are read where they are needed (the epilogue's after
+// the product loop), so that they do not occupy scalar registers across it.
+__device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs* ea, const Item& it, int8_t* W0, int8_t* W1,
                                    uint32_t* S0, uint32_t* S1, double* red, double* wrow, uint8_t* srow) {
-  const int q = a.q, N = a.N, NG = a.NG;
+  const int q = load_uniform(&ea->q), N = load_uniform(&ea->N), NG = load_uniform(&ea->NG);
+  const int B_pad = load_uniform(&ea->B_pad);
+  const int32_t* jexp = load_uniform(&ea->jexp);
+  const int8_t* Wq = load_uniform(&ea->Wq);
+  const uint32_t* sym3 = load_uniform(&ea->sym3);
   const int tid = item_tid(), lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: copy bookkeeping in scalars
   const int half = lane >> 5, l32 = lane & 31;
@@ -186,7 +216,7 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
 #pragma unroll
   for (int g = 0; g < kG3Sites; ++g) {
     rs[g] = __builtin_amdgcn_readfirstlane(g < cnt ? bt.active[it.first + g] - bt.site_base[it.m] : it.r);
-    ks[g] = gmem(a.jexp)[rs[g]];
+    ks[g] = gmem(jexp)[rs[g]];
   }
   uint32_t boff[2];
 #pragma unroll
@@ -200,39 +230,40 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
   // global -> LDS copies of stage c: the group's digits of triples 4c .. 4c+3
   // (a site's run is contiguous; the last 1 KB copy of a run is moved back to
   // end at the run's end) and the triples' symbols of the item's sequences,
-  // 1 KB per copy, copy k issued by wave k mod 8.  A full stage of a full
+  // 1 KB per copy, copy k issued by wave k mod 4.  A full stage of a full
   // group has the same copies every stage, shifted by the stage's offsets:
-  // each wave's six coupling copies and one symbol copy are set up once.
+  // wave w copies parts w, w + 4, w + 8, w + 12 of each site's run and two
+  // symbol parts.
   constexpr int kSymParts = kFISeqs / 256;  // 1 KB copies of a triple's symbols
   constexpr int kFullPer = (kFISiteBytes + 1023) / 1024;
-  static_assert(kG3Sites * kFullPer == 6 * kFIWaves && kSymParts * kFIStageG == kFIWaves,
-                "six coupling copies and one symbol copy per wave in a full stage");
-  const char* wsrc[6];
-  uint32_t wdst[6];
+  static_assert(kFullPer % kFIWaves == 0 && (kSymParts * kFIStageG) % kFIWaves == 0,
+                "a full stage's copies divide evenly over the waves");
+  const char* sbase[kG3Sites];
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    const int k = wid + kFIWaves * j;
-    const int g = k / kFullPer, part = k - g * kFullPer;
-    const int off = min(part * 1024, kFISiteBytes - 1024);
-    const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
-    wsrc[j] = reinterpret_cast<const char*>(a.Wq) + (size_t)rg * NG * kWqGroupBytes + off;
-    wdst[j] = (uint32_t)(g * kFISiteStride + off);
-  }
-  const uint32_t* ssrc = a.sym3 + (size_t)(wid / kSymParts) * a.B_pad + b0 + (wid % kSymParts) * 256;
-  const uint32_t sdst = (uint32_t)((wid / kSymParts) * kFISeqs + (wid % kSymParts) * 256);
+  for (int g = 0; g < kG3Sites; ++g)
+    sbase[g] = reinterpret_cast<const char*>(Wq) + (size_t)rs[g] * NG * kWqGroupBytes;
   auto fetch = [&](int c, int8_t* Wd, uint32_t* Sd) {
     const int ng = min(kFIStageG, NG - c * kFIStageG);
     if (ng == kFIStageG && cnt == kG3Sites) {
 #pragma unroll
-      for (int j = 0; j < 6; ++j)
+      for (int g = 0; g < kG3Sites; ++g)
+#pragma unroll
+        for (int j = 0; j < kFullPer / kFIWaves; ++j) {
+          const int off = min((wid + kFIWaves * j) * 1024, kFISiteBytes - 1024);
+          __builtin_amdgcn_global_load_lds(
+              (const void __attribute__((address_space(1)))*)(uniform_ptr(sbase[g] + (size_t)c * kFISiteBytes + off) +
+                                                              lane * 16),
+              (void __attribute__((address_space(3)))*)(Wd + g * kFISiteStride + off), 16, 0, 0);
+        }
+#pragma unroll
+      for (int j = 0; j < kSymParts * kFIStageG / kFIWaves; ++j) {
+        const int k = wid + kFIWaves * j, kg = k / kSymParts, part = k - kg * kSymParts;
         __builtin_amdgcn_global_load_lds(
-            (const void __attribute__((address_space(1)))*)(uniform_ptr(wsrc[j] + (size_t)c * kFISiteBytes) +
-                                                            lane * 16),
-            (void __attribute__((address_space(3)))*)(Wd + wdst[j]), 16, 0, 0);
-      __builtin_amdgcn_global_load_lds(
-          (const void __attribute__((address_space(1)))*)(uniform_ptr(ssrc + (size_t)c * kFIStageG * a.B_pad) +
-                                                          lane * 4),
-          (void __attribute__((address_space(3)))*)(Sd + sdst), 16, 0, 0);
+            (const void __attribute__((address_space(1)))*)(uniform_ptr(sym3 + (size_t)(c * kFIStageG + kg) * B_pad +
+                                                                        b0 + part * 256) +
+                                                            lane * 4),
+            (void __attribute__((address_space(3)))*)(Sd + kg * kFISeqs + part * 256), 16, 0, 0);
+      }
       return;
     }
     const int bytes = ng * kWqGroupBytes;
@@ -243,14 +274,14 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
         const int g = k / per, part = k - g * per;
         const int off = min(part * 1024, bytes - 1024);
         const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
-        const char* src = reinterpret_cast<const char*>(a.Wq) +
+        const char* src = reinterpret_cast<const char*>(Wq) +
                           ((size_t)rg * NG + (size_t)c * kFIStageG) * kWqGroupBytes + off + lane * 16;
         __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
                                          (void __attribute__((address_space(3)))*)(Wd + g * kFISiteStride + off),
                                          16, 0, 0);
       } else {
         const int k2 = k - cnt * per, kg = k2 / kSymParts, part = k2 - kg * kSymParts;
-        const uint32_t* src = a.sym3 + (size_t)(c * kFIStageG + kg) * a.B_pad + b0 + part * 256 + lane * 4;
+        const uint32_t* src = sym3 + (size_t)(c * kFIStageG + kg) * B_pad + b0 + part * 256 + lane * 4;
         __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
                                          (void __attribute__((address_space(3)))*)(Sd + kg * kFISeqs + part * 256),
                                          16, 0, 0);
@@ -266,44 +297,43 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
 #pragma unroll
       for (int T = 0; T < 2; ++T) acc[d][m][T] = fi32x16{};
 
+  // the lane's half of the inner index: half 0 = position 0 (offset 0) and
+  // position 1's states 0..10 (offset 21); half 1 = position 2 (offset 42 - 32)
+  // and position 1's states 11..20 (offset 21 - 32)
+  const int shA = half ? 16 : 0, oA = half ? 2 * kSlot - 32 : 0, oB = half ? kSlot - 32 : kSlot;
+  // the sparse one-hot operands of triple kg for the wave's row blocks
+  auto build_a = [&](const uint32_t* Sc, int kg, uint4* av, uint32_t* ap) {
+#pragma unroll
+    for (int m = 0; m < kFIRB; ++m)
+      onehot_sparse(Sc[kg * kFISeqs + (wid * kFIRB + m) * 32 + l32], shA, oA, oB, av[m], ap[m]);
+  };
   auto stage = [&](int c, const int8_t* Wc, const uint32_t* Sc, int8_t* Wn, uint32_t* Sn) {
     if (c + 1 < nst) fetch(c + 1, Wn, Sn);
     const int ng = min(kFIStageG, NG - c * kFIStageG);
     const char* wb = reinterpret_cast<const char*>(Wc);
     for (int kg = 0; kg < ng; ++kg) {
-      // the one-hot mask of each row block's sequence for this triple
-      uint32_t mlo[kFIRB], mhi[kFIRB];
+      uint4 av[kFIRB];
+      uint32_t ap[kFIRB];
+      build_a(Sc, kg, av, ap);
+      // the six B operands (digit, tile) of this triple, each read one ahead of
+      // its use: the digit fragments of steps 0 and 1 of the lane's half
+      const char* fb = wb + kg * kWqGroupBytes;
+      auto ldb = [&](int f) {
+        const char* p = fb + boff[f & 1] + (f >> 1) * (kWqGroupBytes / 3);
+        const uint4 x = *reinterpret_cast<const uint4*>(p);
+        const uint4 y = *reinterpret_cast<const uint4*>(p + 2 * kSlot * 16);
+        return fi32x8{(int)x.x, (int)x.y, (int)x.z, (int)x.w, (int)y.x, (int)y.y, (int)y.z, (int)y.w};
+      };
+      fi32x8 bq0 = ldb(0);
 #pragma unroll
-      for (int m = 0; m < kFIRB; ++m) {
-        const uint32_t s3 = Sc[kg * kFISeqs + (wid * kFIRB + m) * 32 + l32];
-        uint64_t mask = 0;
+      for (int f = 0; f < 6; ++f) {
+        fi32x8 bq1 = bq0;
+        if (f + 1 < 6) bq1 = ldb(f + 1);
 #pragma unroll
-        for (int p = 0; p < 3; ++p) mask |= 1ull << (kSlot * p + ((s3 >> (8 * p)) & 255u));
-        mlo[m] = (uint32_t)mask;
-        mhi[m] = (uint32_t)(mask >> 32);
-      }
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        uint4 av[kFIRB];
-#pragma unroll
-        for (int m = 0; m < kFIRB; ++m) av[m] = spread16(((t ? mhi[m] : mlo[m]) >> (16 * half)) & 0xffffu);
-        // the six B fragments (digit, tile) of this step, each read two ahead of its use
-        const char* fb = wb + kg * kWqGroupBytes + t * (2 * kSlot * 16);
-        auto ldb = [&](int f) {
-          return *reinterpret_cast<const uint4*>(fb + boff[f & 1] + (f >> 1) * 2 * (2 * kSlot * 16));
-        };
-        uint4 bq0 = ldb(0), bq1 = ldb(1);
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-          uint4 bq2 = bq1;
-          if (f + 2 < 6) bq2 = ldb(f + 2);
-#pragma unroll
-          for (int m = 0; m < kFIRB; ++m)
-            acc[f >> 1][m][f & 1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                __builtin_bit_cast(fi32x4, av[m]), __builtin_bit_cast(fi32x4, bq0), acc[f >> 1][m][f & 1], 0, 0, 0);
-          bq0 = bq1;
-          bq1 = bq2;
-        }
+        for (int m = 0; m < kFIRB; ++m)
+          acc[f >> 1][m][f & 1] = __builtin_amdgcn_smfmac_i32_32x32x64_i8(
+              __builtin_bit_cast(fi32x4, av[m]), bq0, acc[f >> 1][m][f & 1], (int)ap[m], 0, 0);
+        bq0 = bq1;
       }
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -313,9 +343,9 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
   fetch(0, W0, S0);
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-  for (int c = 0; c < nst; c += 2) {
-    stage(c, W0, S0, W1, S1);
-    if (c + 1 < nst) stage(c + 1, W1, S1, W0, S0);
+  for (int c = 0; c < nst; ++c) {
+    const bool odd = c & 1;
+    stage(c, odd ? W1 : W0, odd ? S1 : S0, odd ? W0 : W1, odd ? S0 : S1);
   }
 
   // ---- epilogue: energies -> log-softmax, objective, residual digits, dh ----
@@ -328,7 +358,11 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
   // per digit and row block) and copied out 16 bytes per lane.  The field
   // gradient sums the staged digits (exact integers).  Park, weights, symbols
   // and staging are this wave's own, so the epilogue needs no block barrier.
-  const int nch = a.B_pad >> 8;
+  const int nch = B_pad >> 8;
+  const float* hfield = load_uniform(&ea->h);
+  const double* wts = load_uniform(&ea->w);
+  const uint8_t* msa_cm = load_uniform(&ea->msa_cm);
+  const int Bn = load_uniform(&ea->B);
   float* park = wid < 4 ? reinterpret_cast<float*>(W0) + wid * kFIParkFloats
                         : reinterpret_cast<float*>(W1) + (wid - 4) * kFIParkFloats;
   uint8_t* stg = reinterpret_cast<uint8_t*>(park);
@@ -336,7 +370,7 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
   if (tid < 3 * 24) {
     const int g = tid / 24, ss = tid - g * 24;
     const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
-    hsh[tid] = (g < cnt && ss < q) ? gmem(a.h)[rg * q + ss] : 0.f;
+    hsh[tid] = (g < cnt && ss < q) ? gmem(hfield)[rg * q + ss] : 0.f;
   }
   __syncthreads();
   double* wv = wrow + wid * 32;    // this wave's row block: weights and
@@ -348,14 +382,14 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
 #pragma unroll
   for (int m = 0; m < kFIRB; ++m) {
     const int brow = b0 + (wid * kFIRB + m) * 32;
-    if (lane < 32) wv[lane] = brow + lane < a.B ? gmem(a.w)[brow + lane] : 0.0;
+    if (lane < 32) wv[lane] = brow + lane < Bn ? gmem(wts)[brow + lane] : 0.0;
 #pragma unroll
     for (int k2 = 0; k2 < 2; ++k2) {
       const int e2 = lane + 64 * k2;
       if (e2 < 96) {
         const int g2 = e2 >> 5, row2 = e2 & 31;
         const int r2 = g2 == 0 ? rs[0] : (g2 == 1 ? rs[1] : rs[2]);
-        sv[e2] = gmem(a.msa_cm)[((size_t)(r2 / kFwdChunk) * a.B_pad + brow + row2) * kFwdChunk + r2 % kFwdChunk];
+        sv[e2] = gmem(msa_cm)[((size_t)(r2 / kFwdChunk) * B_pad + brow + row2) * kFwdChunk + r2 % kFwdChunk];
       }
     }
     // this row block's energies without h
@@ -430,7 +464,7 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
       }
     }
     // staged digits -> the fragment layout, 16 bytes per lane (sites of the group only)
-    auto Ri = gmem_w(reinterpret_cast<int8_t*>(a.R));
+    auto Ri = gmem_w(reinterpret_cast<int8_t*>(load_uniform(&ea->R)));
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       const int k = lane + 64 * i;  // (site, digit) segment k / 42, 16-byte part k % 42
@@ -481,7 +515,7 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
     double t = 0.0;
     for (int w = 0; w < kFIWaves; ++w) t += red[w * 64 + tid];
     const int rg = tid == 0 ? rs[0] : (tid == 1 ? rs[1] : rs[2]);
-    gmem_w(a.f_part)[(size_t)tile * N + rg] = t;
+    gmem_w(load_uniform(&ea->f_part))[(size_t)tile * N + rg] = t;
   }
   __syncthreads();
   red[wid * 64 + lane] = (double)ghi;
@@ -491,7 +525,7 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs& a, const
     double t = 0.0;
     for (int w = 0; w < kFIWaves; ++w) t += red[w * 64 + tid];
     const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
-    gmem_w(a.gh_part)[((size_t)tile * N + rg) * kSlot + ss] = ss < q ? t * (1.0 / (double)(1 << kRiScaleLog2)) : 0.0;
+    gmem_w(load_uniform(&ea->gh_part))[((size_t)tile * N + rg) * kSlot + ss] = ss < q ? t * (1.0 / (double)(1 << kRiScaleLog2)) : 0.0;
   }
 }
 
@@ -512,8 +546,7 @@ __global__ __launch_bounds__(kFIThreads) void fwd_i8_kernel(BatchArgs b) {
     const int32_t t = __builtin_amdgcn_readfirstlane(item_s);
     if (t < 0) break;
     const Item it = decode_item(b, KIND_FWD, t);
-    const EvalArgs a = load_uniform(b.ev + it.m);
-    fwd_i8_item(b, a, it, W0, W1, S0, S1, red, wrow, srow);
+    fwd_i8_item(b, b.ev + it.m, it, W0, W1, S0, S1, red, wrow, srow);
     __syncthreads();
   }
 }
