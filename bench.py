@@ -63,6 +63,9 @@ PATH_NAMES = {0: "gather_fp32", 1: "mfma_bf16x2", 2: "gather_mfma_fp32", 3: "mfm
 PATH_PIECES = {0: (0, 0), 1: (2, 2), 2: (0, 3), 3: (3, 3), 4: (0, 2), 5: (0, 3), 6: (3, 3), 7: (0, 6)}
 # the int8 matrix-core kernels (path, direction)
 INT8_KERNELS = {(5, "backward"), (6, "backward"), (6, "forward"), (7, "backward")}
+# kernels on the 4:2 structured-sparse matrix-core product (one instruction slot
+# covers two dense-equivalent operations)
+SPARSE_KERNELS = {(6, "forward")}
 # reduced-precision first paths and the FP32-class path the library refines them on
 REFINED = {6: 5, 1: 3}
 # the refinement's tolerance on its FP32-class evaluation: at N = 500 its gradient
@@ -389,6 +392,8 @@ def main():
                 int8 = (path, dom) in INT8_KERNELS
                 peak = MFMA_I8_PEAK if int8 else MFMA_BF16_PEAK
                 dense_per_unit = 2 * Q * npc
+                sparse = (path, dom) in SPARSE_KERNELS
+                issued_per_unit = dense_per_unit // 2 if sparse else dense_per_unit
                 # the method's own work: one add per unit in this direction
                 roofline = {"bound": "mfma", "achieved": units_main / t_dom / 1e12, "peak": peak / 1e12,
                             "unit": "TOP/s" if int8 else "TFLOP/s", "frac": units_main / t_dom / peak,
@@ -396,6 +401,8 @@ def main():
                             "dense_ops_per_unit": dense_per_unit,
                             "dense_achieved": units_main * dense_per_unit / t_dom / 1e12,
                             "dense_frac": units_main * dense_per_unit / t_dom / peak,
+                            "structured_sparse_4to2": sparse,
+                            "matrix_core_frac": units_main * issued_per_unit / t_dom / peak,
                             "alu_add_equivalent_frac": units_main / t_dom / ALU_ADD_PEAK}
             else:
                 kname = dom
