@@ -366,11 +366,13 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs* ea, cons
   float* park = wid < 4 ? reinterpret_cast<float*>(W0) + wid * kFIParkFloats
                         : reinterpret_cast<float*>(W1) + (wid - 4) * kFIParkFloats;
   uint8_t* stg = reinterpret_cast<uint8_t*>(park);
-  float* hsh = reinterpret_cast<float*>(S0);  // fields of the group's sites, [site][24]
+  // fields of the group's sites, [site][24]; states >= q get -inf, so that
+  // their energies drop out of the softmax and their residuals are exactly 0
+  float* hsh = reinterpret_cast<float*>(S0);
   if (tid < 3 * 24) {
     const int g = tid / 24, ss = tid - g * 24;
     const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
-    hsh[tid] = (g < cnt && ss < q) ? gmem(hfield)[rg * q + ss] : 0.f;
+    hsh[tid] = ss >= q ? -INFINITY : (g < cnt ? gmem(hfield)[rg * q + ss] : 0.f);
   }
   __syncthreads();
   double* wv = wrow + wid * 32;    // this wave's row block: weights and
@@ -427,13 +429,12 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs* ea, cons
       }
       const int sr = sv[g * 32 + row];
       const double wb = wv[row];
-      float mx = -INFINITY, esr = 0.f;
+      // the observed state's energy read back by index (no per-state compare
+      // masks kept alive between the loops)
+      const float esr = park[(g * 32 + row) * 24 + sr] + hsh[g * 24 + sr];
+      float mx = -INFINITY;
 #pragma unroll
-      for (int st = 0; st < kSlot; ++st) {
-        if (st >= q) e[st] = -INFINITY;
-        mx = fmaxf(mx, e[st]);
-        esr = st == sr ? e[st] : esr;
-      }
+      for (int st = 0; st < kSlot; ++st) mx = fmaxf(mx, e[st]);
       // exp(x) = 2^(x log2 e) on the hardware exponential; x <= 0, so no range
       // handling is needed (|x| log2 e is rounded to 2^-24 relative, i.e. the
       // probability e^x moves by at most 2^-24 |x| e^x < 2.2e-8 absolute)
@@ -452,7 +453,7 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs* ea, cons
 #pragma unroll
       for (int st = 0; st < kSlot; ++st) {
         const float P = e[st] * inv;
-        const float Rv = st < q ? wf * (P - (st == sr ? 1.f : 0.f)) : 0.f;
+        const float Rv = wf * (P - (st == sr ? 1.f : 0.f));  // P = 0 for states >= q
         const int v = (int)rintf(Rv * (float)(1 << kRiScaleLog2));
         const int lo = (int)(int8_t)(v & 255);
         const int v1 = (v - lo) >> 8;
