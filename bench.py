@@ -34,7 +34,7 @@ The evaluation schedule (path, forward tile) is the autotuner's choice for
 the workload, timed on the device before the warm-up (--path to force one).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload W] [--path auto|0..6]
-                       [--method asymmetric|symmetric] [--init zero|mf]
+                       [--method asymmetric|symmetric [--split]] [--init zero|mf]
 """
 from __future__ import annotations
 
@@ -200,6 +200,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--refine-tol", type=float, default=FIT_TOL_FINAL)
     ap.add_argument("--history-fp64", action="store_true")
+    ap.add_argument("--split", action="store_true",
+                    help="symmetric fit with the parameters carried as FP32 pairs (plm_fit_symmetric_split)")
     ap.add_argument("--plain-sites", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -300,7 +302,7 @@ def main():
         elif symmetric:
             _, w, beff = ws[0]
             h0, J0 = start_point(w, beff)
-            res = [plm.fit_symmetric(msas[0], w, beff, o, h0=h0, J0=J0)]
+            res = [plm.fit_symmetric(msas[0], w, beff, o, h0=h0, J0=J0, split=args.split)]
         else:
             _, w, beff = ws[0]
             h0, J0 = start_point(w, beff)
@@ -454,6 +456,7 @@ def main():
                 "refine_tol": refine_tol if refined else None, "first_fit_tol": main_tol if refined else None,
                 "path": PATH_NAMES[path], "tile_seqs": tile, "schedule": "autotuned" if tuned else "fixed",
                 "method": args.method, "init": args.init, "history_fp64": args.history_fp64,
+                "parameters": "FP32 pairs (high + low word, FP64 sums)" if (symmetric and args.split) else "FP32",
                 "refine": (PATH_NAMES[7] if symmetric else PATH_NAMES[REFINED[path]]) if refined else None,
                 "fit_launch": "captured graph, one replay per iteration"})
     if mf_start:

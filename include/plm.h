@@ -359,6 +359,25 @@ int plm_fit_symmetric(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, in
                       void *workspace, size_t workspace_bytes, float *h_io, float *J_io,
                       plm_site_stats *stats_out);
 
+/* The symmetric fit with every parameter carried as a pair of FP32 words
+ * (a high word and a low word; the parameter is their sum, formed in FP64,
+ * about 48 significant bits), for tolerances below what FP32 storage of the
+ * parameters allows: at N = 500 the rounding of h and J to FP32 alone leaves
+ * ||grad|| near 3e-6.  h_lo_io [N][q] and J_lo_io [N][N][q][q] (DEVICE,
+ * float) hold the low words of the start point on entry (zeros for an FP32
+ * start; J_lo_io is made consistent like J_io) and of the result on return;
+ * h_io, J_io hold the high words (hi = fl32(hi + lo)).  The optimiser forms
+ * every iterate and trial point in FP64 and splits it; the precise path
+ * (PLM_PATH_GATHER64_MFMA_I8X6, the automatic refinement of the fixed-point
+ * paths) evaluates at the FP64 sums, the other paths at the high words (their
+ * own rounding is far above the difference).  Both low-order pointers must be
+ * given; plm_fit_symmetric is this call with both NULL.  Workspace, options,
+ * statistics and errors as for plm_fit_symmetric. */
+int plm_fit_symmetric_split(plm_ctx *ctx, const uint8_t *msa, int32_t B, int32_t N, int32_t q,
+                            const double *w, const double *beff, const plm_fit_opts *opts,
+                            void *workspace, size_t workspace_bytes, float *h_io, float *J_io,
+                            float *h_lo_io, float *J_lo_io, plm_site_stats *stats_out);
+
 /* ---- Mean-field starting guess (sec. 2, sec. 7) ------------------------------
  * Couplings from the inverse of the connected correlation matrix
  * c_ij(k,l) = f_ij(k,l) - f_i(k) f_j(l) over the states k, l < q-1 (the last

@@ -173,6 +173,8 @@ def lib():
             "plm_fit_symmetric_workspace_bytes": (SZ, [I32, I32, I32, ctypes.POINTER(FitOpts)]),
             "plm_fit_symmetric": (ctypes.c_int, [P, P, I32, I32, I32, P, P, ctypes.POINTER(FitOpts), P, SZ, P,
                                                  P, ctypes.POINTER(SiteStats)]),
+            "plm_fit_symmetric_split": (ctypes.c_int, [P, P, I32, I32, I32, P, P, ctypes.POINTER(FitOpts), P, SZ,
+                                                       P, P, P, P, ctypes.POINTER(SiteStats)]),
             "plm_mf_init_workspace_bytes": (SZ, [I32, I32, I32]),
             "plm_mf_init": (ctypes.c_int, [P, P, I32, I32, I32, P, P, D, P, SZ, P, P]),
             "plm_tune": (ctypes.c_int, [P, ctypes.POINTER(MsaDesc), I32, I32, ctypes.POINTER(FitOpts), I32, P,
@@ -194,5 +196,5 @@ def exported_symbols():
             "plm_fit_workspace_bytes", "plm_fit", "plm_score", "plm_fit_last_timing",
             "plm_fit_batch_workspace_bytes", "plm_fit_batch", "plm_tune", "plm_score_opts_default",
             "plm_frequencies", "plm_score_ex", "plm_contact_tpr", "plm_parse_alignment",
-            "plm_fit_symmetric_workspace_bytes", "plm_fit_symmetric", "plm_mf_init_workspace_bytes",
-            "plm_mf_init"]
+            "plm_fit_symmetric_workspace_bytes", "plm_fit_symmetric", "plm_fit_symmetric_split",
+            "plm_mf_init_workspace_bytes", "plm_mf_init"]

@@ -216,6 +216,10 @@ class FitResult:
     status: int = 0
     # probe entries (numpy [count, 2 + n]: time s, max over sites, per site), if probed
     probe: object = None
+    # low-order words of the parameters (fit_symmetric(..., split=True)): the
+    # point is h + h_lo, J + J_lo, each pair summed in FP64
+    h_lo: object = None
+    J_lo: object = None
 
     @property
     def evaluations(self) -> int:
@@ -266,12 +270,16 @@ def fit(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None, probe: P
     return FitResult(h, J, _stats_list(stats), rc, entries)
 
 
-def fit_symmetric(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None) -> FitResult:
+def fit_symmetric(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None, split: bool = False,
+                  h0_lo=None, J0_lo=None) -> FitResult:
     """Symmetric pseudolikelihood maximisation (sec. 3.2, eqs. npll_1 / l2reg):
     one minimisation of sum_r g_r + lambda_h sum ||h||^2 + lambda_J sum_{i<j} ||J_ij||^2
     with every J_ij shared by sites i and j.  The start point takes the blocks
     J0[r][i], r < i (zeros by default); the result holds J[i][r] = J[r][i]
-    with the state axes swapped.  stats holds one record for the whole problem."""
+    with the state axes swapped.  stats holds one record for the whole problem.
+    split=True carries every parameter as two FP32 words (plm_fit_symmetric_split;
+    start low words h0_lo, J0_lo, zeros by default): the result's h_lo, J_lo
+    hold the low words."""
     opts = opts or FitOptions()
     dev = msa.device
     _dev_tensor(msa, torch.uint8, dev, "msa")
@@ -295,10 +303,24 @@ def fit_symmetric(msa, w, beff, opts: FitOptions | None = None, h0=None, J0=None
     ws = workspace(nbytes, dev)
     stats = (L.SiteStats * 1)()
     ctx = context(dev)
-    rc = _check(L.lib().plm_fit_symmetric(ctx, _ptr(msa), B, N, q, _ptr(w), _ptr(beff), ctypes.byref(co),
-                                          _ptr(ws), ws.numel(), _ptr(h), _ptr(J), stats), ctx)
+    if not split:
+        if h0_lo is not None or J0_lo is not None:
+            raise ValueError("start low words need split=True")
+        rc = _check(L.lib().plm_fit_symmetric(ctx, _ptr(msa), B, N, q, _ptr(w), _ptr(beff), ctypes.byref(co),
+                                              _ptr(ws), ws.numel(), _ptr(h), _ptr(J), stats), ctx)
+        del ws
+        return FitResult(h, J, _stats_list(stats), rc)
+    hl = torch.zeros_like(h) if h0_lo is None else h0_lo.clone().contiguous()
+    Jl = torch.zeros_like(J) if J0_lo is None else J0_lo.clone().contiguous()
+    _dev_tensor(hl, torch.float32, dev, "h0_lo")
+    _dev_tensor(Jl, torch.float32, dev, "J0_lo")
+    if hl.shape != h.shape or Jl.shape != J.shape:
+        raise ValueError("low-order words must have the shapes of h and J")
+    rc = _check(L.lib().plm_fit_symmetric_split(ctx, _ptr(msa), B, N, q, _ptr(w), _ptr(beff), ctypes.byref(co),
+                                                _ptr(ws), ws.numel(), _ptr(h), _ptr(J), _ptr(hl), _ptr(Jl),
+                                                stats), ctx)
     del ws
-    return FitResult(h, J, _stats_list(stats), rc)
+    return FitResult(h, J, _stats_list(stats), rc, h_lo=hl, J_lo=Jl)
 
 
 def mf_init(msa, w, beff, pseudocount: float = 0.5, q: int = 21):

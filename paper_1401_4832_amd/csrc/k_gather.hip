@@ -60,10 +60,12 @@ constexpr int kPosBytes = kQMax * kRowF * 4;  // 5376
 static_assert((kFwdPos - 1) * kPosBytes + 20 * 256 + 255 < 65536, "LDS offsets fit the immediate field");
 constexpr int kFwdJFloats = kFwdPos * kQMax * kRowF;
 constexpr int kFwdParkFloats = kFwdWaves * 16 * 64;
-// LDS floats of the forward block: the J chunk, or the parked energies (AT values)
-template <class AT>
+// LDS floats of the forward block: the J chunk (and, with LO, the chunk of the
+// couplings' low-order words after it), or the parked energies (AT values)
+template <class AT, bool LO>
 constexpr int fwd_lds_floats() {
-  return kFwdJFloats > kFwdParkFloats * (int)(sizeof(AT) / 4) ? kFwdJFloats : kFwdParkFloats * (int)(sizeof(AT) / 4);
+  return kFwdJFloats * (LO ? 2 : 1) > kFwdParkFloats * (int)(sizeof(AT) / 4) ? kFwdJFloats * (LO ? 2 : 1)
+                                                                             : kFwdParkFloats * (int)(sizeof(AT) / 4);
 }
 
 // One forward work item: site r x sequence tile `tile` of one alignment.
@@ -72,10 +74,13 @@ constexpr int fwd_lds_floats() {
 // later the parked energies); sgl: the tile's symbols for those columns; red:
 // FP64 reduction scratch.  AT is the accumulation type of the energies and of
 // the log-softmax and residuals: float, or double (the precise path, whose
-// residuals go out as two sets of int8 digits, rfrag = 3).
-template <int NB, class AT>
+// residuals go out as two sets of int8 digits, rfrag = 3).  LO (with double):
+// the point is h + h_lo, J + J_lo; the low words are staged and gathered like
+// the high ones, and each pair is summed in FP64.
+template <int NB, class AT, bool LO>
 __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, uint2* sgl,
                                 double* red) {
+  static_assert(!LO || sizeof(AT) == 8, "low-order words only with FP64 accumulation");
   constexpr int tileSeq = kFwdWaves * kSlots * NB;
   const int q = a.q, N = a.N, qq = q * q;
   const int tid = item_tid(), lane = tid & 63, wid = tid >> 6;
@@ -87,7 +92,8 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
   const int bw = tile0 + tw;
 
   AT E[NB];
-  const AT hv = act ? (AT)gmem(a.h)[r * q + s] : (AT)0;
+  AT hv = act ? (AT)gmem(a.h)[r * q + s] : (AT)0;
+  if (LO && act) hv += (AT)gmem(a.h_lo)[r * q + s];
 #pragma unroll
   for (int j = 0; j < NB; ++j) E[j] = hv;
 
@@ -102,7 +108,7 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
   // current chunk is gathered
   constexpr int kJPer = (kFwdPos * kQMax * kQMax + kFwdThreads - 1) / kFwdThreads;
   constexpr int kSPer = (tileSeq + kFwdThreads - 1) / kFwdThreads;
-  float jv[kJPer];
+  float jv[kJPer], jl[LO ? kJPer : 1];
   uint2 sv[kSPer];
   auto load = [&](int c) {
 #pragma unroll
@@ -110,7 +116,9 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
       const int e = tid + k * kFwdThreads;
       const int p = e / qq, rem = e - p * qq;
       const int i = c * kFwdPos + p;
-      jv[k] = (e < kFwdPos * qq && i < N && i != r) ? gmem(a.J)[Jr + (size_t)i * qq + rem] : 0.f;
+      const bool in = e < kFwdPos * qq && i < N && i != r;
+      jv[k] = in ? gmem(a.J)[Jr + (size_t)i * qq + rem] : 0.f;
+      if (LO) jl[k] = in ? gmem(a.J_lo)[Jr + (size_t)i * qq + rem] : 0.f;
     }
 #pragma unroll
     for (int k = 0; k < kSPer; ++k) {
@@ -129,6 +137,12 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
         row[ss] = jv[k];
         row[ss + kSlot] = jv[k];
         row[ss + 2 * kSlot] = jv[k];
+        if (LO) {
+          float* rl = row + kFwdJFloats;
+          rl[ss] = jl[k];
+          rl[ss + kSlot] = jl[k];
+          rl[ss + 2 * kSlot] = jl[k];
+        }
       }
     }
 #pragma unroll
@@ -152,7 +166,8 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
       for (int p = 0; p < kFwdPos; ++p) {
         const uint32_t word = p < 4 ? sg.x : sg.y;
         const uint32_t addr = __builtin_amdgcn_perm(lane4, word, 0x0c0c0004u | ((uint32_t)(p & 3) << 8));
-        const AT v = (AT)*reinterpret_cast<const float*>(L + addr + p * kPosBytes);
+        AT v = (AT)*reinterpret_cast<const float*>(L + addr + p * kPosBytes);
+        if (LO) v += (AT)*reinterpret_cast<const float*>(L + kFwdJFloats * 4 + addr + p * kPosBytes);
         if (p == 1) acc1 = v;
         else if (p & 1) acc1 += v;
         else acc0 += v;
@@ -270,9 +285,9 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
 }
 
 // Persistent forward kernel: drains the forward work items of the batch.
-template <int NB, class AT>
+template <int NB, class AT, bool LO>
 __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(BatchArgs b) {
-  __shared__ __attribute__((aligned(16))) float lds[fwd_lds_floats<AT>()];
+  __shared__ __attribute__((aligned(16))) float lds[fwd_lds_floats<AT, LO>()];
   __shared__ uint2 sgl[kFwdWaves * kSlots * NB];
   __shared__ double red[kFwdWaves * 64];
   __shared__ int32_t item_s;
@@ -285,7 +300,7 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(BatchArgs b) {
     if (t < 0) break;
     const Item it = decode_item(b, KIND_FWD, t);
     const EvalArgs a = load_uniform(b.ev + it.m);
-    fwd_item<NB, AT>(a, it.r, it.sub, lds, sgl, red);
+    fwd_item<NB, AT, LO>(a, it.r, it.sub, lds, sgl, red);
     __syncthreads();
   }
 }
@@ -295,14 +310,18 @@ constexpr int kFwdF64Rows = 32;
 int32_t forward_f64_tile_seqs() { return kFwdWaves * kSlots * kFwdF64Rows; }
 
 hipError_t launch_forward(const BatchArgs& b, int32_t nb, int32_t nblocks, int32_t f64, hipStream_t st) {
+  if (f64 == 2) {
+    hipLaunchKernelGGL((fwd_kernel<kFwdF64Rows, double, true>), dim3(nblocks), dim3(kFwdThreads), 0, st, b);
+    return hipGetLastError();
+  }
   if (f64) {
-    hipLaunchKernelGGL((fwd_kernel<kFwdF64Rows, double>), dim3(nblocks), dim3(kFwdThreads), 0, st, b);
+    hipLaunchKernelGGL((fwd_kernel<kFwdF64Rows, double, false>), dim3(nblocks), dim3(kFwdThreads), 0, st, b);
     return hipGetLastError();
   }
   switch (nb) {
-    case 16: hipLaunchKernelGGL((fwd_kernel<16, float>), dim3(nblocks), dim3(kFwdThreads), 0, st, b); break;
-    case 32: hipLaunchKernelGGL((fwd_kernel<32, float>), dim3(nblocks), dim3(kFwdThreads), 0, st, b); break;
-    case 64: hipLaunchKernelGGL((fwd_kernel<64, float>), dim3(nblocks), dim3(kFwdThreads), 0, st, b); break;
+    case 16: hipLaunchKernelGGL((fwd_kernel<16, float, false>), dim3(nblocks), dim3(kFwdThreads), 0, st, b); break;
+    case 32: hipLaunchKernelGGL((fwd_kernel<32, float, false>), dim3(nblocks), dim3(kFwdThreads), 0, st, b); break;
+    case 64: hipLaunchKernelGGL((fwd_kernel<64, float, false>), dim3(nblocks), dim3(kFwdThreads), 0, st, b); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -312,13 +331,16 @@ int32_t forward_resident_blocks(int32_t nb, int32_t f64) {
   int per = 0;
   hipError_t e = hipErrorInvalidValue;
   if (f64) {
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<kFwdF64Rows, double>, kFwdThreads, 0);
+    e = f64 == 2
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<kFwdF64Rows, double, true>, kFwdThreads, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<kFwdF64Rows, double, false>, kFwdThreads,
+                                                           0);
     return (e == hipSuccess && per > 0) ? per : 1;
   }
   switch (nb) {
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<16, float>, kFwdThreads, 0); break;
-    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<32, float>, kFwdThreads, 0); break;
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<64, float>, kFwdThreads, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<16, float, false>, kFwdThreads, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<32, float, false>, kFwdThreads, 0); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fwd_kernel<64, float, false>, kFwdThreads, 0); break;
     default: break;
   }
   return (e == hipSuccess && per > 0) ? per : 1;

@@ -5,6 +5,9 @@
 //
 // The couplings live in the asymmetric layout J[r][i][k][s] (s the state of
 // r), filled consistently: J[i][r] is J[r][i] with the state axes swapped.
+// Optionally every parameter carries an FP32 low-order word (the parameter is
+// hi + lo in FP64): the optimiser forms iterates and trial points in FP64 and
+// stores them as such pairs, and the precise evaluation reads both words.
 // The parameters are h and the blocks J[r][i], r < i.  Every iteration
 // evaluates all N sites with the batch kernels (forward and gradient), then
 // a fixed sequence of kernels runs one limited-memory BFGS step for the whole
@@ -86,15 +89,27 @@ __device__ inline double wave_sum_strided(const double* base, int count, int str
   return t;
 }
 
+// A parameter: its FP32 high word plus, when the low words are carried, the
+// low word, summed in FP64 (about 48 significant bits).
+__device__ inline double pval(const float* hi, const float* lo, size_t j) {
+  return lo ? (double)hi[j] + (double)lo[j] : (double)hi[j];
+}
+// Store v as hi = fl32(v) and, when carried, lo = fl32(v - hi).
+__device__ inline void pstore(float* hi, float* lo, size_t j, double v) {
+  const float h = (float)v;
+  hi[j] = h;
+  if (lo) lo[j] = (float)(v - (double)h);
+}
+
 // gradient of F at the trial point for one parameter (h entry or block entry)
 __device__ inline double sym_grad(const SymArgs& a, bool is_h, size_t j, size_t jm, double ib) {
   if (is_h) {
     const int r = (int)(j / a.q), s = (int)(j - (size_t)r * a.q);
     double t = 0.0;
     for (int k = 0; k < a.tiles; ++k) t += a.gh_part[((size_t)k * a.N + r) * kSlot + s];
-    return t * ib + 2.0 * a.lambda_h * (double)a.Th[j];
+    return t * ib + 2.0 * a.lambda_h * pval(a.Th, a.Thl, j);
   }
-  return (a.gJ[j] + a.gJ[jm]) * ib + 2.0 * a.lambda_J * (double)a.TJ[j];
+  return (a.gJ[j] + a.gJ[jm]) * ib + 2.0 * a.lambda_J * pval(a.TJ, a.TJl, j);
 }
 
 __global__ __launch_bounds__(kSymThreads) void sym_eval_kernel(SymArgs a) {
@@ -103,7 +118,7 @@ __global__ __launch_bounds__(kSymThreads) void sym_eval_kernel(SymArgs a) {
   const double ib = 1.0 / *a.beff;
   double v[3] = {0.0, 0.0, 0.0};  // l2 term, |g|^2, data term (unnormalised)
   for_each_param(a, [&](bool is_h, size_t j, size_t jm) {
-    const double t = is_h ? (double)a.Th[j] : (double)a.TJ[j];
+    const double t = is_h ? pval(a.Th, a.Thl, j) : pval(a.TJ, a.TJl, j);
     const double g = sym_grad(a, is_h, j, jm, ib);
     v[0] += (is_h ? a.lambda_h : a.lambda_J) * t * t;
     v[1] += g * g;
@@ -207,8 +222,8 @@ __global__ __launch_bounds__(kSymThreads) void sym_accept_kernel(SymArgs a) {
         }
       }
       double* Gp = is_h ? a.Gh + j : a.GJ + j;
-      const double t = is_h ? (double)a.Th[j] : (double)a.TJ[j];
-      const double x = is_h ? (double)a.Xh[j] : (double)a.XJ[j];
+      const double t = is_h ? pval(a.Th, a.Thl, j) : pval(a.TJ, a.TJl, j);
+      const double x = is_h ? pval(a.Xh, a.Xhl, j) : pval(a.XJ, a.XJl, j);
       const double gold = *Gp;
       const double g = sym_grad(a, is_h, j, jm, ib);
       if (pair) {
@@ -233,9 +248,14 @@ __global__ __launch_bounds__(kSymThreads) void sym_accept_kernel(SymArgs a) {
       *Gp = g;
       if (is_h) {
         a.Xh[j] = a.Th[j];
+        if (a.Xhl) a.Xhl[j] = a.Thl[j];
       } else {
         a.XJ[j] = a.TJ[j];
         a.XJ[jm] = a.TJ[jm];
+        if (a.XJl) {
+          a.XJl[j] = a.TJl[j];
+          a.XJl[jm] = a.TJl[jm];
+        }
       }
     });
   };
@@ -416,11 +436,11 @@ __global__ __launch_bounds__(kSymThreads) void sym_direct_kernel(SymArgs a) {
     }
     (is_h ? a.Dh : a.DJ)[j] = d;
     if (is_h) {
-      a.Th[j] = (float)((double)a.Xh[j] + d);
+      pstore(a.Th, a.Thl, j, pval(a.Xh, a.Xhl, j) + d);
     } else {
-      const float tv = (float)((double)a.XJ[j] + d);
-      a.TJ[j] = tv;
-      a.TJ[jm] = tv;
+      const double tv = pval(a.XJ, a.XJl, j) + d;
+      pstore(a.TJ, a.TJl, j, tv);
+      pstore(a.TJ, a.TJl, jm, tv);
     }
     v[0] += d * g;
   });
@@ -460,11 +480,11 @@ __global__ __launch_bounds__(kSymThreads) void sym_move_kernel(SymArgs a) {
     if (steep) *Dp = -(is_h ? a.Gh : a.GJ)[j];
     const double d = *Dp;
     if (is_h) {
-      a.Th[j] = (float)((double)a.Xh[j] + alpha * d);
+      pstore(a.Th, a.Thl, j, pval(a.Xh, a.Xhl, j) + alpha * d);
     } else {
-      const float tv = (float)((double)a.XJ[j] + alpha * d);
-      a.TJ[j] = tv;
-      a.TJ[jm] = tv;
+      const double tv = pval(a.XJ, a.XJl, j) + alpha * d;
+      pstore(a.TJ, a.TJl, j, tv);
+      pstore(a.TJ, a.TJl, jm, tv);
     }
   });
 }
@@ -495,23 +515,36 @@ __global__ void sym_finish_kernel(SymArgs a, BatchArgs b) {
   }
 }
 
-// Start point: J made consistent (J[i][r] = J[r][i] transposed, self blocks
-// zero) in place, trial point = start point, optimiser state reset.
+// Start point: J (and its low words) made consistent (J[i][r] = J[r][i]
+// transposed, self blocks zero) in place, trial point = start point, optimiser
+// state reset.
 __global__ __launch_bounds__(kSymThreads) void sym_init_kernel(SymArgs a) {
   const int q = a.q, qq = q * q, N = a.N;
   for (int r = blockIdx.x; r < N; r += gridDim.x)
-    for (int t = threadIdx.x; t < qq; t += blockDim.x) a.XJ[((size_t)r * N + r) * qq + t] = 0.f;
+    for (int t = threadIdx.x; t < qq; t += blockDim.x) {
+      a.XJ[((size_t)r * N + r) * qq + t] = 0.f;
+      if (a.XJl) a.XJl[((size_t)r * N + r) * qq + t] = 0.f;
+    }
   for_each_param(a, [&](bool is_h, size_t j, size_t jm) {
     if (is_h) {
       a.Th[j] = a.Xh[j];
+      if (a.Xhl) a.Thl[j] = a.Xhl[j];
     } else {
       a.XJ[jm] = a.XJ[j];
       a.TJ[j] = a.XJ[j];
       a.TJ[jm] = a.XJ[j];
+      if (a.XJl) {
+        a.XJl[jm] = a.XJl[j];
+        a.TJl[j] = a.XJl[j];
+        a.TJl[jm] = a.XJl[j];
+      }
     }
   });
   for (int r = blockIdx.x; r < N; r += gridDim.x)
-    for (int t = threadIdx.x; t < qq; t += blockDim.x) a.TJ[((size_t)r * N + r) * qq + t] = 0.f;
+    for (int t = threadIdx.x; t < qq; t += blockDim.x) {
+      a.TJ[((size_t)r * N + r) * qq + t] = 0.f;
+      if (a.TJl) a.TJl[((size_t)r * N + r) * qq + t] = 0.f;
+    }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     SymState s;
     s.phase = PH_INIT;

@@ -206,7 +206,7 @@ BatchArgs batch_args(const Tables& t, int32_t n_msas, int32_t total, int32_t gro
 // buffers of the symmetric fit
 struct SymBufs {
   EvalBufs ev;
-  float *Th, *TJ;
+  float *Th, *TJ, *Thl, *TJl;  // trial point and its low-order words
   double *Gh, *GJ, *Dh, *DJ, *part, *small;
   float *Sh, *SJ, *Yh, *YJ;
   SymCoef* coef;
@@ -220,6 +220,8 @@ void layout_sym(Bump& bp, int32_t B, int32_t N, int32_t q, int32_t m, int32_t nb
   const size_t Nq = (size_t)N * q, NNqq = (size_t)N * N * q * q;
   f.Th = bp.take<float>(Nq);
   f.TJ = bp.take<float>(NNqq);
+  f.Thl = bp.take<float>(Nq);
+  f.TJl = bp.take<float>(NNqq);
   f.Gh = bp.take<double>(Nq);
   f.GJ = bp.take<double>(NNqq);
   f.Dh = bp.take<double>(Nq);
@@ -405,6 +407,8 @@ EvalArgs eval_args(const EvalBufs& e, const uint8_t* msa_unused, int32_t B, int3
   a.NG = e.NG;
   a.pad_ = 0;
   a.sorted = e.sorted;
+  a.h_lo = nullptr;
+  a.J_lo = nullptr;
   return a;
 }
 
@@ -1175,15 +1179,21 @@ namespace {
 
 int run_sym_once(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
                  const double* beff, const plm_fit_opts* o, void* ws, size_t ws_bytes, float* h_io,
-                 float* J_io, plm_site_stats* stats_out) {
+                 float* J_io, float* h_lo_io, float* J_lo_io, plm_site_stats* stats_out) {
   if (!c) return PLM_E_INVALID;
   if (!msa || !w || !beff || !o || !h_io || !J_io) return set_err(c, PLM_E_INVALID, "null pointer");
+  if ((h_lo_io == nullptr) != (J_lo_io == nullptr))
+    return set_err(c, PLM_E_INVALID, "pass both low-order arrays or neither");
+  const bool lo = h_lo_io != nullptr;
   int rc = check_sizes(c, B, N, q);
   if (rc) return rc;
   if (!fit_opts_ok(o) || o->single_site) return set_err(c, PLM_E_INVALID, "invalid fit options");
   PathSpec ps;
   if (!path_spec(o->path, &ps))
     return set_err(c, PLM_E_UNSUPPORTED, "evaluation path %d is not available", o->path);
+  // the precise path evaluates at high + low words (its forward's low-word
+  // instance); the other paths read the high words
+  if (lo && ps.f64) ps.f64 = 2;
   if (!path_fits(ps, B)) return set_err(c, PLM_E_UNSUPPORTED, "path %d sums at most 2^24 - 1 sequences exactly", o->path);
   HIPCHK(c, hipSetDevice(c->device));
   const int32_t nblk = 4 * c->ncu;
@@ -1214,8 +1224,16 @@ int run_sym_once(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q
   HIPCHK(c, launch_check_f64(w, (size_t)B, c->pin_dev, st));
   HIPCHK(c, launch_check_f32(h_io, (size_t)N * q, c->pin_dev, st));
   HIPCHK(c, launch_check_f32(J_io, (size_t)N * N * q * q, c->pin_dev, st));
+  if (lo) {
+    HIPCHK(c, launch_check_f32(h_lo_io, (size_t)N * q, c->pin_dev, st));
+    HIPCHK(c, launch_check_f32(J_lo_io, (size_t)N * N * q * q, c->pin_dev, st));
+  }
   HIPCHK(c, launch_pad_msa(msa, B, N, q, f.ev.msa_cm, f.ev.B_pad, f.ev.N_pad, c->pin_dev, st));
-  const EvalArgs a = eval_args(f.ev, msa, B, N, q, w, f.Th, f.TJ, eval_tiles(ps, B, nb), ps);
+  EvalArgs a = eval_args(f.ev, msa, B, N, q, w, f.Th, f.TJ, eval_tiles(ps, B, nb), ps);
+  if (ps.f64 == 2) {
+    a.h_lo = f.Thl;
+    a.J_lo = f.TJl;
+  }
   HIPCHK(c, eval_prepare(ps, a, f.ev.msaT, f.ev.sorted, st));
   HIPCHK(c, launch_setup_msa(b, 0, a, nullptr, 0, N, a.tiles, eval_bwd_blocks(ps, N, q), nullptr, st));
   HIPCHK(c, launch_list_tables(b, nullptr, 0, N, nullptr, st));
@@ -1226,6 +1244,8 @@ int run_sym_once(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q
   S.tol = o->tol; S.lambda_h = o->lambda_h; S.lambda_J = o->lambda_J; S.c1 = 1e-4; S.noise = ps.f64 ? 2e-14 : 1e-7;
   S.beff = beff;
   S.Xh = h_io; S.XJ = J_io; S.Th = f.Th; S.TJ = f.TJ;
+  S.Xhl = h_lo_io; S.XJl = J_lo_io;
+  S.Thl = lo ? f.Thl : nullptr; S.TJl = lo ? f.TJl : nullptr;
   S.Gh = f.Gh; S.GJ = f.GJ; S.Dh = f.Dh; S.DJ = f.DJ;
   S.Sh = f.Sh; S.SJ = f.SJ; S.Yh = f.Yh; S.YJ = f.YJ;
   S.f_part = f.ev.f_part; S.gh_part = f.ev.gh_part; S.gJ = f.ev.gJ;
@@ -1342,9 +1362,9 @@ int32_t refine_path_sym(const plm_fit_opts* o) {
 
 extern "C" {
 
-int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
-                      const double* beff, const plm_fit_opts* o, void* ws, size_t ws_bytes, float* h_io,
-                      float* J_io, plm_site_stats* stats_out) {
+int plm_fit_symmetric_split(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
+                            const double* beff, const plm_fit_opts* o, void* ws, size_t ws_bytes, float* h_io,
+                            float* J_io, float* h_lo_io, float* J_lo_io, plm_site_stats* stats_out) {
   if (!c) return PLM_E_INVALID;
   if (!o) return set_err(c, PLM_E_INVALID, "null pointer");
   const int32_t rp = refine_path_sym(o);
@@ -1352,7 +1372,7 @@ int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int3
     return set_err(c, PLM_E_INVALID, "refine: unknown path %d", rp);
   plm_site_stats first;
   memset(&first, 0, sizeof(first));
-  int rc = run_sym_once(c, msa, B, N, q, w, beff, o, ws, ws_bytes, h_io, J_io, &first);
+  int rc = run_sym_once(c, msa, B, N, q, w, beff, o, ws, ws_bytes, h_io, J_io, h_lo_io, J_lo_io, &first);
   if (rp < 0 || (rc != PLM_OK && rc != PLM_W_MAXITER)) {
     if (stats_out && (rc == PLM_OK || rc == PLM_W_MAXITER)) *stats_out = first;
     return rc;
@@ -1367,7 +1387,7 @@ int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int3
   if (o->refine_tol > 0.0) o2.tol = o->refine_tol;
   plm_site_stats second;
   memset(&second, 0, sizeof(second));
-  const int rc2 = run_sym_once(c, msa, B, N, q, w, beff, &o2, ws, ws_bytes, h_io, J_io, &second);
+  const int rc2 = run_sym_once(c, msa, B, N, q, w, beff, &o2, ws, ws_bytes, h_io, J_io, h_lo_io, J_lo_io, &second);
   if (rc2 != PLM_OK && rc2 != PLM_W_MAXITER) return rc2;
   second.iterations += first.iterations;
   second.evaluations += first.evaluations;
@@ -1388,6 +1408,13 @@ int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int3
     t.site_evals += t1.site_evals;
   }
   return rc2;
+}
+
+int plm_fit_symmetric(plm_ctx* c, const uint8_t* msa, int32_t B, int32_t N, int32_t q, const double* w,
+                      const double* beff, const plm_fit_opts* o, void* ws, size_t ws_bytes, float* h_io,
+                      float* J_io, plm_site_stats* stats_out) {
+  return plm_fit_symmetric_split(c, msa, B, N, q, w, beff, o, ws, ws_bytes, h_io, J_io, nullptr, nullptr,
+                                 stats_out);
 }
 
 void plm_score_opts_default(plm_score_opts* o) {

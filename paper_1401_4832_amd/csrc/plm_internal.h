@@ -95,6 +95,10 @@ struct EvalArgs {
   const uint32_t* sym3;    // [NG][B_pad] symbols of positions 3G, 3G+1, 3G+2 (bytes 0..2)
   int32_t NG;              // position triples, ceil(N / 3)
   int32_t pad_;
+  // low-order words of the evaluation point (the point is h + h_lo, J + J_lo,
+  // summed in FP64); read only by the precise forward's low-word instance
+  const float* h_lo;       // [N][q] or null
+  const float* J_lo;       // [N][N][q][q] or null
 };
 
 // Residuals in gradient-fragment order (rfrag = 1): R_b(s) * kRfScale split
@@ -338,6 +342,9 @@ struct SymArgs {
   double tol, lambda_h, lambda_J, c1, noise;
   const double* beff;
   float *Xh, *XJ, *Th, *TJ;  // iterate (caller's h, J) and trial point, couplings mirrored
+  // low-order words of the iterate (caller's) and of the trial point, or null:
+  // the parameters are then hi + lo, each pair summed in FP64
+  float *Xhl, *XJl, *Thl, *TJl;
   double *Gh, *GJ, *Dh, *DJ;  // full-layout vectors, blocks r < i used
   float *Sh, *SJ, *Yh, *YJ;    // curvature pairs, FP32 (used as stored)
   const double *f_part, *gh_part, *gJ;            // evaluation of the trial point
@@ -395,6 +402,8 @@ hipError_t launch_transpose_msa(const uint8_t* msa_cm, int32_t B_pad, int32_t N_
 hipError_t launch_chunk_sort(const uint8_t* msa_cm, int32_t B3, int32_t B_pad, int32_t N, int32_t q,
                              uint16_t* sorted, hipStream_t st);
 int32_t forward_tile_seqs(int32_t nb);
+// f64: 0 FP32 accumulation, 1 FP64 (the precise path), 2 FP64 reading the
+// low-order words of the point as well (EvalArgs.h_lo, J_lo)
 int32_t forward_resident_blocks(int32_t nb, int32_t f64);
 // f64: the precise path's forward (FP64 energies, log-softmax and residuals,
 // residuals out as two int8 digit sets; its own tile of forward_f64_tile_seqs rows)

@@ -110,3 +110,12 @@ def fixed_point_bounds(msa, w, beff, J, sites):
         Jr[r] = 0
         eps = max(eps, (N - 1) * 2.0 ** -22 * float(Jr.max()))
     return 2 * eps, 2 * eps + 2.0 ** -23 * msa.shape[0] / beff
+
+
+def split_words_ok(hi, lo):
+    """The low word of an FP32 pair is within half the FP32 spacing above the
+    high word's magnitude (hi = fl32(v), lo = fl32(v - hi))."""
+    import torch
+    a = hi.abs()
+    spacing = torch.nextafter(a, torch.full_like(a, float("inf"))) - a
+    return bool(torch.all(lo.abs() <= 0.5 * spacing))

@@ -31,7 +31,7 @@ import torch
 
 import oracle
 import synth
-from tests.helpers import clustered_msa, fixed_point_bounds, hilo_bounds
+from tests.helpers import clustered_msa, fixed_point_bounds, hilo_bounds, split_words_ok
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -242,3 +242,42 @@ def test_fit_full_size_per_path(plm, full, sites_gold, path, tol, refine):
     res, dt = _timed_fit(plm, msa, w, beff, opts)
     label = f"fit, path {path}" + (f" to {tol:g}, refined on path {refine}" if refine >= 0 else "")
     _check_fit(plm, full, sites_gold, res, label, path, dt)
+
+
+@pytest.mark.timeout(900)
+def test_symmetric_split_fit_full_size(plm, full):
+    """The symmetric fit (sec. 3.2, eqs. npll_1, l2reg) at the full size with
+    every parameter carried as a pair of FP32 words (plm_fit_symmetric_split):
+    the int8-gradient path to five times its rounding-floor estimate, then the
+    precise path, evaluating at the FP64 sums, to ||grad F|| <= 1e-6 over all
+    55 M parameters.  The oracle's FP64 gradient (its own weights) at
+    h + h_lo, J + J_lo agrees with the device's norm and is at most 1e-6, so
+    every parameter is within ||grad F|| / mu <= 5e-5 of the exact minimiser
+    (mu = 2 min(lambda_h, lambda_J) = 0.02).  The high words alone (the FP32
+    arrays plm_fit_symmetric returns) are a little further from stationarity
+    and meet the same bar too (measured 8.9e-7; the run is deterministic): an
+    FP32-stored fit stalls near 2.9e-6 because its steps below half an FP32
+    spacing vanish, not for want of a good FP32 point."""
+    import oracle.symmetric as sym
+    s, msa, m, w, beff, g = full
+    print("[case] symmetric split fit N=500 B=50000 to 1e-6", flush=True)
+    floor = plm.autotune.symmetric_floor((msa, w, beff), 21)
+    res = plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=5 * floor, refine_tol=1e-6, path=5), split=True)
+    st = res.stats[0]
+    print(f"  device ||grad F|| {st['gnorm']:.3e} after {st['iterations']} iterations", flush=True)
+    assert st["status"] == "converged" and st["gnorm"] <= 1e-6, st
+    assert split_words_ok(res.h, res.h_lo) and split_words_ok(res.J, res.J_lo)
+    beff_o = float(g["beff"][0])
+
+    def certificate(h, J):
+        _, gh, gJ = sym.objective(s.msa, g["w"], beff_o, h, J, LH, LJ)
+        return float(np.sqrt(np.sum(gh ** 2) + np.sum(gJ ** 2)))
+
+    gn = certificate((res.h.double() + res.h_lo.double()).cpu().numpy(),
+                     (res.J.double() + res.J_lo.double()).cpu().numpy())
+    print(f"  oracle ||grad F|| at the FP64 sums {gn:.3e}", flush=True)
+    assert abs(gn - st["gnorm"]) <= 2e-9, (gn, st["gnorm"])
+    assert gn <= 1e-6 and gn / (2 * min(LH, LJ)) <= 5e-5
+    gn32 = certificate(res.h.cpu().numpy().astype(np.float64), res.J.cpu().numpy().astype(np.float64))
+    print(f"  oracle ||grad F|| at the high words alone {gn32:.3e}", flush=True)
+    assert gn < gn32 <= 1e-6

@@ -17,6 +17,7 @@ import torch
 import oracle
 import synth
 from oracle import symmetric as sym
+from tests.helpers import split_words_ok
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -201,6 +202,73 @@ def test_symmetric_fit_gapped_n120_precise_refinement(plm):
           f"(refinement {tm['refine_iterations']})", flush=True)
     assert abs(gn - st["gnorm"]) <= 1e-9, (gn, st["gnorm"])
     assert gn <= 1e-6 and gn / 0.02 <= 5e-5
+
+
+def test_symmetric_split_fit_n120(plm):
+    """The symmetric fit with the parameters carried as FP32 pairs (high and
+    low word, plm_fit_symmetric_split), N = 120, B = 5000 with gaps: the
+    int8-gradient path to 1e-5, then the precise path, which evaluates at the
+    FP64 sums, to 3e-7.  The oracle's FP64 gradient at h + h_lo, J + J_lo is
+    within 1e-9 of the device's norm and at most 3e-7; every low word is within
+    half the FP32 spacing of its high word and the low-word blocks are
+    consistent like J; the high words alone are further from stationarity (at this size only
+    slightly: FP32 storage matters at N = 500, where an FP32-stored fit stalls
+    near 2.9e-6 -- the full-size test)."""
+    print("[case] split symmetric fit potts_n120_b5000_gaps to 3e-7", flush=True)
+    s = synth.workload("potts_n120_b5000_gaps")
+    msa, w, beff = _gpu_problem(plm, s)
+    res = plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=1e-5, refine_tol=3e-7, path=5), split=True)
+    st = res.stats[0]
+    assert st["status"] == "converged" and st["gnorm"] <= 3e-7, st
+    h64 = res.h.double() + res.h_lo.double()
+    J64 = res.J.double() + res.J_lo.double()
+    assert split_words_ok(res.h, res.h_lo) and split_words_ok(res.J, res.J_lo)
+    h = h64.cpu().numpy()
+    J = J64.cpu().numpy()
+    _check_consistent(res.J_lo.cpu().numpy())
+    _check_consistent(J)
+    F, gn = _certificate(s, h, J, 0.01, 0.01)
+    print(f"  device ||grad F|| {st['gnorm']:.3e}, oracle at the FP64 sums {gn:.3e}, "
+          f"iterations {st['iterations']}", flush=True)
+    assert abs(gn - st["gnorm"]) <= 1e-9, (gn, st["gnorm"])
+    assert gn <= 3e-7
+    # the high words alone: FP32 storage moves the gradient well above the pairs'
+    _, gn32 = _certificate(s, res.h.cpu().numpy().astype(np.float64), res.J.cpu().numpy().astype(np.float64),
+                           0.01, 0.01)
+    print(f"  oracle at the high words alone {gn32:.3e}", flush=True)
+    assert gn32 > gn
+
+
+def test_symmetric_split_start_words_and_errors(plm, small):
+    """A split fit from a split start point: the low words given on entry are
+    part of the point (a start that is already the result of a split fit stays
+    converged at once); both low-order arrays or neither."""
+    s, _, _ = small
+    msa, w, beff = _gpu_problem(plm, s)
+    opts = plm.FitOptions(tol=1e-6, refine_tol=1e-8, path=5)
+    a = plm.fit_symmetric(msa, w, beff, opts, split=True)
+    assert a.stats[0]["status"] == "converged" and a.stats[0]["gnorm"] <= 1e-8, a.stats
+    b = plm.fit_symmetric(msa, w, beff, plm.FitOptions(tol=1e-8, path=7), h0=a.h, J0=a.J, split=True,
+                          h0_lo=a.h_lo, J0_lo=a.J_lo)
+    assert b.stats[0]["status"] == "converged" and b.stats[0]["iterations"] == 0, b.stats
+    assert torch.equal(a.h, b.h) and torch.equal(a.J, b.J)
+    assert torch.equal(a.h_lo, b.h_lo) and torch.equal(a.J_lo, b.J_lo)
+    with pytest.raises(ValueError):
+        plm.fit_symmetric(msa, w, beff, opts, h0_lo=a.h_lo, J0_lo=a.J_lo)
+    import ctypes
+    from paper_1401_4832_amd import _lib as L
+    from paper_1401_4832_amd.api import _ptr, context, workspace
+    B, N = msa.shape
+    co = opts.to_c()
+    nbytes = L.lib().plm_fit_symmetric_workspace_bytes(B, N, 21, ctypes.byref(co))
+    ws = workspace(nbytes, DEV)
+    h = torch.zeros(N, 21, device=DEV)
+    J = torch.zeros(N, N, 21, 21, device=DEV)
+    hl = torch.zeros_like(h)
+    stats = (L.SiteStats * 1)()
+    rc = L.lib().plm_fit_symmetric_split(context(DEV), _ptr(msa), B, N, 21, _ptr(w), _ptr(beff), ctypes.byref(co),
+                                         _ptr(ws), ws.numel(), _ptr(h), _ptr(J), _ptr(hl), None, stats)
+    assert rc == L.PLM_E_INVALID
 
 
 def test_symmetric_errors(plm, small):
