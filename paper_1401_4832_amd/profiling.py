@@ -7,6 +7,9 @@ python -m paper_1401_4832_amd.profiling drive [workload] [path]
     for kernel traces and counters.
 python -m paper_1401_4832_amd.profiling stats <kernel_stats.csv> <out.md> <command...>
     short markdown summary of a rocprofv3 --stats kernel table.
+python -m paper_1401_4832_amd.profiling readbw
+    reference stream rates of the device: a 2 GiB float32 tensor summed
+    (read only), copied (read + write) and filled (write only), best of 5.
 python -m paper_1401_4832_amd.profiling traffic <fetch.csv> <write.csv> <workload> <out_prefix>
     HBM bytes per launch of the forward and backward kernels from FETCH_SIZE
     and WRITE_SIZE (KiB per dispatch), each scaled by what the same counter
@@ -74,6 +77,28 @@ def drive(workload: str = "potts_n500_b50000", path: str = "2"):
     b.copy_(a)
     torch.cuda.synchronize()
     print("drive done", workload, float(f.sum()), flush=True)
+
+
+def readbw():
+    import json
+    import torch
+    dev = torch.device("cuda:0")
+    n = (2 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {}
+    for name, fn, nbytes in (("sum_read", lambda: a.sum(), 4 * n), ("copy_read_write", lambda: b.copy_(a), 8 * n),
+                             ("fill_write", lambda: b.fill_(2.0), 4 * n)):
+        best = 1e9
+        for _ in range(5):
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        out[name] = {"ms": best, "TB_per_s": nbytes / (best * 1e-3) / 1e12}
+    print(json.dumps(out), flush=True)
 
 
 def _rows(path):
@@ -148,7 +173,9 @@ def traffic(fetch_csv: str, write_csv: str, workload: str, out_prefix: str, path
 
 if __name__ == "__main__":
     cmd = sys.argv[1]
-    if cmd == "drive":
+    if cmd == "readbw":
+        readbw()
+    elif cmd == "drive":
         drive(*(sys.argv[2:4]))
     elif cmd == "stats":
         stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
