@@ -230,10 +230,9 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs* ea, cons
   // global -> LDS copies of stage c: the group's digits of triples 4c .. 4c+3
   // (a site's run is contiguous; the last 1 KB copy of a run is moved back to
   // end at the run's end) and the triples' symbols of the item's sequences,
-  // 1 KB per copy, copy k issued by wave k mod 4.  A full stage of a full
+  // 1 KB per copy, copy k issued by wave k mod 8.  A full stage of a full
   // group has the same copies every stage, shifted by the stage's offsets:
-  // wave w copies parts w, w + 4, w + 8, w + 12 of each site's run and two
-  // symbol parts.
+  // wave w copies parts w and w + 8 of each site's run and symbol part w.
   constexpr int kSymParts = kFISeqs / 256;  // 1 KB copies of a triple's symbols
   constexpr int kFullPer = (kFISiteBytes + 1023) / 1024;
   static_assert(kFullPer % kFIWaves == 0 && (kSymParts * kFIStageG) % kFIWaves == 0,
