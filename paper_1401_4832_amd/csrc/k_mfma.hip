@@ -777,10 +777,27 @@ __device__ inline uint4 onehot16_i8(uint4 s16, uint32_t kk) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// The same indicator scaled by -128 (byte 0x80 where the symbol equals the
+// state), in two instructions per word: 0x80808080 - (s ^ k) taken bytewise
+// (no byte of s ^ k exceeds 31, so no borrow crosses a byte) is written as
+// (s ^ ~k) + 0x80808081, one xor-add, and its top bits are the indicator.
+// The products then sum -128 times the digits, each term in [-2^14 + 2^7,
+// 2^14]: exact in int32 while a row collects fewer than 2^31 / 2^14 = 2^17
+// sequences (padded counts are multiples of 3072, so at most 129 024).
+constexpr int kNegSeqMax = 1 << 17;
+__device__ inline uint4 onehot16_neg(uint4 s16, uint32_t nkk) {
+  uint32_t w[4] = {s16.x, s16.y, s16.z, s16.w};
+#pragma unroll
+  for (int h = 0; h < 4; ++h) w[h] = ((w[h] ^ nkk) + 0x80808081u) & 0x80808080u;
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 // LO = false: the residual digits of round(R * 2^22), written to the gradient
 // data part; LO = true (second pass of the precise path): the digits of the
 // remainder, round((R * 2^22 - v) * 2^22), added to it scaled by 2^-44.
-template <bool LO>
+// NEG: the one-hot operand holds -128 for a one (alignments of fewer than
+// kNegSeqMax padded sequences), and the epilogue divides it out exactly.
+template <bool LO, bool NEG>
 __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Item& it, int8_t* Rb0, int8_t* Rb1,
                                uint8_t* sig0, uint8_t* sig1) {
   const int npos_blk = g3_block_positions(a.q);
@@ -805,6 +822,7 @@ __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Ite
     const bool ok = rho < nrows;
     arow_off[m] = ok ? (rho / q) * kSigPitch : 0;
     arow_kk[m] = (ok ? (uint32_t)(rho % q) : 31u) * 0x01010101u;
+    if (NEG) arow_kk[m] = ~arow_kk[m];
   }
   const bool wave_live = wid * kGRB * 32 < nrows;
   uint32_t boff[kGT];
@@ -891,7 +909,8 @@ __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Ite
         uint4 av[kGRB];
 #pragma unroll
         for (int m = 0; m < kGRB; ++m)
-          av[m] = onehot16_i8(*reinterpret_cast<const uint4*>(sgb + arow_off[m] + t * 32), arow_kk[m]);
+          av[m] = NEG ? onehot16_neg(*reinterpret_cast<const uint4*>(sgb + arow_off[m] + t * 32), arow_kk[m])
+                      : onehot16_i8(*reinterpret_cast<const uint4*>(sgb + arow_off[m] + t * 32), arow_kk[m]);
         // the six B fragments (digit, tile) of this step, each read two ahead of its use
         static_assert(kGT == 2, "two column tiles");
         auto ldb = [&](int f) {
@@ -926,8 +945,9 @@ __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Ite
     if (c + 1 < nchunks) chunk(c + 1, Rb1, Rb0, sig1, sig0);
   }
   if (!wave_live) return;
-  constexpr double kScale = LO ? 1.0 / ((double)(1 << kRiScaleLog2) * (double)(1 << kRiScaleLog2))
-                               : 1.0 / (double)(1 << kRiScaleLog2);
+  constexpr double kScale = (LO ? 1.0 / ((double)(1 << kRiScaleLog2) * (double)(1 << kRiScaleLog2))
+                                : 1.0 / (double)(1 << kRiScaleLog2)) *
+                           (NEG ? -1.0 / 128.0 : 1.0);
 #pragma unroll
   for (int T = 0; T < kGT; ++T) {
     const int col = 32 * T + l32;
@@ -971,7 +991,8 @@ __global__ __launch_bounds__(kGThreads) void bwd_i8_kernel(BatchArgs b) {
     if (t < 0) break;
     const Item it = decode_item(b, KIND_BWD, t);
     const EvalArgs a = load_uniform(b.ev + it.m);
-    i8_item<LO>(b, a, it, Rb0, Rb1, sig0, sig1);
+    if (a.B_pad < kNegSeqMax) i8_item<LO, true>(b, a, it, Rb0, Rb1, sig0, sig1);
+    else i8_item<LO, false>(b, a, it, Rb0, Rb1, sig0, sig1);
     __syncthreads();
   }
 }

@@ -198,6 +198,54 @@ def test_objgrad_precise_path_is_fp64_class(plm, B, N, q):
         assert np.all(gJ[r, r] == 0)
 
 
+@pytest.mark.parametrize("path", [5, 6, 7])
+def test_objgrad_int8_gradient_either_side_of_2e17_sequences(plm, path):
+    """The int8 gradient builds its one-hot operand with -128 for a one while an
+    alignment has fewer than 2^17 padded sequences (the int32 sums then hold
+    -128 times the digit sums exactly) and with +1 beyond.  One more sequence
+    of weight zero moves an alignment of 42 * 3072 = 129 024 sequences (the
+    largest multiple of the 3072-sequence padding below 2^17) across that
+    limit: the
+    coupling gradient stays the same bit for bit (its digit sums are exact
+    either way), the objective and field gradient agree to FP64 rounding, and
+    the larger call matches the oracle (FP32 tolerance on paths 5 and 6,
+    FP64 class on path 7)."""
+    B, N, q = 42 * 3072, 5, 21
+    _note(f"objgrad int8 gradient B={B}/{B + 1} N={N} path={path}")
+    rng = np.random.default_rng(131)
+    msa = rng.integers(0, q, size=(B + 1, N), dtype=np.uint8)
+    w_o = rng.uniform(0.2, 1.0, size=B + 1)
+    w_o[B] = 0.0
+    beff_o = float(np.sum(w_o))
+    h, J = random_params(131, N, q, 0.3, 0.2)
+    h32, J32 = h.astype(np.float32), J.astype(np.float32)
+    outs = []
+    for n in (B, B + 1):
+        f, gh, gJ = plm.objgrad(_to(msa[:n]), _to(w_o[:n]), _to(np.array([beff_o])), _to(h32), _to(J32),
+                                0.01, 0.01, path=path)
+        plm.sync(DEV)
+        outs.append((f.cpu().numpy(), gh.cpu().numpy(), gJ.cpu().numpy()))
+    (fa, gha, gJa), (fb, ghb, gJb) = outs
+    assert np.array_equal(gJa, gJb)
+    assert np.all(np.abs(fa - fb) <= 1e-12 * np.abs(fb)), np.max(np.abs(fa - fb) / np.abs(fb))
+    gha64, ghb64 = gha.astype(np.float64), ghb.astype(np.float64)
+    assert np.all(np.abs(gha64 - ghb64) <= 2.0 ** -22 * np.abs(ghb64) + 1e-12 * beff_o)
+    Jz = J32.astype(np.float64)
+    for r in range(N):
+        Jz[r, r] = 0
+    fo, gho, gJo = oracle.objgrad(msa, w_o, beff_o, h32.astype(np.float64), Jz, 0.01, 0.01)
+    frel = float(np.max(np.abs(fb - fo) / np.abs(fo)))
+    if path == 7:
+        excess = max(float(np.max(np.abs(gJb - gJo) - 2.0 ** -24 * np.abs(gJo))),
+                     float(np.max(np.abs(ghb - gho) - 2.0 ** -24 * np.abs(gho)))) / beff_o
+        assert frel <= 1e-11 and excess <= 1e-11, (frel, excess)
+    else:
+        gerr = max(float(np.max(np.abs(gJb - gJo))), float(np.max(np.abs(ghb - gho)))) / beff_o
+        assert frel <= 1e-5 and gerr <= 2e-6, (frel, gerr)
+    for r in range(N):
+        assert np.all(gJb[r, r] == 0)
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_objgrad_workload_gapped(plm, path):
     s = synth.workload("potts_n120_b5000_gaps")
