@@ -342,9 +342,12 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs* ea, cons
   fetch(0, W0, S0);
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-  for (int c = 0; c < nst; ++c) {
-    const bool odd = c & 1;
-    stage(c, odd ? W1 : W0, odd ? S1 : S0, odd ? W0 : W1, odd ? S0 : S1);
+  // unrolled by two so that each stage names its buffers at compile time: with
+  // the buffers picked at run time the compiler cannot tell the copies' target
+  // from the buffer being read and waits for the copies inside the triple loop
+  for (int c = 0; c < nst; c += 2) {
+    stage(c, W0, S0, W1, S1);
+    if (c + 1 < nst) stage(c + 1, W1, S1, W0, S0);
   }
 
   // ---- epilogue: energies -> log-softmax, objective, residual digits, dh ----
