@@ -212,12 +212,10 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs* ea, cons
   const int cnt = it.cnt;
   const int tile = it.sub;
   const int b0 = tile * kFISeqs;
-  int32_t rs[kG3Sites], ks[kG3Sites];
+  int32_t rs[kG3Sites];
 #pragma unroll
-  for (int g = 0; g < kG3Sites; ++g) {
+  for (int g = 0; g < kG3Sites; ++g)
     rs[g] = __builtin_amdgcn_readfirstlane(g < cnt ? bt.active[it.first + g] - bt.site_base[it.m] : it.r);
-    ks[g] = gmem(jexp)[rs[g]];
-  }
   uint32_t boff[2];
 #pragma unroll
   for (int T = 0; T < 2; ++T) {
@@ -300,21 +298,22 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs* ea, cons
   // position 1's states 0..10 (offset 21); half 1 = position 2 (offset 42 - 32)
   // and position 1's states 11..20 (offset 21 - 32)
   const int shA = half ? 16 : 0, oA = half ? 2 * kSlot - 32 : 0, oB = half ? kSlot - 32 : kSlot;
-  // the sparse one-hot operands of triple kg for the wave's row blocks
-  auto build_a = [&](const uint32_t* Sc, int kg, uint4* av, uint32_t* ap) {
+  // the packed symbols of triple kg for the wave's row blocks
+  auto load_s3 = [&](const uint32_t* Sc, int kg, uint32_t* s3) {
 #pragma unroll
-    for (int m = 0; m < kFIRB; ++m)
-      onehot_sparse(Sc[kg * kFISeqs + (wid * kFIRB + m) * 32 + l32], shA, oA, oB, av[m], ap[m]);
+    for (int m = 0; m < kFIRB; ++m) s3[m] = Sc[kg * kFISeqs + (wid * kFIRB + m) * 32 + l32];
   };
   auto stage = [&](int c, const int8_t* Wc, const uint32_t* Sc, int8_t* Wn, uint32_t* Sn) {
     if (c + 1 < nst) fetch(c + 1, Wn, Sn);
     const int ng = min(kFIStageG, NG - c * kFIStageG);
     const char* wb = reinterpret_cast<const char*>(Wc);
+    // each triple's symbols are read one triple ahead
+    uint32_t s3n[kFIRB];
+    load_s3(Sc, 0, s3n);
     for (int kg = 0; kg < ng; ++kg) {
       uint4 av[kFIRB];
       uint32_t ap[kFIRB];
-      build_a(Sc, kg, av, ap);
-      // the six B operands (digit, tile) of this triple, each read one ahead of
+      // the six B operands (digit, tile) of this triple, each read two ahead of
       // its use: the digit fragments of steps 0 and 1 of the lane's half
       const char* fb = wb + kg * kWqGroupBytes;
       auto ldb = [&](int f) {
@@ -323,16 +322,35 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs* ea, cons
         const uint4 y = *reinterpret_cast<const uint4*>(p + 2 * kSlot * 16);
         return fi32x8{(int)x.x, (int)x.y, (int)x.z, (int)x.w, (int)y.x, (int)y.y, (int)y.z, (int)y.w};
       };
-      fi32x8 bq0 = ldb(0);
+      // the symbols read one triple ahead have arrived (lgkmcnt 0, vmcnt and
+      // expcnt left at their maxima, so the stage copies stay in flight): the
+      // one-hot operands are then built while the first B operands are read
+      __builtin_amdgcn_s_waitcnt(0xc07f);
+      fi32x8 bq0 = ldb(0), bq1 = ldb(1);
+#pragma unroll
+      for (int m = 0; m < kFIRB; ++m) onehot_sparse(s3n[m], shA, oA, oB, av[m], ap[m]);
+      load_s3(Sc, min(kg + 1, ng - 1), s3n);
 #pragma unroll
       for (int f = 0; f < 6; ++f) {
-        fi32x8 bq1 = bq0;
-        if (f + 1 < 6) bq1 = ldb(f + 1);
+        fi32x8 bq2 = bq1;
+        if (f + 2 < 6) bq2 = ldb(f + 2);
 #pragma unroll
         for (int m = 0; m < kFIRB; ++m)
           acc[f >> 1][m][f & 1] = __builtin_amdgcn_smfmac_i32_32x32x64_i8(
               __builtin_bit_cast(fi32x4, av[m]), bq0, acc[f >> 1][m][f & 1], (int)ap[m], 0, 0);
         bq0 = bq1;
+        bq1 = bq2;
+      }
+      // issue order: the first two B operands, the one-hot operands and the next
+      // symbols, then each pair of products followed by the reads of the B
+      // operand two ahead
+      __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 80, 0);
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        if (f == 0) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        if (f + 2 < 6) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
       }
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -360,6 +378,22 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs* ea, cons
   // per digit and row block) and copied out 16 bytes per lane.  The field
   // gradient sums the staged digits (exact integers).  Park, weights, symbols
   // and staging are this wave's own, so the epilogue needs no block barrier.
+  // An opaque zero defined here: the epilogue's LDS addresses are offset by it,
+  // so that they are formed after the product loop instead of being held in
+  // vector registers across it (the loop needs every register for its
+  // accumulators and operands); the sites' scale exponents are loaded here for
+  // the same reason.
+  uint32_t zo;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(zo));
+  W0 += zo;
+  W1 += zo;
+  S0 += zo;
+  red = reinterpret_cast<double*>(reinterpret_cast<char*>(red) + zo);
+  wrow = reinterpret_cast<double*>(reinterpret_cast<char*>(wrow) + zo);
+  srow += zo;
+  int32_t ks[kG3Sites];
+#pragma unroll
+  for (int g = 0; g < kG3Sites; ++g) ks[g] = gmem(jexp)[rs[g]];
   const int nch = B_pad >> 8;
   const float* hfield = load_uniform(&ea->h);
   const double* wts = load_uniform(&ea->w);
