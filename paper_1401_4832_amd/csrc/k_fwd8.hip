@@ -247,19 +247,13 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs* ea, cons
 #pragma unroll
         for (int j = 0; j < kFullPer / kFIWaves; ++j) {
           const int off = min((wid + kFIWaves * j) * 1024, kFISiteBytes - 1024);
-          __builtin_amdgcn_global_load_lds(
-              (const void __attribute__((address_space(1)))*)(uniform_ptr(sbase[g] + (size_t)c * kFISiteBytes + off) +
-                                                              lane * 16),
-              (void __attribute__((address_space(3)))*)(Wd + g * kFISiteStride + off), 16, 0, 0);
+          copy16_to_lds(sbase[g] + (size_t)c * kFISiteBytes + off, Wd + g * kFISiteStride + off, lane);
         }
 #pragma unroll
       for (int j = 0; j < kSymParts * kFIStageG / kFIWaves; ++j) {
         const int k = wid + kFIWaves * j, kg = k / kSymParts, part = k - kg * kSymParts;
-        __builtin_amdgcn_global_load_lds(
-            (const void __attribute__((address_space(1)))*)(uniform_ptr(sym3 + (size_t)(c * kFIStageG + kg) * B_pad +
-                                                                        b0 + part * 256) +
-                                                            lane * 4),
-            (void __attribute__((address_space(3)))*)(Sd + kg * kFISeqs + part * 256), 16, 0, 0);
+        copy16_to_lds(sym3 + (size_t)(c * kFIStageG + kg) * B_pad + b0 + part * 256, Sd + kg * kFISeqs + part * 256,
+                      lane);
       }
       return;
     }
@@ -272,16 +266,12 @@ __device__ inline void fwd_i8_item(const BatchArgs& bt, const EvalArgs* ea, cons
         const int off = min(part * 1024, bytes - 1024);
         const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
         const char* src = reinterpret_cast<const char*>(Wq) +
-                          ((size_t)rg * NG + (size_t)c * kFIStageG) * kWqGroupBytes + off + lane * 16;
-        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
-                                         (void __attribute__((address_space(3)))*)(Wd + g * kFISiteStride + off),
-                                         16, 0, 0);
+                          ((size_t)rg * NG + (size_t)c * kFIStageG) * kWqGroupBytes + off;
+        copy16_to_lds(src, Wd + g * kFISiteStride + off, lane);
       } else {
         const int k2 = k - cnt * per, kg = k2 / kSymParts, part = k2 - kg * kSymParts;
-        const uint32_t* src = sym3 + (size_t)(c * kFIStageG + kg) * B_pad + b0 + part * 256 + lane * 4;
-        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
-                                         (void __attribute__((address_space(3)))*)(Sd + kg * kFISeqs + part * 256),
-                                         16, 0, 0);
+        copy16_to_lds(sym3 + (size_t)(c * kFIStageG + kg) * B_pad + b0 + part * 256, Sd + kg * kFISeqs + part * 256,
+                      lane);
       }
     }
   };

@@ -579,12 +579,8 @@ __device__ inline void g3_item(const BatchArgs& bt, const EvalArgs& a, const Ite
     for (int k = wid; k < ninst; k += kGWaves) {
       const int g = k / (kRfChunkBytes / 1024), part = k - g * (kRfChunkBytes / 1024);
       const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
-      const char* src = reinterpret_cast<const char*>(a.R) +
-                        ((size_t)rg * nch_site + c) * kRfChunkBytes + part * 1024 + lane * 16;
-      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
-                                       (void __attribute__((address_space(3)))*)(
-                                           reinterpret_cast<char*>(dst) + g * kGSiteStride + part * 1024),
-                                       16, 0, 0);
+      const char* src = reinterpret_cast<const char*>(a.R) + ((size_t)rg * nch_site + c) * kRfChunkBytes + part * 1024;
+      copy16_to_lds(src, reinterpret_cast<char*>(dst) + g * kGSiteStride + part * 1024, lane);
     }
   };
   uint4 sv;
@@ -857,10 +853,7 @@ __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Ite
     if (cnt == kG3Sites) {
 #pragma unroll
       for (int j = 0; j < 6; ++j)
-        __builtin_amdgcn_global_load_lds(
-            (const void __attribute__((address_space(1)))*)(uniform_ptr(rsrc[j] + (size_t)c * kRiChunkBytes) +
-                                                            lane * 16),
-            (void __attribute__((address_space(3)))*)(reinterpret_cast<char*>(dst) + rdst[j]), 16, 0, 0);
+        copy16_to_lds(rsrc[j] + (size_t)c * kRiChunkBytes, reinterpret_cast<char*>(dst) + rdst[j], lane);
       return;
     }
     const int ninst = cnt * 16;
@@ -869,11 +862,8 @@ __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Ite
       const int off = min(part * 1024, kRiChunkBytes - 1024);
       const int rg = g == 0 ? rs[0] : (g == 1 ? rs[1] : rs[2]);
       const char* src = reinterpret_cast<const char*>(a.R) + (LO ? (size_t)N * nch_site * kRiChunkBytes : 0) +
-                        ((size_t)rg * nch_site + c) * kRiChunkBytes + off + lane * 16;
-      __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
-                                       (void __attribute__((address_space(3)))*)(
-                                           reinterpret_cast<char*>(dst) + g * kISiteStride + off),
-                                       16, 0, 0);
+                        ((size_t)rg * nch_site + c) * kRiChunkBytes + off;
+      copy16_to_lds(src, reinterpret_cast<char*>(dst) + g * kISiteStride + off, lane);
     }
   };
   uint4 sv;
@@ -904,19 +894,28 @@ __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Ite
     if (wave_live) {
       const char* rb = reinterpret_cast<const char*>(cur);
       const uint8_t* sgb = scur + half * 16;
+      static_assert(kGRB == 2 && kGT == 2, "two row blocks, two column tiles");
+      auto ldsym = [&](int m, int t) { return *reinterpret_cast<const uint4*>(sgb + arow_off[m] + t * 32); };
+      auto onehot = [&](uint4 s16, int m) {
+        return NEG ? onehot16_neg(s16, arow_kk[m]) : onehot16_i8(s16, arow_kk[m]);
+      };
+      // row block 0's symbols are read one step ahead
+      uint4 s0 = ldsym(0, 0);
 #pragma unroll 2
       for (int t = 0; t < kISteps; ++t) {
-        uint4 av[kGRB];
-#pragma unroll
-        for (int m = 0; m < kGRB; ++m)
-          av[m] = NEG ? onehot16_neg(*reinterpret_cast<const uint4*>(sgb + arow_off[m] + t * 32), arow_kk[m])
-                      : onehot16_i8(*reinterpret_cast<const uint4*>(sgb + arow_off[m] + t * 32), arow_kk[m]);
+        // the symbols read ahead have arrived (lgkmcnt 0; vmcnt and expcnt at
+        // their maxima, so the chunk copies stay in flight)
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        const uint4 s1 = ldsym(1, t);
         // the six B fragments (digit, tile) of this step, each read two ahead of its use
-        static_assert(kGT == 2, "two column tiles");
         auto ldb = [&](int f) {
           return *reinterpret_cast<const uint4*>(rb + boff[f & 1] + ((f >> 1) * kISteps + t) * (2 * kSlot * 16));
         };
         uint4 bq0 = ldb(0), bq1 = ldb(1);
+        uint4 av[kGRB];
+        av[0] = onehot(s0, 0);
+        s0 = ldsym(0, min(t + 1, kISteps - 1));
+        av[1] = onehot(s1, 1);
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
           uint4 bq2 = bq1;
@@ -927,6 +926,22 @@ __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Ite
                 __builtin_bit_cast(i32x4, av[m]), __builtin_bit_cast(i32x4, bq0), acc[f >> 1][m][f & 1], 0, 0, 0);
           bq0 = bq1;
           bq1 = bq2;
+        }
+        // issue order: row block 1's symbols and the first two B fragments, row
+        // block 0's one-hot operand, its first product, the next symbols, row
+        // block 1's one-hot operand, then each product pair followed by the read
+        // of the B fragment two ahead
+        __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, NEG ? 8 : 16, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, NEG ? 8 : 16, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+#pragma unroll
+        for (int f = 1; f < 6; ++f) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+          if (f + 2 < 6) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
         }
       }
     }

@@ -291,6 +291,20 @@ __device__ inline const T* uniform_ptr(const T* p) {
   return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
 }
 
+// Global -> LDS copy of 16 bytes per lane: lane l moves src + 16 l to
+// dst + 16 l, with src and dst uniform over the wave.  It is issued as a
+// buffer load with an LDS destination rather than the global form: the
+// compiler's wait-count pass takes the global (FLAT-encoded) form for a
+// possible LDS access, and while such a copy is in flight it waits for every
+// outstanding LDS read (lgkmcnt 0) where a use needs only the older ones.
+// The buffer spans 2^31 - 1 bytes from src; offsets here stay below 1 KB.
+__device__ inline void copy16_to_lds(const void* src, void* dst, int lane) {
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<char*>(uniform_ptr(static_cast<const char*>(src))), (short)0, 0x7fffffff, 0x00020000);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)dst, 16, lane * 16, 0, 0,
+                                           0);
+}
+
 __device__ inline int item_tid() {
   int t = (int)threadIdx.x;
   asm volatile("" : "+v"(t));
