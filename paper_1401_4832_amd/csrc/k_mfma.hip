@@ -906,42 +906,41 @@ __device__ inline void i8_item(const BatchArgs& bt, const EvalArgs& a, const Ite
         // the symbols read ahead have arrived (lgkmcnt 0; vmcnt and expcnt at
         // their maxima, so the chunk copies stay in flight)
         __builtin_amdgcn_s_waitcnt(0xc07f);
-        const uint4 s1 = ldsym(1, t);
         // the six B fragments (digit, tile) of this step, each read two ahead of its use
         auto ldb = [&](int f) {
           return *reinterpret_cast<const uint4*>(rb + boff[f & 1] + ((f >> 1) * kISteps + t) * (2 * kSlot * 16));
         };
-        uint4 bq0 = ldb(0), bq1 = ldb(1);
-        uint4 av[kGRB];
-        av[0] = onehot(s0, 0);
+        auto prod = [&](int f, int m, const uint4& av, const uint4& bq) {
+          acc[f >> 1][m][f & 1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+              __builtin_bit_cast(i32x4, av), __builtin_bit_cast(i32x4, bq), acc[f >> 1][m][f & 1], 0, 0, 0);
+        };
+        // issue order, fixed by scheduling fences: row block 1's symbols and the
+        // first two B fragments; row block 0's one-hot operand and its first
+        // product; the next symbols and the third fragment; row block 1's
+        // one-hot operand; then each product pair followed by the read of the
+        // fragment two ahead (an LDS wait then covers only the reads a product
+        // needs)
+        const uint4 s1 = ldsym(1, t);
+        uint4 bq[6];
+        bq[0] = ldb(0);
+        bq[1] = ldb(1);
+        __builtin_amdgcn_sched_barrier(0);
+        const uint4 av0 = onehot(s0, 0);
+        prod(0, 0, av0, bq[0]);
+        __builtin_amdgcn_sched_barrier(0);
         s0 = ldsym(0, min(t + 1, kISteps - 1));
-        av[1] = onehot(s1, 1);
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-          uint4 bq2 = bq1;
-          if (f + 2 < 6) bq2 = ldb(f + 2);
-#pragma unroll
-          for (int m = 0; m < kGRB; ++m)
-            acc[f >> 1][m][f & 1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                __builtin_bit_cast(i32x4, av[m]), __builtin_bit_cast(i32x4, bq0), acc[f >> 1][m][f & 1], 0, 0, 0);
-          bq0 = bq1;
-          bq1 = bq2;
-        }
-        // issue order: row block 1's symbols and the first two B fragments, row
-        // block 0's one-hot operand, its first product, the next symbols, row
-        // block 1's one-hot operand, then each product pair followed by the read
-        // of the B fragment two ahead
-        __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
-        __builtin_amdgcn_sched_group_barrier(0x002, NEG ? 8 : 16, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x002, NEG ? 8 : 16, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        bq[2] = ldb(2);
+        __builtin_amdgcn_sched_barrier(0);
+        const uint4 av1 = onehot(s1, 1);
+        prod(0, 1, av1, bq[0]);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int f = 1; f < 6; ++f) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-          if (f + 2 < 6) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          prod(f, 0, av0, bq[f]);
+          prod(f, 1, av1, bq[f]);
+          __builtin_amdgcn_sched_barrier(0);
+          if (f + 2 < 6) bq[f + 2] = ldb(f + 2);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
