@@ -23,8 +23,9 @@
 // Each digit plane accumulates exactly in int32 (|digit| <= 128, at most
 // 3 ceil(N/3) one-hot terms per output); the planes are combined and scaled
 // back in FP64 once at the end.  The couplings stream through LDS four
-// triples at a time (global -> LDS copies, double-buffered in two separate
-// arrays), the triples' symbols likewise.
+// triples at a time (global -> LDS copies as buffer loads with an LDS
+// destination, double-buffered in two separate arrays), the triples' symbols
+// likewise.
 #include <math.h>
 
 #include "plm_internal.h"

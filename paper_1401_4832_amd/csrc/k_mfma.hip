@@ -510,8 +510,9 @@ __global__ __launch_bounds__(kMThreads) void bwd_mfma_kernel(BatchArgs b) {
 // site product leaves 11 of its 32 columns empty), so every one-hot A
 // fragment feeds four products (two tiles x two pieces).  The residuals come
 // from the forward already split (FP16 hi/lo of R * 2^12, fragment order) and
-// are copied global -> LDS by the load unit (16 bytes per lane, no registers,
-// no conversion), double-buffered one 256-sequence chunk ahead.  One block =
+// are copied global -> LDS by the load unit (buffer loads with an LDS
+// destination, 16 bytes per lane, no registers, no conversion),
+// double-buffered one 256-sequence chunk ahead.  One block =
 // three sites x 512 rows (i, k) (24 columns at q = 21): 8 waves x 2 row blocks
 // of 32 rows; FP32 accumulators folded into FP64 every chunk, as in the
 // single-site kernel, so every output is summed in the same order.
