@@ -78,6 +78,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def plm_default_m() -> int:
+    import dataclasses
+    import paper_1401_4832_amd as plm
+    return next(f.default for f in dataclasses.fields(plm.FitOptions) if f.name == "lbfgs_m")
+
+
 def measured_traffic(kernel: str, workload: str):
     """Per-launch HBM bytes from the committed PMC summary, if it was taken on
     the current kernel sources (else None)."""
@@ -200,6 +206,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--refine-tol", type=float, default=FIT_TOL_FINAL)
     ap.add_argument("--history-fp64", action="store_true")
+    ap.add_argument("--lbfgs-m", type=int, default=plm_default_m(),
+                    help="L-BFGS history size (curvature pairs kept per site)")
     ap.add_argument("--split", action="store_true",
                     help="symmetric fit with the parameters carried as FP32 pairs (plm_fit_symmetric_split)")
     ap.add_argument("--plain-sites", type=int, default=4)
@@ -269,7 +277,7 @@ def main():
     # (the symmetric fit is refined on the precise path, whose gradient norm is the FP64 one)
     refine_tol = (args.tol if symmetric else args.refine_tol) if refined else 0.0
     opts = plm.FitOptions(tol=main_tol if refined else args.tol, refine_tol=refine_tol, path=path,
-                          tile_seqs=tile, history_fp64=args.history_fp64)
+                          tile_seqs=tile, history_fp64=args.history_fp64, lbfgs_m=args.lbfgs_m)
 
     # the convergence probe: eight sampled sites against the oracle's stored minimisers
     probe = None
@@ -455,7 +463,7 @@ def main():
     cfg.update({"q": Q, "theta": 0.8, "lambda_h": 0.01, "lambda_J": 0.01, "tol": args.tol,
                 "refine_tol": refine_tol if refined else None, "first_fit_tol": main_tol if refined else None,
                 "path": PATH_NAMES[path], "tile_seqs": tile, "schedule": "autotuned" if tuned else "fixed",
-                "method": args.method, "init": args.init, "history_fp64": args.history_fp64,
+                "method": args.method, "init": args.init, "history_fp64": args.history_fp64, "lbfgs_m": args.lbfgs_m,
                 "parameters": "FP32 pairs (high + low word, FP64 sums)" if (symmetric and args.split) else "FP32",
                 "refine": (PATH_NAMES[7] if symmetric else PATH_NAMES[REFINED[path]]) if refined else None,
                 "fit_launch": "captured graph, one replay per iteration"})
