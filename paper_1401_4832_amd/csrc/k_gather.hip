@@ -60,8 +60,9 @@ constexpr int kPosBytes = kQMax * kRowF * 4;  // 5376
 static_assert((kFwdPos - 1) * kPosBytes + 20 * 256 + 255 < 65536, "LDS offsets fit the immediate field");
 constexpr int kFwdJFloats = kFwdPos * kQMax * kRowF;
 constexpr int kFwdParkFloats = kFwdWaves * 16 * 64;
-// LDS floats of the forward block: the J chunk (and, with LO, the chunk of the
-// couplings' low-order words after it), or the parked energies (AT values)
+// LDS floats of the forward block: the J chunk (with LO, as the FP64 sums of
+// the couplings' high and low words, twice the bytes), or the parked energies
+// (AT values)
 template <class AT, bool LO>
 constexpr int fwd_lds_floats() {
   return kFwdJFloats * (LO ? 2 : 1) > kFwdParkFloats * (int)(sizeof(AT) / 4) ? kFwdJFloats * (LO ? 2 : 1)
@@ -133,15 +134,20 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
       const int e = tid + k * kFwdThreads;
       if (e < kFwdPos * qq) {
         const int p = e / qq, rem = e - p * qq, kk = rem / q, ss = rem - kk * q;
-        float* row = lds + (p * kQMax + kk) * kRowF;
-        row[ss] = jv[k];
-        row[ss + kSlot] = jv[k];
-        row[ss + 2 * kSlot] = jv[k];
         if (LO) {
-          float* rl = row + kFwdJFloats;
-          rl[ss] = jl[k];
-          rl[ss + kSlot] = jl[k];
-          rl[ss + 2 * kSlot] = jl[k];
+          // the pair's exact FP64 sum (two 24-bit significands 2^24 apart fit
+          // 53 bits), one 8-byte word per entry: the gather then reads one
+          // word and adds once per term
+          double* row = reinterpret_cast<double*>(lds) + (p * kQMax + kk) * kRowF;
+          const double v = (double)jv[k] + (double)jl[k];
+          row[ss] = v;
+          row[ss + kSlot] = v;
+          row[ss + 2 * kSlot] = v;
+        } else {
+          float* row = lds + (p * kQMax + kk) * kRowF;
+          row[ss] = jv[k];
+          row[ss + kSlot] = jv[k];
+          row[ss + 2 * kSlot] = jv[k];
         }
       }
     }
@@ -166,8 +172,15 @@ __device__ inline void fwd_item(const EvalArgs& a, int r, int tile, float* lds, 
       for (int p = 0; p < kFwdPos; ++p) {
         const uint32_t word = p < 4 ? sg.x : sg.y;
         const uint32_t addr = __builtin_amdgcn_perm(lane4, word, 0x0c0c0004u | ((uint32_t)(p & 3) << 8));
-        AT v = (AT)*reinterpret_cast<const float*>(L + addr + p * kPosBytes);
-        if (LO) v += (AT)*reinterpret_cast<const float*>(L + kFwdJFloats * 4 + addr + p * kPosBytes);
+        AT v;
+        if (LO) {
+          // 8-byte rows: twice the float row's byte address, from a base per
+          // four positions so that the offset fits the immediate field
+          const char* L2 = L + (p < 4 ? 0 : 4 * 2 * kPosBytes);
+          v = *reinterpret_cast<const double*>(L2 + 2 * addr + (p & 3) * 2 * kPosBytes);
+        } else {
+          v = (AT)*reinterpret_cast<const float*>(L + addr + p * kPosBytes);
+        }
         if (p == 1) acc1 = v;
         else if (p & 1) acc1 += v;
         else acc0 += v;
