@@ -53,6 +53,9 @@ Q = 21
 # 39.3 T adds/s (the published 157.3 TFLOP/s FP32 peak counts packed FMAs:
 # 2 operations x 2 packed lanes on top of this)
 ALU_ADD_PEAK = 256 * 64 * 2.4e9
+# HBM3E; L2: 16 channels x 128 B per clock per XCD, 8 XCDs, 2.4 GHz
+HBM_PEAK = 8.0e12
+L2_PEAK = 16 * 128 * 8 * 2.4e9
 # dense BF16 matrix-core peak of the MI355X
 MFMA_BF16_PEAK = 2.5e15
 # dense int8 matrix-core peak (ops/s)
@@ -82,6 +85,23 @@ def plm_default_m() -> int:
     import dataclasses
     import paper_1401_4832_amd as plm
     return next(f.default for f in dataclasses.fields(plm.FitOptions) if f.name == "lbfgs_m")
+
+
+def measured_onchip(kernel: str, workload: str):
+    """L2 bytes and LDS busy percentage per all-sites launch from the committed
+    counter summary, if it was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"onchip_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except Exception:
+        return None
+    from paper_1401_4832_amd.profiling import source_hash
+    if d.get("source_hash") != source_hash(kernel):
+        return None
+    return d
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -430,6 +450,19 @@ def main():
                              "kernel": kname, "launches": main_launches, "avg_launch_ms": t_kern / max(1, main_launches),
                              "units_per_launch": units_launch, "timing": "HIP events on the fit's stream, "
                              "separate eager fit of the same workload and schedule"})
+            # the memory-side fractions of the same launches: HBM from the counted
+            # bytes; L2 from the L2 sector counters (scaled like the HBM bytes)
+            # against the nominal L2 rate; the LDS busy share of CU cycles as
+            # counted on an all-sites launch
+            t_launch = t_kern / max(1, main_launches) * 1e-3
+            oc = None if symmetric or ragged else measured_onchip(kname, args.workload)
+            l2 = oc["l2_bytes_per_launch"] * units_launch / (s0.B * s0.N * s0.N * Q) if oc else None
+            roofline.update({
+                "hbm_frac": traffic / t_launch / HBM_PEAK if traffic else None,
+                "l2_bytes": l2,
+                "l2_frac": l2 / t_launch / L2_PEAK if l2 else None,
+                "l2_peak_TB_per_s": L2_PEAK / 1e12,
+                "lds_util_all_sites_launch": oc["lds_util_pct"] / 100.0 if oc else None})
 
     plain = None
     if not args.no_plain and not ragged and not symmetric and not mf_start:

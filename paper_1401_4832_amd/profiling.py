@@ -14,6 +14,10 @@ python -m paper_1401_4832_amd.profiling traffic <fetch.csv> <write.csv> <workloa
     HBM bytes per launch of the forward and backward kernels from FETCH_SIZE
     and WRITE_SIZE (KiB per dispatch), each scaled by what the same counter
     reads for the 1 GiB copy; writes <out_prefix>_<kernel>_<workload>.json.
+python -m paper_1401_4832_amd.profiling onchip <l2.csv> <lds.csv> <workload> <out_prefix>
+    L2 bytes per launch (TCC_READ_SECTORS_sum + TCC_WRITE_SECTORS_sum, scaled
+    by what they read for the 1 GiB copy) and the LDS busy percentage
+    (LdsUtil) of each kernel; writes <out_prefix>_<kernel>_<workload>.txt.
 """
 from __future__ import annotations
 
@@ -171,6 +175,53 @@ def traffic(fetch_csv: str, write_csv: str, workload: str, out_prefix: str, path
         print(out, json.dumps(d))
 
 
+def onchip(l2_csv: str, lds_csv: str, workload: str, out_prefix: str, path: str = "6"):
+    """L2 bytes (TCC_READ_SECTORS_sum + TCC_WRITE_SECTORS_sum, 32-byte sectors,
+    scaled by what they read for the calibration copy) and the LDS busy
+    percentage (LdsUtil: SQ_LDS_IDX_ACTIVE over GRBM_GUI_ACTIVE x CUs) per
+    launch of each kernel of one evaluation."""
+    lr, dr = _rows(l2_csv), _rows(lds_csv)
+    rk, wk = _per_kernel(lr, "TCC_READ_SECTORS_sum"), _per_kernel(lr, "TCC_WRITE_SECTORS_sum")
+    uk = _per_kernel(dr, "LdsUtil")
+
+    def copy_value(d):
+        vals = [v for k, vs in d.items() if "copy" in k.lower() or "elementwise" in k.lower()
+                for v in vs if v > 0]
+        return max(vals) if vals else None
+
+    cr, cw = copy_value(rk), copy_value(wk)
+    if not cr or not cw:
+        raise SystemExit("copy calibration kernel not found in the counter files")
+    sr, sw = COPY_BYTES / cr, COPY_BYTES / cw  # bytes per sector as counted
+    for kname, sym in KERNELS.items():
+        rd = [v for k, vs in rk.items() if sym in k for v in vs]
+        wr = [v for k, vs in wk.items() if sym in k for v in vs]
+        ut = [v for k, vs in uk.items() if sym in k for v in vs]
+        if not rd or not wr or not ut:
+            continue
+        d = {"kernel": kname, "workload": workload, "source_hash": source_hash(kname),
+             "l2_read_bytes_per_launch": sum(rd) / len(rd) * sr,
+             "l2_write_bytes_per_launch": sum(wr) / len(wr) * sw,
+             "l2_bytes_per_launch": sum(rd) / len(rd) * sr + sum(wr) / len(wr) * sw,
+             "lds_util_pct": sum(ut) / len(ut),
+             "copy_read_sectors": cr, "copy_write_sectors": cw,
+             "commands": [
+                 f"rocprofv3 --pmc TCC_READ_SECTORS_sum TCC_WRITE_SECTORS_sum --output-format csv -d "
+                 f"{os.path.dirname(l2_csv)} -o run -- python3 -u -m paper_1401_4832_amd.profiling drive "
+                 f"{workload} {path}",
+                 f"rocprofv3 --pmc LdsUtil --output-format csv -d {os.path.dirname(lds_csv)} -o run -- "
+                 f"python3 -u -m paper_1401_4832_amd.profiling drive {workload} {path}",
+                 f"python -m paper_1401_4832_amd.profiling onchip {l2_csv} {lds_csv} {workload} {out_prefix}"
+                 + ("" if path == "6" else f" {path}")],
+             "note": f"one all-sites evaluation on evaluation path {path}; sectors scaled by {sr:.1f} (read) and "
+                     f"{sw:.1f} (write) bytes, from the {COPY_BYTES >> 30} GiB copy of the same run; LdsUtil is "
+                     "the share of CU cycles the LDS was busy during the launch"}
+        out = f"{out_prefix}_{kname}_{workload}.txt"
+        with open(out, "w") as fh:
+            json.dump(d, fh, indent=1)
+        print(out, json.dumps(d))
+
+
 if __name__ == "__main__":
     cmd = sys.argv[1]
     if cmd == "readbw":
@@ -181,5 +232,7 @@ if __name__ == "__main__":
         stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
     elif cmd == "traffic":
         traffic(*sys.argv[2:7])
+    elif cmd == "onchip":
+        onchip(*sys.argv[2:7])
     else:
         raise SystemExit(__doc__)
